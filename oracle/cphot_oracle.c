@@ -1,0 +1,672 @@
+/*
+ * cphot_oracle.c -- plain, slow FP64 CPU oracle for Cherenkov photon generation
+ * and atmospheric propagation (D. Baack, "Optical Photon Emission in Extended
+ * Airshowers", arXiv 2405.04229).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library. It shares no code,
+ * header, table or constant generator with the HIP library; both sides are
+ * driven by the same seeded inputs and the same counter-based random words,
+ * so every photon can be compared one to one.
+ *
+ * Every function follows the thesis step by step in FP64 with no blocking,
+ * fusion or reordering. Readings taken where the thesis is silent or garbled
+ * are stated next to the step. Build with -ffp-contract=off: the integer photon
+ * count per segment is decided by floating point and must come out identical
+ * to the GPU's.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_ALPHA (1.0 / 137.035999084)  /* fine-structure constant, CODATA 2018 */
+#define ORC_C_M_PER_NS 0.299792458
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based      */
+/* generator family the thesis adopts for reproducible, race-free streams    */
+/* (Sec. 3.1). Written from the published round definition.                   */
+/* ------------------------------------------------------------------------- */
+void orc_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Random word -> uniform on [0,1) with 24 bits, exactly representable in FP32. */
+static double u24(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+/* Random word -> uniform on [0,1) with 32 bits (segment count rounding). */
+static double u32d(uint32_t w) { return (double)w * (1.0 / 4294967296.0); }
+
+enum { TAG_SEGMENT = 0, TAG_CHERENKOV = 1, TAG_FLUOR = 2, TAG_TRAIN = 8 };
+
+static void draw(uint64_t seed, uint32_t k, uint64_t seg, uint32_t tag, uint32_t out[4]) {
+  uint32_t ctr[4] = {k, (uint32_t)seg, (uint32_t)(seg >> 32), tag};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Atmosphere (Sec. 2.3.1, 3.3, 4.1)                                          */
+/* ------------------------------------------------------------------------- */
+enum { PROFILE_LINSLEY5 = 0, PROFILE_HOMOGENEOUS = 1, PROFILE_LINEAR = 2 };
+
+typedef struct {
+  int32_t profile;
+  int32_t n_layers;        /* equal homogeneous layers on [0, h_top) */
+  double a[5], b[5], c[5]; /* Linsley X(h) = a + b exp(-h/c), c in cm */
+  double hb[5];            /* layer lower bounds, m */
+  double kappa;            /* n - 1 = kappa rho / rho(0) */
+  double delta0;           /* homogeneous: n - 1; linear: n - 1 at h = 0 */
+  double h_top;            /* m */
+  double step;             /* refractivity table spacing, m */
+  double rayleigh400;      /* Rayleigh attenuation length at 400 nm, g/cm^2 (0: none) */
+  double aer_tau350;       /* vertical aerosol optical depth at 350 nm (0: none) */
+  double aer_H;            /* aerosol scale height, m */
+  double aer_angstrom;     /* aerosol wavelength exponent */
+  double lam_min, lam_max; /* nm */
+  int32_t n_lam;           /* wavelength bins of the layer absorption table */
+  int32_t pad;
+  double earth_radius;     /* m */
+} orc_atmo_params;
+
+typedef struct {
+  orc_atmo_params p;
+  double rho0;
+  int64_t n_tab;  /* entries 0..n_tab */
+  double* tab;
+  double* layer_delta; /* n_layers */
+  double* layer_ext;   /* n_layers * n_lam, extinction per metre */
+} orc_atmo;
+
+static int linsley_layer(const orc_atmo_params* p, double h) {
+  int i = 0;
+  while (i < 4 && h >= p->hb[i + 1]) ++i;
+  return i;
+}
+
+/* Vertical depth X(h) in g/cm^2 (Linsley parametrisation). */
+double orc_depth(const orc_atmo* A, double h) {
+  const orc_atmo_params* p = &A->p;
+  int i = linsley_layer(p, h);
+  double hcm = h * 100.0;
+  if (i < 4) return p->a[i] + p->b[i] * exp(-hcm / p->c[i]);
+  return p->a[4] - p->b[4] * hcm / p->c[4];
+}
+
+/* Density rho(h) = -dX/dh in g/cm^3. */
+double orc_density(const orc_atmo* A, double h) {
+  const orc_atmo_params* p = &A->p;
+  int i = linsley_layer(p, h);
+  if (i < 4) return (p->b[i] / p->c[i]) * exp(-(h * 100.0) / p->c[i]);
+  return p->b[4] / p->c[4];
+}
+
+/* Refractivity n - 1 from the closed-form profile. The thesis works with the
+ * reduced refractive index n - 1 following density (Sec. 2.3.1, 5.2). */
+double orc_delta_closed(const orc_atmo* A, double h) {
+  const orc_atmo_params* p = &A->p;
+  if (p->profile == PROFILE_HOMOGENEOUS) return p->delta0;
+  if (p->profile == PROFILE_LINEAR) {
+    if (h >= p->h_top) return 0.0;
+    if (h < 0.0) h = 0.0;
+    return p->delta0 * (1.0 - h / p->h_top);
+  }
+  return p->kappa * (orc_density(A, h) / A->rho0);
+}
+
+/* Constant-time lookup in the 1 m table by direct index mapping and linear
+ * interpolation between neighbours (Sec. 4.1, Eq. 4.1). Heights outside the
+ * table are clamped to its ends (the thesis assumes in-range heights). */
+double orc_delta_table(const orc_atmo* A, double h) {
+  double x = h / A->p.step;
+  if (x < 0.0) x = 0.0;
+  if (x > (double)A->n_tab) x = (double)A->n_tab;
+  double fi = floor(x);
+  int64_t idx = (int64_t)fi;
+  if (idx > A->n_tab - 1) { idx = A->n_tab - 1; fi = (double)idx; }
+  double frac = x - fi;
+  return (1.0 - frac) * A->tab[idx] + frac * A->tab[idx + 1];
+}
+
+/* Integral of n - 1 over height between h_lo and h_hi (m * 1). */
+static double delta_integral(const orc_atmo* A, double h_lo, double h_hi) {
+  const orc_atmo_params* p = &A->p;
+  if (p->profile == PROFILE_HOMOGENEOUS) return p->delta0 * (h_hi - h_lo);
+  if (p->profile == PROFILE_LINEAR) {
+    double lo = h_lo < 0 ? 0 : (h_lo > p->h_top ? p->h_top : h_lo);
+    double hi = h_hi < 0 ? 0 : (h_hi > p->h_top ? p->h_top : h_hi);
+    double F_hi = hi - hi * hi / (2.0 * p->h_top);
+    double F_lo = lo - lo * lo / (2.0 * p->h_top);
+    return p->delta0 * (F_hi - F_lo);
+  }
+  /* Linsley: integral of kappa rho/rho0 dh = kappa/rho0 * (X(lo) - X(hi)) / 100 */
+  return p->kappa / A->rho0 * (orc_depth(A, h_lo) - orc_depth(A, h_hi)) / 100.0;
+}
+
+static double rayleigh_length(const orc_atmo* A, double lam_nm) {
+  double r = lam_nm / 400.0;
+  return A->p.rayleigh400 * r * r * r * r;
+}
+
+static double aerosol_tau(const orc_atmo* A, double lam_nm) {
+  return A->p.aer_tau350 * pow(lam_nm / 350.0, -A->p.aer_angstrom);
+}
+
+/* Vertical optical depth between heights lo < hi at wavelength lam. */
+static double vertical_tau(const orc_atmo* A, double lo, double hi, double lam) {
+  double tau = 0.0;
+  if (A->p.rayleigh400 > 0.0) tau += (orc_depth(A, lo) - orc_depth(A, hi)) / rayleigh_length(A, lam);
+  if (A->p.aer_tau350 > 0.0)
+    tau += aerosol_tau(A, lam) * (exp(-lo / A->p.aer_H) - exp(-hi / A->p.aer_H));
+  return tau;
+}
+
+int orc_atmo_create(const orc_atmo_params* p, orc_atmo** out) {
+  if (p->step <= 0 || p->h_top <= 0) return -1;
+  if (p->profile != PROFILE_LINSLEY5 && p->rayleigh400 > 0) return -1;
+  orc_atmo* A = (orc_atmo*)calloc(1, sizeof(orc_atmo));
+  A->p = *p;
+  A->rho0 = p->b[0] / p->c[0];
+  A->n_tab = (int64_t)ceil(p->h_top / p->step);
+  A->tab = (double*)malloc(sizeof(double) * (size_t)(A->n_tab + 1));
+  for (int64_t j = 0; j <= A->n_tab; ++j) A->tab[j] = orc_delta_closed(A, (double)j * p->step);
+  if (p->n_layers > 0) {
+    int L = p->n_layers;
+    double dh = p->h_top / L;
+    A->layer_delta = (double*)malloc(sizeof(double) * (size_t)L);
+    A->layer_ext = (double*)calloc((size_t)L * (size_t)(p->n_lam > 0 ? p->n_lam : 1), sizeof(double));
+    for (int i = 0; i < L; ++i) {
+      double lo = i * dh, hi = (i + 1) * dh;
+      A->layer_delta[i] = orc_delta_closed(A, 0.5 * (lo + hi));
+      for (int k = 0; k < p->n_lam; ++k) {
+        double lam = p->lam_min + (k + 0.5) * (p->lam_max - p->lam_min) / p->n_lam;
+        A->layer_ext[(size_t)i * p->n_lam + k] = vertical_tau(A, lo, hi, lam) / dh;
+      }
+    }
+  }
+  *out = A;
+  return 0;
+}
+
+void orc_atmo_free(orc_atmo* A) {
+  if (!A) return;
+  free(A->tab); free(A->layer_delta); free(A->layer_ext); free(A);
+}
+
+void orc_layer_tables(const orc_atmo* A, double* delta_out, double* ext_out) {
+  int L = A->p.n_layers, K = A->p.n_lam;
+  for (int i = 0; i < L; ++i) delta_out[i] = A->layer_delta[i];
+  for (int i = 0; i < L * K; ++i) ext_out[i] = A->layer_ext[i];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Run description                                                            */
+/* ------------------------------------------------------------------------- */
+enum { TRANSPORT_STRAIGHT = 0, TRANSPORT_LAYERED = 1 };
+enum { DETECTOR_GRID = 0, DETECTOR_SPHERES = 1 };
+enum { SPECTRUM_UNIFORM = 0, SPECTRUM_FRANK_TAMM = 1 };
+
+typedef struct {
+  int32_t transport, detector, spectrum, bunch;
+  uint64_t seed;
+  double h_obs;
+  int32_t nx, ny;       /* ground grid cells */
+  double cell;          /* m */
+  int32_t snx, sny;     /* sphere grid */
+  double pitch, radius; /* m */
+  int32_t n_t, pad;     /* time bins per sphere (+1 overflow) */
+  double dt;            /* ns */
+} orc_run;
+
+enum { ST_BINNED = 0, ST_UPWARD = 1, ST_ABSORBED = 2, ST_OUTSIDE = 3 };
+
+typedef struct {
+  int64_t seg;
+  int32_t k, state;
+  int32_t bin, tbin;
+  double x, y, z;       /* arrival point: ground or sphere entry */
+  double t;             /* ns after the plane front */
+  double tau;           /* optical depth */
+  double lambda;        /* nm */
+  double u_abs;         /* survival uniform */
+  double margin;        /* distance of the arrival point to the nearest bin edge, m */
+  double tmargin;       /* distance of t to the nearest time-bin edge, ns */
+  double ex, ey, ez;    /* emission point */
+  double dx, dy, dz;    /* emission direction */
+} orc_photon;
+
+typedef struct {
+  int32_t n;      /* records drawn */
+  int32_t status; /* 0 ok, 1 below threshold, 2 skipped (non-finite/degenerate/invalid beta) */
+  double mu;      /* expected records */
+  double cos_t, sin2_t;
+} orc_segment;
+
+typedef struct { double core_x, core_y, ax, ay, az; } orc_geom;
+
+/* ------------------------------------------------------------------------- */
+/* Segment yield (Sec. 2.2.1, Eq. 2.2-2.4 and the track integral with the    */
+/* Heaviside step)                                                            */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double S[3], E[3], L, beta, z2;
+  double cos_t, sin_t, sin2;
+  double M[3][3]; /* rotation taking the cone axis (0,0,-1) onto the track direction */
+} seg_setup;
+
+static double frank_tamm_K(double lam_min_nm, double lam_max_nm) {
+  /* integral over lambda of 2 pi alpha / lambda^2, lambda in metres */
+  double l1 = lam_min_nm * 1e-9, l2 = lam_max_nm * 1e-9;
+  return 2.0 * ORC_PI * ORC_ALPHA * (1.0 / l1 - 1.0 / l2);
+}
+
+/* Fills `st` and returns the segment record. The count is the expected number
+ * of records mu = K z^2 L sin^2(theta) / bunch, rounded stochastically:
+ * N = floor(mu) + [u < mu - floor(mu)]. The thesis computes the number of
+ * photons from the yield rather than sampling it (Sec. 4.2); this rounding is
+ * the reading that keeps the mean and needs only IEEE basic operations. */
+static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
+                                 float x0, float y0, float z0, float x1, float y1, float z1,
+                                 float beta_f, float charge_f, uint64_t seg_id, seg_setup* st) {
+  orc_segment out = {0, 0, 0.0, 0.0, 0.0};
+  if (!isfinite(x0) || !isfinite(y0) || !isfinite(z0) || !isfinite(x1) || !isfinite(y1) ||
+      !isfinite(z1) || !isfinite(beta_f) || !isfinite(charge_f)) { out.status = 2; return out; }
+  double beta = (double)beta_f;
+  if (!(beta > 0.0 && beta < 1.0)) { out.status = 2; return out; }
+  double dx = (double)x1 - (double)x0, dy = (double)y1 - (double)y0, dz = (double)z1 - (double)z0;
+  double L = sqrt(dx * dx + dy * dy + dz * dz);
+  if (!(L > 0.0)) { out.status = 2; return out; }
+  /* refractivity at the segment midpoint from the 1 m table */
+  double hm = 0.5 * ((double)z0 + (double)z1);
+  double delta = orc_delta_table(A, hm);
+  /* threshold beta n > 1, with g = beta n - 1 written through eps = 1 - beta */
+  double eps = 1.0 - beta;
+  double g = delta - eps - eps * delta;
+  if (!(g > 0.0)) { out.status = 1; return out; }
+  /* sin^2(theta) = 1 - 1/(beta n)^2 (Eq. 2.3, 2.4) */
+  double s2 = g * (g + 2.0) / ((1.0 + g) * (1.0 + g));
+  double z2 = (double)charge_f * (double)charge_f;
+  double mu = K * z2;
+  mu = mu * L;
+  mu = mu * s2;
+  mu = mu / (double)R->bunch;
+  double fl = floor(mu);
+  uint32_t w[4];
+  draw(R->seed, 0u, seg_id, TAG_SEGMENT, w);
+  int32_t n = (int32_t)fl + (u32d(w[0]) < mu - fl ? 1 : 0);
+  out.n = n; out.mu = mu; out.cos_t = 1.0 / (1.0 + g); out.sin2_t = s2;
+  st->S[0] = x0; st->S[1] = y0; st->S[2] = z0;
+  st->E[0] = x1; st->E[1] = y1; st->E[2] = z1;
+  st->L = L; st->beta = beta; st->z2 = z2;
+  st->cos_t = out.cos_t; st->sin_t = sqrt(s2); st->sin2 = s2;
+  /* Rotation of the cone axis D = (0,0,-1) onto the track direction P by the
+   * 180-degree Euler-Rodrigues rotation about the normalised bisector
+   * A = (D + P)/|D + P| (Sec. 4.2, M = 1 + 2 R^2). The thesis leaves A
+   * unnormalised; the matrix needs |A| = 1. When P is (nearly) opposite to D
+   * the bisector vanishes; then the 180-degree turn about the x axis is used. */
+  double P[3] = {dx / L, dy / L, dz / L};
+  if (1.0 - P[2] < 1e-6) {
+    double Md[3][3] = {{1, 0, 0}, {0, -1, 0}, {0, 0, -1}};
+    memcpy(st->M, Md, sizeof(Md));
+  } else {
+    double a[3] = {P[0], P[1], P[2] - 1.0};
+    double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    a[0] /= na; a[1] /= na; a[2] /= na;
+    st->M[0][0] = -2.0 * a[1] * a[1] - 2.0 * a[2] * a[2] + 1.0;
+    st->M[0][1] = 2.0 * a[0] * a[1];
+    st->M[0][2] = 2.0 * a[0] * a[2];
+    st->M[1][0] = 2.0 * a[0] * a[1];
+    st->M[1][1] = -2.0 * a[0] * a[0] - 2.0 * a[2] * a[2] + 1.0;
+    st->M[1][2] = 2.0 * a[1] * a[2];
+    st->M[2][0] = 2.0 * a[0] * a[2];
+    st->M[2][1] = 2.0 * a[1] * a[2];
+    st->M[2][2] = -2.0 * a[0] * a[0] - 2.0 * a[1] * a[1] + 1.0;
+  }
+  return out;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Transport                                                                  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double pos[3], dir[3];
+  double len;   /* total geometric path */
+  double geo;   /* sum of l (1 - u . axis) */
+  double opt;   /* sum of (n - 1) l */
+  double tau;   /* optical depth */
+  int ok;       /* 0: does not reach the observation level */
+} path_state;
+
+static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Straight line to the horizontal plane z = h (Sec. 3.4.1, Eq. 3.3 with the
+ * sign restored: I = A + ((h - A_z) / u_z) u, a finite point iff u_z != 0). */
+static double straight_to_plane(const double* pos, const double* dir, double h) {
+  return (h - pos[2]) / dir[2];
+}
+
+/* Advance the path state by a straight leg of length s in a medium with
+ * refractivity delta and extinction ext (per metre). */
+static void leg(path_state* ps, const double* axis, double s, double delta, double ext) {
+  for (int j = 0; j < 3; ++j) ps->pos[j] += s * ps->dir[j];
+  ps->len += s;
+  ps->geo += s * (1.0 - dot3(ps->dir, axis));
+  ps->opt += s * delta;
+  ps->tau += s * ext;
+}
+
+/* Refraction at a horizontal boundary in the vector form of Snell's law
+ * (Sec. 3.4.2, Eq. 3.15): A2' = A1' + (sqrt(n2^2 - n1^2 + n1^2 cos^2 a1) - n1 cos a1) N,
+ * with optical vectors A' = n A and N the unit normal pointing along travel. */
+static void refract(double* dir, const double* N, double n1, double n2) {
+  double A1[3] = {n1 * dir[0], n1 * dir[1], n1 * dir[2]};
+  double cos1 = dot3(dir, N);
+  double c = sqrt(n2 * n2 - n1 * n1 + n1 * n1 * cos1 * cos1) - n1 * cos1;
+  for (int j = 0; j < 3; ++j) dir[j] = (A1[j] + c * N[j]) / n2;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One photon record                                                          */
+/* ------------------------------------------------------------------------- */
+static void sphere_candidate(const orc_run* R, const orc_geom* G, double x, double y,
+                             int* isph, double C[3]) {
+  double cx0 = G->core_x - 0.5 * (R->snx - 1) * R->pitch;
+  double cy0 = G->core_y - 0.5 * (R->sny - 1) * R->pitch;
+  double fi = floor((x - cx0) / R->pitch + 0.5);
+  double fj = floor((y - cy0) / R->pitch + 0.5);
+  if (fi < 0 || fj < 0 || fi >= R->snx || fj >= R->sny) { *isph = -1; return; }
+  *isph = (int)fj * R->snx + (int)fi;
+  C[0] = cx0 + fi * R->pitch; C[1] = cy0 + fj * R->pitch; C[2] = R->h_obs;
+}
+
+static double min4(double a, double b, double c, double d) {
+  double m = a < b ? a : b; m = m < c ? m : c; return m < d ? m : d;
+}
+
+static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G, double K,
+                         const seg_setup* st, uint64_t seg_id, uint32_t k, orc_photon* out) {
+  (void)K;
+  const orc_atmo_params* p = &A->p;
+  memset(out, 0, sizeof(*out));
+  out->seg = (int64_t)seg_id; out->k = (int32_t)k; out->bin = -1; out->tbin = -1;
+  uint32_t w[4];
+  draw(R->seed, k, seg_id, TAG_CHERENKOV, w);
+  double f = u24(w[0]);
+  double phi = 2.0 * ORC_PI * u24(w[1]);
+  double lam;
+  if (R->spectrum == SPECTRUM_UNIFORM) lam = p->lam_min + (p->lam_max - p->lam_min) * u24(w[2]);
+  else lam = 1.0 / (1.0 / p->lam_min - u24(w[2]) * (1.0 / p->lam_min - 1.0 / p->lam_max));
+  double u3 = u24(w[3]);
+  out->lambda = lam; out->u_abs = u3;
+  /* photon on the cone around (0,0,-1) (Sec. 4.2), rotated onto the track */
+  double pl[3] = {cos(phi) * st->sin_t, sin(phi) * st->sin_t, -st->cos_t};
+  double u[3];
+  for (int i = 0; i < 3; ++i) u[i] = st->M[i][0] * pl[0] + st->M[i][1] * pl[1] + st->M[i][2] * pl[2];
+  /* emission at a random point along the track (Sec. 4.2, third step) */
+  double P[3];
+  for (int i = 0; i < 3; ++i) P[i] = st->S[i] + f * (st->E[i] - st->S[i]);
+  out->ex = P[0]; out->ey = P[1]; out->ez = P[2];
+  out->dx = u[0]; out->dy = u[1]; out->dz = u[2];
+  double axis[3] = {G->ax, G->ay, G->az};
+  /* upward photons are discarded first (Sec. 5.3.4) */
+  if (!(u[2] < 0.0)) { out->state = ST_UPWARD; return; }
+  if (P[2] < R->h_obs) { out->state = ST_OUTSIDE; out->x = P[0]; out->y = P[1]; out->z = P[2]; return; }
+  path_state ps;
+  memset(&ps, 0, sizeof(ps));
+  memcpy(ps.pos, P, sizeof(P));
+  memcpy(ps.dir, u, sizeof(u));
+  int kbin = 0;
+  if (p->n_lam > 0) {
+    kbin = (int)floor((lam - p->lam_min) / (p->lam_max - p->lam_min) * p->n_lam);
+    if (kbin < 0) kbin = 0;
+    if (kbin > p->n_lam - 1) kbin = p->n_lam - 1;
+  }
+  int layer = 0;
+  double dh = 0.0;
+  if (R->transport == TRANSPORT_LAYERED) {
+    /* homogeneous layers with Snell's law at each boundary (Sec. 3.4.2) */
+    dh = p->h_top / p->n_layers;
+    layer = (int)floor(P[2] / dh);
+    if (layer > p->n_layers - 1) layer = p->n_layers - 1;
+    int obs_layer = (int)floor(R->h_obs / dh);
+    double N[3] = {0.0, 0.0, -1.0};
+    while (layer > obs_layer) {
+      double zb = layer * dh;
+      double s = straight_to_plane(ps.pos, ps.dir, zb);
+      leg(&ps, axis, s, A->layer_delta[layer], A->layer_ext[(size_t)layer * p->n_lam + kbin]);
+      ps.pos[2] = zb;
+      refract(ps.dir, N, 1.0 + A->layer_delta[layer], 1.0 + A->layer_delta[layer - 1]);
+      --layer;
+    }
+  }
+  /* final straight leg to the observation level (ground grid) or a sphere */
+  double s_plane = straight_to_plane(ps.pos, ps.dir, R->h_obs);
+  double s_end = s_plane;
+  double Q[3];
+  for (int j = 0; j < 3; ++j) Q[j] = ps.pos[j] + s_plane * ps.dir[j];
+  int bin = -1;
+  double margin = 0.0;
+  if (R->detector == DETECTOR_GRID) {
+    double gx0 = G->core_x - 0.5 * R->nx * R->cell, gy0 = G->core_y - 0.5 * R->ny * R->cell;
+    double fx = (Q[0] - gx0) / R->cell, fy = (Q[1] - gy0) / R->cell;
+    double ix = floor(fx), iy = floor(fy);
+    margin = min4(fx - ix, ix + 1.0 - fx, fy - iy, iy + 1.0 - fy) * R->cell;
+    if (ix >= 0 && iy >= 0 && ix < R->nx && iy < R->ny) bin = (int)iy * R->nx + (int)ix;
+  } else {
+    int isph; double C[3];
+    sphere_candidate(R, G, Q[0], Q[1], &isph, C);
+    if (isph >= 0) {
+      double q[3] = {Q[0] - C[0], Q[1] - C[1], Q[2] - C[2]};
+      double b = dot3(q, ps.dir);
+      double cc = dot3(q, q) - R->radius * R->radius;
+      double disc = b * b - cc;
+      double dperp2 = dot3(q, q) - b * b;
+      margin = fabs(sqrt(dperp2 > 0 ? dperp2 : 0.0) - R->radius);
+      if (disc >= 0.0) {
+        double s_in = -b - sqrt(disc);
+        s_end = s_plane + s_in;
+        bin = isph;
+      }
+    } else {
+      margin = 1e30;
+    }
+  }
+  /* last leg up to the arrival point */
+  double delta_last = (R->transport == TRANSPORT_LAYERED) ? A->layer_delta[layer] : 0.0;
+  double ext_last = (R->transport == TRANSPORT_LAYERED) ? A->layer_ext[(size_t)layer * p->n_lam + kbin] : 0.0;
+  double start_z = ps.pos[2], dir_z = ps.dir[2];
+  leg(&ps, axis, s_end, delta_last, ext_last);
+  if (R->transport == TRANSPORT_STRAIGHT) {
+    /* straight line in a planar atmosphere: closed forms over the height span */
+    double zlo = ps.pos[2], zhi = start_z;
+    ps.opt = delta_integral(A, zlo, zhi) / fabs(dir_z);
+    ps.tau = 0.0;
+    if (p->rayleigh400 > 0.0 || p->aer_tau350 > 0.0) ps.tau = vertical_tau(A, zlo, zhi, lam) / fabs(dir_z);
+  }
+  out->x = ps.pos[0]; out->y = ps.pos[1]; out->z = ps.pos[2];
+  out->tau = ps.tau;
+  out->t = (ps.geo + ps.opt) / ORC_C_M_PER_NS;
+  out->margin = margin;
+  /* absorption and scattering remove the photon (Sec. 2.3.2): survival iff u < exp(-tau) */
+  if (!(u3 < exp(-ps.tau))) { out->state = ST_ABSORBED; return; }
+  if (bin < 0) { out->state = ST_OUTSIDE; return; }
+  out->state = ST_BINNED;
+  out->bin = bin;
+  if (R->detector == DETECTOR_SPHERES && R->n_t > 0) {
+    double tb = floor(out->t / R->dt);
+    double e0 = fabs(out->t - tb * R->dt), e1 = fabs((tb + 1.0) * R->dt - out->t);
+    out->tmargin = e0 < e1 ? e0 : e1;
+    if (tb < 0) tb = 0;
+    out->tbin = tb >= R->n_t ? R->n_t : (int32_t)tb;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Exported drivers                                                           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const float *x0, *y0, *z0, *x1, *y1, *z1, *beta, *charge;
+  int64_t n;
+  int64_t first_id;
+} orc_segments;
+
+double orc_frank_tamm_K(double lam_min, double lam_max) { return frank_tamm_K(lam_min, lam_max); }
+
+void orc_segment_counts(const orc_atmo* A, const orc_run* R, const orc_segments* S, orc_segment* out) {
+  double K = frank_tamm_K(A->p.lam_min, A->p.lam_max);
+  for (int64_t i = 0; i < S->n; ++i) {
+    seg_setup st;
+    out[i] = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
+                           S->beta[i], S->charge[i], (uint64_t)(S->first_id + i), &st);
+  }
+}
+
+/* All photon records of segments [0, n). Returns the number of records, or
+ * -(needed) when `cap` is too small (nothing written beyond cap). */
+int64_t orc_trace(const orc_atmo* A, const orc_run* R, const orc_segments* S, const orc_geom* G,
+                  orc_photon* out, int64_t cap) {
+  double K = frank_tamm_K(A->p.lam_min, A->p.lam_max);
+  int64_t m = 0;
+  for (int64_t i = 0; i < S->n; ++i) {
+    seg_setup st;
+    orc_segment sg = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
+                                   S->beta[i], S->charge[i], (uint64_t)(S->first_id + i), &st);
+    for (int32_t k = 0; k < sg.n; ++k) {
+      if (m < cap) trace_photon(A, R, G, K, &st, (uint64_t)(S->first_id + i), (uint32_t)k, &out[m]);
+      ++m;
+    }
+  }
+  return m <= cap ? m : -m;
+}
+
+enum {
+  C_SEG_IN = 0, C_SEG_SKIPPED, C_SEG_BELOW, C_REC_GEN, C_REC_UP, C_REC_ABS, C_REC_OUT, C_REC_BIN,
+  C_PHOT_BIN, C_SURR_FALLBACK, N_COUNTERS = 16
+};
+
+typedef struct {
+  const orc_atmo* A; const orc_run* R; const orc_segments* S;
+  int32_t n_showers; const int64_t* offsets; const orc_geom* geoms;
+  int64_t begin, end;
+  uint64_t* bins; uint64_t* thist; uint64_t counters[N_COUNTERS];
+  int64_t bins_per_shower, thist_per_shower;
+} worker_arg;
+
+static void* worker(void* vp) {
+  worker_arg* W = (worker_arg*)vp;
+  const orc_atmo* A = W->A; const orc_run* R = W->R; const orc_segments* S = W->S;
+  double K = frank_tamm_K(A->p.lam_min, A->p.lam_max);
+  int32_t sh = 0;
+  for (int64_t i = W->begin; i < W->end; ++i) {
+    while (W->offsets && i >= W->offsets[sh + 1]) ++sh;
+    seg_setup st;
+    uint64_t sid = (uint64_t)(S->first_id + i);
+    orc_segment sg = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
+                                   S->beta[i], S->charge[i], sid, &st);
+    W->counters[C_SEG_IN] += 1;
+    if (sg.status == 2) { W->counters[C_SEG_SKIPPED] += 1; continue; }
+    if (sg.status == 1) { W->counters[C_SEG_BELOW] += 1; continue; }
+    for (int32_t k = 0; k < sg.n; ++k) {
+      orc_photon ph;
+      trace_photon(A, R, &W->geoms[sh], K, &st, sid, (uint32_t)k, &ph);
+      W->counters[C_REC_GEN] += 1;
+      switch (ph.state) {
+        case ST_UPWARD: W->counters[C_REC_UP] += 1; break;
+        case ST_ABSORBED: W->counters[C_REC_ABS] += 1; break;
+        case ST_OUTSIDE: W->counters[C_REC_OUT] += 1; break;
+        default:
+          W->counters[C_REC_BIN] += 1;
+          W->counters[C_PHOT_BIN] += (uint64_t)R->bunch;
+          W->bins[(int64_t)sh * W->bins_per_shower + ph.bin] += (uint64_t)R->bunch;
+          if (W->thist && ph.tbin >= 0)
+            W->thist[(int64_t)sh * W->thist_per_shower + (int64_t)ph.bin * (R->n_t + 1) + ph.tbin] +=
+                (uint64_t)R->bunch;
+      }
+    }
+  }
+  return NULL;
+}
+
+/* Full propagation: bins (u64, [n_showers][cells or spheres]), optional time
+ * histograms (u64, [n_showers][spheres][n_t + 1]) and counters (u64 x 16) are
+ * accumulated (+=). Threads split the segment range; counts are integers, so
+ * the result does not depend on the thread count. */
+int orc_propagate(const orc_atmo* A, const orc_run* R, const orc_segments* S, int32_t n_showers,
+                  const int64_t* offsets, const orc_geom* geoms, uint64_t* bins, uint64_t* thist,
+                  uint64_t* counters, int32_t n_threads) {
+  if (n_threads < 1) n_threads = 1;
+  int64_t bps = R->detector == DETECTOR_GRID ? (int64_t)R->nx * R->ny : (int64_t)R->snx * R->sny;
+  int64_t tps = R->detector == DETECTOR_SPHERES && R->n_t > 0 ? bps * (R->n_t + 1) : 0;
+  worker_arg* W = (worker_arg*)calloc((size_t)n_threads, sizeof(worker_arg));
+  pthread_t* th = (pthread_t*)calloc((size_t)n_threads, sizeof(pthread_t));
+  int64_t chunk = (S->n + n_threads - 1) / n_threads;
+  for (int t = 0; t < n_threads; ++t) {
+    W[t].A = A; W[t].R = R; W[t].S = S; W[t].n_showers = n_showers;
+    W[t].offsets = n_showers > 1 ? offsets : NULL; W[t].geoms = geoms;
+    W[t].begin = t * chunk < S->n ? t * chunk : S->n;
+    W[t].end = (t + 1) * chunk < S->n ? (t + 1) * chunk : S->n;
+    W[t].bins_per_shower = bps; W[t].thist_per_shower = tps;
+    W[t].bins = (uint64_t*)calloc((size_t)(bps * n_showers), sizeof(uint64_t));
+    W[t].thist = tps ? (uint64_t*)calloc((size_t)(tps * n_showers), sizeof(uint64_t)) : NULL;
+    pthread_create(&th[t], NULL, worker, &W[t]);
+  }
+  for (int t = 0; t < n_threads; ++t) {
+    pthread_join(th[t], NULL);
+    for (int64_t j = 0; j < bps * n_showers; ++j) bins[j] += W[t].bins[j];
+    if (tps && thist)
+      for (int64_t j = 0; j < tps * n_showers; ++j) thist[j] += W[t].thist[j];
+    for (int c = 0; c < N_COUNTERS; ++c) counters[c] += W[t].counters[c];
+    free(W[t].bins); free(W[t].thist);
+  }
+  free(W); free(th);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Reference paths used by the pins                                           */
+/* ------------------------------------------------------------------------- */
+
+/* Trace one ray (start point, unit direction) through the layered atmosphere to
+ * the plane z = h_end, for the analytic and closed-form checks. Writes the end
+ * point and the n sin(theta) value of every layer crossed (max `cap`). */
+int orc_layered_ray(const orc_atmo* A, const double* P, const double* u, double h_end,
+                    double* end_out, double* snell_out, int cap) {
+  const orc_atmo_params* p = &A->p;
+  double dh = p->h_top / p->n_layers;
+  double pos[3] = {P[0], P[1], P[2]}, dir[3] = {u[0], u[1], u[2]};
+  int layer = (int)floor(pos[2] / dh);
+  if (layer > p->n_layers - 1) layer = p->n_layers - 1;
+  int end_layer = (int)floor(h_end / dh);
+  double N[3] = {0.0, 0.0, -1.0};
+  int m = 0;
+  while (layer > end_layer) {
+    double zb = layer * dh;
+    double s = straight_to_plane(pos, dir, zb);
+    for (int j = 0; j < 3; ++j) pos[j] += s * dir[j];
+    pos[2] = zb;
+    if (m < cap) snell_out[m] = (1.0 + A->layer_delta[layer]) * sqrt(dir[0] * dir[0] + dir[1] * dir[1]);
+    ++m;
+    refract(dir, N, 1.0 + A->layer_delta[layer], 1.0 + A->layer_delta[layer - 1]);
+    --layer;
+  }
+  if (m < cap) snell_out[m] = (1.0 + A->layer_delta[layer]) * sqrt(dir[0] * dir[0] + dir[1] * dir[1]);
+  ++m;
+  double s = straight_to_plane(pos, dir, h_end);
+  for (int j = 0; j < 3; ++j) end_out[j] = pos[j] + s * dir[j];
+  return m;
+}
