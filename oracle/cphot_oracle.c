@@ -305,6 +305,9 @@ static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
   mu = mu * L;
   mu = mu * s2;
   mu = mu / (double)R->bunch;
+  /* A segment asking for 2^20 records or more (or a non-finite yield) is
+   * rejected as invalid input rather than truncated. */
+  if (!(mu < 1048576.0)) { out.status = 2; return out; }
   double fl = floor(mu);
   uint32_t w[4];
   draw(R->seed, 0u, seg_id, TAG_SEGMENT, w);

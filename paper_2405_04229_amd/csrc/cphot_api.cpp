@@ -1,0 +1,422 @@
+// Host side of libcphot: argument checks, atmosphere tables, launch set-up.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "cphot_internal.h"
+
+struct cphot_atmosphere {
+  cphot_atmosphere_desc d;
+  int device = 0;
+  double rho0 = 1.0;
+  int64_t n_tab = 0;
+  cphot::AtmoDevice dev;
+  std::vector<double> layer_delta;  // host copies (FP64) for checks
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return CPHOT_ERR_HIP;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kAlpha = 1.0 / 137.035999084;  // fine-structure constant, CODATA 2018
+
+// ---- atmosphere closed forms (FP64, host) -------------------------------------------
+
+int linsley_layer(const cphot_atmosphere_desc& d, double h) {
+  int i = 0;
+  while (i < 4 && h >= d.lin_hb[i + 1]) ++i;
+  return i;
+}
+
+double depth(const cphot_atmosphere_desc& d, double h) {
+  const int i = linsley_layer(d, h);
+  const double hcm = h * 100.0;
+  if (i < 4) return d.lin_a[i] + d.lin_b[i] * std::exp(-hcm / d.lin_c[i]);
+  return d.lin_a[4] - d.lin_b[4] * hcm / d.lin_c[4];
+}
+
+double density(const cphot_atmosphere_desc& d, double h) {
+  const int i = linsley_layer(d, h);
+  if (i < 4) return (d.lin_b[i] / d.lin_c[i]) * std::exp(-(h * 100.0) / d.lin_c[i]);
+  return d.lin_b[4] / d.lin_c[4];
+}
+
+// n - 1 of the profile. The expression order is fixed: the FP64 table built
+// from it decides integer photon counts.
+double refractivity(const cphot_atmosphere& a, double h) {
+  const cphot_atmosphere_desc& d = a.d;
+  if (d.profile == CPHOT_PROFILE_HOMOGENEOUS) return d.delta0;
+  if (d.profile == CPHOT_PROFILE_LINEAR) {
+    if (h >= d.h_top) return 0.0;
+    if (h < 0.0) h = 0.0;
+    return d.delta0 * (1.0 - h / d.h_top);
+  }
+  return d.kappa * (density(d, h) / a.rho0);
+}
+
+double vertical_tau(const cphot_atmosphere_desc& d, double lo, double hi, double lam) {
+  double tau = 0.0;
+  if (d.rayleigh400 > 0.0) {
+    const double r = lam / 400.0;
+    tau += (depth(d, lo) - depth(d, hi)) / (d.rayleigh400 * r * r * r * r);
+  }
+  if (d.aerosol_tau350 > 0.0)
+    tau += d.aerosol_tau350 * std::pow(lam / 350.0, -d.aerosol_angstrom) *
+           (std::exp(-lo / d.aerosol_height) - std::exp(-hi / d.aerosol_height));
+  return tau;
+}
+
+std::mutex g_dev_mu;
+int g_cu_count[64] = {0};
+
+int cu_count(int dev) {
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if (dev < 0 || dev >= 64) return 256;
+  if (!g_cu_count[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    g_cu_count[dev] = v;
+  }
+  return g_cu_count[dev];
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ---- launch parameters ----------------------------------------------------------------
+
+int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KParams& p, bool need_bins,
+                const cphot_bins* out) {
+  if (!seg || !det) return fail(CPHOT_ERR_INVALID_ARG, "null segments or detector");
+  const cphot_atmosphere* a = det->atm;
+  if (!a) return fail(CPHOT_ERR_INVALID_ARG, "detector has no atmosphere");
+  const cphot_atmosphere_desc& d = a->d;
+  if (seg->n < 0) return fail(CPHOT_ERR_INVALID_ARG, "negative segment count");
+  if (seg->first_id < 0) return fail(CPHOT_ERR_INVALID_ARG, "negative first_id");
+  if (seg->n > 0 && (!seg->x0 || !seg->y0 || !seg->z0 || !seg->x1 || !seg->y1 || !seg->z1 || !seg->beta ||
+                     !seg->charge))
+    return fail(CPHOT_ERR_INVALID_ARG, "null segment array");
+  if (seg->n_showers < 1) return fail(CPHOT_ERR_INVALID_ARG, "n_showers must be >= 1");
+  if (seg->n_showers > 1 && !seg->shower_offsets)
+    return fail(CPHOT_ERR_INVALID_ARG, "shower_offsets required for several showers");
+  if (!seg->shower_geom) return fail(CPHOT_ERR_INVALID_ARG, "shower_geom is required");
+  if (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED)
+    return fail(CPHOT_ERR_INVALID_ARG, "unknown transport");
+  if (det->detector != CPHOT_DETECTOR_GRID && det->detector != CPHOT_DETECTOR_SPHERES)
+    return fail(CPHOT_ERR_INVALID_ARG, "unknown detector");
+  if (det->spectrum != CPHOT_SPECTRUM_UNIFORM && det->spectrum != CPHOT_SPECTRUM_FRANK_TAMM)
+    return fail(CPHOT_ERR_INVALID_ARG, "unknown spectrum");
+  if (det->bunch < 1) return fail(CPHOT_ERR_INVALID_ARG, "bunch must be >= 1");
+  if (!std::isfinite(det->h_obs) || det->h_obs < 0.0 || det->h_obs >= d.h_top)
+    return fail(CPHOT_ERR_INVALID_ARG, "h_obs must lie in [0, h_top)");
+
+  std::memset(&p, 0, sizeof(p));
+  p.x0 = seg->x0; p.y0 = seg->y0; p.z0 = seg->z0;
+  p.x1 = seg->x1; p.y1 = seg->y1; p.z1 = seg->z1;
+  p.beta = seg->beta; p.charge = seg->charge;
+  p.n = seg->n;
+  p.first_id = (uint64_t)seg->first_id;
+  p.n_showers = seg->n_showers;
+  p.offsets = seg->shower_offsets;
+  p.geom = seg->shower_geom;
+  p.tab = a->dev.delta_table;
+  p.n_tab = a->n_tab;
+  p.step = d.table_step;
+  {
+    const double l1 = d.lambda_min_nm * 1e-9, l2 = d.lambda_max_nm * 1e-9;
+    p.K = 2.0 * kPi * kAlpha * (1.0 / l1 - 1.0 / l2);
+  }
+  p.bunch = (uint32_t)det->bunch;
+  p.key0 = (uint32_t)det->seed;
+  p.key1 = (uint32_t)(det->seed >> 32);
+  p.profile = d.profile;
+  for (int i = 0; i < 5; ++i) {
+    p.hb[i] = (float)d.lin_hb[i];
+    p.la[i] = (float)d.lin_a[i];
+    p.lb[i] = (float)d.lin_b[i];
+    p.linv_c[i] = d.profile == CPHOT_PROFILE_LINSLEY5 ? (float)(1.0 / d.lin_c[i]) : 0.f;
+  }
+  p.opt_scale = d.profile == CPHOT_PROFILE_LINSLEY5 ? (float)(d.kappa / a->rho0 / 100.0) : (float)d.delta0;
+  p.h_top = (float)d.h_top;
+  p.has_ray = d.rayleigh400 > 0.0;
+  p.has_aer = d.aerosol_tau350 > 0.0;
+  p.inv_ray400 = p.has_ray ? (float)(1.0 / d.rayleigh400) : 0.f;
+  p.aer_tau350 = (float)d.aerosol_tau350;
+  p.aer_inv_h = p.has_aer ? (float)(1.0 / d.aerosol_height) : 0.f;
+  p.aer_ang = (float)d.aerosol_angstrom;
+  p.lam_min = (float)d.lambda_min_nm;
+  p.lam_max = (float)d.lambda_max_nm;
+  p.inv_lam_min = (float)(1.0 / d.lambda_min_nm);
+  p.inv_lam_max = (float)(1.0 / d.lambda_max_nm);
+  p.spectrum = det->spectrum;
+  p.h_obs = (float)det->h_obs;
+  p.X_obs = d.profile == CPHOT_PROFILE_LINSLEY5 ? (float)depth(d, det->h_obs) : 0.f;
+  p.transport = det->transport;
+  p.detector = det->detector;
+  if (det->transport == CPHOT_TRANSPORT_LAYERED) {
+    if (d.n_layers < 1) return fail(CPHOT_ERR_INVALID_ARG, "layered transport needs an atmosphere with layers");
+    p.n_layers = d.n_layers;
+    p.n_lam = d.n_lambda_bins;
+    p.dh = (float)(d.h_top / d.n_layers);
+    p.inv_dh = (float)(d.n_layers / d.h_top);
+    p.obs_layer = (int)std::floor(det->h_obs / (d.h_top / d.n_layers));
+    p.layer_delta = a->dev.layer_delta;
+    p.layer_inv_n = a->dev.layer_inv_n;
+    p.layer_ext = a->dev.layer_ext;
+  }
+  const int64_t ns = seg->n_showers;
+  if (det->detector == CPHOT_DETECTOR_GRID) {
+    if (det->nx < 1 || det->ny < 1 || !finite_pos(det->cell))
+      return fail(CPHOT_ERR_INVALID_ARG, "grid needs nx, ny >= 1 and cell > 0");
+    p.nx = det->nx; p.ny = det->ny;
+    p.cell = (float)det->cell;
+    p.inv_cell = (float)(1.0 / det->cell);
+    if (need_bins && out->bins_capacity < ns * (int64_t)det->nx * det->ny)
+      return fail(CPHOT_ERR_INVALID_ARG, "bins_capacity below n_showers * nx * ny");
+  } else {
+    if (det->snx < 1 || det->sny < 1 || !finite_pos(det->pitch) || !finite_pos(det->radius))
+      return fail(CPHOT_ERR_INVALID_ARG, "spheres need snx, sny >= 1, pitch > 0, radius > 0");
+    if (4.0 * det->radius > det->pitch)
+      return fail(CPHOT_ERR_INVALID_ARG, "spheres must satisfy pitch >= 4 radius (one candidate per cell)");
+    if (det->transport == CPHOT_TRANSPORT_LAYERED) {
+      const double dh = d.h_top / d.n_layers;
+      const double lo = p.obs_layer * dh, hi = (p.obs_layer + 1) * dh;
+      if (det->h_obs - det->radius < lo || det->h_obs + det->radius >= hi)
+        return fail(CPHOT_ERR_INVALID_ARG, "spheres must lie inside the layer containing h_obs");
+    }
+    p.snx = det->snx; p.sny = det->sny;
+    p.pitch = (float)det->pitch;
+    p.inv_pitch = (float)(1.0 / det->pitch);
+    p.radius = (float)det->radius;
+    p.n_t = det->n_time_bins;
+    if (p.n_t < 0) return fail(CPHOT_ERR_INVALID_ARG, "n_time_bins must be >= 0");
+    if (p.n_t > 0 && !finite_pos(det->time_bin_ns)) return fail(CPHOT_ERR_INVALID_ARG, "time_bin_ns must be > 0");
+    p.inv_dt = p.n_t > 0 ? (float)(1.0 / det->time_bin_ns) : 0.f;
+    const int64_t nsph = (int64_t)det->snx * det->sny;
+    if (need_bins) {
+      if (out->bins_capacity < ns * nsph) return fail(CPHOT_ERR_INVALID_ARG, "bins_capacity below n_showers * spheres");
+      if (p.n_t > 0 && (!out->time_hist || out->time_capacity < ns * nsph * (p.n_t + 1)))
+        return fail(CPHOT_ERR_INVALID_ARG, "time_hist missing or below n_showers * spheres * (n_time_bins + 1)");
+    }
+  }
+  if (need_bins) {
+    if (!out) return fail(CPHOT_ERR_INVALID_ARG, "null bins");
+    if (out->bins_dtype != CPHOT_BINS_U32 && out->bins_dtype != CPHOT_BINS_U64)
+      return fail(CPHOT_ERR_INVALID_ARG, "unknown bins dtype");
+    if (!out->bins) return fail(CPHOT_ERR_INVALID_ARG, "null bins buffer");
+    p.bins = out->bins;
+    p.bins_u64 = out->bins_dtype == CPHOT_BINS_U64;
+    p.thist = out->time_hist;
+    p.counters = out->counters;
+  }
+  return CPHOT_OK;
+}
+
+struct LaunchShape {
+  int block, grid;
+  size_t lds;
+};
+
+int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchShape& s) {
+  int bs = det->block_size ? det->block_size : 256;
+  if (bs != 128 && bs != 256 && bs != 512) return fail(CPHOT_ERR_INVALID_ARG, "block_size must be 0, 128, 256 or 512");
+  size_t lds = 0;
+  if (p.transport == CPHOT_TRANSPORT_LAYERED) lds += (size_t)(p.n_layers * p.n_lam + 2 * p.n_layers) * 4;
+  p.lds_hist = 0;
+  if (mode == cphot::MODE_PROPAGATE && p.detector == CPHOT_DETECTOR_GRID && p.n_showers == 1) {
+    const size_t hb = (size_t)p.nx * p.ny * 4;
+    const bool fits = lds + hb <= 64 * 1024;
+    if (det->lds_hist == 1 && !fits) return fail(CPHOT_ERR_INVALID_ARG, "grid too large for an LDS histogram");
+    p.lds_hist = (det->lds_hist == 1 || (det->lds_hist < 0 && fits)) ? 1 : 0;
+    if (p.lds_hist) lds += hb;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const int64_t tiles = (p.n + bs - 1) / bs;
+  int64_t g = det->grid_blocks > 0 ? det->grid_blocks : (int64_t)cu_count(dev) * (2048 / bs);
+  if (g > tiles) g = tiles;
+  if (g < 1) g = 1;
+  s.block = bs;
+  s.grid = (int)g;
+  s.lds = lds;
+  return CPHOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cphot_version(void) { return CPHOT_ABI_VERSION; }
+
+const char* cphot_status_string(int status) {
+  switch (status) {
+    case CPHOT_OK: return "ok";
+    case CPHOT_ERR_INVALID_ARG: return "invalid argument";
+    case CPHOT_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case CPHOT_ERR_HIP: return "HIP runtime error";
+    case CPHOT_ERR_UNSUPPORTED: return "unsupported";
+    case CPHOT_ERR_CAPACITY: return "capacity exceeded";
+    default: return "unknown status";
+  }
+}
+
+const char* cphot_last_error(void) { return g_err.c_str(); }
+
+int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** out) {
+  if (!desc || !out) return fail(CPHOT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  const cphot_atmosphere_desc& d = *desc;
+  if (d.profile != CPHOT_PROFILE_LINSLEY5 && d.profile != CPHOT_PROFILE_HOMOGENEOUS &&
+      d.profile != CPHOT_PROFILE_LINEAR)
+    return fail(CPHOT_ERR_INVALID_ARG, "unknown profile");
+  if (!finite_pos(d.h_top) || !finite_pos(d.table_step) || d.h_top / d.table_step > 1e8)
+    return fail(CPHOT_ERR_INVALID_ARG, "h_top and table_step must be > 0 with at most 1e8 table entries");
+  if (!(d.lambda_min_nm > 0 && d.lambda_max_nm > d.lambda_min_nm && std::isfinite(d.lambda_max_nm)))
+    return fail(CPHOT_ERR_INVALID_ARG, "need 0 < lambda_min < lambda_max");
+  if (d.profile == CPHOT_PROFILE_LINSLEY5) {
+    for (int i = 0; i < 5; ++i)
+      if (!finite_pos(d.lin_c[i]) || !std::isfinite(d.lin_a[i]) || !std::isfinite(d.lin_b[i]))
+        return fail(CPHOT_ERR_INVALID_ARG, "Linsley parameters must be finite with c > 0");
+    if (d.lin_hb[0] != 0.0) return fail(CPHOT_ERR_INVALID_ARG, "lin_hb[0] must be 0");
+    for (int i = 1; i < 5; ++i)
+      if (!(d.lin_hb[i] > d.lin_hb[i - 1])) return fail(CPHOT_ERR_INVALID_ARG, "lin_hb must ascend");
+    if (!finite_pos(d.lin_b[0])) return fail(CPHOT_ERR_INVALID_ARG, "lin_b[0] must be > 0");
+    if (!std::isfinite(d.kappa) || d.kappa < 0) return fail(CPHOT_ERR_INVALID_ARG, "kappa must be >= 0");
+  } else {
+    if (!std::isfinite(d.delta0) || d.delta0 < 0) return fail(CPHOT_ERR_INVALID_ARG, "delta0 must be >= 0");
+    if (d.rayleigh400 > 0) return fail(CPHOT_ERR_INVALID_ARG, "Rayleigh absorption needs the LINSLEY5 profile");
+  }
+  if (d.rayleigh400 < 0 || !std::isfinite(d.rayleigh400)) return fail(CPHOT_ERR_INVALID_ARG, "bad rayleigh400");
+  if (d.aerosol_tau350 < 0 || !std::isfinite(d.aerosol_tau350)) return fail(CPHOT_ERR_INVALID_ARG, "bad aerosol_tau350");
+  if (d.aerosol_tau350 > 0 && !finite_pos(d.aerosol_height)) return fail(CPHOT_ERR_INVALID_ARG, "bad aerosol_height");
+  if (d.n_layers < 0 || d.n_layers > cphot::kMaxLayers)
+    return fail(CPHOT_ERR_INVALID_ARG, "n_layers must be in [0, 128]");
+  if (d.n_layers > 0 && (d.n_lambda_bins < 1 || d.n_lambda_bins > cphot::kMaxLambdaBins))
+    return fail(CPHOT_ERR_INVALID_ARG, "n_lambda_bins must be in [1, 64] with layers");
+
+  cphot_atmosphere* a = new (std::nothrow) cphot_atmosphere();
+  if (!a) return fail(CPHOT_ERR_OUT_OF_MEMORY, "host allocation");
+  a->d = d;
+  (void)hipGetDevice(&a->device);
+  a->rho0 = d.profile == CPHOT_PROFILE_LINSLEY5 ? d.lin_b[0] / d.lin_c[0] : 1.0;
+  a->n_tab = (int64_t)std::ceil(d.h_top / d.table_step);
+  std::vector<double> tab((size_t)a->n_tab + 1);
+  for (int64_t j = 0; j <= a->n_tab; ++j) tab[(size_t)j] = refractivity(*a, (double)j * d.table_step);
+  std::vector<float> ld, linv, lext;
+  if (d.n_layers > 0) {
+    const int L = d.n_layers, K = d.n_lambda_bins;
+    const double dh = d.h_top / L;
+    a->layer_delta.resize(L);
+    ld.resize(L);
+    linv.resize(L);
+    lext.resize((size_t)L * K);
+    for (int i = 0; i < L; ++i) {
+      const double lo = i * dh, hi = (i + 1) * dh;
+      const double dl = refractivity(*a, 0.5 * (lo + hi));
+      a->layer_delta[i] = dl;
+      ld[i] = (float)dl;
+      linv[i] = (float)(1.0 / (1.0 + dl));
+      for (int k = 0; k < K; ++k) {
+        const double lam = d.lambda_min_nm + (k + 0.5) * (d.lambda_max_nm - d.lambda_min_nm) / K;
+        lext[(size_t)i * K + k] = (float)(vertical_tau(d, lo, hi, lam) / dh);
+      }
+    }
+  }
+  auto cleanup = [&](int code, const char* what, hipError_t e) {
+    cphot_destroy_atmosphere(a);
+    if (e == hipErrorOutOfMemory) return fail(CPHOT_ERR_OUT_OF_MEMORY, what);
+    return hip_fail(e, what);
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&a->dev.delta_table, tab.size() * sizeof(double))) != hipSuccess)
+    return cleanup(0, "hipMalloc(delta_table)", e);
+  if ((e = hipMemcpy(a->dev.delta_table, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return cleanup(0, "hipMemcpy(delta_table)", e);
+  if (d.n_layers > 0) {
+    if ((e = hipMalloc(&a->dev.layer_delta, ld.size() * 4)) != hipSuccess) return cleanup(0, "hipMalloc", e);
+    if ((e = hipMalloc(&a->dev.layer_inv_n, linv.size() * 4)) != hipSuccess) return cleanup(0, "hipMalloc", e);
+    if ((e = hipMalloc(&a->dev.layer_ext, lext.size() * 4)) != hipSuccess) return cleanup(0, "hipMalloc", e);
+    if ((e = hipMemcpy(a->dev.layer_delta, ld.data(), ld.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(a->dev.layer_inv_n, linv.data(), linv.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(a->dev.layer_ext, lext.data(), lext.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(0, "hipMemcpy(layers)", e);
+  }
+  *out = a;
+  return CPHOT_OK;
+}
+
+void cphot_destroy_atmosphere(cphot_atmosphere* a) {
+  if (!a) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(a->device);
+  if (a->dev.delta_table) (void)hipFree(a->dev.delta_table);
+  if (a->dev.layer_delta) (void)hipFree(a->dev.layer_delta);
+  if (a->dev.layer_inv_n) (void)hipFree(a->dev.layer_inv_n);
+  if (a->dev.layer_ext) (void)hipFree(a->dev.layer_ext);
+  (void)hipSetDevice(prev);
+  delete a;
+}
+
+int cphot_propagate(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out, void* stream) {
+  if (!out) return fail(CPHOT_ERR_INVALID_ARG, "null bins");
+  cphot::KParams p;
+  int rc = fill_params(seg, det, p, true, out);
+  if (rc) return rc;
+  if (p.n == 0) return CPHOT_OK;
+  LaunchShape s;
+  if ((rc = choose_shape(det, p, cphot::MODE_PROPAGATE, s))) return rc;
+  hipError_t e = cphot::launch_propagate(p, cphot::MODE_PROPAGATE, s.block, s.grid, s.lds, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "launch propagate");
+  return CPHOT_OK;
+}
+
+int cphot_segment_counts(const cphot_segments* seg, const cphot_detector* det, int32_t* counts, void* stream) {
+  if (!counts && seg && seg->n > 0) return fail(CPHOT_ERR_INVALID_ARG, "null counts");
+  cphot::KParams p;
+  int rc = fill_params(seg, det, p, false, nullptr);
+  if (rc) return rc;
+  if (p.n == 0) return CPHOT_OK;
+  p.counts = counts;
+  LaunchShape s;
+  if ((rc = choose_shape(det, p, cphot::MODE_COUNTS, s))) return rc;
+  hipError_t e = cphot::launch_propagate(p, cphot::MODE_COUNTS, s.block, s.grid, s.lds, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "launch counts");
+  return CPHOT_OK;
+}
+
+int cphot_trace_records(const cphot_segments* seg, const cphot_detector* det, const int64_t* record_offsets,
+                        cphot_photon_record* records, int64_t capacity, void* stream) {
+  if (seg && seg->n > 0 && (!record_offsets || !records || capacity < 0))
+    return fail(CPHOT_ERR_INVALID_ARG, "null record buffers or negative capacity");
+  cphot::KParams p;
+  int rc = fill_params(seg, det, p, false, nullptr);
+  if (rc) return rc;
+  if (p.n == 0) return CPHOT_OK;
+  p.rec_off = record_offsets;
+  p.rec = records;
+  p.rec_cap = capacity;
+  LaunchShape s;
+  if ((rc = choose_shape(det, p, cphot::MODE_RECORDS, s))) return rc;
+  hipError_t e = cphot::launch_propagate(p, cphot::MODE_RECORDS, s.block, s.grid, s.lds, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "launch records");
+  return CPHOT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal declarations shared by the host API and the kernels of libcphot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cphot.h"
+
+namespace cphot {
+
+constexpr int kMaxLayers = 128;
+constexpr int kMaxLambdaBins = 64;
+
+// Device-side tables owned by an atmosphere handle.
+struct AtmoDevice {
+  double* delta_table = nullptr;   // n_tab + 1 entries, FP64 (per-segment yield)
+  float* layer_delta = nullptr;    // n_layers
+  float* layer_inv_n = nullptr;    // n_layers: 1 / (1 + delta)
+  float* layer_ext = nullptr;      // n_layers * n_lam, extinction per metre
+};
+
+// Everything a launch needs, passed by value as the kernel argument.
+struct KParams {
+  // segments
+  const float *x0, *y0, *z0, *x1, *y1, *z1, *beta, *charge;
+  int64_t n;
+  uint64_t first_id;
+  int32_t n_showers;
+  const int64_t* offsets;
+  const double* geom;
+  // refractivity table (FP64) and Frank-Tamm constant
+  const double* tab;
+  int64_t n_tab;
+  double step;
+  double K;
+  uint32_t bunch;
+  uint32_t key0, key1;
+  // atmosphere profile for the straight closed forms (FP32)
+  int32_t profile;
+  float hb[5], la[5], lb[5], linv_c[5];   // Linsley bounds (m), a, b, 1/c (1/cm)
+  float opt_scale;                        // LINSLEY5: kappa/rho0/100 (m per g/cm^2); others: delta0
+  float h_top;
+  int32_t has_ray, has_aer;
+  float inv_ray400, aer_tau350, aer_inv_h, aer_ang;
+  float lam_min, lam_max, inv_lam_min, inv_lam_max;
+  int32_t spectrum;
+  // observation level quantities (FP32)
+  float h_obs, X_obs, I_obs, A_obs;
+  // transport / detector
+  int32_t transport, detector;
+  int32_t n_layers, n_lam;
+  float dh, inv_dh;
+  int32_t obs_layer;
+  const float* layer_delta;
+  const float* layer_inv_n;
+  const float* layer_ext;
+  int32_t nx, ny;
+  float cell, inv_cell;
+  int32_t snx, sny;
+  float pitch, inv_pitch, radius;
+  int32_t n_t;
+  float inv_dt;
+  // outputs
+  void* bins;
+  int32_t bins_u64;
+  int32_t lds_hist;
+  uint32_t* thist;
+  unsigned long long* counters;
+  // debug outputs
+  int32_t* counts;
+  const int64_t* rec_off;
+  cphot_photon_record* rec;
+  int64_t rec_cap;
+};
+
+enum Mode { MODE_PROPAGATE = 0, MODE_COUNTS = 1, MODE_RECORDS = 2 };
+
+hipError_t launch_propagate(const KParams& p, int mode, int block_size, int grid_blocks, size_t lds_hist_bytes,
+                            hipStream_t stream);
+
+}  // namespace cphot

@@ -1,0 +1,559 @@
+// Photon generation and propagation kernels for gfx950.
+//
+// One persistent kernel per (block size, transport, detector, mode). Each block
+// walks tiles of `BS` consecutive segments:
+//   1. coalesced SoA load, one segment per thread; FP64 yield and the
+//      stochastically rounded record count (Sec. 2.2.1); FP32 per-segment
+//      geometry (cone angle, rotation bisector, start point, depth) into LDS;
+//   2. block exclusive scan of the counts -> a flat record index space;
+//   3. every thread takes records j = tid, tid + BS, ... and finds its segment
+//      by binary search over the LDS offsets, then draws the record's Philox
+//      block, builds the photon on the cone (Sec. 4.2), transports it
+//      (Sec. 3.4.1 straight / Sec. 3.4.2 layered), applies absorption
+//      (Sec. 2.3.2) and bins it (LDS-privatised grid histogram or global
+//      atomics); upward photons leave first (Sec. 5.3.4).
+// Photons live in registers only; nothing per photon touches HBM except the
+// final bin increment.
+#include "cphot_internal.h"
+
+namespace cphot {
+
+namespace {
+
+constexpr uint32_t TAG_SEGMENT = 0;
+constexpr uint32_t TAG_CHERENKOV = 1;
+constexpr int kMaxRecordsPerSegmentLog2 = 20;
+constexpr float kCmPerNs = 0.299792458f;  // metres per ns
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }
+
+struct SegResult {
+  int32_t n;       // records
+  int32_t status;  // 0 ok, 1 below threshold, 2 skipped
+  float cos_t, sin_t, a0, a1, a2;
+};
+
+// Per-segment yield in FP64 with IEEE basic operations only and no
+// contraction, in the fixed order that makes the record count reproducible
+// bit for bit on any IEEE machine.
+__device__ __noinline__ SegResult segment_setup(const KParams& p, float fx0, float fy0, float fz0, float fx1,
+                                                float fy1, float fz1, float fbeta, float fq, uint64_t id) {
+#pragma clang fp contract(off)
+  SegResult r{0, 0, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (!__builtin_isfinite(fx0) || !__builtin_isfinite(fy0) || !__builtin_isfinite(fz0) ||
+      !__builtin_isfinite(fx1) || !__builtin_isfinite(fy1) || !__builtin_isfinite(fz1) ||
+      !__builtin_isfinite(fbeta) || !__builtin_isfinite(fq)) {
+    r.status = 2;
+    return r;
+  }
+  const double beta = (double)fbeta;
+  if (!(beta > 0.0 && beta < 1.0)) {
+    r.status = 2;
+    return r;
+  }
+  const double dx = (double)fx1 - (double)fx0, dy = (double)fy1 - (double)fy0, dz = (double)fz1 - (double)fz0;
+  const double L = sqrt(dx * dx + dy * dy + dz * dz);
+  if (!(L > 0.0)) {
+    r.status = 2;
+    return r;
+  }
+  // refractivity at the midpoint: direct index mapping into the FP64 table and
+  // linear interpolation (Sec. 4.1), heights clamped to the table
+  const double hm = 0.5 * ((double)fz0 + (double)fz1);
+  double x = hm / p.step;
+  if (x < 0.0) x = 0.0;
+  if (x > (double)p.n_tab) x = (double)p.n_tab;
+  double fi = floor(x);
+  int64_t idx = (int64_t)fi;
+  if (idx > p.n_tab - 1) {
+    idx = p.n_tab - 1;
+    fi = (double)idx;
+  }
+  const double frac = x - fi;
+  const double delta = (1.0 - frac) * p.tab[idx] + frac * p.tab[idx + 1];
+  // threshold beta n > 1 through g = beta n - 1 = delta - eps - eps delta, eps = 1 - beta
+  const double eps = 1.0 - beta;
+  const double g = delta - eps - eps * delta;
+  if (!(g > 0.0)) {
+    r.status = 1;
+    return r;
+  }
+  const double s2 = g * (g + 2.0) / ((1.0 + g) * (1.0 + g));
+  const double z2 = (double)fq * (double)fq;
+  double mu = p.K * z2;
+  mu = mu * L;
+  mu = mu * s2;
+  mu = mu / (double)p.bunch;
+  if (!(mu < (double)(1 << kMaxRecordsPerSegmentLog2))) {
+    r.status = 2;
+    return r;
+  }
+  const double fl = floor(mu);
+  const uint4 w = philox(0u, (uint32_t)id, (uint32_t)(id >> 32), TAG_SEGMENT, p.key0, p.key1);
+  const double u = (double)w.x * (1.0 / 4294967296.0);
+  r.n = (int32_t)fl + (u < mu - fl ? 1 : 0);
+  r.cos_t = (float)(1.0 / (1.0 + g));
+  r.sin_t = (float)sqrt(s2);
+  // bisector of the cone axis (0,0,-1) and the track direction; the rotation
+  // is M = 2 a a^T - I (Euler-Rodrigues, 180 degrees, Sec. 4.2)
+  const double P0 = dx / L, P1 = dy / L, P2 = dz / L;
+  if (1.0 - P2 < 1e-6) {
+    r.a0 = 1.f;  // 2 a a^T - I with a = x-hat: a half turn about x
+  } else {
+    const double b2 = P2 - 1.0;
+    const double na = sqrt(P0 * P0 + P1 * P1 + b2 * b2);
+    r.a0 = (float)(P0 / na);
+    r.a1 = (float)(P1 / na);
+    r.a2 = (float)(b2 / na);
+  }
+  return r;
+}
+
+// Linsley vertical depth in FP32 (g/cm^2).
+__device__ __forceinline__ float depth_f(const KParams& p, float h) {
+  int i = 0;
+#pragma unroll
+  for (int j = 1; j < 5; ++j) i += (h >= p.hb[j]) ? 1 : 0;
+  const float hcm = h * 100.0f;
+  if (i < 4) return p.la[i] + p.lb[i] * __expf(-hcm * p.linv_c[i]);
+  return p.la[4] - p.lb[4] * hcm * p.linv_c[4];
+}
+
+// Integral of n - 1 from height lo to height hi (m), closed form per profile.
+__device__ __forceinline__ float opt_integral(const KParams& p, float lo, float hi, float X_lo, float X_hi) {
+  if (p.profile == CPHOT_PROFILE_LINSLEY5) return p.opt_scale * (X_lo - X_hi);
+  if (p.profile == CPHOT_PROFILE_HOMOGENEOUS) return p.opt_scale * (hi - lo);
+  const float t = p.h_top;
+  const float a = fminf(fmaxf(lo, 0.f), t), b = fminf(fmaxf(hi, 0.f), t);
+  return p.opt_scale * ((b - a) - (b * b - a * a) / (2.f * t));
+}
+
+struct Photon {
+  int32_t state, bin, tbin;
+  float x, y, z, t, tau, lam, u3, ux, uy, uz;
+};
+
+template <int TRANSPORT, int DETECTOR, bool NEED_TIME>
+__device__ __forceinline__ void trace(const KParams& p, const float* __restrict__ s_ext,
+                                      const float* __restrict__ s_ldelta, const float* __restrict__ s_linvn,
+                                      float sx, float sy,
+                                      float sz, float dx, float dy, float dz, float ax, float ay, float az,
+                                      float cos_t, float sin_t, float X0, float dX, float core_x, float core_y,
+                                      float axx, float axy, float axz, uint32_t id_lo, uint32_t id_hi,
+                                      uint32_t k, Photon& o) {
+  const uint4 w = philox(k, id_lo, id_hi, TAG_CHERENKOV, p.key0, p.key1);
+  const float f = u24(w.x);
+  float sphi, cphi;
+  sincospif(2.0f * u24(w.y), &sphi, &cphi);
+  const float u2 = u24(w.z);
+  const float lam = (p.spectrum == CPHOT_SPECTRUM_UNIFORM)
+                        ? p.lam_min + (p.lam_max - p.lam_min) * u2
+                        : 1.0f / (p.inv_lam_min - u2 * (p.inv_lam_min - p.inv_lam_max));
+  const float u3 = u24(w.w);
+  o.lam = lam;
+  o.u3 = u3;
+  o.bin = -1;
+  o.tbin = -1;
+  o.t = 0.f;
+  o.tau = 0.f;
+  // photon on the cone around (0,0,-1), turned onto the track: u = 2 a (a.p) - p
+  const float plx = cphi * sin_t, ply = sphi * sin_t, plz = -cos_t;
+  const float d2 = 2.0f * (ax * plx + ay * ply + az * plz);
+  const float ux = d2 * ax - plx, uy = d2 * ay - ply, uz = d2 * az - plz;
+  o.ux = ux;
+  o.uy = uy;
+  o.uz = uz;
+  const float Px = fmaf(f, dx, sx), Py = fmaf(f, dy, sy), Pz = fmaf(f, dz, sz);
+  o.x = Px;
+  o.y = Py;
+  o.z = Pz;
+  if (!(uz < 0.f)) {
+    o.state = 1;
+    return;
+  }
+  if (Pz < p.h_obs) {
+    o.state = 3;
+    return;
+  }
+  float x, y, z;                 // start of the final leg
+  float vx, vy, vz;              // direction of the final leg
+  float tau = 0.f, geo = 0.f, opt = 0.f;
+  float last_delta = 0.f, last_ext = 0.f;
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_LAYERED) {
+    // Homogeneous layers (Sec. 3.4.2): within a layer the ray is straight; at a
+    // horizontal boundary the horizontal part of n u is conserved (the vector
+    // form of Snell's law, Eq. 3.15, with a vertical normal), so every layer is
+    // entered with sin(theta_i) = K / n_i, K = n_e sin(theta_e).
+    int i = min((int)(Pz * p.inv_dh), p.n_layers - 1);
+    const float sh = sqrtf(ux * ux + uy * uy);
+    float hx = 1.f, hy = 0.f;
+    if (sh > 0.f) {
+      const float ish = 1.0f / sh;
+      hx = ux * ish;
+      hy = uy * ish;
+    }
+    const float Kc = fmaf(sh, s_ldelta[i], sh);
+    int kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
+    kb = min(max(kb, 0), p.n_lam - 1);
+    x = Px;
+    y = Py;
+    z = Pz;
+    while (i > p.obs_layer) {
+      const float zb = (float)i * p.dh;
+      const float span = z - zb;
+      const float s = Kc * s_linvn[i];
+      const float c2 = (1.f - s) * (1.f + s);
+      const float ic = rsqrtf(c2);
+      const float path = span * ic;
+      const float adv = path * s;
+      x = fmaf(hx, adv, x);
+      y = fmaf(hy, adv, y);
+      tau = fmaf(s_ext[i * p.n_lam + kb], path, tau);
+      if constexpr (NEED_TIME) {
+        const float ex = s * hx - axx, ey = s * hy - axy, ez = -c2 * ic - axz;
+        geo = fmaf(path, 0.5f * (ex * ex + ey * ey + ez * ez), geo);
+        opt = fmaf(s_ldelta[i], path, opt);
+      }
+      z = zb;
+      --i;
+    }
+    const float s = Kc * s_linvn[i];
+    const float c = sqrtf((1.f - s) * (1.f + s));
+    vx = s * hx;
+    vy = s * hy;
+    vz = -c;
+    last_delta = s_ldelta[i];
+    last_ext = s_ext[i * p.n_lam + kb];
+  } else {
+    x = Px;
+    y = Py;
+    z = Pz;
+    vx = ux;
+    vy = uy;
+    vz = uz;
+  }
+  // final straight leg: crossing of the observation level
+  const float s_plane = (p.h_obs - z) / vz;
+  const float Qx = fmaf(s_plane, vx, x), Qy = fmaf(s_plane, vy, y);
+  float s_end = s_plane;
+  int32_t bin = -1;
+  if constexpr (DETECTOR == CPHOT_DETECTOR_GRID) {
+    const float gx0 = core_x - 0.5f * (float)p.nx * p.cell;
+    const float gy0 = core_y - 0.5f * (float)p.ny * p.cell;
+    const float fxc = floorf((Qx - gx0) * p.inv_cell), fyc = floorf((Qy - gy0) * p.inv_cell);
+    if (fxc >= 0.f && fyc >= 0.f && fxc < (float)p.nx && fyc < (float)p.ny) bin = (int)fyc * p.nx + (int)fxc;
+  } else {
+    const float cx0 = core_x - 0.5f * (float)(p.snx - 1) * p.pitch;
+    const float cy0 = core_y - 0.5f * (float)(p.sny - 1) * p.pitch;
+    const float fi = floorf((Qx - cx0) * p.inv_pitch + 0.5f), fj = floorf((Qy - cy0) * p.inv_pitch + 0.5f);
+    if (fi >= 0.f && fj >= 0.f && fi < (float)p.snx && fj < (float)p.sny) {
+      const float qx = Qx - (cx0 + fi * p.pitch), qy = Qy - (cy0 + fj * p.pitch);
+      const float b = qx * vx + qy * vy;  // q_z = 0 on the observation level
+      const float cc = qx * qx + qy * qy - p.radius * p.radius;
+      const float disc = b * b - cc;
+      if (disc >= 0.f) {
+        s_end = s_plane + (-b - sqrtf(disc));
+        bin = (int)fj * p.snx + (int)fi;
+      }
+    }
+  }
+  const float ex = fmaf(s_end, vx, x), ey = fmaf(s_end, vy, y), ez = fmaf(s_end, vz, z);
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_LAYERED) {
+    tau = fmaf(last_ext, s_end, tau);
+    if constexpr (NEED_TIME) {
+      const float gx = vx - axx, gy = vy - axy, gz = vz - axz;
+      geo = fmaf(s_end, 0.5f * (gx * gx + gy * gy + gz * gz), geo);
+      opt = fmaf(last_delta, s_end, opt);
+    }
+  } else {
+    // straight line in a planar atmosphere: closed forms over the height span
+    const float inv_uz = -1.0f / vz;  // 1/|u_z|
+    const float Xe = fmaf(f, dX, X0);
+    float X_end = p.X_obs;
+    if constexpr (DETECTOR == CPHOT_DETECTOR_SPHERES) {
+      if (p.profile == CPHOT_PROFILE_LINSLEY5) X_end = depth_f(p, ez);
+    }
+    if (p.has_ray) {
+      const float r = 400.0f / lam;
+      const float r2 = r * r;
+      tau = (X_end - Xe) * inv_uz * (r2 * r2 * p.inv_ray400);
+    }
+    if (p.has_aer) {
+      const float taua = p.aer_tau350 * __powf(lam * (1.0f / 350.0f), -p.aer_ang);
+      tau = fmaf(taua * (__expf(-ez * p.aer_inv_h) - __expf(-Pz * p.aer_inv_h)), inv_uz, tau);
+    }
+    if constexpr (NEED_TIME) {
+      const float gx = vx - axx, gy = vy - axy, gz = vz - axz;
+      geo = s_end * 0.5f * (gx * gx + gy * gy + gz * gz);
+      opt = opt_integral(p, ez, Pz, X_end, Xe) * inv_uz;
+    }
+  }
+  o.x = ex;
+  o.y = ey;
+  o.z = ez;
+  o.tau = tau;
+  if constexpr (NEED_TIME) o.t = (geo + opt) * (1.0f / kCmPerNs);
+  if (!(u3 < __expf(-tau))) {
+    o.state = 2;
+    return;
+  }
+  if (bin < 0) {
+    o.state = 3;
+    return;
+  }
+  o.state = 0;
+  o.bin = bin;
+  if constexpr (DETECTOR == CPHOT_DETECTOR_SPHERES) {
+    if (p.n_t > 0) {
+      const float tb = floorf(o.t * p.inv_dt);
+      o.tbin = tb < 0.f ? 0 : (tb >= (float)p.n_t ? p.n_t : (int)tb);
+    }
+  }
+}
+
+template <int BS>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_wave[wid] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < BS / 64; ++q) {
+    const uint32_t t = s_wave[q];
+    pre += (q < wid) ? t : 0u;
+    tot += t;
+  }
+  total = tot;
+  return pre + x - v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+}  // namespace
+
+template <int BS, int TRANSPORT, int DETECTOR, int MODE>
+__global__ __launch_bounds__(BS) void k_propagate(KParams p) {
+  constexpr bool kTime = (DETECTOR == CPHOT_DETECTOR_SPHERES) || (MODE == MODE_RECORDS);
+  __shared__ float s_sx[BS], s_sy[BS], s_sz[BS], s_dx[BS], s_dy[BS], s_dz[BS];
+  __shared__ float s_ax[BS], s_ay[BS], s_az[BS], s_cos[BS], s_sin[BS], s_X0[BS], s_dXs[BS];
+  __shared__ float s_cx[BS], s_cy[BS], s_axx[BS], s_axy[BS], s_axz[BS];
+  __shared__ uint32_t s_idlo[BS], s_idhi[BS], s_sh[BS];
+  __shared__ uint32_t s_off[BS + 1];
+  __shared__ uint32_t s_wave[BS / 64];
+  // dynamic LDS: [layer extinction L*K][layer n-1 L][layer 1/n L][grid histogram]
+  extern __shared__ uint32_t s_dyn[];
+  const int n_lay = (TRANSPORT == CPHOT_TRANSPORT_LAYERED) ? p.n_layers : 0;
+  const int n_ext = n_lay * p.n_lam;
+  float* s_ext = reinterpret_cast<float*>(s_dyn);
+  float* s_ldelta = s_ext + n_ext;
+  float* s_linvn = s_ldelta + n_lay;
+  uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_linvn + n_lay);
+  const int n_hist = (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_GRID && p.lds_hist) ? p.nx * p.ny : 0;
+  const int tid = threadIdx.x;
+
+  for (int i = tid; i < n_ext; i += BS) s_ext[i] = p.layer_ext[i];
+  for (int i = tid; i < n_lay; i += BS) {
+    s_ldelta[i] = p.layer_delta[i];
+    s_linvn[i] = p.layer_inv_n[i];
+  }
+  for (int i = tid; i < n_hist; i += BS) s_hist[i] = 0u;
+  __syncthreads();
+
+  uint32_t c_in = 0, c_skip = 0, c_below = 0, c_gen = 0, c_up = 0, c_abs = 0, c_out = 0, c_bin = 0;
+  const int64_t n_tiles = (p.n + BS - 1) / BS;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t i = tile * BS + tid;
+    uint32_t nrec = 0;
+    if (i < p.n) {
+      const float fx0 = p.x0[i], fy0 = p.y0[i], fz0 = p.z0[i], fx1 = p.x1[i], fy1 = p.y1[i], fz1 = p.z1[i];
+      const uint64_t id = p.first_id + (uint64_t)i;
+      const SegResult r = segment_setup(p, fx0, fy0, fz0, fx1, fy1, fz1, p.beta[i], p.charge[i], id);
+      c_in += 1;
+      c_skip += r.status == 2;
+      c_below += r.status == 1;
+      nrec = (uint32_t)r.n;
+      if constexpr (MODE == MODE_COUNTS) p.counts[i] = r.n;
+      int sh = 0;
+      if (p.n_showers > 1) {
+        int lo = 0, hi = p.n_showers;  // offsets[lo] <= i < offsets[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (p.offsets[mid] <= i) lo = mid; else hi = mid;
+        }
+        sh = lo;
+      }
+      s_sx[tid] = fx0; s_sy[tid] = fy0; s_sz[tid] = fz0;
+      s_dx[tid] = fx1 - fx0; s_dy[tid] = fy1 - fy0; s_dz[tid] = fz1 - fz0;
+      s_ax[tid] = r.a0; s_ay[tid] = r.a1; s_az[tid] = r.a2;
+      s_cos[tid] = r.cos_t; s_sin[tid] = r.sin_t;
+      if (TRANSPORT == CPHOT_TRANSPORT_STRAIGHT && p.profile == CPHOT_PROFILE_LINSLEY5 && nrec) {
+        const float X0 = depth_f(p, fz0);
+        s_X0[tid] = X0;
+        s_dXs[tid] = depth_f(p, fz1) - X0;
+      } else {
+        s_X0[tid] = 0.f;
+        s_dXs[tid] = 0.f;
+      }
+      const double* g = p.geom + 5 * sh;
+      s_cx[tid] = (float)g[0]; s_cy[tid] = (float)g[1];
+      s_axx[tid] = (float)g[2]; s_axy[tid] = (float)g[3]; s_axz[tid] = (float)g[4];
+      s_idlo[tid] = (uint32_t)id;
+      s_idhi[tid] = (uint32_t)(id >> 32);
+      s_sh[tid] = (uint32_t)sh;
+    }
+    if constexpr (MODE == MODE_COUNTS) continue;
+    uint32_t total;
+    const uint32_t excl = block_exclusive_scan<BS>(nrec, s_wave, total);
+    s_off[tid] = excl;
+    if (tid == BS - 1) s_off[BS] = total;
+    __syncthreads();
+    for (uint32_t j = tid; j < total; j += BS) {
+      int lo = 0, hi = BS;
+#pragma unroll
+      for (int it = 0; it < 12; ++it) {
+        if (hi - lo <= 1) break;
+        const int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= j) lo = mid; else hi = mid;
+      }
+      const uint32_t k = j - s_off[lo];
+      Photon ph;
+      trace<TRANSPORT, DETECTOR, kTime>(p, s_ext, s_ldelta, s_linvn, s_sx[lo], s_sy[lo], s_sz[lo], s_dx[lo], s_dy[lo], s_dz[lo],
+                                        s_ax[lo], s_ay[lo], s_az[lo], s_cos[lo], s_sin[lo], s_X0[lo],
+                                        s_dXs[lo], s_cx[lo], s_cy[lo], s_axx[lo], s_axy[lo], s_axz[lo],
+                                        s_idlo[lo], s_idhi[lo], k, ph);
+      if constexpr (MODE == MODE_RECORDS) {
+        const int64_t seg_local = tile * BS + lo;
+        const int64_t slot = p.rec_off[seg_local] + (int64_t)k;
+        if (slot < p.rec_cap) {
+          cphot_photon_record rr;
+          rr.seg = ((uint64_t)s_idhi[lo] << 32) | s_idlo[lo];
+          rr.k = k;
+          rr.state = ph.state;
+          rr.bin = ph.bin;
+          rr.tbin = ph.tbin;
+          rr.x = ph.x; rr.y = ph.y; rr.z = ph.z;
+          rr.t = ph.t; rr.tau = ph.tau; rr.lambda = ph.lam;
+          rr.dx = ph.ux; rr.dy = ph.uy; rr.dz = ph.uz;
+          rr.u_abs = ph.u3;
+          p.rec[slot] = rr;
+        }
+      } else {
+        c_gen += 1;
+        c_up += ph.state == 1;
+        c_abs += ph.state == 2;
+        c_out += ph.state == 3;
+        if (ph.state == 0) {
+          c_bin += 1;
+          const uint32_t sh = s_sh[lo];
+          if constexpr (DETECTOR == CPHOT_DETECTOR_GRID) {
+            if (n_hist) {
+              atomicAdd(&s_hist[ph.bin], p.bunch);
+            } else {
+              const int64_t gb = (int64_t)sh * p.nx * p.ny + ph.bin;
+              if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
+              else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + gb, p.bunch);
+            }
+          } else {
+            const int64_t nsph = (int64_t)p.snx * p.sny;
+            const int64_t gb = (int64_t)sh * nsph + ph.bin;
+            if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
+            else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + gb, p.bunch);
+            if (p.n_t > 0) atomicAdd(p.thist + gb * (p.n_t + 1) + ph.tbin, p.bunch);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (MODE == MODE_PROPAGATE) {
+    if (n_hist) {
+      __syncthreads();
+      for (int b = tid; b < n_hist; b += BS) {
+        const uint32_t v = s_hist[b];
+        if (v) {
+          if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + b, (unsigned long long)v);
+          else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + b, v);
+        }
+      }
+    }
+    if (p.counters) {
+      const uint32_t v[8] = {c_in, c_skip, c_below, c_gen, c_up, c_abs, c_out, c_bin};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t s = wave_sum(v[q]);
+        if ((tid & 63) == 0 && s) atomicAdd(p.counters + q, (unsigned long long)s);
+      }
+      const uint32_t sb = wave_sum(c_bin);
+      if ((tid & 63) == 0 && sb) atomicAdd(p.counters + CPHOT_C_PHOTONS_BINNED, (unsigned long long)sb * p.bunch);
+    }
+  }
+}
+
+namespace {
+
+template <int BS, int T, int D, int M>
+hipError_t launch_one(const KParams& p, int grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_propagate<BS, T, D, M>), dim3(grid), dim3(BS), lds, s, p);
+  return hipGetLastError();
+}
+
+template <int BS, int T, int D>
+hipError_t launch_mode(const KParams& p, int mode, int grid, size_t lds, hipStream_t s) {
+  switch (mode) {
+    case MODE_PROPAGATE: return launch_one<BS, T, D, MODE_PROPAGATE>(p, grid, lds, s);
+    case MODE_COUNTS: return launch_one<BS, T, D, MODE_COUNTS>(p, grid, lds, s);
+    default: return launch_one<BS, T, D, MODE_RECORDS>(p, grid, lds, s);
+  }
+}
+
+template <int BS>
+hipError_t launch_bs(const KParams& p, int mode, int grid, size_t lds, hipStream_t s) {
+  if (p.transport == CPHOT_TRANSPORT_STRAIGHT) {
+    if (p.detector == CPHOT_DETECTOR_GRID) return launch_mode<BS, 0, 0>(p, mode, grid, lds, s);
+    return launch_mode<BS, 0, 1>(p, mode, grid, lds, s);
+  }
+  if (p.detector == CPHOT_DETECTOR_GRID) return launch_mode<BS, 1, 0>(p, mode, grid, lds, s);
+  return launch_mode<BS, 1, 1>(p, mode, grid, lds, s);
+}
+
+}  // namespace
+
+hipError_t launch_propagate(const KParams& p, int mode, int block_size, int grid_blocks, size_t lds_bytes,
+                            hipStream_t stream) {
+  switch (block_size) {
+    case 128: return launch_bs<128>(p, mode, grid_blocks, lds_bytes, stream);
+    case 512: return launch_bs<512>(p, mode, grid_blocks, lds_bytes, stream);
+    default: return launch_bs<256>(p, mode, grid_blocks, lds_bytes, stream);
+  }
+}
+
+}  // namespace cphot
