@@ -220,8 +220,12 @@ void cphot_destroy_atmosphere(cphot_atmosphere* atm);
 int cphot_propagate(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out, void* stream);
 
 /* Records per segment (0 for skipped or below-threshold segments) into the
- * device int32 array `counts` [seg->n]. Asynchronous. Errors: INVALID_ARG, HIP. */
-int cphot_segment_counts(const cphot_segments* seg, const cphot_detector* det, int32_t* counts, void* stream);
+ * device int32 array `counts` [seg->n] and, if `expected` is not NULL, the
+ * expected number of records mu (FP64, 0 where no photons are drawn) into the
+ * device array `expected` [seg->n]. Same arithmetic as cphot_propagate.
+ * Asynchronous. Errors: INVALID_ARG, HIP. */
+int cphot_segment_counts(const cphot_segments* seg, const cphot_detector* det, int32_t* counts, double* expected,
+                         void* stream);
 
 /* Every record of every segment, written to the device array `records` at
  * position record_offsets[i] + k for record k of segment i (record_offsets is

@@ -95,7 +95,7 @@ def lib():
             L.cphot_destroy_atmosphere.argtypes = [P]
             L.cphot_propagate.argtypes = [C.POINTER(Segments), C.POINTER(Detector), C.POINTER(Bins), P]
             L.cphot_propagate.restype = C.c_int
-            L.cphot_segment_counts.argtypes = [C.POINTER(Segments), C.POINTER(Detector), P, P]
+            L.cphot_segment_counts.argtypes = [C.POINTER(Segments), C.POINTER(Detector), P, P, P]
             L.cphot_segment_counts.restype = C.c_int
             L.cphot_trace_records.argtypes = [C.POINTER(Segments), C.POINTER(Detector), P, P, C.c_int64, P]
             L.cphot_trace_records.restype = C.c_int
@@ -225,11 +225,12 @@ def propagate(seg: Segments, det: Detector, bins, time_hist=None, counters=None,
     _check("cphot_propagate", lib().cphot_propagate(C.byref(seg), C.byref(det), C.byref(b), _stream_ptr(stream)))
 
 
-def segment_counts(seg: Segments, det: Detector, counts, stream=None):
+def segment_counts(seg: Segments, det: Detector, counts, expected=None, stream=None):
     import torch
+    ex = C.c_void_p(_dptr(expected, torch.float64, "expected")) if expected is not None else C.c_void_p()
     _check("cphot_segment_counts", lib().cphot_segment_counts(C.byref(seg), C.byref(det),
                                                                C.c_void_p(_dptr(counts, torch.int32, "counts")),
-                                                               _stream_ptr(stream)))
+                                                               ex, _stream_ptr(stream)))
 
 
 def trace_records(seg: Segments, det: Detector, record_offsets, records, stream=None):

@@ -387,13 +387,15 @@ int cphot_propagate(const cphot_segments* seg, const cphot_detector* det, cphot_
   return CPHOT_OK;
 }
 
-int cphot_segment_counts(const cphot_segments* seg, const cphot_detector* det, int32_t* counts, void* stream) {
+int cphot_segment_counts(const cphot_segments* seg, const cphot_detector* det, int32_t* counts, double* expected,
+                         void* stream) {
   if (!counts && seg && seg->n > 0) return fail(CPHOT_ERR_INVALID_ARG, "null counts");
   cphot::KParams p;
   int rc = fill_params(seg, det, p, false, nullptr);
   if (rc) return rc;
   if (p.n == 0) return CPHOT_OK;
   p.counts = counts;
+  p.expected = expected;
   LaunchShape s;
   if ((rc = choose_shape(det, p, cphot::MODE_COUNTS, s))) return rc;
   hipError_t e = cphot::launch_propagate(p, cphot::MODE_COUNTS, s.block, s.grid, s.lds, (hipStream_t)stream);

@@ -68,6 +68,7 @@ struct KParams {
   unsigned long long* counters;
   // debug outputs
   int32_t* counts;
+  double* expected;
   const int64_t* rec_off;
   cphot_photon_record* rec;
   int64_t rec_cap;

@@ -50,15 +50,16 @@ struct SegResult {
   int32_t n;       // records
   int32_t status;  // 0 ok, 1 below threshold, 2 skipped
   float cos_t, sin_t, a0, a1, a2;
+  double mu;       // expected records
 };
 
 // Per-segment yield in FP64 with IEEE basic operations only and no
 // contraction, in the fixed order that makes the record count reproducible
 // bit for bit on any IEEE machine.
-__device__ __noinline__ SegResult segment_setup(const KParams& p, float fx0, float fy0, float fz0, float fx1,
+__device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, float fy0, float fz0, float fx1,
                                                 float fy1, float fz1, float fbeta, float fq, uint64_t id) {
 #pragma clang fp contract(off)
-  SegResult r{0, 0, 0.f, 0.f, 0.f, 0.f, 0.f};
+  SegResult r{0, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0};
   if (!__builtin_isfinite(fx0) || !__builtin_isfinite(fy0) || !__builtin_isfinite(fz0) ||
       !__builtin_isfinite(fx1) || !__builtin_isfinite(fy1) || !__builtin_isfinite(fz1) ||
       !__builtin_isfinite(fbeta) || !__builtin_isfinite(fq)) {
@@ -107,6 +108,7 @@ __device__ __noinline__ SegResult segment_setup(const KParams& p, float fx0, flo
     r.status = 2;
     return r;
   }
+  r.mu = mu;
   const double fl = floor(mu);
   const uint4 w = philox(0u, (uint32_t)id, (uint32_t)(id >> 32), TAG_SEGMENT, p.key0, p.key1);
   const double u = (double)w.x * (1.0 / 4294967296.0);
@@ -401,7 +403,10 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       c_skip += r.status == 2;
       c_below += r.status == 1;
       nrec = (uint32_t)r.n;
-      if constexpr (MODE == MODE_COUNTS) p.counts[i] = r.n;
+      if constexpr (MODE == MODE_COUNTS) {
+        p.counts[i] = r.n;
+        if (p.expected) p.expected[i] = r.status == 0 ? r.mu : 0.0;
+      }
       int sh = 0;
       if (p.n_showers > 1) {
         int lo = 0, hi = p.n_showers;  // offsets[lo] <= i < offsets[hi]
@@ -437,13 +442,10 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     if (tid == BS - 1) s_off[BS] = total;
     __syncthreads();
     for (uint32_t j = tid; j < total; j += BS) {
-      int lo = 0, hi = BS;
+      // largest segment slot lo in [0, BS) with s_off[lo] <= j (offsets never decrease)
+      int lo = 0;
 #pragma unroll
-      for (int it = 0; it < 12; ++it) {
-        if (hi - lo <= 1) break;
-        const int mid = (lo + hi) >> 1;
-        if (s_off[mid] <= j) lo = mid; else hi = mid;
-      }
+      for (int step = BS / 2; step >= 1; step >>= 1) lo += (s_off[lo + step] <= j) ? step : 0;
       const uint32_t k = j - s_off[lo];
       Photon ph;
       trace<TRANSPORT, DETECTOR, kTime>(p, s_ext, s_ldelta, s_linvn, s_sx[lo], s_sy[lo], s_sz[lo], s_dx[lo], s_dy[lo], s_dz[lo],

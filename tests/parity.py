@@ -47,15 +47,18 @@ def device_run(atm_kw, run_kw, seg_np, geom, offsets=None, first_id=0, counters=
     return out
 
 
-def device_counts(atm_kw, run_kw, seg_np, geom, first_id=0):
+def device_counts(atm_kw, run_kw, seg_np, geom, first_id=0, with_mu=False):
     import torch
     atm = cphot.Atmosphere(**atm_kw)
     det = cphot.make_detector(atm, **run_kw)
     seg, g, off = cphot.upload(seg_np, geom)
     S = cphot.make_segments(seg, g, off, first_id=first_id)
     counts = torch.zeros(S.n, dtype=torch.int32, device="cuda")
-    cphot.segment_counts(S, det, counts)
+    mu = torch.zeros(S.n, dtype=torch.float64, device="cuda") if with_mu else None
+    cphot.segment_counts(S, det, counts, mu)
     torch.cuda.synchronize()
+    if with_mu:
+        return counts.cpu().numpy(), mu.cpu().numpy()
     return counts.cpu().numpy()
 
 

@@ -45,9 +45,12 @@ def test_counts_bit_exact_telescope_full_size():
     configuration the benchmark uses."""
     sh = W.workload_telescope("R")
     run = {**cases.RUN_TELESCOPE, "seed": 2}
-    g = parity.device_counts(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
+    g, mu = parity.device_counts(cases.ATMO_LAYERED, run, sh.seg, _geom(sh), with_mu=True)
     o = O.segment_counts(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(cases.RUN_TELESCOPE, 2), sh.seg)
     np.testing.assert_array_equal(g, o["n"])
+    # the FP64 yield itself is bit-identical, not only its rounding
+    omu = np.where(o["status"] == 0, o["mu"], 0.0)
+    np.testing.assert_array_equal(mu.view(np.uint64), omu.view(np.uint64))
     assert g.sum() > 1e7
 
 
