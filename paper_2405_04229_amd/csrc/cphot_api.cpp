@@ -70,18 +70,6 @@ double refractivity(const cphot_atmosphere& a, double h) {
   return d.kappa * (density(d, h) / a.rho0);
 }
 
-double vertical_tau(const cphot_atmosphere_desc& d, double lo, double hi, double lam) {
-  double tau = 0.0;
-  if (d.rayleigh400 > 0.0) {
-    const double r = lam / 400.0;
-    tau += (depth(d, lo) - depth(d, hi)) / (d.rayleigh400 * r * r * r * r);
-  }
-  if (d.aerosol_tau350 > 0.0)
-    tau += d.aerosol_tau350 * std::pow(lam / 350.0, -d.aerosol_angstrom) *
-           (std::exp(-lo / d.aerosol_height) - std::exp(-hi / d.aerosol_height));
-  return tau;
-}
-
 std::mutex g_dev_mu;
 int g_cu_count[64] = {0};
 
@@ -175,9 +163,8 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     p.dh = (float)(d.h_top / d.n_layers);
     p.inv_dh = (float)(d.n_layers / d.h_top);
     p.obs_layer = (int)std::floor(det->h_obs / (d.h_top / d.n_layers));
-    p.layer_delta = a->dev.layer_delta;
-    p.layer_inv_n = a->dev.layer_inv_n;
-    p.layer_ext = a->dev.layer_ext;
+    p.layers = a->dev.layers;
+    p.lambins = a->dev.lambins;
   }
   const int64_t ns = seg->n_showers;
   if (det->detector == CPHOT_DETECTOR_GRID) {
@@ -236,7 +223,6 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
   int bs = det->block_size ? det->block_size : 256;
   if (bs != 128 && bs != 256 && bs != 512) return fail(CPHOT_ERR_INVALID_ARG, "block_size must be 0, 128, 256 or 512");
   size_t lds = 0;
-  if (p.transport == CPHOT_TRANSPORT_LAYERED) lds += (size_t)(p.n_layers * p.n_lam + 2 * p.n_layers) * 4;
   p.lds_hist = 0;
   if (mode == cphot::MODE_PROPAGATE && p.detector == CPHOT_DETECTOR_GRID && p.n_showers == 1) {
     const size_t hb = (size_t)p.nx * p.ny * 4;
@@ -248,7 +234,10 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   const int64_t tiles = (p.n + bs - 1) / bs;
-  int64_t g = det->grid_blocks > 0 ? det->grid_blocks : (int64_t)cu_count(dev) * (2048 / bs);
+  // One block per tile lets the dispatcher balance uneven tiles. With an LDS
+  // histogram a persistent grid (a few blocks per CU walking the tiles)
+  // amortises the histogram's zeroing and flush.
+  int64_t g = det->grid_blocks > 0 ? det->grid_blocks : (p.lds_hist ? (int64_t)cu_count(dev) * 4 : tiles);
   if (g > tiles) g = tiles;
   if (g < 1) g = 1;
   s.block = bs;
@@ -317,24 +306,33 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
   a->n_tab = (int64_t)std::ceil(d.h_top / d.table_step);
   std::vector<double> tab((size_t)a->n_tab + 1);
   for (int64_t j = 0; j <= a->n_tab; ++j) tab[(size_t)j] = refractivity(*a, (double)j * d.table_step);
-  std::vector<float> ld, linv, lext;
+  // Layer tables. Each layer's extinction per metre factorises into a height
+  // part and a wavelength part: Rayleigh (X(lo) - X(hi)) / dh times 1/Lambda(lambda_k),
+  // plus the aerosol column (exp(-lo/H) - exp(-hi/H)) / dh times tau_A(lambda_k).
+  std::vector<float4> lay;
+  std::vector<float2> lamb;
   if (d.n_layers > 0) {
     const int L = d.n_layers, K = d.n_lambda_bins;
     const double dh = d.h_top / L;
     a->layer_delta.resize(L);
-    ld.resize(L);
-    linv.resize(L);
-    lext.resize((size_t)L * K);
+    lay.resize(L);
+    lamb.resize(K);
     for (int i = 0; i < L; ++i) {
       const double lo = i * dh, hi = (i + 1) * dh;
       const double dl = refractivity(*a, 0.5 * (lo + hi));
       a->layer_delta[i] = dl;
-      ld[i] = (float)dl;
-      linv[i] = (float)(1.0 / (1.0 + dl));
-      for (int k = 0; k < K; ++k) {
-        const double lam = d.lambda_min_nm + (k + 0.5) * (d.lambda_max_nm - d.lambda_min_nm) / K;
-        lext[(size_t)i * K + k] = (float)(vertical_tau(d, lo, hi, lam) / dh);
-      }
+      const double ray = d.rayleigh400 > 0.0 ? (depth(d, lo) - depth(d, hi)) / dh : 0.0;
+      const double aer = d.aerosol_tau350 > 0.0
+                             ? (std::exp(-lo / d.aerosol_height) - std::exp(-hi / d.aerosol_height)) / dh
+                             : 0.0;
+      lay[i] = make_float4((float)dl, (float)(1.0 / (1.0 + dl)), (float)ray, (float)aer);
+    }
+    for (int k = 0; k < K; ++k) {
+      const double lam = d.lambda_min_nm + (k + 0.5) * (d.lambda_max_nm - d.lambda_min_nm) / K;
+      const double r = lam / 400.0;
+      const double inv_ray = d.rayleigh400 > 0.0 ? 1.0 / (d.rayleigh400 * r * r * r * r) : 0.0;
+      const double taua = d.aerosol_tau350 > 0.0 ? d.aerosol_tau350 * std::pow(lam / 350.0, -d.aerosol_angstrom) : 0.0;
+      lamb[k] = make_float2((float)inv_ray, (float)taua);
     }
   }
   auto cleanup = [&](int code, const char* what, hipError_t e) {
@@ -349,12 +347,10 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
       hipSuccess)
     return cleanup(0, "hipMemcpy(delta_table)", e);
   if (d.n_layers > 0) {
-    if ((e = hipMalloc(&a->dev.layer_delta, ld.size() * 4)) != hipSuccess) return cleanup(0, "hipMalloc", e);
-    if ((e = hipMalloc(&a->dev.layer_inv_n, linv.size() * 4)) != hipSuccess) return cleanup(0, "hipMalloc", e);
-    if ((e = hipMalloc(&a->dev.layer_ext, lext.size() * 4)) != hipSuccess) return cleanup(0, "hipMalloc", e);
-    if ((e = hipMemcpy(a->dev.layer_delta, ld.data(), ld.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(a->dev.layer_inv_n, linv.data(), linv.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(a->dev.layer_ext, lext.data(), lext.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMalloc(&a->dev.layers, lay.size() * sizeof(float4))) != hipSuccess) return cleanup(0, "hipMalloc", e);
+    if ((e = hipMalloc(&a->dev.lambins, lamb.size() * sizeof(float2))) != hipSuccess) return cleanup(0, "hipMalloc", e);
+    if ((e = hipMemcpy(a->dev.layers, lay.data(), lay.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(a->dev.lambins, lamb.data(), lamb.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup(0, "hipMemcpy(layers)", e);
   }
   *out = a;
@@ -367,9 +363,8 @@ void cphot_destroy_atmosphere(cphot_atmosphere* a) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(a->device);
   if (a->dev.delta_table) (void)hipFree(a->dev.delta_table);
-  if (a->dev.layer_delta) (void)hipFree(a->dev.layer_delta);
-  if (a->dev.layer_inv_n) (void)hipFree(a->dev.layer_inv_n);
-  if (a->dev.layer_ext) (void)hipFree(a->dev.layer_ext);
+  if (a->dev.layers) (void)hipFree(a->dev.layers);
+  if (a->dev.lambins) (void)hipFree(a->dev.lambins);
   (void)hipSetDevice(prev);
   delete a;
 }

@@ -14,9 +14,10 @@ constexpr int kMaxLambdaBins = 64;
 // Device-side tables owned by an atmosphere handle.
 struct AtmoDevice {
   double* delta_table = nullptr;   // n_tab + 1 entries, FP64 (per-segment yield)
-  float* layer_delta = nullptr;    // n_layers
-  float* layer_inv_n = nullptr;    // n_layers: 1 / (1 + delta)
-  float* layer_ext = nullptr;      // n_layers * n_lam, extinction per metre
+  // per layer: (n - 1, 1/n, Rayleigh depth per metre in g/cm^2/m, aerosol column per metre);
+  // the extinction of layer i at wavelength bin k is lay.z * lam[k].x + lay.w * lam[k].y
+  float4* layers = nullptr;        // n_layers
+  float2* lambins = nullptr;       // n_lam: (1 / Rayleigh length in g/cm^2, aerosol vertical depth)
 };
 
 // Everything a launch needs, passed by value as the kernel argument.
@@ -51,9 +52,8 @@ struct KParams {
   int32_t n_layers, n_lam;
   float dh, inv_dh;
   int32_t obs_layer;
-  const float* layer_delta;
-  const float* layer_inv_n;
-  const float* layer_ext;
+  const float4* layers;
+  const float2* lambins;
   int32_t nx, ny;
   float cell, inv_cell;
   int32_t snx, sny;

@@ -155,14 +155,16 @@ struct Photon {
 };
 
 template <int TRANSPORT, int DETECTOR, bool NEED_TIME>
-__device__ __forceinline__ void trace(const KParams& p, const float* __restrict__ s_ext,
-                                      const float* __restrict__ s_ldelta, const float* __restrict__ s_linvn,
-                                      float sx, float sy,
-                                      float sz, float dx, float dy, float dz, float ax, float ay, float az,
-                                      float cos_t, float sin_t, float X0, float dX, float core_x, float core_y,
-                                      float axx, float axy, float axz, uint32_t id_lo, uint32_t id_hi,
+__device__ __forceinline__ void trace(const KParams& p, const float4* __restrict__ s_lay,
+                                      const float2* __restrict__ s_lam, const float4 q0, const float4 q1,
+                                      const float4 q2, const float4 q3, const float4 q4, const float axz,
                                       uint32_t k, Photon& o) {
-  const uint4 w = philox(k, id_lo, id_hi, TAG_CHERENKOV, p.key0, p.key1);
+  const float sx = q0.x, sy = q0.y, sz = q0.z, cos_t = q0.w;
+  const float dx = q1.x, dy = q1.y, dz = q1.z, sin_t = q1.w;
+  const float ax = q2.x, ay = q2.y, az = q2.z, X0 = q2.w;
+  const float dX = q3.x;
+  const float core_x = q4.x, core_y = q4.y, axx = q4.z, axy = q4.w;
+  const uint4 w = philox(k, __float_as_uint(q3.y), __float_as_uint(q3.z), TAG_CHERENKOV, p.key0, p.key1);
   const float f = u24(w.x);
   float sphi, cphi;
   sincospif(2.0f * u24(w.y), &sphi, &cphi);
@@ -196,15 +198,14 @@ __device__ __forceinline__ void trace(const KParams& p, const float* __restrict_
     o.state = 3;
     return;
   }
-  float x, y, z;                 // start of the final leg
-  float vx, vy, vz;              // direction of the final leg
+  float x, y, z;     // start of the final leg
+  float vx, vy, vz;  // direction of the final leg
   float tau = 0.f, geo = 0.f, opt = 0.f;
   float last_delta = 0.f, last_ext = 0.f;
   if constexpr (TRANSPORT == CPHOT_TRANSPORT_LAYERED) {
-    // Homogeneous layers (Sec. 3.4.2): within a layer the ray is straight; at a
-    // horizontal boundary the horizontal part of n u is conserved (the vector
-    // form of Snell's law, Eq. 3.15, with a vertical normal), so every layer is
-    // entered with sin(theta_i) = K / n_i, K = n_e sin(theta_e).
+    // Homogeneous layers (Sec. 3.4.2): straight within a layer; at a horizontal
+    // boundary the horizontal part of n u is conserved (Eq. 3.15 with a vertical
+    // normal), so layer i is crossed with sin(theta_i) = K / n_i, K = n_e sin(theta_e).
     int i = min((int)(Pz * p.inv_dh), p.n_layers - 1);
     const float sh = sqrtf(ux * ux + uy * uy);
     float hx = 1.f, hy = 0.f;
@@ -213,38 +214,41 @@ __device__ __forceinline__ void trace(const KParams& p, const float* __restrict_
       hx = ux * ish;
       hy = uy * ish;
     }
-    const float Kc = fmaf(sh, s_ldelta[i], sh);
+    float4 L = s_lay[i];
+    const float Kc = fmaf(sh, L.x, sh);
     int kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
     kb = min(max(kb, 0), p.n_lam - 1);
+    const float2 sp = s_lam[kb];
     x = Px;
     y = Py;
     z = Pz;
     while (i > p.obs_layer) {
       const float zb = (float)i * p.dh;
       const float span = z - zb;
-      const float s = Kc * s_linvn[i];
+      const float s = Kc * L.y;
       const float c2 = (1.f - s) * (1.f + s);
       const float ic = rsqrtf(c2);
       const float path = span * ic;
       const float adv = path * s;
       x = fmaf(hx, adv, x);
       y = fmaf(hy, adv, y);
-      tau = fmaf(s_ext[i * p.n_lam + kb], path, tau);
+      tau = fmaf(fmaf(L.z, sp.x, L.w * sp.y), path, tau);
       if constexpr (NEED_TIME) {
         const float ex = s * hx - axx, ey = s * hy - axy, ez = -c2 * ic - axz;
         geo = fmaf(path, 0.5f * (ex * ex + ey * ey + ez * ez), geo);
-        opt = fmaf(s_ldelta[i], path, opt);
+        opt = fmaf(L.x, path, opt);
       }
       z = zb;
       --i;
+      L = s_lay[i];
     }
-    const float s = Kc * s_linvn[i];
+    const float s = Kc * L.y;
     const float c = sqrtf((1.f - s) * (1.f + s));
     vx = s * hx;
     vy = s * hy;
     vz = -c;
-    last_delta = s_ldelta[i];
-    last_ext = s_ext[i * p.n_lam + kb];
+    last_delta = L.x;
+    last_ext = fmaf(L.z, sp.x, L.w * sp.y);
   } else {
     x = Px;
     y = Py;
@@ -365,27 +369,26 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 template <int BS, int TRANSPORT, int DETECTOR, int MODE>
 __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   constexpr bool kTime = (DETECTOR == CPHOT_DETECTOR_SPHERES) || (MODE == MODE_RECORDS);
-  __shared__ float s_sx[BS], s_sy[BS], s_sz[BS], s_dx[BS], s_dy[BS], s_dz[BS];
-  __shared__ float s_ax[BS], s_ay[BS], s_az[BS], s_cos[BS], s_sin[BS], s_X0[BS], s_dXs[BS];
-  __shared__ float s_cx[BS], s_cy[BS], s_axx[BS], s_axy[BS], s_axz[BS];
-  __shared__ uint32_t s_idlo[BS], s_idhi[BS], s_sh[BS];
+  constexpr bool kSort = (TRANSPORT == CPHOT_TRANSPORT_LAYERED) && (MODE != MODE_COUNTS);
+  // per-segment state for the record loop, one slot per segment of the tile:
+  // q0 = start point, cos(theta); q1 = end - start, sin(theta); q2 = rotation
+  // bisector, depth at the start; q3 = depth change, id low, id high, shower
+  // (bit patterns); q4 = core x, core y, axis x, axis y; axz = axis z
+  __shared__ float4 s_q0[BS], s_q1[BS], s_q2[BS], s_q3[BS], s_q4[BS];
+  __shared__ float s_axz[BS];
   __shared__ uint32_t s_off[BS + 1];
   __shared__ uint32_t s_wave[BS / 64];
-  // dynamic LDS: [layer extinction L*K][layer n-1 L][layer 1/n L][grid histogram]
-  extern __shared__ uint32_t s_dyn[];
-  const int n_lay = (TRANSPORT == CPHOT_TRANSPORT_LAYERED) ? p.n_layers : 0;
-  const int n_ext = n_lay * p.n_lam;
-  float* s_ext = reinterpret_cast<float*>(s_dyn);
-  float* s_ldelta = s_ext + n_ext;
-  float* s_linvn = s_ldelta + n_lay;
-  uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_linvn + n_lay);
+  __shared__ uint32_t s_src[kSort ? BS : 1];          // tile-local segment index of each slot
+  __shared__ uint32_t s_bucket[kSort ? kMaxLayers + 1 : 1];
+  __shared__ float4 s_lay[TRANSPORT == CPHOT_TRANSPORT_LAYERED ? kMaxLayers : 1];
+  __shared__ float2 s_lam[TRANSPORT == CPHOT_TRANSPORT_LAYERED ? kMaxLambdaBins : 1];
+  extern __shared__ uint32_t s_hist[];  // optional LDS grid histogram
   const int n_hist = (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_GRID && p.lds_hist) ? p.nx * p.ny : 0;
   const int tid = threadIdx.x;
 
-  for (int i = tid; i < n_ext; i += BS) s_ext[i] = p.layer_ext[i];
-  for (int i = tid; i < n_lay; i += BS) {
-    s_ldelta[i] = p.layer_delta[i];
-    s_linvn[i] = p.layer_inv_n[i];
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_LAYERED) {
+    for (int i = tid; i < p.n_layers; i += BS) s_lay[i] = p.layers[i];
+    for (int i = tid; i < p.n_lam; i += BS) s_lam[i] = p.lambins[i];
   }
   for (int i = tid; i < n_hist; i += BS) s_hist[i] = 0u;
   __syncthreads();
@@ -395,6 +398,9 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t i = tile * BS + tid;
     uint32_t nrec = 0;
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
+    float axz = 0.f;
+    int key = kMaxLayers;  // segments without records sort last
     if (i < p.n) {
       const float fx0 = p.x0[i], fy0 = p.y0[i], fz0 = p.z0[i], fx1 = p.x1[i], fy1 = p.y1[i], fz1 = p.z1[i];
       const uint64_t id = p.first_id + (uint64_t)i;
@@ -406,58 +412,91 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       if constexpr (MODE == MODE_COUNTS) {
         p.counts[i] = r.n;
         if (p.expected) p.expected[i] = r.status == 0 ? r.mu : 0.0;
-      }
-      int sh = 0;
-      if (p.n_showers > 1) {
-        int lo = 0, hi = p.n_showers;  // offsets[lo] <= i < offsets[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (p.offsets[mid] <= i) lo = mid; else hi = mid;
+      } else if (nrec) {
+        int sh = 0;
+        if (p.n_showers > 1) {
+          int lo = 0, hi = p.n_showers;  // offsets[lo] <= i < offsets[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (p.offsets[mid] <= i) lo = mid; else hi = mid;
+          }
+          sh = lo;
         }
-        sh = lo;
+        float X0 = 0.f, dXs = 0.f;
+        if (TRANSPORT == CPHOT_TRANSPORT_STRAIGHT && p.profile == CPHOT_PROFILE_LINSLEY5) {
+          X0 = depth_f(p, fz0);
+          dXs = depth_f(p, fz1) - X0;
+        }
+        const double* g = p.geom + 5 * sh;
+        q0 = make_float4(fx0, fy0, fz0, r.cos_t);
+        q1 = make_float4(fx1 - fx0, fy1 - fy0, fz1 - fz0, r.sin_t);
+        q2 = make_float4(r.a0, r.a1, r.a2, X0);
+        q3 = make_float4(dXs, __uint_as_float((uint32_t)id), __uint_as_float((uint32_t)(id >> 32)),
+                         __uint_as_float((uint32_t)sh));
+        q4 = make_float4((float)g[0], (float)g[1], (float)g[2], (float)g[3]);
+        axz = (float)g[4];
+        if constexpr (kSort) key = min(max((int)(0.5f * (fz0 + fz1) * p.inv_dh), 0), p.n_layers - 1);
       }
-      s_sx[tid] = fx0; s_sy[tid] = fy0; s_sz[tid] = fz0;
-      s_dx[tid] = fx1 - fx0; s_dy[tid] = fy1 - fy0; s_dz[tid] = fz1 - fz0;
-      s_ax[tid] = r.a0; s_ay[tid] = r.a1; s_az[tid] = r.a2;
-      s_cos[tid] = r.cos_t; s_sin[tid] = r.sin_t;
-      if (TRANSPORT == CPHOT_TRANSPORT_STRAIGHT && p.profile == CPHOT_PROFILE_LINSLEY5 && nrec) {
-        const float X0 = depth_f(p, fz0);
-        s_X0[tid] = X0;
-        s_dXs[tid] = depth_f(p, fz1) - X0;
-      } else {
-        s_X0[tid] = 0.f;
-        s_dXs[tid] = 0.f;
-      }
-      const double* g = p.geom + 5 * sh;
-      s_cx[tid] = (float)g[0]; s_cy[tid] = (float)g[1];
-      s_axx[tid] = (float)g[2]; s_axy[tid] = (float)g[3]; s_axz[tid] = (float)g[4];
-      s_idlo[tid] = (uint32_t)id;
-      s_idhi[tid] = (uint32_t)(id >> 32);
-      s_sh[tid] = (uint32_t)sh;
     }
     if constexpr (MODE == MODE_COUNTS) continue;
+    // slot of this segment in the tile: sorted by start layer under layered
+    // transport, so that the lanes of a wave cross similar numbers of layers
+    int slot = tid;
+    if constexpr (kSort) {
+      for (int b = tid; b <= kMaxLayers; b += BS) s_bucket[b] = 0u;
+      __syncthreads();
+      const uint32_t rank = atomicAdd(&s_bucket[key], 1u);
+      __syncthreads();
+      if (tid < 64) {  // exclusive scan of the bucket sizes by one wave
+        uint32_t carry = 0;
+        for (int base = 0; base <= kMaxLayers; base += 64) {
+          const int b = base + tid;
+          const uint32_t v = b <= kMaxLayers ? s_bucket[b] : 0u;
+          uint32_t x = v;
+#pragma unroll
+          for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (tid >= d) x += y;
+          }
+          if (b <= kMaxLayers) s_bucket[b] = carry + x - v;
+          carry += __shfl(x, 63, 64);
+        }
+      }
+      __syncthreads();
+      slot = (int)(s_bucket[key] + rank);
+      s_src[slot] = (uint32_t)tid;
+    }
+    s_q0[slot] = q0;
+    s_q1[slot] = q1;
+    s_q2[slot] = q2;
+    s_q3[slot] = q3;
+    s_q4[slot] = q4;
+    s_axz[slot] = axz;
+    s_off[slot] = nrec;
+    __syncthreads();
     uint32_t total;
-    const uint32_t excl = block_exclusive_scan<BS>(nrec, s_wave, total);
+    const uint32_t mine = s_off[tid];
+    const uint32_t excl = block_exclusive_scan<BS>(mine, s_wave, total);
+    __syncthreads();
     s_off[tid] = excl;
     if (tid == BS - 1) s_off[BS] = total;
     __syncthreads();
     for (uint32_t j = tid; j < total; j += BS) {
-      // largest segment slot lo in [0, BS) with s_off[lo] <= j (offsets never decrease)
+      // largest slot lo in [0, BS) with s_off[lo] <= j (offsets never decrease)
       int lo = 0;
 #pragma unroll
       for (int step = BS / 2; step >= 1; step >>= 1) lo += (s_off[lo + step] <= j) ? step : 0;
       const uint32_t k = j - s_off[lo];
       Photon ph;
-      trace<TRANSPORT, DETECTOR, kTime>(p, s_ext, s_ldelta, s_linvn, s_sx[lo], s_sy[lo], s_sz[lo], s_dx[lo], s_dy[lo], s_dz[lo],
-                                        s_ax[lo], s_ay[lo], s_az[lo], s_cos[lo], s_sin[lo], s_X0[lo],
-                                        s_dXs[lo], s_cx[lo], s_cy[lo], s_axx[lo], s_axy[lo], s_axz[lo],
-                                        s_idlo[lo], s_idhi[lo], k, ph);
+      const float4 r3 = s_q3[lo];
+      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_q0[lo], s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], k,
+                                        ph);
       if constexpr (MODE == MODE_RECORDS) {
-        const int64_t seg_local = tile * BS + lo;
-        const int64_t slot = p.rec_off[seg_local] + (int64_t)k;
-        if (slot < p.rec_cap) {
+        const uint32_t src = kSort ? s_src[lo] : (uint32_t)lo;
+        const int64_t slot_out = p.rec_off[tile * BS + src] + (int64_t)k;
+        if (slot_out < p.rec_cap) {
           cphot_photon_record rr;
-          rr.seg = ((uint64_t)s_idhi[lo] << 32) | s_idlo[lo];
+          rr.seg = ((uint64_t)__float_as_uint(r3.z) << 32) | __float_as_uint(r3.y);
           rr.k = k;
           rr.state = ph.state;
           rr.bin = ph.bin;
@@ -466,7 +505,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
           rr.t = ph.t; rr.tau = ph.tau; rr.lambda = ph.lam;
           rr.dx = ph.ux; rr.dy = ph.uy; rr.dz = ph.uz;
           rr.u_abs = ph.u3;
-          p.rec[slot] = rr;
+          p.rec[slot_out] = rr;
         }
       } else {
         c_gen += 1;
@@ -475,7 +514,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
         c_out += ph.state == 3;
         if (ph.state == 0) {
           c_bin += 1;
-          const uint32_t sh = s_sh[lo];
+          const uint32_t sh = __float_as_uint(r3.w);
           if constexpr (DETECTOR == CPHOT_DETECTOR_GRID) {
             if (n_hist) {
               atomicAdd(&s_hist[ph.bin], p.bunch);
@@ -508,14 +547,20 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       }
     }
     if (p.counters) {
+      // block-level reduction: one global atomic per counter per block (same-address
+      // device atomics serialise, so their number must stay small)
+      __shared__ uint32_t s_cnt[8];
+      if (tid < 8) s_cnt[tid] = 0u;
+      __syncthreads();
       const uint32_t v[8] = {c_in, c_skip, c_below, c_gen, c_up, c_abs, c_out, c_bin};
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const uint32_t s = wave_sum(v[q]);
-        if ((tid & 63) == 0 && s) atomicAdd(p.counters + q, (unsigned long long)s);
+        const uint32_t sw = wave_sum(v[q]);
+        if ((tid & 63) == 0 && sw) atomicAdd(&s_cnt[q], sw);
       }
-      const uint32_t sb = wave_sum(c_bin);
-      if ((tid & 63) == 0 && sb) atomicAdd(p.counters + CPHOT_C_PHOTONS_BINNED, (unsigned long long)sb * p.bunch);
+      __syncthreads();
+      if (tid < 8 && s_cnt[tid]) atomicAdd(p.counters + tid, (unsigned long long)s_cnt[tid]);
+      if (tid == 8 && s_cnt[7]) atomicAdd(p.counters + CPHOT_C_PHOTONS_BINNED, (unsigned long long)s_cnt[7] * p.bunch);
     }
   }
 }
