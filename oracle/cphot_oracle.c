@@ -673,3 +673,82 @@ int orc_layered_ray(const orc_atmo* A, const double* P, const double* u, double 
   for (int j = 0; j < 3; ++j) end_out[j] = pos[j] + s * dir[j];
   return m;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Transport surrogate: training inputs and exact targets                     */
+/* ------------------------------------------------------------------------- */
+/* The MLP surrogate of this build replaces the layered tracer's correction to
+ * the straight line, the role the thesis gives to its precomputed correction
+ * table (Sec. 4.4.1: the difference between the straight-line and the
+ * iterative propagation). Inputs per photon: emission height h_e (m), cos of the
+ * photon zenith angle, azimuth phi (rad), wavelength-bin centre (nm),
+ * observation level h_obs (m). Targets: the landing offset (dx, dy) of the
+ * layered path from the straight line started at the same point and direction,
+ * the optical path excess e = sum n_i l_i - l_straight (m) and log T = -tau. */
+
+/* Training inputs i = first .. first+n-1 drawn from two Philox blocks with
+ * counters (i low, 0, i high, 8) and (i low, 1, i high, 8): h_obs, h_e, cos(theta), phi uniform in
+ * the domain box (h_e at or above h_obs), the wavelength a uniformly drawn bin. */
+void orc_surrogate_inputs(const orc_atmo* A, uint64_t seed, const double* lo, const double* hi, int64_t first,
+                          int64_t n, double* X) {
+  for (int64_t j = 0; j < n; ++j) {
+    uint64_t i = (uint64_t)(first + j);
+    uint32_t ctr0[4] = {(uint32_t)i, 0u, (uint32_t)(i >> 32), TAG_TRAIN};
+    uint32_t ctr1[4] = {(uint32_t)i, 1u, (uint32_t)(i >> 32), TAG_TRAIN};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4], v[4];
+    orc_philox(ctr0, key, w);
+    orc_philox(ctr1, key, v);
+    double h_obs = lo[4] + (hi[4] - lo[4]) * u24(w[0]);
+    double he_lo = lo[0] > h_obs ? lo[0] : h_obs;
+    double h_e = he_lo + (hi[0] - he_lo) * u24(w[1]);
+    double ct = lo[1] + (hi[1] - lo[1]) * u24(w[2]);
+    double phi = lo[2] + (hi[2] - lo[2]) * u24(w[3]);
+    int K = A->p.n_lam;
+    int k = (int)floor(u24(v[0]) * K);
+    if (k > K - 1) k = K - 1;
+    double lam = A->p.lam_min + (k + 0.5) * (A->p.lam_max - A->p.lam_min) / K;
+    double* x = X + 5 * j;
+    x[0] = h_e; x[1] = ct; x[2] = phi; x[3] = lam; x[4] = h_obs;
+  }
+}
+
+void orc_surrogate_targets(const orc_atmo* A, int64_t n, const double* X, double* Y) {
+  const orc_atmo_params* p = &A->p;
+  double dh = p->h_top / p->n_layers;
+  double N[3] = {0.0, 0.0, -1.0};
+  for (int64_t j = 0; j < n; ++j) {
+    const double* x = X + 5 * j;
+    double h_e = x[0], ct = x[1], phi = x[2], lam = x[3], h_obs = x[4];
+    double st = sqrt(1.0 - ct * ct);
+    double u[3] = {st * cos(phi), st * sin(phi), -ct};
+    int kbin = (int)floor((lam - p->lam_min) / (p->lam_max - p->lam_min) * p->n_lam);
+    if (kbin < 0) kbin = 0;
+    if (kbin > p->n_lam - 1) kbin = p->n_lam - 1;
+    double pos[3] = {0.0, 0.0, h_e}, dir[3] = {u[0], u[1], u[2]};
+    double optical = 0.0, tau = 0.0;
+    int layer = (int)floor(h_e / dh);
+    if (layer > p->n_layers - 1) layer = p->n_layers - 1;
+    int obs_layer = (int)floor(h_obs / dh);
+    while (layer > obs_layer) {
+      double zb = layer * dh;
+      double s = straight_to_plane(pos, dir, zb);
+      for (int q = 0; q < 3; ++q) pos[q] += s * dir[q];
+      pos[2] = zb;
+      optical += (1.0 + A->layer_delta[layer]) * s;
+      tau += A->layer_ext[(size_t)layer * p->n_lam + kbin] * s;
+      refract(dir, N, 1.0 + A->layer_delta[layer], 1.0 + A->layer_delta[layer - 1]);
+      --layer;
+    }
+    double s = straight_to_plane(pos, dir, h_obs);
+    for (int q = 0; q < 3; ++q) pos[q] += s * dir[q];
+    optical += (1.0 + A->layer_delta[layer]) * s;
+    tau += A->layer_ext[(size_t)layer * p->n_lam + kbin] * s;
+    double s_straight = (h_obs - h_e) / u[2];
+    double* y = Y + 4 * j;
+    y[0] = pos[0] - s_straight * u[0];
+    y[1] = pos[1] - s_straight * u[1];
+    y[2] = optical - s_straight;
+    y[3] = -tau;
+  }
+}

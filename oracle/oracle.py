@@ -106,6 +106,9 @@ def lib():
             L.orc_layered_ray.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), C.c_double,
                                           P(C.c_double), P(C.c_double), C.c_int]
             L.orc_layered_ray.restype = C.c_int
+            L.orc_surrogate_inputs.argtypes = [C.c_void_p, C.c_uint64, P(C.c_double), P(C.c_double), C.c_int64,
+                                               C.c_int64, P(C.c_double)]
+            L.orc_surrogate_targets.argtypes = [C.c_void_p, C.c_int64, P(C.c_double), P(C.c_double)]
             _lib = L
     return _lib
 
@@ -272,3 +275,21 @@ def layered_ray(atm: Atmosphere, start, direction, h_end, cap=4096):
     m = lib().orc_layered_ray(atm.handle, _ptr(P, C.c_double), _ptr(u, C.c_double), float(h_end),
                               _ptr(end, C.c_double), _ptr(snell, C.c_double), cap)
     return end, snell[: min(m, cap)]
+
+
+def surrogate_inputs(atm: Atmosphere, seed, lo, hi, first, n):
+    """Training inputs [n, 5] = (h_e, cos zenith, azimuth, wavelength-bin centre, h_obs)."""
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    X = np.zeros((int(n), 5))
+    lib().orc_surrogate_inputs(atm.handle, int(seed) & (2**64 - 1), _ptr(lo, C.c_double), _ptr(hi, C.c_double),
+                               int(first), int(n), _ptr(X, C.c_double))
+    return X
+
+
+def surrogate_targets(atm: Atmosphere, X):
+    """Exact layered targets [n, 4] = (dx, dy, optical path excess, log T) for inputs X [n, 5]."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.zeros((X.shape[0], 4))
+    lib().orc_surrogate_targets(atm.handle, X.shape[0], _ptr(X, C.c_double), _ptr(Y, C.c_double))
+    return Y
