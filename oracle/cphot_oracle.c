@@ -217,7 +217,8 @@ void orc_layer_tables(const orc_atmo* A, double* delta_out, double* ext_out) {
 /* ------------------------------------------------------------------------- */
 /* Run description                                                            */
 /* ------------------------------------------------------------------------- */
-enum { TRANSPORT_STRAIGHT = 0, TRANSPORT_LAYERED = 1 };
+enum { TRANSPORT_STRAIGHT = 0, TRANSPORT_LAYERED = 1, TRANSPORT_CURVED = 2 };
+enum { EMIT_CHERENKOV = 1, EMIT_FLUORESCENCE = 2 };
 enum { DETECTOR_GRID = 0, DETECTOR_SPHERES = 1 };
 enum { SPECTRUM_UNIFORM = 0, SPECTRUM_FRANK_TAMM = 1 };
 
@@ -231,13 +232,17 @@ typedef struct {
   double pitch, radius; /* m */
   int32_t n_t, pad;     /* time bins per sphere (+1 overflow) */
   double dt;            /* ns */
+  int32_t emission;     /* bit 0: Cherenkov, bit 1: fluorescence */
+  int32_t pad2;
+  double fl_yield[3];   /* fluorescence photons per MeV deposited, per band */
+  double fl_lambda[3];  /* band wavelengths, nm */
 } orc_run;
 
 enum { ST_BINNED = 0, ST_UPWARD = 1, ST_ABSORBED = 2, ST_OUTSIDE = 3 };
 
 typedef struct {
   int64_t seg;
-  int32_t k, state;
+  int32_t k, state;    /* k: record index within the segment (Cherenkov first, then the bands) */
   int32_t bin, tbin;
   double x, y, z;       /* arrival point: ground or sphere entry */
   double t;             /* ns after the plane front */
@@ -248,13 +253,18 @@ typedef struct {
   double tmargin;       /* distance of t to the nearest time-bin edge, ns */
   double ex, ey, ez;    /* emission point */
   double dx, dy, dz;    /* emission direction */
+  int32_t source;       /* 0 Cherenkov, 1 + b fluorescence band b */
+  int32_t pad;
 } orc_photon;
 
 typedef struct {
-  int32_t n;      /* records drawn */
-  int32_t status; /* 0 ok, 1 below threshold, 2 skipped (non-finite/degenerate/invalid beta) */
-  double mu;      /* expected records */
+  int32_t n;      /* Cherenkov records drawn */
+  int32_t status; /* 0 ok, 1 below the Cherenkov threshold, 2 skipped (non-finite/degenerate/invalid beta) */
+  double mu;      /* expected Cherenkov records */
   double cos_t, sin2_t;
+  int32_t nf[3];  /* fluorescence records per band */
+  int32_t pad;
+  double muf[3];  /* expected fluorescence records per band */
 } orc_segment;
 
 typedef struct { double core_x, core_y, ax, ay, az; } orc_geom;
@@ -282,41 +292,68 @@ static double frank_tamm_K(double lam_min_nm, double lam_max_nm) {
  * the reading that keeps the mean and needs only IEEE basic operations. */
 static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
                                  float x0, float y0, float z0, float x1, float y1, float z1,
-                                 float beta_f, float charge_f, uint64_t seg_id, seg_setup* st) {
-  orc_segment out = {0, 0, 0.0, 0.0, 0.0};
+                                 float beta_f, float charge_f, float dedx_f, uint64_t seg_id, seg_setup* st) {
+  orc_segment out;
+  memset(&out, 0, sizeof(out));
+  int emit = R->emission ? R->emission : EMIT_CHERENKOV;
+  int fluor = (emit & EMIT_FLUORESCENCE) != 0;
   if (!isfinite(x0) || !isfinite(y0) || !isfinite(z0) || !isfinite(x1) || !isfinite(y1) ||
-      !isfinite(z1) || !isfinite(beta_f) || !isfinite(charge_f)) { out.status = 2; return out; }
+      !isfinite(z1) || !isfinite(beta_f) || !isfinite(charge_f) || (fluor && !isfinite(dedx_f))) {
+    out.status = 2;
+    return out;
+  }
   double beta = (double)beta_f;
   if (!(beta > 0.0 && beta < 1.0)) { out.status = 2; return out; }
   double dx = (double)x1 - (double)x0, dy = (double)y1 - (double)y0, dz = (double)z1 - (double)z0;
   double L = sqrt(dx * dx + dy * dy + dz * dz);
   if (!(L > 0.0)) { out.status = 2; return out; }
-  /* refractivity at the segment midpoint from the 1 m table */
-  double hm = 0.5 * ((double)z0 + (double)z1);
-  double delta = orc_delta_table(A, hm);
-  /* threshold beta n > 1, with g = beta n - 1 written through eps = 1 - beta */
-  double eps = 1.0 - beta;
-  double g = delta - eps - eps * delta;
-  if (!(g > 0.0)) { out.status = 1; return out; }
-  /* sin^2(theta) = 1 - 1/(beta n)^2 (Eq. 2.3, 2.4) */
-  double s2 = g * (g + 2.0) / ((1.0 + g) * (1.0 + g));
-  double z2 = (double)charge_f * (double)charge_f;
-  double mu = K * z2;
-  mu = mu * L;
-  mu = mu * s2;
-  mu = mu / (double)R->bunch;
-  /* A segment asking for 2^20 records or more (or a non-finite yield) is
-   * rejected as invalid input rather than truncated. */
-  if (!(mu < 1048576.0)) { out.status = 2; return out; }
-  double fl = floor(mu);
+  /* one Philox block per segment: word 0 rounds the Cherenkov yield, words
+   * 1..3 the three fluorescence bands */
   uint32_t w[4];
   draw(R->seed, 0u, seg_id, TAG_SEGMENT, w);
-  int32_t n = (int32_t)fl + (u32d(w[0]) < mu - fl ? 1 : 0);
-  out.n = n; out.mu = mu; out.cos_t = 1.0 / (1.0 + g); out.sin2_t = s2;
+  if (emit & EMIT_CHERENKOV) {
+    /* refractivity at the segment midpoint from the 1 m table */
+    double hm = 0.5 * ((double)z0 + (double)z1);
+    double delta = orc_delta_table(A, hm);
+    /* threshold beta n > 1, with g = beta n - 1 written through eps = 1 - beta */
+    double eps = 1.0 - beta;
+    double g = delta - eps - eps * delta;
+    if (!(g > 0.0)) {
+      out.status = 1;
+    } else {
+      /* sin^2(theta) = 1 - 1/(beta n)^2 (Eq. 2.3, 2.4) */
+      double s2 = g * (g + 2.0) / ((1.0 + g) * (1.0 + g));
+      double z2 = (double)charge_f * (double)charge_f;
+      double mu = K * z2;
+      mu = mu * L;
+      mu = mu * s2;
+      mu = mu / (double)R->bunch;
+      /* A segment asking for 2^20 records or more (or a non-finite yield) is
+       * rejected as invalid input rather than truncated. */
+      if (!(mu < 1048576.0)) { memset(&out, 0, sizeof(out)); out.status = 2; return out; }
+      double fl = floor(mu);
+      out.n = (int32_t)fl + (u32d(w[0]) < mu - fl ? 1 : 0);
+      out.mu = mu; out.cos_t = 1.0 / (1.0 + g); out.sin2_t = s2;
+    }
+  }
+  if (fluor && dedx_f > 0.0f) {
+    /* fluorescence yield per band (Eq. 2.6 folded into a per-band photons/MeV
+     * constant), emitted into the lower hemisphere only (Sec. 4.2.2), hence 1/2 */
+    for (int b = 0; b < 3; ++b) {
+      double mu = R->fl_yield[b] * (double)dedx_f;
+      mu = mu * L;
+      mu = mu * 0.5;
+      mu = mu / (double)R->bunch;
+      if (!(mu < 1048576.0)) { memset(&out, 0, sizeof(out)); out.status = 2; return out; }
+      double fl = floor(mu);
+      out.nf[b] = (int32_t)fl + (u32d(w[1 + b]) < mu - fl ? 1 : 0);
+      out.muf[b] = mu;
+    }
+  }
   st->S[0] = x0; st->S[1] = y0; st->S[2] = z0;
   st->E[0] = x1; st->E[1] = y1; st->E[2] = z1;
-  st->L = L; st->beta = beta; st->z2 = z2;
-  st->cos_t = out.cos_t; st->sin_t = sqrt(s2); st->sin2 = s2;
+  st->L = L; st->beta = beta; st->z2 = (double)charge_f * (double)charge_f;
+  st->cos_t = out.cos_t; st->sin_t = sqrt(out.sin2_t); st->sin2 = out.sin2_t;
   /* Rotation of the cone axis D = (0,0,-1) onto the track direction P by the
    * 180-degree Euler-Rodrigues rotation about the normalised bisector
    * A = (D + P)/|D + P| (Sec. 4.2, M = 1 + 2 R^2). The thesis leaves A
@@ -342,6 +379,8 @@ static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
   }
   return out;
 }
+
+static int32_t segment_records(const orc_segment* sg) { return sg->n + sg->nf[0] + sg->nf[1] + sg->nf[2]; }
 
 /* ------------------------------------------------------------------------- */
 /* Transport                                                                  */
@@ -401,34 +440,155 @@ static double min4(double a, double b, double c, double d) {
   double m = a < b ? a : b; m = m < c ? m : c; return m < d ? m : d;
 }
 
+/* Refraction at a spherical shell boundary (the vector form, Eq. 3.15, with
+ * the radial normal N pointing along travel). Going outwards into thinner air
+ * the radicand can turn negative: the ray is then totally reflected. Returns 1
+ * if the ray crossed, 0 if it was reflected. */
+static int refract_or_reflect(double* dir, const double* N, double n1, double n2) {
+  double cos1 = dot3(dir, N);
+  double rad = n2 * n2 - n1 * n1 + n1 * n1 * cos1 * cos1;
+  if (rad < 0.0) {
+    for (int j = 0; j < 3; ++j) dir[j] -= 2.0 * cos1 * N[j];
+    return 0;
+  }
+  double c = sqrt(rad) - n1 * cos1;
+  for (int j = 0; j < 3; ++j) dir[j] = (n1 * dir[j] + c * N[j]) / n2;
+  return 1;
+}
+
+/* Distance along dir from pos to the sphere of radius r about C, first
+ * crossing ahead (inward when `inward`), or -1 if there is none. Written as
+ * c / (-b + sqrt(b^2 - c)) where the plain root would cancel. */
+static double to_sphere(const double* pos, const double* dir, const double* C, double r, int inward) {
+  double q[3] = {pos[0] - C[0], pos[1] - C[1], pos[2] - C[2]};
+  double b = dot3(q, dir);
+  double qq = dot3(q, q);
+  double rq = sqrt(qq);
+  double c = (rq - r) * (rq + r);
+  double disc = b * b - c;
+  if (disc < 0.0) return -1.0;
+  double sq = sqrt(disc);
+  if (inward) {
+    if (!(b < 0.0) || !(c > 0.0)) return -1.0;
+    return c / (-b + sq);
+  }
+  /* outward from inside (c < 0): the positive root */
+  return b > 0.0 ? b + sq : -c / (sq - b);
+}
+
+/* Curved Earth (Sec. 3.3.4, spherical model): the layer refractivities become
+ * shells about the Earth centre (0, 0, -R_E); the ray is straight inside a
+ * shell and refracted with the vector form at every shell boundary. Ends on
+ * the observation sphere r = R_E + h_obs (returns 1) or leaves the top of the
+ * atmosphere (returns 0). */
+static int curved_walk_rec(const orc_atmo* A, const orc_run* R, int kbin, const double* axis, path_state* ps,
+                           double* inv_out, int cap, int* m_out);
+
+static int curved_walk(const orc_atmo* A, const orc_run* R, int kbin, const double* axis, path_state* ps) {
+  return curved_walk_rec(A, R, kbin, axis, ps, NULL, 0, NULL);
+}
+
+/* Bouguer's invariant n r sin(angle to the radial) of the ray in shell i. */
+static double bouguer(const double* pos, const double* dir, const double* C, double n) {
+  double q[3] = {pos[0] - C[0], pos[1] - C[1], pos[2] - C[2]};
+  double cr[3] = {q[1] * dir[2] - q[2] * dir[1], q[2] * dir[0] - q[0] * dir[2], q[0] * dir[1] - q[1] * dir[0]};
+  return n * sqrt(dot3(cr, cr));
+}
+
+static int curved_walk_rec(const orc_atmo* A, const orc_run* R, int kbin, const double* axis, path_state* ps,
+                           double* inv_out, int cap, int* m_out) {
+  const orc_atmo_params* p = &A->p;
+  double Re = p->earth_radius;
+  double C[3] = {0.0, 0.0, -Re};
+  double dh = p->h_top / p->n_layers;
+  double q[3] = {ps->pos[0] - C[0], ps->pos[1] - C[1], ps->pos[2] - C[2]};
+  double h = sqrt(dot3(q, q)) - Re;
+  int i = (int)floor(h / dh);
+  if (i > p->n_layers - 1) i = p->n_layers - 1;
+  int obs = (int)floor(R->h_obs / dh);
+  double r_obs = Re + R->h_obs;
+  int m = 0;
+  for (int iter = 0; iter < 8 * p->n_layers; ++iter) {
+    double delta = A->layer_delta[i], ext = A->layer_ext[(size_t)i * p->n_lam + kbin];
+    if (inv_out && m < cap) inv_out[m] = bouguer(ps->pos, ps->dir, C, 1.0 + delta);
+    ++m;
+    if (m_out) *m_out = m;
+    if (i == obs) {
+      double s = to_sphere(ps->pos, ps->dir, C, r_obs, 1);
+      if (s >= 0.0) { leg(ps, axis, s, delta, ext); return 1; }
+    } else if (i > obs) {
+      double s = to_sphere(ps->pos, ps->dir, C, Re + i * dh, 1);
+      if (s >= 0.0) {
+        leg(ps, axis, s, delta, ext);
+        double qn[3] = {ps->pos[0] - C[0], ps->pos[1] - C[1], ps->pos[2] - C[2]};
+        double nq = sqrt(dot3(qn, qn));
+        double N[3] = {-qn[0] / nq, -qn[1] / nq, -qn[2] / nq};
+        if (refract_or_reflect(ps->dir, N, 1.0 + delta, 1.0 + A->layer_delta[i - 1])) --i;
+        continue;
+      }
+    }
+    double s = to_sphere(ps->pos, ps->dir, C, Re + (i + 1) * dh, 0);
+    leg(ps, axis, s, delta, ext);
+    if (i + 1 >= p->n_layers) return 0;
+    double qn[3] = {ps->pos[0] - C[0], ps->pos[1] - C[1], ps->pos[2] - C[2]};
+    double nq = sqrt(dot3(qn, qn));
+    double N[3] = {qn[0] / nq, qn[1] / nq, qn[2] / nq};
+    if (refract_or_reflect(ps->dir, N, 1.0 + delta, 1.0 + A->layer_delta[i + 1])) ++i;
+  }
+  return 0;
+}
+
+/* Record k of a segment: Cherenkov records first, then the fluorescence bands. */
 static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G, double K,
-                         const seg_setup* st, uint64_t seg_id, uint32_t k, orc_photon* out) {
+                         const seg_setup* st, const orc_segment* sg, uint64_t seg_id, uint32_t k,
+                         orc_photon* out) {
   (void)K;
   const orc_atmo_params* p = &A->p;
   memset(out, 0, sizeof(*out));
   out->seg = (int64_t)seg_id; out->k = (int32_t)k; out->bin = -1; out->tbin = -1;
   uint32_t w[4];
-  draw(R->seed, k, seg_id, TAG_CHERENKOV, w);
-  double f = u24(w[0]);
-  double phi = 2.0 * ORC_PI * u24(w[1]);
-  double lam;
-  if (R->spectrum == SPECTRUM_UNIFORM) lam = p->lam_min + (p->lam_max - p->lam_min) * u24(w[2]);
-  else lam = 1.0 / (1.0 / p->lam_min - u24(w[2]) * (1.0 / p->lam_min - 1.0 / p->lam_max));
-  double u3 = u24(w[3]);
+  double P[3], u[3], lam, u3;
+  if ((int32_t)k < sg->n) {
+    draw(R->seed, k, seg_id, TAG_CHERENKOV, w);
+    double f = u24(w[0]);
+    double phi = 2.0 * ORC_PI * u24(w[1]);
+    if (R->spectrum == SPECTRUM_UNIFORM) lam = p->lam_min + (p->lam_max - p->lam_min) * u24(w[2]);
+    else lam = 1.0 / (1.0 / p->lam_min - u24(w[2]) * (1.0 / p->lam_min - 1.0 / p->lam_max));
+    u3 = u24(w[3]);
+    /* photon on the cone around (0,0,-1) (Sec. 4.2), rotated onto the track */
+    double pl[3] = {cos(phi) * st->sin_t, sin(phi) * st->sin_t, -st->cos_t};
+    for (int i = 0; i < 3; ++i) u[i] = st->M[i][0] * pl[0] + st->M[i][1] * pl[1] + st->M[i][2] * pl[2];
+    /* emission at a random point along the track (Sec. 4.2, third step) */
+    for (int i = 0; i < 3; ++i) P[i] = st->S[i] + f * (st->E[i] - st->S[i]);
+  } else {
+    /* fluorescence (Sec. 4.2.2): isotropic, restricted to the lower hemisphere;
+     * the thesis samples the polar angle uniformly, which is not isotropic -- the
+     * cosine is drawn uniformly instead */
+    int32_t kk = (int32_t)k - sg->n, band = 0;
+    while (kk >= sg->nf[band]) { kk -= sg->nf[band]; ++band; }
+    out->source = 1 + band;
+    draw(R->seed, (uint32_t)kk, seg_id, TAG_FLUOR + (uint32_t)band, w);
+    double f = u24(w[0]);
+    double cz = 1.0 - u24(w[1]);
+    double phi = 2.0 * ORC_PI * u24(w[2]);
+    double sz = sqrt(1.0 - cz * cz);
+    u[0] = sz * cos(phi); u[1] = sz * sin(phi); u[2] = -cz;
+    lam = R->fl_lambda[band];
+    u3 = u24(w[3]);
+    for (int i = 0; i < 3; ++i) P[i] = st->S[i] + f * (st->E[i] - st->S[i]);
+  }
   out->lambda = lam; out->u_abs = u3;
-  /* photon on the cone around (0,0,-1) (Sec. 4.2), rotated onto the track */
-  double pl[3] = {cos(phi) * st->sin_t, sin(phi) * st->sin_t, -st->cos_t};
-  double u[3];
-  for (int i = 0; i < 3; ++i) u[i] = st->M[i][0] * pl[0] + st->M[i][1] * pl[1] + st->M[i][2] * pl[2];
-  /* emission at a random point along the track (Sec. 4.2, third step) */
-  double P[3];
-  for (int i = 0; i < 3; ++i) P[i] = st->S[i] + f * (st->E[i] - st->S[i]);
   out->ex = P[0]; out->ey = P[1]; out->ez = P[2];
   out->dx = u[0]; out->dy = u[1]; out->dz = u[2];
   double axis[3] = {G->ax, G->ay, G->az};
   /* upward photons are discarded first (Sec. 5.3.4) */
   if (!(u[2] < 0.0)) { out->state = ST_UPWARD; return; }
-  if (P[2] < R->h_obs) { out->state = ST_OUTSIDE; out->x = P[0]; out->y = P[1]; out->z = P[2]; return; }
+  double h_e = P[2];
+  if (R->transport == TRANSPORT_CURVED) {
+    double q[3] = {P[0], P[1], P[2] + p->earth_radius};
+    h_e = sqrt(dot3(q, q)) - p->earth_radius;
+  }
+  if (h_e < R->h_obs) { out->state = ST_OUTSIDE; out->x = P[0]; out->y = P[1]; out->z = P[2]; return; }
   path_state ps;
   memset(&ps, 0, sizeof(ps));
   memcpy(ps.pos, P, sizeof(P));
@@ -438,6 +598,23 @@ static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G,
     kbin = (int)floor((lam - p->lam_min) / (p->lam_max - p->lam_min) * p->n_lam);
     if (kbin < 0) kbin = 0;
     if (kbin > p->n_lam - 1) kbin = p->n_lam - 1;
+  }
+  if (R->transport == TRANSPORT_CURVED) {
+    int arrived = curved_walk(A, R, kbin, axis, &ps);
+    out->x = ps.pos[0]; out->y = ps.pos[1]; out->z = ps.pos[2];
+    out->tau = ps.tau;
+    out->t = (ps.geo + ps.opt) / ORC_C_M_PER_NS;
+    if (!arrived) { out->state = ST_OUTSIDE; out->margin = 1e30; return; }
+    /* bins: the arrival point's coordinates in the tangent plane at the core */
+    double gx0 = G->core_x - 0.5 * R->nx * R->cell, gy0 = G->core_y - 0.5 * R->ny * R->cell;
+    double fx = (ps.pos[0] - gx0) / R->cell, fy = (ps.pos[1] - gy0) / R->cell;
+    double ix = floor(fx), iy = floor(fy);
+    out->margin = min4(fx - ix, ix + 1.0 - fx, fy - iy, iy + 1.0 - fy) * R->cell;
+    if (!(u3 < exp(-ps.tau))) { out->state = ST_ABSORBED; return; }
+    if (!(ix >= 0 && iy >= 0 && ix < R->nx && iy < R->ny)) { out->state = ST_OUTSIDE; return; }
+    out->state = ST_BINNED;
+    out->bin = (int)iy * R->nx + (int)ix;
+    return;
   }
   int layer = 0;
   double dh = 0.0;
@@ -526,7 +703,10 @@ typedef struct {
   const float *x0, *y0, *z0, *x1, *y1, *z1, *beta, *charge;
   int64_t n;
   int64_t first_id;
+  const float* dedx;  /* MeV/m, may be NULL (no fluorescence) */
 } orc_segments;
+
+static float seg_dedx(const orc_segments* S, int64_t i) { return S->dedx ? S->dedx[i] : 0.0f; }
 
 double orc_frank_tamm_K(double lam_min, double lam_max) { return frank_tamm_K(lam_min, lam_max); }
 
@@ -535,7 +715,7 @@ void orc_segment_counts(const orc_atmo* A, const orc_run* R, const orc_segments*
   for (int64_t i = 0; i < S->n; ++i) {
     seg_setup st;
     out[i] = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
-                           S->beta[i], S->charge[i], (uint64_t)(S->first_id + i), &st);
+                           S->beta[i], S->charge[i], seg_dedx(S, i), (uint64_t)(S->first_id + i), &st);
   }
 }
 
@@ -548,9 +728,10 @@ int64_t orc_trace(const orc_atmo* A, const orc_run* R, const orc_segments* S, co
   for (int64_t i = 0; i < S->n; ++i) {
     seg_setup st;
     orc_segment sg = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
-                                   S->beta[i], S->charge[i], (uint64_t)(S->first_id + i), &st);
-    for (int32_t k = 0; k < sg.n; ++k) {
-      if (m < cap) trace_photon(A, R, G, K, &st, (uint64_t)(S->first_id + i), (uint32_t)k, &out[m]);
+                                   S->beta[i], S->charge[i], seg_dedx(S, i), (uint64_t)(S->first_id + i), &st);
+    int32_t nrec = segment_records(&sg);
+    for (int32_t k = 0; k < nrec; ++k) {
+      if (m < cap) trace_photon(A, R, G, K, &st, &sg, (uint64_t)(S->first_id + i), (uint32_t)k, &out[m]);
       ++m;
     }
   }
@@ -580,13 +761,14 @@ static void* worker(void* vp) {
     seg_setup st;
     uint64_t sid = (uint64_t)(S->first_id + i);
     orc_segment sg = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
-                                   S->beta[i], S->charge[i], sid, &st);
+                                   S->beta[i], S->charge[i], seg_dedx(S, i), sid, &st);
     W->counters[C_SEG_IN] += 1;
     if (sg.status == 2) { W->counters[C_SEG_SKIPPED] += 1; continue; }
-    if (sg.status == 1) { W->counters[C_SEG_BELOW] += 1; continue; }
-    for (int32_t k = 0; k < sg.n; ++k) {
+    if (sg.status == 1) W->counters[C_SEG_BELOW] += 1;
+    int32_t nrec = segment_records(&sg);
+    for (int32_t k = 0; k < nrec; ++k) {
       orc_photon ph;
-      trace_photon(A, R, &W->geoms[sh], K, &st, sid, (uint32_t)k, &ph);
+      trace_photon(A, R, &W->geoms[sh], K, &st, &sg, sid, (uint32_t)k, &ph);
       W->counters[C_REC_GEN] += 1;
       switch (ph.state) {
         case ST_UPWARD: W->counters[C_REC_UP] += 1; break;
@@ -684,6 +866,8 @@ int orc_layered_ray(const orc_atmo* A, const double* P, const double* u, double 
  * photon zenith angle, azimuth phi (rad), wavelength-bin centre (nm),
  * observation level h_obs (m). Targets: the landing offset (dx, dy) of the
  * layered path from the straight line started at the same point and direction,
+ * expressed along and across the photon's horizontal direction (the frame the
+ * configuration leaves open; in a planar atmosphere the offset lies along it),
  * the optical path excess e = sum n_i l_i - l_straight (m) and log T = -tau. */
 
 /* Training inputs i = first .. first+n-1 drawn from two Philox blocks with
@@ -746,9 +930,31 @@ void orc_surrogate_targets(const orc_atmo* A, int64_t n, const double* X, double
     tau += A->layer_ext[(size_t)layer * p->n_lam + kbin] * s;
     double s_straight = (h_obs - h_e) / u[2];
     double* y = Y + 4 * j;
-    y[0] = pos[0] - s_straight * u[0];
-    y[1] = pos[1] - s_straight * u[1];
+    /* landing offset in the photon's azimuthal frame: along and across its
+     * horizontal direction (cos phi, sin phi) */
+    double ox = pos[0] - s_straight * u[0], oy = pos[1] - s_straight * u[1];
+    y[0] = ox * cos(phi) + oy * sin(phi);
+    y[1] = -ox * sin(phi) + oy * cos(phi);
     y[2] = optical - s_straight;
     y[3] = -tau;
   }
+}
+
+/* One ray through the curved atmosphere from P along u (checks): end point
+ * (3), path length excess unused; Bouguer invariant per shell visited. Returns
+ * the number of shells visited (negative if the ray left the atmosphere). */
+int orc_curved_ray(const orc_atmo* A, double h_obs, const double* P, const double* u, double* end_out,
+                   double* inv_out, int cap) {
+  orc_run R;
+  memset(&R, 0, sizeof(R));
+  R.h_obs = h_obs;
+  path_state ps;
+  memset(&ps, 0, sizeof(ps));
+  memcpy(ps.pos, P, 3 * sizeof(double));
+  memcpy(ps.dir, u, 3 * sizeof(double));
+  double axis[3] = {0.0, 0.0, -1.0};
+  int m = 0;
+  int arrived = curved_walk_rec(A, &R, 0, axis, &ps, inv_out, cap, &m);
+  memcpy(end_out, ps.pos, 3 * sizeof(double));
+  return arrived ? m : -m;
 }

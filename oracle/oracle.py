@@ -44,12 +44,14 @@ class Run(C.Structure):
                 ("bunch", C.c_int32), ("seed", C.c_uint64), ("h_obs", C.c_double),
                 ("nx", C.c_int32), ("ny", C.c_int32), ("cell", C.c_double),
                 ("snx", C.c_int32), ("sny", C.c_int32), ("pitch", C.c_double), ("radius", C.c_double),
-                ("n_t", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double)]
+                ("n_t", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double),
+                ("emission", C.c_int32), ("pad2", C.c_int32), ("fl_yield", C.c_double * 3),
+                ("fl_lambda", C.c_double * 3)]
 
 
 class Segments(C.Structure):
     _fields_ = [(f, C.POINTER(C.c_float)) for f in ("x0", "y0", "z0", "x1", "y1", "z1", "beta", "charge")] + \
-               [("n", C.c_int64), ("first_id", C.c_int64)]
+               [("n", C.c_int64), ("first_id", C.c_int64), ("dedx", C.POINTER(C.c_float))]
 
 
 class Geom(C.Structure):
@@ -62,10 +64,11 @@ PHOTON_DTYPE = np.dtype([
     ("x", np.float64), ("y", np.float64), ("z", np.float64), ("t", np.float64), ("tau", np.float64),
     ("lambda", np.float64), ("u_abs", np.float64), ("margin", np.float64), ("tmargin", np.float64),
     ("ex", np.float64), ("ey", np.float64), ("ez", np.float64),
-    ("dx", np.float64), ("dy", np.float64), ("dz", np.float64)])
+    ("dx", np.float64), ("dy", np.float64), ("dz", np.float64), ("source", np.int32), ("pad", np.int32)])
 
 SEGMENT_DTYPE = np.dtype([("n", np.int32), ("status", np.int32), ("mu", np.float64),
-                          ("cos_t", np.float64), ("sin2_t", np.float64)])
+                          ("cos_t", np.float64), ("sin2_t", np.float64), ("nf", np.int32, 3), ("pad", np.int32),
+                          ("muf", np.float64, 3)])
 
 STATE = {"binned": 0, "upward": 1, "absorbed": 2, "outside": 3}
 COUNTERS = ["segments_in", "segments_skipped", "segments_below_threshold", "records_generated",
@@ -74,7 +77,11 @@ COUNTERS = ["segments_in", "segments_skipped", "segments_below_threshold", "reco
 N_COUNTERS = 16
 
 PROFILES = {"linsley5": 0, "homogeneous": 1, "linear": 2}
-TRANSPORTS = {"straight": 0, "layered": 1}
+TRANSPORTS = {"straight": 0, "layered": 1, "curved": 2}
+EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
+# synthetic fluorescence bands (nm) and yields (photons per MeV deposited)
+FL_LAMBDA = (337.0, 357.0, 391.0)
+FL_YIELD = (7.0, 5.0, 2.0)
 DETECTORS = {"grid": 0, "spheres": 1}
 SPECTRA = {"uniform": 0, "frank_tamm": 1}
 
@@ -109,6 +116,9 @@ def lib():
             L.orc_surrogate_inputs.argtypes = [C.c_void_p, C.c_uint64, P(C.c_double), P(C.c_double), C.c_int64,
                                                C.c_int64, P(C.c_double)]
             L.orc_surrogate_targets.argtypes = [C.c_void_p, C.c_int64, P(C.c_double), P(C.c_double)]
+            L.orc_curved_ray.argtypes = [C.c_void_p, C.c_double, P(C.c_double), P(C.c_double), P(C.c_double),
+                                         P(C.c_double), C.c_int]
+            L.orc_curved_ray.restype = C.c_int
             _lib = L
     return _lib
 
@@ -184,13 +194,17 @@ class Atmosphere:
 
 
 def make_run(transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0, h_obs=2200.0,
-             nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0, dt=1.0) -> Run:
+             nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0, dt=1.0,
+             emission="cherenkov", fl_yield=FL_YIELD, fl_lambda=FL_LAMBDA, **_ignored) -> Run:
     r = Run()
     r.transport, r.detector, r.spectrum = TRANSPORTS[transport], DETECTORS[detector], SPECTRA[spectrum]
     r.bunch, r.seed, r.h_obs = int(bunch), int(seed) & (2**64 - 1), float(h_obs)
     r.nx, r.ny, r.cell = int(nx), int(ny), float(cell)
     r.snx, r.sny, r.pitch, r.radius = int(snx), int(sny), float(pitch), float(radius)
     r.n_t, r.dt = int(n_t), float(dt)
+    r.emission = EMISSION[emission]
+    r.fl_yield[:] = tuple(float(v) for v in fl_yield)
+    r.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
     return r
 
 
@@ -202,6 +216,9 @@ def _segments(seg: dict, first_id: int):
         setattr(s, k, _ptr(v, C.c_float))
     s.n = int(arrs["x0"].shape[0])
     s.first_id = int(first_id)
+    if seg.get("dedx") is not None:
+        arrs["dedx"] = np.ascontiguousarray(seg["dedx"], dtype=np.float32)
+        s.dedx = _ptr(arrs["dedx"], C.c_float)
     return s, arrs  # keep arrays alive
 
 
@@ -293,3 +310,14 @@ def surrogate_targets(atm: Atmosphere, X):
     Y = np.zeros((X.shape[0], 4))
     lib().orc_surrogate_targets(atm.handle, X.shape[0], _ptr(X, C.c_double), _ptr(Y, C.c_double))
     return Y
+
+
+def curved_ray(atm: Atmosphere, h_obs, start, direction, cap=4096):
+    """(arrived, end point, Bouguer invariant per shell visited)."""
+    P = np.ascontiguousarray(start, dtype=np.float64)
+    u = np.ascontiguousarray(direction, dtype=np.float64)
+    end = np.zeros(3)
+    inv = np.zeros(cap)
+    m = lib().orc_curved_ray(atm.handle, float(h_obs), _ptr(P, C.c_double), _ptr(u, C.c_double),
+                             _ptr(end, C.c_double), _ptr(inv, C.c_double), cap)
+    return m > 0, end, inv[: min(abs(m), cap)]

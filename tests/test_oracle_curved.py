@@ -1,0 +1,136 @@
+"""Pins of the oracle's curved-Earth transport and fluorescence emission."""
+import math
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import oracle as O
+from paper_2405_04229_amd import workload as W
+from tests import cases
+
+RE = 6.371e6
+
+
+def _atm(**kw):
+    return O.Atmosphere(**{**cases.ATMO_LAYERED, **kw})
+
+
+def _dir(zen, azi):
+    z, a = math.radians(zen), math.radians(azi)
+    return np.array([math.sin(z) * math.cos(a), math.sin(z) * math.sin(a), -math.cos(z)])
+
+
+@pytest.mark.parametrize("zen", [10.0, 45.0, 70.0, 85.0])
+def test_bouguer_invariant(zen):
+    """n r sin(angle to the radial) is conserved across every shell (Snell's law
+    on spheres; the vector form of Eq. 3.15 with radial normals)."""
+    atm = _atm()
+    ok, end, inv = O.curved_ray(atm, 2200.0, [3000.0, -1000.0, 12000.0], _dir(zen, 30.0))
+    assert len(inv) > 5
+    np.testing.assert_allclose(inv, inv[0], rtol=1e-12)
+    if ok:
+        assert math.hypot(end[0], end[1], end[2] + RE) == pytest.approx(RE + 2200.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("zen", [5.0, 40.0, 60.0])
+def test_flat_earth_limit_equals_planar_layers(zen):
+    atm_big = _atm(earth_radius=1e12)
+    P = np.array([0.0, 0.0, 9876.0])
+    u = _dir(zen, 0.0)
+    ok, end, _ = O.curved_ray(atm_big, 2200.0, P, u)
+    assert ok
+    end_planar, _ = O.layered_ray(_atm(), P, u, 2200.0)
+    # the sphere of radius 1e12 m sags by x^2 / 2R below the plane over the path
+    np.testing.assert_allclose(end[:2], end_planar[:2], rtol=1e-6, atol=1e-4)
+
+
+def test_homogeneous_medium_hits_observation_sphere_on_straight_line():
+    """No refraction: the arrival point is the straight ray's intersection with
+    the sphere R + h_obs, solved here in 50-digit decimal arithmetic."""
+    atm = O.Atmosphere(profile="homogeneous", delta0=2e-4, h_top=25000.0, n_layers=100, n_lam=8, earth_radius=RE)
+    getcontext().prec = 50
+    for zen, azi in [(30.0, 10.0), (60.0, 200.0), (80.0, 45.0)]:
+        P = np.array([2000.0, 500.0, 15000.0])
+        u = _dir(zen, azi)
+        ok, end, _ = O.curved_ray(atm, 2200.0, P, u)
+        assert ok
+        D = [Decimal(v) for v in u]
+        Q = [Decimal(P[0]), Decimal(P[1]), Decimal(P[2]) + Decimal(RE)]
+        b = sum(q * d for q, d in zip(Q, D))
+        c = sum(q * q for q in Q) - (Decimal(RE) + Decimal(2200)) ** 2
+        s = -b - (b * b - c).sqrt()
+        want = [float(Q[0] + s * D[0]), float(Q[1] + s * D[1]), float(Q[2] + s * D[2] - Decimal(RE))]
+        np.testing.assert_allclose(end, want, rtol=0, atol=1e-6)
+
+
+def test_central_angle_by_impact_parameter_closed_form():
+    """Independent 2-D route: in shell i the ray keeps the impact parameter
+    p_i = K / n_i (K = n r sin(angle) at the start); a chord from radius r_a down
+    to r_b sweeps the central angle asin(p l / (r_a r_b)) with
+    l = sqrt(r_a^2 - p^2) - sqrt(r_b^2 - p^2)."""
+    atm = _atm()
+    d, _ = atm.layer_tables()
+    dh = 250.0
+    P = np.array([0.0, 0.0, 11111.0])
+    for zen in (20.0, 55.0, 75.0):
+        u = _dir(zen, 0.0)
+        ok, end, _ = O.curved_ray(atm, 2200.0, P, u)
+        assert ok
+        r0 = RE + P[2]
+        i0 = int(P[2] // dh)
+        K = (1 + d[i0]) * r0 * math.sin(math.radians(zen))
+        radii = [r0] + [RE + i * dh for i in range(i0, int(2200.0 // dh), -1)] + [RE + 2200.0]
+        shells = [i0] + list(range(i0 - 1, int(2200.0 // dh) - 1, -1))
+        psi = 0.0
+        for (ra, rb), i in zip(zip(radii[:-1], radii[1:]), shells):
+            p = K / (1 + d[i])
+            ell = math.sqrt(ra * ra - p * p) - math.sqrt(rb * rb - p * p)
+            psi += math.asin(p * ell / (ra * rb))
+        q0 = P + np.array([0, 0, RE])
+        q1 = end + np.array([0, 0, RE])
+        psi_tracer = math.atan2(np.linalg.norm(np.cross(q0, q1)), q0 @ q1)
+        assert psi_tracer == pytest.approx(psi, rel=1e-9)
+
+
+def test_fluorescence_counts_and_isotropy():
+    atm = _atm()
+    sh = W.make_shower(4000, seed=3, zenith_deg=60.0, beta="R", dedx=(0.1, 2.0))
+    run = O.make_run(transport="curved", detector="grid", spectrum="frank_tamm", emission="both", bunch=1,
+                     nx=200, ny=200, cell=50.0, seed=5)
+    sc = O.segment_counts(atm, run, sh.seg)
+    L = np.sqrt((sh.seg["x1"].astype(np.float64) - sh.seg["x0"]) ** 2 + (sh.seg["y1"].astype(np.float64) - sh.seg["y0"]) ** 2
+                + (sh.seg["z1"].astype(np.float64) - sh.seg["z0"]) ** 2)
+    for b, y in enumerate(O.FL_YIELD):
+        np.testing.assert_allclose(sc["muf"][:, b], y * sh.seg["dedx"].astype(np.float64) * L * 0.5, rtol=1e-12)
+        nf = sc["nf"][:, b]
+        assert np.all((nf == np.floor(sc["muf"][:, b])) | (nf == np.ceil(sc["muf"][:, b])))
+    ph = O.trace(atm, run, sh.seg, core=sh.core, axis=sh.axis)
+    fl = ph[ph["source"] > 0]
+    assert len(fl) == int(sc["nf"].sum())
+    np.testing.assert_array_equal(np.sort(np.unique(fl["lambda"])), np.array(O.FL_LAMBDA))
+    assert np.all(fl["dz"] < 0)
+    assert stats.kstest(-fl["dz"], "uniform").pvalue > 1e-3          # isotropic: cos uniform
+    az = np.arctan2(fl["dy"], fl["dx"])
+    assert stats.kstest((az + math.pi) / (2 * math.pi), "uniform").pvalue > 1e-3
+    # records per segment: Cherenkov first, then the bands in order
+    first = ph[ph["seg"] == ph["seg"][0]]
+    src = first["source"]
+    assert np.all(np.diff(src) >= 0)
+
+
+def test_curved_conservation_and_thread_invariance():
+    atm = _atm()
+    sh = W.make_shower(3000, seed=8, zenith_deg=60.0, beta="R", dedx=(0.1, 2.0))
+    run = O.make_run(transport="curved", detector="grid", spectrum="frank_tamm", emission="both", bunch=2,
+                     nx=300, ny=300, cell=30.0, seed=6)
+    geo = [[*sh.core, *sh.axis]]
+    b1, _, c1 = O.propagate(atm, run, sh.seg, geo, threads=1)
+    b4, _, c4 = O.propagate(atm, run, sh.seg, geo, threads=4)
+    np.testing.assert_array_equal(b1, b4)
+    np.testing.assert_array_equal(c1, c4)
+    assert c1[3] == c1[4] + c1[5] + c1[6] + c1[7]
+    assert int(b1.sum()) == int(c1[8]) == 2 * int(c1[7])
+    sc = O.segment_counts(atm, run, sh.seg)
+    assert int(c1[3]) == int(sc["n"].sum() + sc["nf"].sum())
