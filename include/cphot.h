@@ -57,6 +57,16 @@ extern "C" {
  * (Sec. 3.4.2, Eq. 3.15). */
 #define CPHOT_TRANSPORT_STRAIGHT 0
 #define CPHOT_TRANSPORT_LAYERED 1
+/* SURROGATE: straight line plus the correction predicted by a trained network
+ * (see cphot_surrogate_*); photons outside the network's training domain fall
+ * back to LAYERED transport and are counted in CPHOT_C_SURROGATE_FALLBACK. */
+#define CPHOT_TRANSPORT_SURROGATE 2
+/* CURVED: the layers become spherical shells about the Earth centre
+ * (0, 0, -earth_radius) (Sec. 3.3.4, spherical model), refraction at every
+ * shell boundary, arrival on the sphere of radius earth_radius + h_obs; GRID
+ * bins then use the arrival point's (x, y) in the tangent plane at the core
+ * (the core lies at (0, 0, h_obs)). */
+#define CPHOT_TRANSPORT_CURVED 3
 
 /* Detectors. GRID: nx x ny square cells of `cell` metres on the observation
  * level, centred on each shower's core. SPHERES: snx x sny bounding spheres of
@@ -70,9 +80,17 @@ extern "C" {
 #define CPHOT_SPECTRUM_UNIFORM 0
 #define CPHOT_SPECTRUM_FRANK_TAMM 1
 
-/* Bin element types of cphot_bins.bins. */
+/* Emission (bit set). CHERENKOV (Sec. 2.2.1); FLUORESCENCE (Sec. 2.2.2, 4.2.2):
+ * per band b, mu_b = fl_yield[b] x dE/dx x L / 2 records (lower hemisphere
+ * only), isotropic with cos(polar) uniform, wavelength fl_lambda[b]. A segment's
+ * records are its Cherenkov records followed by band 0, 1, 2. 0 = CHERENKOV. */
+#define CPHOT_EMIT_CHERENKOV 1
+#define CPHOT_EMIT_FLUORESCENCE 2
+
+/* Bin element types of cphot_bins.bins (F64: FP64 sums of the FP32 bunch weights). */
 #define CPHOT_BINS_U32 0
 #define CPHOT_BINS_U64 1
+#define CPHOT_BINS_F64 2
 
 /* Counter slots (uint64) of cphot_bins.counters. After a call,
  * records_generated = records_upward + records_absorbed + records_outside + records_binned. */
@@ -85,8 +103,11 @@ extern "C" {
 #define CPHOT_C_RECORDS_OUTSIDE 6           /* missed the grid / every sphere, or emitted below h_obs */
 #define CPHOT_C_RECORDS_BINNED 7
 #define CPHOT_C_PHOTONS_BINNED 8            /* records_binned x bunch size */
+#define CPHOT_C_SURROGATE_FALLBACK 9        /* records traced exactly because outside the surrogate's domain */
+#define CPHOT_C_RECORDS_FLUORESCENCE 10     /* fluorescence records among records_generated */
 
 typedef struct cphot_atmosphere cphot_atmosphere;
+typedef struct cphot_surrogate cphot_surrogate;
 
 /* Host description of an atmosphere. All fields are read during
  * cphot_make_atmosphere only. */
@@ -109,7 +130,8 @@ typedef struct {
   double lambda_max_nm;
   int32_t n_lambda_bins;    /* wavelength bins of the per-layer absorption table (LAYERED), >= 1 */
   int32_t reserved0;
-  double reserved[4];
+  double earth_radius;      /* m, CURVED transport (6.371e6) */
+  double reserved[3];
 } cphot_atmosphere_desc;
 
 /* Track segments, structure of arrays, float32 device arrays of length n. The
@@ -130,6 +152,7 @@ typedef struct {
                                      may be NULL when n_showers == 1 */
   const double* shower_geom;      /* device float64 [n_showers * 5]: core x, core y (m, on the
                                      observation level), shower axis unit vector (direction of travel) */
+  const float* dedx;              /* device float32 [n], energy deposit in MeV/m (FLUORESCENCE); may be NULL */
 } cphot_segments;
 
 /* What to simulate and where to collect. Host struct, read at call time. */
@@ -153,13 +176,18 @@ typedef struct {
   int32_t grid_blocks;      /* tuning: blocks of the persistent grid (0 = library choice) */
   int32_t lds_hist;         /* tuning: 1 = privatise the grid histogram in LDS, 0 = global atomics, -1 = library choice */
   int32_t reserved1;
+  const cphot_surrogate* surrogate; /* SURROGATE transport: a trained network (else NULL) */
+  int32_t emission;         /* CPHOT_EMIT_* bits (0 = Cherenkov) */
+  int32_t reserved2;
+  double fl_yield[3];       /* fluorescence photons per MeV deposited, per band */
+  double fl_lambda[3];      /* band wavelengths, nm (inside the atmosphere's band) */
 } cphot_detector;
 
 /* Outputs, accumulated (+=) so that chunked calls need no host work; the caller
  * zeroes them first. Device buffers owned by the caller. */
 typedef struct {
   void* bins;               /* GRID: [n_showers][ny][nx]; SPHERES: [n_showers][snx*sny] */
-  int32_t bins_dtype;       /* CPHOT_BINS_U32 | CPHOT_BINS_U64 */
+  int32_t bins_dtype;       /* CPHOT_BINS_U32 | CPHOT_BINS_U64 | CPHOT_BINS_F64 */
   int32_t reserved0;
   int64_t bins_capacity;    /* elements available at `bins` */
   uint32_t* time_hist;      /* SPHERES with n_time_bins > 0: [n_showers][snx*sny][n_time_bins + 1],
@@ -182,6 +210,9 @@ typedef struct {
   float dx, dy, dz; /* emission direction */
   float u_abs;      /* survival uniform */
 } cphot_photon_record;
+/* For fluorescence records, k counts from the segment's first record: Cherenkov
+ * records come first, then bands 0, 1, 2 (the record's source follows from the
+ * segment's counts). */
 
 /* ABI version (CPHOT_ABI_VERSION). */
 int cphot_version(void);
@@ -235,6 +266,109 @@ int cphot_segment_counts(const cphot_segments* seg, const cphot_detector* det, i
  * are not touched. Asynchronous. Errors: INVALID_ARG, HIP. */
 int cphot_trace_records(const cphot_segments* seg, const cphot_detector* det, const int64_t* record_offsets,
                         cphot_photon_record* records, int64_t capacity, void* stream);
+
+/* ---------------------------------------------------------------- captured steps, tuning
+ * A "step" is one whole propagation of a batch: clear the outputs (with a fill
+ * kernel, no memset nodes), then cphot_propagate. cphot_step_create captures it
+ * into an executable HIP graph bound to the given buffers (their pointers,
+ * sizes and the detector settings are baked in); cphot_step_launch replays it
+ * with one graph launch. Batches of many showers (segments with
+ * shower_offsets) run as one kernel launch inside the step.
+ * Errors: as cphot_propagate, plus HIP for capture failures. */
+typedef struct cphot_step cphot_step;
+
+int cphot_step_create(const cphot_segments* seg, const cphot_detector* det, const cphot_bins* out,
+                      int32_t clear_outputs, cphot_step** step);
+int cphot_step_launch(cphot_step* step, void* stream);
+void cphot_step_destroy(cphot_step* step);
+
+/* Result of cphot_autotune: the launch shape to put into cphot_detector. */
+typedef struct {
+  int32_t block_size;
+  int32_t grid_blocks;   /* 0 = one block per tile */
+  int32_t lds_hist;
+  int32_t bunch;
+  double ms;             /* mean time of one propagation with this shape */
+  double photons_per_s;  /* records generated x bunch / time */
+} cphot_tuning;
+
+/* Times cphot_propagate over candidate launch shapes (block size 128 / 256 /
+ * 512; one block per tile or a persistent grid of 2 or 4 blocks per CU; LDS grid
+ * histogram on / off where it fits) and over the bunch sizes in
+ * `bunch_candidates` (n_bunch values >= 1; NULL = the detector's own), `reps`
+ * timed launches each after one warm-up, and returns the shape and bunch with
+ * the most photons per second. Larger bunches trade statistical resolution for
+ * speed: the caller lists only bunch sizes its bins can afford. The outputs in
+ * `out` are overwritten by the trial runs. Synchronous (waits on `stream`).
+ * Errors: INVALID_ARG, HIP. */
+int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
+                   const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, cphot_tuning* best, void* stream);
+
+/* ---------------------------------------------------------------- transport surrogate
+ * A network 5 -> 64 -> 64 -> 4 (ReLU hidden units, linear output, bf16 weights on
+ * the matrix cores with FP32 accumulation) that maps a photon's (emission height
+ * h_e in m, cos of its zenith angle, azimuth atan2(u_y, u_x) in rad, wavelength
+ * in nm (the centre of its absorption-table bin), observation level in m) to
+ * (dx, dy): the offset of the layered landing point from the straight-line
+ * landing point, e: the optical path excess sum(n l) - straight length (m), and
+ * log T = -tau. It plays the role of the thesis's precomputed correction
+ * between straight-line and iterative propagation (Sec. 4.4.1), learned from
+ * photons the exact layered tracer produces. Inputs are mapped from the
+ * domain box to [-1, 1]; outputs are standardised by the training targets'
+ * mean and standard deviation. Parameters: one FP32 vector of 4804 values,
+ * W1[5][64], b1[64], W2[64][64], b2[64], W3[64][4], b3[4] (W[in][out]).
+ * Normalisation vector (24 floats): in_lo[5], in_hi[5], 2/(in_hi - in_lo)[5],
+ * 0, out_mean[4], out_std[4]. */
+typedef struct {
+  double in_lo[5];     /* domain box, inputs in the order above; cos zenith in [0, 1] */
+  double in_hi[5];
+  int32_t max_batch;   /* largest training batch (multiple of 64, <= 2^22) */
+  int32_t reserved0;
+  uint64_t init_seed;  /* He-uniform initial weights, zero biases */
+} cphot_surrogate_desc;
+
+/* Allocate a surrogate on the current device. Synchronous.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP. */
+int cphot_surrogate_create(const cphot_surrogate_desc* desc, cphot_surrogate** out);
+
+/* Release a surrogate (NULL allowed); no enqueued work may still use it. */
+void cphot_surrogate_destroy(cphot_surrogate* s);
+
+/* Training samples first .. first+n-1 into device float32 X [n][5] and Y [n][4]:
+ * inputs drawn uniformly in the domain box (emission height at or above the
+ * observation level, a uniformly drawn wavelength bin) from Philox blocks with
+ * counters (i low, 0 or 1, i high, 8) keyed by `seed`, targets from the exact
+ * layered tracer of `atm` (which must have layers). Asynchronous.
+ * Errors: INVALID_ARG (domain outside the atmosphere's layers or band), HIP. */
+int cphot_surrogate_make_training_set(const cphot_surrogate* s, const cphot_atmosphere* atm, int64_t first,
+                                      int64_t n, uint64_t seed, float* X, float* Y, void* stream);
+
+/* Output normalisation from the targets Y [n][4] (device): mean and standard
+ * deviation per output. Must precede training. Asynchronous. */
+int cphot_surrogate_fit_normalization(cphot_surrogate* s, const float* Y, int64_t n, void* stream);
+
+/* `steps` Adam steps (beta 0.9/0.999, lr cosine-decayed to lr/100) on the mean
+ * squared error of standardised outputs, minibatches of `batch` consecutive
+ * samples cycling through X [n][5], Y [n][4] (device). loss_out (device float
+ * [steps], may be NULL) receives each step's loss. Asynchronous.
+ * Errors: INVALID_ARG, UNSUPPORTED (normalisation not set), HIP. */
+int cphot_surrogate_train(cphot_surrogate* s, const float* X, const float* Y, int64_t n, int32_t batch,
+                          int32_t steps, float lr, float* loss_out, void* stream);
+
+/* Gradient of the loss over the n samples (n a multiple of 64, <= max_batch)
+ * with respect to the parameter vector into device float grad [4804], and the
+ * loss into device float loss [1] (may be NULL); no update. Asynchronous. */
+int cphot_surrogate_gradient(cphot_surrogate* s, const float* X, const float* Y, int64_t n, float* grad,
+                             float* loss, void* stream);
+
+/* Network outputs Y [n][4] for inputs X [n][5] (device, raw units). Asynchronous. */
+int cphot_surrogate_forward(const cphot_surrogate* s, const float* X, float* Y, int64_t n, void* stream);
+
+/* Copy the parameter vector (4804 floats) and the normalisation (24 floats)
+ * to / from host memory; either pointer may be NULL. Synchronous (waits for
+ * the device). */
+int cphot_surrogate_get_params(const cphot_surrogate* s, float* params, float* norm);
+int cphot_surrogate_set_params(cphot_surrogate* s, const float* params, const float* norm);
 
 #ifdef __cplusplus
 }

@@ -7,12 +7,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcphot.so")
-SOURCES = ["cphot_api.cpp", "cphot_kernels.hip"]
+SOURCES = ["cphot_api.cpp", "cphot_kernels.hip", "cphot_surrogate.hip"]
 ARCH = os.environ.get("CPHOT_OFFLOAD_ARCH", "gfx950")
 
-# Packed FP32 instructions stay off: they are avoided on this target.
+# Packed FP32 instructions stay off: they are avoided on this target. No implicit
+# FMA contraction: fused operations are written out (fmaf), so one source line
+# gives the same bits in every kernel instantiation it is inlined into.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-             "-packed-fp32-ops", "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
+             "-packed-fp32-ops", "-ffp-contract=off", "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
 
 
 def hipcc() -> str:

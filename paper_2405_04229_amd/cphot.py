@@ -23,12 +23,14 @@ ERR_CAPACITY = -5
 NCOUNTERS = 16
 
 PROFILE = {"linsley5": 0, "homogeneous": 1, "linear": 2}
-TRANSPORT = {"straight": 0, "layered": 1}
+TRANSPORT = {"straight": 0, "layered": 1, "surrogate": 2, "curved": 3}
+EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
 DETECTOR = {"grid": 0, "spheres": 1}
 SPECTRUM = {"uniform": 0, "frank_tamm": 1}
-BINS = {"u32": 0, "u64": 1}
+BINS = {"u32": 0, "u64": 1, "f64": 2}
 COUNTERS = ["segments_in", "segments_skipped", "segments_below_threshold", "records_generated",
-            "records_upward", "records_absorbed", "records_outside", "records_binned", "photons_binned"]
+            "records_upward", "records_absorbed", "records_outside", "records_binned", "photons_binned",
+            "surrogate_fallback", "records_fluorescence"]
 
 
 class CphotError(RuntimeError):
@@ -44,13 +46,13 @@ class AtmosphereDesc(C.Structure):
                 ("table_step", C.c_double), ("rayleigh400", C.c_double), ("aerosol_tau350", C.c_double),
                 ("aerosol_height", C.c_double), ("aerosol_angstrom", C.c_double), ("lambda_min_nm", C.c_double),
                 ("lambda_max_nm", C.c_double), ("n_lambda_bins", C.c_int32), ("reserved0", C.c_int32),
-                ("reserved", C.c_double * 4)]
+                ("earth_radius", C.c_double), ("reserved", C.c_double * 3)]
 
 
 class Segments(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in ("x0", "y0", "z0", "x1", "y1", "z1", "beta", "charge")] + \
                [("n", C.c_int64), ("first_id", C.c_int64), ("n_showers", C.c_int32), ("reserved0", C.c_int32),
-                ("shower_offsets", C.c_void_p), ("shower_geom", C.c_void_p)]
+                ("shower_offsets", C.c_void_p), ("shower_geom", C.c_void_p), ("dedx", C.c_void_p)]
 
 
 class Detector(C.Structure):
@@ -59,7 +61,19 @@ class Detector(C.Structure):
                 ("ny", C.c_int32), ("cell", C.c_double), ("snx", C.c_int32), ("sny", C.c_int32),
                 ("pitch", C.c_double), ("radius", C.c_double), ("n_time_bins", C.c_int32),
                 ("reserved0", C.c_int32), ("time_bin_ns", C.c_double), ("block_size", C.c_int32),
-                ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("reserved1", C.c_int32)]
+                ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("reserved1", C.c_int32),
+                ("surrogate", C.c_void_p), ("emission", C.c_int32), ("reserved2", C.c_int32),
+                ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3)]
+
+
+class SurrogateDesc(C.Structure):
+    _fields_ = [("in_lo", C.c_double * 5), ("in_hi", C.c_double * 5), ("max_batch", C.c_int32),
+                ("reserved0", C.c_int32), ("init_seed", C.c_uint64)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32),
+                ("bunch", C.c_int32), ("ms", C.c_double), ("photons_per_s", C.c_double)]
 
 
 class Bins(C.Structure):
@@ -99,6 +113,27 @@ def lib():
             L.cphot_segment_counts.restype = C.c_int
             L.cphot_trace_records.argtypes = [C.POINTER(Segments), C.POINTER(Detector), P, P, C.c_int64, P]
             L.cphot_trace_records.restype = C.c_int
+            L.cphot_surrogate_create.argtypes = [C.POINTER(SurrogateDesc), C.POINTER(C.c_void_p)]
+            L.cphot_surrogate_destroy.argtypes = [P]
+            L.cphot_surrogate_make_training_set.argtypes = [P, P, C.c_int64, C.c_int64, C.c_uint64, P, P, P]
+            L.cphot_surrogate_fit_normalization.argtypes = [P, P, C.c_int64, P]
+            L.cphot_surrogate_train.argtypes = [P, P, P, C.c_int64, C.c_int32, C.c_int32, C.c_float, P, P]
+            L.cphot_surrogate_gradient.argtypes = [P, P, P, C.c_int64, P, P, P]
+            L.cphot_surrogate_forward.argtypes = [P, P, P, C.c_int64, P]
+            L.cphot_surrogate_get_params.argtypes = [P, P, P]
+            L.cphot_surrogate_set_params.argtypes = [P, P, P]
+            L.cphot_step_create.argtypes = [C.POINTER(Segments), C.POINTER(Detector), C.POINTER(Bins), C.c_int32,
+                                            C.POINTER(C.c_void_p)]
+            L.cphot_step_create.restype = C.c_int
+            L.cphot_step_launch.argtypes = [P, P]
+            L.cphot_step_launch.restype = C.c_int
+            L.cphot_step_destroy.argtypes = [P]
+            L.cphot_autotune.argtypes = [C.POINTER(Segments), C.POINTER(Detector), C.POINTER(Bins), P, C.c_int32,
+                                         C.c_int32, C.POINTER(Tuning), P]
+            L.cphot_autotune.restype = C.c_int
+            for fn in ("create", "make_training_set", "fit_normalization", "train", "gradient", "forward",
+                       "get_params", "set_params"):
+                getattr(L, "cphot_surrogate_" + fn).restype = C.c_int
             _lib = L
     return _lib
 
@@ -130,7 +165,7 @@ class Atmosphere:
 
     def __init__(self, profile="linsley5", n_layers=0, a=None, b=None, c=None, hb=None, kappa=2.83e-4,
                  delta0=0.0, h_top=25000.0, step=1.0, rayleigh400=0.0, aer_tau350=0.0, aer_H=1200.0,
-                 aer_angstrom=1.0, lam_min=300.0, lam_max=600.0, n_lam=1, **_ignored):
+                 aer_angstrom=1.0, lam_min=300.0, lam_max=600.0, n_lam=1, earth_radius=6.371e6, **_ignored):
         d = AtmosphereDesc()
         d.profile = PROFILE[profile]
         d.n_layers = int(n_layers)
@@ -141,6 +176,7 @@ class Atmosphere:
         d.rayleigh400, d.aerosol_tau350, d.aerosol_height, d.aerosol_angstrom = rayleigh400, aer_tau350, aer_H, aer_angstrom
         d.lambda_min_nm, d.lambda_max_nm = lam_min, lam_max
         d.n_lambda_bins = max(int(n_lam), 1)
+        d.earth_radius = float(earth_radius)
         self.desc = d
         h = C.c_void_p()
         _check("cphot_make_atmosphere", lib().cphot_make_atmosphere(C.byref(d), C.byref(h)))
@@ -161,7 +197,8 @@ class Atmosphere:
 
 def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0,
                   h_obs=2200.0, nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0,
-                  dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1) -> Detector:
+                  dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, surrogate=None, emission="cherenkov",
+                  fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0)) -> Detector:
     d = Detector()
     d.atm = atm.handle
     d.transport, d.detector, d.spectrum = TRANSPORT[transport], DETECTOR[detector], SPECTRUM[spectrum]
@@ -170,7 +207,12 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
     d.snx, d.sny, d.pitch, d.radius = int(snx), int(sny), float(pitch), float(radius)
     d.n_time_bins, d.time_bin_ns = int(n_t), float(dt)
     d.block_size, d.grid_blocks, d.lds_hist = int(block_size), int(grid_blocks), int(lds_hist)
-    d._atm_ref = atm  # keep the handle alive
+    d.emission = EMISSION[emission]
+    d.fl_yield[:] = tuple(float(v) for v in fl_yield)
+    d.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
+    if surrogate is not None:
+        d.surrogate = surrogate.handle
+    d._refs = (atm, surrogate)  # keep the handles alive
     return d
 
 
@@ -190,6 +232,10 @@ def make_segments(seg: dict, geom, offsets=None, first_id: int = 0) -> Segments:
     ns = int(geom.shape[0])
     s.n_showers = ns
     s.shower_geom = _dptr(geom, torch.float64, "geom")
+    if seg.get("dedx") is not None:
+        if int(seg["dedx"].shape[0]) != n:
+            raise ValueError("dedx must have one value per segment")
+        s.dedx = _dptr(seg["dedx"], torch.float32, "dedx")
     if geom.dim() != 2 or geom.shape[1] != 5:
         raise ValueError("geom must be [n_showers, 5]")
     if offsets is not None:
@@ -202,17 +248,19 @@ def make_segments(seg: dict, geom, offsets=None, first_id: int = 0) -> Segments:
     return s
 
 
-def propagate(seg: Segments, det: Detector, bins, time_hist=None, counters=None, stream=None):
-    """Accumulates into `bins` (uint32 -> int32 tensor view or int64 tensor),
-    `time_hist` (int32 tensor viewed as uint32) and `counters` (int64 [16])."""
+def make_bins(bins, time_hist=None, counters=None) -> Bins:
+    """Output descriptor: `bins` int32 (read as uint32) or int64 (read as uint64),
+    `time_hist` int32 (read as uint32), `counters` int64 [16]."""
     import torch
     b = Bins()
-    if bins.dtype in (torch.int32,):
+    if bins.dtype == torch.int32:
         b.bins_dtype = BINS["u32"]
-    elif bins.dtype in (torch.int64,):
+    elif bins.dtype == torch.int64:
         b.bins_dtype = BINS["u64"]
+    elif bins.dtype == torch.float64:
+        b.bins_dtype = BINS["f64"]
     else:
-        raise TypeError("bins must be int32 (read as uint32) or int64 (read as uint64)")
+        raise TypeError("bins must be int32 (read as uint32), int64 (read as uint64) or float64")
     b.bins = _dptr(bins, None, "bins")
     b.bins_capacity = bins.numel()
     if time_hist is not None:
@@ -222,7 +270,52 @@ def propagate(seg: Segments, det: Detector, bins, time_hist=None, counters=None,
         if counters.numel() < NCOUNTERS:
             raise ValueError("counters needs 16 entries")
         b.counters = _dptr(counters, torch.int64, "counters")
+    b._keep = (bins, time_hist, counters)
+    return b
+
+
+def propagate(seg: Segments, det: Detector, bins, time_hist=None, counters=None, stream=None):
+    """Accumulates into `bins`, `time_hist` and `counters` (see make_bins)."""
+    b = make_bins(bins, time_hist, counters)
     _check("cphot_propagate", lib().cphot_propagate(C.byref(seg), C.byref(det), C.byref(b), _stream_ptr(stream)))
+
+
+class Step:
+    """A captured propagation step (HIP graph): clear outputs + propagate."""
+
+    def __init__(self, seg: Segments, det: Detector, bins, time_hist=None, counters=None, clear=True):
+        self._b = make_bins(bins, time_hist, counters)
+        self._refs = (seg, det)
+        h = C.c_void_p()
+        _check("cphot_step_create", lib().cphot_step_create(C.byref(seg), C.byref(det), C.byref(self._b),
+                                                            1 if clear else 0, C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check("cphot_step_launch", lib().cphot_step_launch(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.cphot_step_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def autotune(seg: Segments, det: Detector, bins, time_hist=None, counters=None, bunches=None, reps=3, stream=None):
+    """Fastest launch shape (and bunch among `bunches`) for these inputs; the
+    outputs are overwritten by the trials."""
+    import numpy as np
+    b = make_bins(bins, time_hist, counters)
+    t = Tuning()
+    bc = None if not bunches else np.ascontiguousarray(bunches, dtype=np.int32)
+    _check("cphot_autotune", lib().cphot_autotune(C.byref(seg), C.byref(det), C.byref(b),
+                                                  None if bc is None else bc.ctypes.data_as(C.c_void_p),
+                                                  0 if bc is None else len(bc), int(reps), C.byref(t),
+                                                  _stream_ptr(stream)))
+    return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, bunch=t.bunch, ms=t.ms,
+                photons_per_s=t.photons_per_s)
 
 
 def segment_counts(seg: Segments, det: Detector, counts, expected=None, stream=None):
@@ -259,8 +352,101 @@ def upload(seg_np: dict, geom_np, offsets_np=None, device="cuda"):
     import numpy as np
     import torch
     seg = {k: torch.from_numpy(np.ascontiguousarray(seg_np[k], dtype=np.float32)).to(device) for k in SEGMENT_FIELDS}
+    if seg_np.get("dedx") is not None:
+        seg["dedx"] = torch.from_numpy(np.ascontiguousarray(seg_np["dedx"], dtype=np.float32)).to(device)
     geom = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(geom_np), dtype=np.float64)).to(device)
     off = None
     if offsets_np is not None:
         off = torch.from_numpy(np.ascontiguousarray(offsets_np, dtype=np.int64)).to(device)
     return seg, geom, off
+
+
+N_PARAMS = 4804
+N_NORM = 24
+
+
+class Surrogate:
+    """Transport surrogate network (cphot_surrogate_*): training and inference
+    run in the library's kernels; tensors are plain device buffers."""
+
+    def __init__(self, lo, hi, max_batch=8192, init_seed=0):
+        d = SurrogateDesc()
+        d.in_lo[:] = tuple(float(v) for v in lo)
+        d.in_hi[:] = tuple(float(v) for v in hi)
+        d.max_batch, d.init_seed = int(max_batch), int(init_seed)
+        self.desc = d
+        h = C.c_void_p()
+        _check("cphot_surrogate_create", lib().cphot_surrogate_create(C.byref(d), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.cphot_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def make_training_set(self, atm: Atmosphere, n, seed, first=0, stream=None):
+        import torch
+        X = torch.empty((int(n), 5), dtype=torch.float32, device="cuda")
+        Y = torch.empty((int(n), 4), dtype=torch.float32, device="cuda")
+        _check("cphot_surrogate_make_training_set",
+               lib().cphot_surrogate_make_training_set(self._h, atm.handle, int(first), int(n), int(seed),
+                                                       C.c_void_p(_dptr(X, torch.float32, "X")),
+                                                       C.c_void_p(_dptr(Y, torch.float32, "Y")), _stream_ptr(stream)))
+        return X, Y
+
+    def fit_normalization(self, Y, stream=None):
+        import torch
+        _check("cphot_surrogate_fit_normalization",
+               lib().cphot_surrogate_fit_normalization(self._h, C.c_void_p(_dptr(Y, torch.float32, "Y")),
+                                                       Y.shape[0], _stream_ptr(stream)))
+
+    def train(self, X, Y, batch, steps, lr, stream=None):
+        import torch
+        loss = torch.zeros(max(int(steps), 1), dtype=torch.float32, device="cuda")
+        _check("cphot_surrogate_train",
+               lib().cphot_surrogate_train(self._h, C.c_void_p(_dptr(X, torch.float32, "X")),
+                                           C.c_void_p(_dptr(Y, torch.float32, "Y")), X.shape[0], int(batch),
+                                           int(steps), float(lr), C.c_void_p(loss.data_ptr()), _stream_ptr(stream)))
+        return loss
+
+    def gradient(self, X, Y, stream=None):
+        import torch
+        g = torch.zeros(N_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        _check("cphot_surrogate_gradient",
+               lib().cphot_surrogate_gradient(self._h, C.c_void_p(_dptr(X, torch.float32, "X")),
+                                              C.c_void_p(_dptr(Y, torch.float32, "Y")), X.shape[0],
+                                              C.c_void_p(g.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                              _stream_ptr(stream)))
+        return g, loss
+
+    def forward(self, X, stream=None):
+        import torch
+        Y = torch.empty((X.shape[0], 4), dtype=torch.float32, device="cuda")
+        _check("cphot_surrogate_forward",
+               lib().cphot_surrogate_forward(self._h, C.c_void_p(_dptr(X, torch.float32, "X")),
+                                             C.c_void_p(Y.data_ptr()), X.shape[0], _stream_ptr(stream)))
+        return Y
+
+    def get_params(self):
+        import numpy as np
+        p = np.zeros(N_PARAMS, dtype=np.float32)
+        n = np.zeros(N_NORM, dtype=np.float32)
+        _check("cphot_surrogate_get_params", lib().cphot_surrogate_get_params(
+            self._h, p.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p)))
+        return p, n
+
+    def set_params(self, params=None, norm=None):
+        import numpy as np
+        pa = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        na = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        _check("cphot_surrogate_set_params", lib().cphot_surrogate_set_params(
+            self._h, None if pa is None else pa.ctypes.data_as(C.c_void_p),
+            None if na is None else na.ctypes.data_as(C.c_void_p)))

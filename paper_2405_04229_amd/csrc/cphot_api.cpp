@@ -1,6 +1,7 @@
 // Host side of libcphot: argument checks, atmosphere tables, launch set-up.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,8 +21,14 @@ struct cphot_atmosphere {
 };
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace cphot {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace cphot
+
+namespace {
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -103,8 +110,19 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   if (seg->n_showers > 1 && !seg->shower_offsets)
     return fail(CPHOT_ERR_INVALID_ARG, "shower_offsets required for several showers");
   if (!seg->shower_geom) return fail(CPHOT_ERR_INVALID_ARG, "shower_geom is required");
-  if (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED)
+  if (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED &&
+      det->transport != CPHOT_TRANSPORT_SURROGATE && det->transport != CPHOT_TRANSPORT_CURVED)
     return fail(CPHOT_ERR_INVALID_ARG, "unknown transport");
+  if (det->transport == CPHOT_TRANSPORT_CURVED && det->detector != CPHOT_DETECTOR_GRID)
+    return fail(CPHOT_ERR_UNSUPPORTED, "curved transport collects on a ground grid");
+  if (det->transport == CPHOT_TRANSPORT_CURVED && !(d.earth_radius > 1e5 && std::isfinite(d.earth_radius)))
+    return fail(CPHOT_ERR_INVALID_ARG, "curved transport needs the atmosphere's earth_radius");
+  if (det->emission & ~(CPHOT_EMIT_CHERENKOV | CPHOT_EMIT_FLUORESCENCE))
+    return fail(CPHOT_ERR_INVALID_ARG, "unknown emission bits");
+  if ((det->emission & CPHOT_EMIT_FLUORESCENCE) && seg->n > 0 && !seg->dedx)
+    return fail(CPHOT_ERR_INVALID_ARG, "fluorescence needs the dedx column");
+  if (det->transport == CPHOT_TRANSPORT_SURROGATE && !cphot::surrogate_ready(det->surrogate))
+    return fail(CPHOT_ERR_UNSUPPORTED, "surrogate transport needs a surrogate with its normalisation set");
   if (det->detector != CPHOT_DETECTOR_GRID && det->detector != CPHOT_DETECTOR_SPHERES)
     return fail(CPHOT_ERR_INVALID_ARG, "unknown detector");
   if (det->spectrum != CPHOT_SPECTRUM_UNIFORM && det->spectrum != CPHOT_SPECTRUM_FRANK_TAMM)
@@ -152,12 +170,24 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   p.inv_lam_min = (float)(1.0 / d.lambda_min_nm);
   p.inv_lam_max = (float)(1.0 / d.lambda_max_nm);
   p.spectrum = det->spectrum;
+  p.dedx = seg->dedx;
+  p.emission = det->emission ? det->emission : CPHOT_EMIT_CHERENKOV;
+  for (int b = 0; b < 3; ++b) {
+    p.fl_yield[b] = det->fl_yield[b];
+    p.fl_lambda[b] = (float)det->fl_lambda[b];
+    if ((p.emission & CPHOT_EMIT_FLUORESCENCE) &&
+        (!(det->fl_yield[b] >= 0.0) || !std::isfinite(det->fl_yield[b]) ||
+         !(det->fl_lambda[b] >= d.lambda_min_nm && det->fl_lambda[b] <= d.lambda_max_nm)))
+      return fail(CPHOT_ERR_INVALID_ARG, "fluorescence yields must be >= 0 and wavelengths inside the band");
+  }
+  p.earth_radius = d.earth_radius;
   p.h_obs = (float)det->h_obs;
   p.X_obs = d.profile == CPHOT_PROFILE_LINSLEY5 ? (float)depth(d, det->h_obs) : 0.f;
   p.transport = det->transport;
   p.detector = det->detector;
-  if (det->transport == CPHOT_TRANSPORT_LAYERED) {
+  if (det->transport != CPHOT_TRANSPORT_STRAIGHT) {
     if (d.n_layers < 1) return fail(CPHOT_ERR_INVALID_ARG, "layered transport needs an atmosphere with layers");
+    if (det->transport == CPHOT_TRANSPORT_SURROGATE) p.mlp = cphot::surrogate_image(det->surrogate);
     p.n_layers = d.n_layers;
     p.n_lam = d.n_lambda_bins;
     p.dh = (float)(d.h_top / d.n_layers);
@@ -180,7 +210,7 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
       return fail(CPHOT_ERR_INVALID_ARG, "spheres need snx, sny >= 1, pitch > 0, radius > 0");
     if (4.0 * det->radius > det->pitch)
       return fail(CPHOT_ERR_INVALID_ARG, "spheres must satisfy pitch >= 4 radius (one candidate per cell)");
-    if (det->transport == CPHOT_TRANSPORT_LAYERED) {
+    if (det->transport != CPHOT_TRANSPORT_STRAIGHT) {
       const double dh = d.h_top / d.n_layers;
       const double lo = p.obs_layer * dh, hi = (p.obs_layer + 1) * dh;
       if (det->h_obs - det->radius < lo || det->h_obs + det->radius >= hi)
@@ -203,11 +233,12 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   }
   if (need_bins) {
     if (!out) return fail(CPHOT_ERR_INVALID_ARG, "null bins");
-    if (out->bins_dtype != CPHOT_BINS_U32 && out->bins_dtype != CPHOT_BINS_U64)
+    if (out->bins_dtype != CPHOT_BINS_U32 && out->bins_dtype != CPHOT_BINS_U64 && out->bins_dtype != CPHOT_BINS_F64)
       return fail(CPHOT_ERR_INVALID_ARG, "unknown bins dtype");
     if (!out->bins) return fail(CPHOT_ERR_INVALID_ARG, "null bins buffer");
     p.bins = out->bins;
     p.bins_u64 = out->bins_dtype == CPHOT_BINS_U64;
+    p.bins_f64 = out->bins_dtype == CPHOT_BINS_F64;
     p.thist = out->time_hist;
     p.counters = out->counters;
   }
@@ -247,6 +278,21 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
 }
 
 }  // namespace
+
+namespace cphot {
+int atmosphere_layer_view(const cphot_atmosphere* a, const float4** layers, const float2** lambins, int* n_layers,
+                          int* n_lam, float* dh, float* lam_min, float* lam_max) {
+  if (!a || a->d.n_layers < 1) return CPHOT_ERR_INVALID_ARG;
+  *layers = a->dev.layers;
+  *lambins = a->dev.lambins;
+  *n_layers = a->d.n_layers;
+  *n_lam = a->d.n_lambda_bins;
+  *dh = (float)(a->d.h_top / a->d.n_layers);
+  *lam_min = (float)a->d.lambda_min_nm;
+  *lam_max = (float)a->d.lambda_max_nm;
+  return CPHOT_OK;
+}
+}  // namespace cphot
 
 extern "C" {
 
@@ -413,6 +459,169 @@ int cphot_trace_records(const cphot_segments* seg, const cphot_detector* det, co
   if ((rc = choose_shape(det, p, cphot::MODE_RECORDS, s))) return rc;
   hipError_t e = cphot::launch_propagate(p, cphot::MODE_RECORDS, s.block, s.grid, s.lds, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "launch records");
+  return CPHOT_OK;
+}
+
+// ---------------------------------------------------------------- captured steps
+
+struct cphot_step {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t clear_words(void* ptr, int64_t bytes, hipStream_t st) {
+  if (!ptr || bytes <= 0) return hipSuccess;
+  const int64_t n = bytes / 4;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, st, (uint32_t*)ptr, n);
+  return hipGetLastError();
+}
+
+hipError_t clear_outputs(const cphot_bins* out, hipStream_t st) {
+  hipError_t e = clear_words(out->bins, out->bins_capacity * (out->bins_dtype == CPHOT_BINS_U32 ? 4 : 8), st);
+  if (e == hipSuccess) e = clear_words(out->time_hist, out->time_capacity * 4, st);
+  if (e == hipSuccess && out->counters) e = clear_words(out->counters, CPHOT_NCOUNTERS * 8, st);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cphot_step_create(const cphot_segments* seg, const cphot_detector* det, const cphot_bins* out,
+                      int32_t clear, cphot_step** step) {
+  if (!step || !out) return fail(CPHOT_ERR_INVALID_ARG, "null argument");
+  *step = nullptr;
+  cphot::KParams p;
+  int rc = fill_params(seg, det, p, true, out);
+  if (rc) return rc;
+  LaunchShape sh{};
+  if (p.n > 0 && (rc = choose_shape(det, p, cphot::MODE_PROPAGATE, sh))) return rc;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  cphot_step* s = new (std::nothrow) cphot_step();
+  if (!s) {
+    (void)hipStreamDestroy(cs);
+    return fail(CPHOT_ERR_OUT_OF_MEMORY, "host allocation");
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess && clear) e = clear_outputs(out, cs);
+  if (e == hipSuccess && p.n > 0) e = cphot::launch_propagate(p, cphot::MODE_PROPAGATE, sh.block, sh.grid, sh.lds, cs);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cs, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0);
+  s->graph = g;
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    cphot_step_destroy(s);
+    return hip_fail(e, "graph capture");
+  }
+  *step = s;
+  return CPHOT_OK;
+}
+
+int cphot_step_launch(cphot_step* s, void* stream) {
+  if (!s || !s->exec) return fail(CPHOT_ERR_INVALID_ARG, "null step");
+  hipError_t e = hipGraphLaunch(s->exec, (hipStream_t)stream);
+  return e == hipSuccess ? CPHOT_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+void cphot_step_destroy(cphot_step* s) {
+  if (!s) return;
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  delete s;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
+                   const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, cphot_tuning* best,
+                   void* stream) {
+  if (!seg || !det || !out || !best) return fail(CPHOT_ERR_INVALID_ARG, "null argument");
+  if (reps < 1) return fail(CPHOT_ERR_INVALID_ARG, "reps must be >= 1");
+  if (n_bunch < 0 || (n_bunch > 0 && !bunch_candidates)) return fail(CPHOT_ERR_INVALID_ARG, "bad bunch list");
+  if (!out->counters) return fail(CPHOT_ERR_INVALID_ARG, "autotune reads the record counter: counters required");
+  std::vector<int32_t> bunches;
+  for (int i = 0; i < n_bunch; ++i) {
+    if (bunch_candidates[i] < 1) return fail(CPHOT_ERR_INVALID_ARG, "bunch candidates must be >= 1");
+    bunches.push_back(bunch_candidates[i]);
+  }
+  if (bunches.empty()) bunches.push_back(det->bunch);
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int cus = cu_count(dev);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(CPHOT_ERR_HIP, "hipEventCreate");
+  cphot_tuning top{};
+  top.photons_per_s = -1.0;
+  int rc = CPHOT_OK;
+  for (int32_t b : bunches) {
+    for (int bs : {128, 256, 512}) {
+      for (int gpol = 0; gpol < 3 && rc == CPHOT_OK; ++gpol) {
+        for (int lh = 0; lh < 2 && rc == CPHOT_OK; ++lh) {
+          cphot_detector d = *det;
+          d.bunch = b;
+          d.block_size = bs;
+          d.grid_blocks = gpol == 0 ? 0 : cus * (gpol == 1 ? 2 : 4);
+          d.lds_hist = lh;
+          cphot::KParams p;
+          if ((rc = fill_params(seg, &d, p, true, out))) break;
+          if (p.n == 0) break;
+          LaunchShape sh;
+          if (choose_shape(&d, p, cphot::MODE_PROPAGATE, sh) != CPHOT_OK) {
+            rc = CPHOT_OK;  // shape not applicable (e.g. LDS histogram too large)
+            continue;
+          }
+          if (lh == 1 && !p.lds_hist) continue;  // the histogram option does not apply here
+          hipError_t e = clear_outputs(out, st);
+          if (e == hipSuccess) e = cphot::launch_propagate(p, cphot::MODE_PROPAGATE, sh.block, sh.grid, sh.lds, st);
+          if (e == hipSuccess) e = clear_outputs(out, st);
+          if (e == hipSuccess) e = hipEventRecord(e0, st);
+          for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = cphot::launch_propagate(p, cphot::MODE_PROPAGATE, sh.block, sh.grid, sh.lds, st);
+          if (e == hipSuccess) e = hipEventRecord(e1, st);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          unsigned long long gen = 0;
+          if (e == hipSuccess)
+            e = hipMemcpy(&gen, out->counters + CPHOT_C_RECORDS_GENERATED, sizeof(gen), hipMemcpyDeviceToHost);
+          if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune trial");
+            break;
+          }
+          const double t = ms / reps;
+          const double pps = (double)gen / reps * b / (t * 1e-3);
+          if (pps > top.photons_per_s) {
+            top.block_size = bs;
+            top.grid_blocks = d.grid_blocks;
+            top.lds_hist = lh;
+            top.bunch = b;
+            top.ms = t;
+            top.photons_per_s = pps;
+          }
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  *best = top;
   return CPHOT_OK;
 }
 

@@ -1,0 +1,344 @@
+// Device helpers shared by the photon and surrogate kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cphot {
+
+constexpr uint32_t TAG_SEGMENT = 0;
+constexpr uint32_t TAG_CHERENKOV = 1;
+constexpr uint32_t TAG_FLUOR = 2;  // + band (2, 3, 4)
+constexpr uint32_t TAG_TRAIN = 8;
+constexpr int kMaxRecordsPerSegmentLog2 = 20;
+constexpr float kCmPerNs = 0.299792458f;  // metres per ns
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// Random word -> uniform on [0, 1) with 24 bits (exact in FP32).
+__device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }
+
+template <int BS>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_wave[wid] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < BS / 64; ++q) {
+    const uint32_t t = s_wave[q];
+    pre += (q < wid) ? t : 0u;
+    tot += t;
+  }
+  total = tot;
+  return pre + x - v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+
+// Walk of a downward photon through equal homogeneous layers (Sec. 3.4.2), from
+// its start point in layer `i` down to the layer `obs_layer`. Within a layer
+// the ray is straight; at a horizontal boundary the horizontal part of n u is
+// conserved (the vector form of Snell's law, Eq. 3.15, with a vertical
+// normal), so layer i is crossed with sine s_i = s_0 n_0 / n_i = s_0 (1 - e_i),
+// e_i = (d_i - d_0) / (1 + d_i), d = n - 1. The cosine is carried without
+// forming 1 - s^2 near s = 1 (which in FP32 would lose every digit of a
+// near-horizontal photon's cosine): c_i^2 = c_0^2 + s_0^2 e_i (2 - e_i), with
+// c_0 = -u_z and s_0 the horizontal part of the start direction. Layer data:
+// lay[i] = (n - 1, 1/n, Rayleigh part, aerosol part); the extinction per metre
+// at wavelength bin k is lay.z * sp.x + lay.w * sp.y with sp = (spectral
+// Rayleigh, spectral aerosol). On return (x, y, z) is the entry point into the
+// observation layer and (vx, vy, vz) the direction there.
+struct LayerWalk {
+  float x, y, z;
+  float vx, vy, vz;
+  float tau;         // optical depth accumulated above the observation layer
+  float geo;         // sum of l (1 - u . axis)                               (NEED_TIME)
+  float opt;         // sum of (n - 1) l                                       (NEED_TIME or NEED_EXCESS)
+  float dr;          // horizontal travel beyond the straight line, along the azimuth (NEED_EXCESS)
+  float gex;         // geometric path beyond the straight line                (NEED_EXCESS)
+  float last_delta;  // n - 1 of the observation layer
+  float last_ext;    // extinction per metre there
+  float s0, c0, d0, hx, hy;  // start sine and cosine, start n - 1, azimuth
+};
+
+// Sine and squared cosine in a layer with n - 1 = d, 1/n = inv_n.
+__device__ __forceinline__ void layer_angle(float s0, float c0, float d0, float d, float inv_n, float& s,
+                                            float& c2, float& e) {
+  e = (d - d0) * inv_n;
+  s = fmaf(-s0, e, s0);
+  c2 = fmaxf(fmaf(s0 * s0 * e, 2.0f - e, c0 * c0), 1e-30f);
+}
+
+// Excess of a leg of vertical extent `span` crossed at sine s (layer with
+// n - 1 = d, 1/n = inv_n) over the same extent crossed at the start sine s0:
+// returns horizontal and path excess without subtracting nearly equal
+// lengths (s - s0 = -s0 e).
+__device__ __forceinline__ void leg_excess(const LayerWalk& w, float span, float d, float inv_n, float& dr,
+                                           float& gex) {
+  float s, c2, e;
+  layer_angle(w.s0, w.c0, w.d0, d, inv_n, s, c2, e);
+  const float c = sqrtf(c2);
+  const float dsq = -w.s0 * e * (s + w.s0);  // s^2 - s0^2
+  const float den = s * w.c0 + w.s0 * c;     // zero only for a vertical photon, whose offset is zero
+  if (den > 0.f) dr = fmaf(span, dsq / (den * c * w.c0), dr);
+  gex = fmaf(span, dsq / (c * w.c0 * (c + w.c0)), gex);
+}
+
+template <bool NEED_TIME, bool NEED_EXCESS>
+__device__ __forceinline__ void layer_walk(const float4* __restrict__ lay, float2 sp, float dh, int i,
+                                           int obs_layer, float Px, float Py, float Pz, float ux, float uy,
+                                           float uz, float axx, float axy, float axz, LayerWalk& w) {
+  const float sh = sqrtf(ux * ux + uy * uy);
+  float hx = 1.f, hy = 0.f;
+  if (sh > 0.f) {
+    const float ish = 1.0f / sh;
+    hx = ux * ish;
+    hy = uy * ish;
+  }
+  float4 L = lay[i];
+  const float s0 = sh, c0 = -uz, d0 = L.x;
+  w.d0 = d0;
+  w.s0 = s0;
+  w.c0 = c0;
+  w.hx = hx;
+  w.hy = hy;
+  w.dr = 0.f;
+  w.gex = 0.f;
+  float x = Px, y = Py, z = Pz, tau = 0.f, geo = 0.f, opt = 0.f;
+  while (i > obs_layer) {
+    const float zb = (float)i * dh;
+    const float span = z - zb;
+    float s, c2, e;
+    layer_angle(s0, c0, d0, L.x, L.y, s, c2, e);
+    const float ic = rsqrtf(c2);
+    const float path = span * ic;
+    const float adv = path * s;
+    x = fmaf(hx, adv, x);
+    y = fmaf(hy, adv, y);
+    tau = fmaf(fmaf(L.z, sp.x, L.w * sp.y), path, tau);
+    if constexpr (NEED_TIME) {
+      const float ex = s * hx - axx, ey = s * hy - axy, ez = -c2 * ic - axz;
+      geo = fmaf(path, 0.5f * (ex * ex + ey * ey + ez * ez), geo);
+    }
+    if constexpr (NEED_TIME || NEED_EXCESS) opt = fmaf(L.x, path, opt);
+    if constexpr (NEED_EXCESS) leg_excess(w, span, L.x, L.y, w.dr, w.gex);
+    z = zb;
+    --i;
+    L = lay[i];
+  }
+  float s, c2, e;
+  layer_angle(s0, c0, d0, L.x, L.y, s, c2, e);
+  const float c = sqrtf(c2);
+  w.x = x;
+  w.y = y;
+  w.z = z;
+  w.vx = s * hx;
+  w.vy = s * hy;
+  w.vz = -c;
+  w.tau = tau;
+  w.geo = geo;
+  w.opt = opt;
+  w.last_delta = L.x;
+  w.last_ext = fmaf(L.z, sp.x, L.w * sp.y);
+}
+
+// Curved Earth (Sec. 3.3.4): the layers are spherical shells about the Earth
+// centre. Within a shell a ray keeps its impact parameter; at a boundary the
+// vector form of Snell's law with the radial normal conserves Bouguer's
+// invariant n r sin(angle to the radial), so in shell i the impact parameter is
+// p_i = n_0 (R + h_0) s_0 / n_i and the path stays in the plane of the Earth
+// centre and the start direction. In FP32 a radius near R carries only half a
+// metre, and the chord lengths of near-horizontal rays amplify that by
+// tan^2 of the angle to the radial; so the walk never forms R + h - p_i by
+// subtraction but carries the deficit
+//   D_i(h) = (R + h) - p_i = (h - h_0) + (R + h_0) [(1 - s_0) - s_0 (d_0 - d_i) / (1 + d_i)],
+// 1 - s_0 = c_0^2 / (1 + s_0), d = n - 1, whose terms are all small or exact. Then
+// r cos(angle to the radial) = sqrt(D (2 r - D)) and a chord from ha down to hb is
+//   l = (ha - hb)(2R + ha + hb) / (ra ca + rb cb),  dpsi = asin(p l / (ra rb)).
+// A ray turns round inside a shell where D would become negative, and is
+// totally reflected at a boundary where the next shell's D is not positive.
+// The swept central angle is summed in FP64 and the arrival point on the
+// sphere R + h_obs is formed from it in FP64.
+struct CurvedWalk {
+  double ax, ay, az;  // arrival point (core frame)
+  float tau, geo, opt;
+  int arrived;        // 0: left the top of the atmosphere
+};
+
+template <bool NEED_TIME>
+__device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, float2 sp, float dh, int n_layers,
+                                            float h_obs, double Re, float Px, float Py, float Pz, float h0,
+                                            float ux, float uy, float uz, float axx, float axy, float axz,
+                                            CurvedWalk& w) {
+  const float Rf = (float)Re, twoR = (float)(2.0 * Re);
+  // emission frame: radial e_r, tangent e_t (photon's horizontal direction), normal e_n
+  const float qz = Pz + Rf;
+  const float rq = sqrtf(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
+  const float irq = 1.0f / rq;
+  const float erx = Px * irq, ery = Py * irq, erz = qz * irq;
+  const float mu = fmaf(ux, erx, fmaf(uy, ery, uz * erz));  // cos of the angle to the upward radial
+  float etx = fmaf(-mu, erx, ux), ety = fmaf(-mu, ery, uy), etz = fmaf(-mu, erz, uz);
+  const float s0 = sqrtf(fmaf(etx, etx, fmaf(ety, ety, etz * etz)));
+  if (s0 > 0.f) {
+    const float is = 1.0f / s0;
+    etx *= is;
+    ety *= is;
+    etz *= is;
+  } else {
+    etx = 1.f;
+    ety = 0.f;
+    etz = 0.f;
+  }
+  float a_r = 0.f, a_t = 0.f, a_n = 0.f;
+  if constexpr (NEED_TIME) {
+    const float enx = ery * etz - erz * ety, eny = erz * etx - erx * etz, enz = erx * ety - ery * etx;
+    a_r = fmaf(axx, erx, fmaf(axy, ery, axz * erz));
+    a_t = fmaf(axx, etx, fmaf(axy, ety, axz * etz));
+    a_n = fmaf(axx, enx, fmaf(axy, eny, axz * enz));
+  }
+  int i = min((int)(h0 / dh), n_layers - 1);
+  const int obs = (int)floorf(h_obs / dh);
+  const float A = Rf + h0;
+  const float c1 = mu * mu / (1.0f + s0);  // 1 - s_0
+  const float d0 = lay[i].x;
+  // bracket of D_i for shell values (d_i, 1 / (1 + d_i))
+  auto bracket = [&](float di, float inv_ni) { return fmaf(-s0, (d0 - di) * inv_ni, c1); };
+  float h = h0, tau = 0.f, geo = 0.f, opt = 0.f;
+  double psi = 0.0;
+  bool down = mu < 0.f;
+  int arrived = 0;
+  for (int iter = 0; iter < 8 * n_layers; ++iter) {
+    const float4 L = lay[i];
+    const float br = bracket(L.x, L.y);
+    const float ra = Rf + h;
+    const float Da = fmaf(A, br, h - h0);
+    const float rca = sqrtf(fmaxf(Da * (2.0f * ra - Da), 0.f));  // ra cos(angle to the radial)
+    const float pa = ra - Da;                                     // impact parameter in this shell
+    const float ext = fmaf(L.z, sp.x, L.w * sp.y);
+    float ell, dpsi, cth;
+    bool to_top = false;
+    if (down) {
+      const float hb = (i == obs) ? h_obs : (float)i * dh;
+      const float Db = fmaf(A, br, hb - h0);
+      if (Db > 0.f) {
+        const float rb = Rf + hb;
+        const float rcb = sqrtf(Db * (2.0f * rb - Db));
+        ell = (h - hb) * (twoR + h + hb) / (rca + rcb);
+        const float x = pa * ell / (ra * rb);
+        dpsi = fmaf(x * x * (1.0f / 6.0f), x, x);
+        cth = rca / ra;
+        h = hb;
+      } else {  // the ray turns round inside the shell and leaves through its top
+        const float ho = (float)(i + 1) * dh;
+        const float ro = Rf + ho;
+        const float Do = fmaf(A, br, ho - h0);
+        const float rco = sqrtf(fmaxf(Do * (2.0f * ro - Do), 0.f));
+        ell = rca + rco;
+        dpsi = atan2f(rca, pa) + atan2f(rco, pa);
+        cth = rca / ra;
+        h = ho;
+        down = false;
+        to_top = true;
+      }
+    } else {
+      const float ho = (float)(i + 1) * dh;
+      const float ro = Rf + ho;
+      const float Do = fmaf(A, br, ho - h0);
+      const float rco = sqrtf(fmaxf(Do * (2.0f * ro - Do), 0.f));
+      ell = (ho - h) * (twoR + ho + h) / (rco + rca);
+      const float x = pa * ell / (ra * ro);
+      dpsi = fmaf(x * x * (1.0f / 6.0f), x, x);
+      cth = -rca / ra;
+      h = ho;
+      to_top = true;
+    }
+    tau = fmaf(ext, ell, tau);
+    if constexpr (NEED_TIME) {
+      const float sa = pa / ra;
+      float sp_, cp_;
+      sincosf((float)psi, &sp_, &cp_);
+      const float cphi = fmaf(cth, cp_, sa * sp_), sphi = fmaf(sa, cp_, -cth * sp_);
+      const float gr = -cphi - a_r, gt = sphi - a_t;
+      geo = fmaf(ell, 0.5f * fmaf(gr, gr, fmaf(gt, gt, a_n * a_n)), geo);
+      opt = fmaf(L.x, ell, opt);
+    }
+    psi += (double)dpsi;
+    if (!to_top) {
+      if (i == obs) {
+        arrived = 1;
+        break;
+      }
+      const float4 Lb = lay[i - 1];
+      if (!(fmaf(A, bracket(Lb.x, Lb.y), h - h0) > 0.f)) {
+        down = false;  // total reflection at the boundary below: back up in shell i
+        continue;
+      }
+      --i;
+      continue;
+    }
+    if (i + 1 >= n_layers) break;  // left the atmosphere
+    const float4 Lt = lay[i + 1];
+    if (!(fmaf(A, bracket(Lt.x, Lt.y), h - h0) > 0.f)) {
+      down = true;  // total reflection at the boundary above: back down in shell i
+      continue;
+    }
+    ++i;
+  }
+  w.tau = tau;
+  w.geo = geo;
+  w.opt = opt;
+  w.arrived = arrived;
+  // arrival point from the swept central angle, in FP64
+  const double dqz = (double)Pz + Re;
+  const double drq = sqrt((double)Px * Px + (double)Py * Py + dqz * dqz);
+  const double dex = Px / drq, dey = Py / drq, dez = dqz / drq;
+  const double dmu = ux * dex + uy * dey + uz * dez;
+  double tx = ux - dmu * dex, ty = uy - dmu * dey, tz = uz - dmu * dez;
+  const double tn = sqrt(tx * tx + ty * ty + tz * tz);
+  if (tn > 0.0) {
+    tx /= tn;
+    ty /= tn;
+    tz /= tn;
+  } else {
+    tx = 1.0;
+    ty = 0.0;
+    tz = 0.0;
+  }
+  double sps, cps;
+  sincos(psi, &sps, &cps);
+  const double robs = Re + (double)h_obs;
+  w.ax = robs * (cps * dex + sps * tx);
+  w.ay = robs * (cps * dey + sps * ty);
+  w.az = robs * (cps * dez + sps * tz) - Re;
+}
+
+}  // namespace cphot

@@ -4,9 +4,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/cphot.h"
 
 namespace cphot {
+
+struct MlpImage;
 
 constexpr int kMaxLayers = 128;
 constexpr int kMaxLambdaBins = 64;
@@ -60,6 +64,16 @@ struct KParams {
   float pitch, inv_pitch, radius;
   int32_t n_t;
   float inv_dt;
+  // surrogate transport
+  const MlpImage* mlp;
+  // emission
+  const float* dedx;
+  int32_t emission;
+  double fl_yield[3];
+  float fl_lambda[3];
+  // curved Earth
+  double earth_radius;
+  int32_t bins_f64;
   // outputs
   void* bins;
   int32_t bins_u64;
@@ -75,6 +89,15 @@ struct KParams {
 };
 
 enum Mode { MODE_PROPAGATE = 0, MODE_COUNTS = 1, MODE_RECORDS = 2 };
+
+// Text returned by cphot_last_error() on this thread.
+void set_last_error(const std::string& msg);
+// Device layer tables of an atmosphere (CPHOT_ERR_INVALID_ARG if it has no layers).
+int atmosphere_layer_view(const cphot_atmosphere* atm, const float4** layers, const float2** lambins, int* n_layers,
+                          int* n_lam, float* dh, float* lam_min, float* lam_max);
+// Inference image of a surrogate and whether its normalisation is set.
+const MlpImage* surrogate_image(const cphot_surrogate* s);
+bool surrogate_ready(const cphot_surrogate* s);
 
 hipError_t launch_propagate(const KParams& p, int mode, int block_size, int grid_blocks, size_t lds_hist_bytes,
                             hipStream_t stream);

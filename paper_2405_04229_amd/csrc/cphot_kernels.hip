@@ -14,55 +14,35 @@
 //      atomics); upward photons leave first (Sec. 5.3.4).
 // Photons live in registers only; nothing per photon touches HBM except the
 // final bin increment.
+#include "cphot_device.h"
 #include "cphot_internal.h"
+#include "cphot_mlp.h"
 
 namespace cphot {
 
 namespace {
 
-constexpr uint32_t TAG_SEGMENT = 0;
-constexpr uint32_t TAG_CHERENKOV = 1;
-constexpr int kMaxRecordsPerSegmentLog2 = 20;
-constexpr float kCmPerNs = 0.299792458f;  // metres per ns
-
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products.
-__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                        uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-    c1 = (uint32_t)p1;
-    c3 = (uint32_t)p0;
-    c0 = n0;
-    c2 = n2;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  return make_uint4(c0, c1, c2, c3);
-}
-
-__device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }
-
 struct SegResult {
-  int32_t n;       // records
-  int32_t status;  // 0 ok, 1 below threshold, 2 skipped
+  int32_t n;       // Cherenkov records
+  int32_t status;  // 0 ok, 1 below the Cherenkov threshold, 2 skipped
   float cos_t, sin_t, a0, a1, a2;
-  double mu;       // expected records
+  double mu;       // expected Cherenkov records
+  int32_t nf[3];   // fluorescence records per band
 };
 
 // Per-segment yield in FP64 with IEEE basic operations only and no
 // contraction, in the fixed order that makes the record count reproducible
 // bit for bit on any IEEE machine.
 __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, float fy0, float fz0, float fx1,
-                                                float fy1, float fz1, float fbeta, float fq, uint64_t id) {
+                                                float fy1, float fz1, float fbeta, float fq, float fdedx,
+                                                uint64_t id) {
 #pragma clang fp contract(off)
-  SegResult r{0, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0};
+  SegResult r{0, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0, {0, 0, 0}};
+  const bool cher = (p.emission & CPHOT_EMIT_CHERENKOV) != 0;
+  const bool fluor = (p.emission & CPHOT_EMIT_FLUORESCENCE) != 0;
   if (!__builtin_isfinite(fx0) || !__builtin_isfinite(fy0) || !__builtin_isfinite(fz0) ||
       !__builtin_isfinite(fx1) || !__builtin_isfinite(fy1) || !__builtin_isfinite(fz1) ||
-      !__builtin_isfinite(fbeta) || !__builtin_isfinite(fq)) {
+      !__builtin_isfinite(fbeta) || !__builtin_isfinite(fq) || (fluor && !__builtin_isfinite(fdedx))) {
     r.status = 2;
     return r;
   }
@@ -77,44 +57,66 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
     r.status = 2;
     return r;
   }
-  // refractivity at the midpoint: direct index mapping into the FP64 table and
-  // linear interpolation (Sec. 4.1), heights clamped to the table
-  const double hm = 0.5 * ((double)fz0 + (double)fz1);
-  double x = hm / p.step;
-  if (x < 0.0) x = 0.0;
-  if (x > (double)p.n_tab) x = (double)p.n_tab;
-  double fi = floor(x);
-  int64_t idx = (int64_t)fi;
-  if (idx > p.n_tab - 1) {
-    idx = p.n_tab - 1;
-    fi = (double)idx;
-  }
-  const double frac = x - fi;
-  const double delta = (1.0 - frac) * p.tab[idx] + frac * p.tab[idx + 1];
-  // threshold beta n > 1 through g = beta n - 1 = delta - eps - eps delta, eps = 1 - beta
-  const double eps = 1.0 - beta;
-  const double g = delta - eps - eps * delta;
-  if (!(g > 0.0)) {
-    r.status = 1;
-    return r;
-  }
-  const double s2 = g * (g + 2.0) / ((1.0 + g) * (1.0 + g));
-  const double z2 = (double)fq * (double)fq;
-  double mu = p.K * z2;
-  mu = mu * L;
-  mu = mu * s2;
-  mu = mu / (double)p.bunch;
-  if (!(mu < (double)(1 << kMaxRecordsPerSegmentLog2))) {
-    r.status = 2;
-    return r;
-  }
-  r.mu = mu;
-  const double fl = floor(mu);
+  // one Philox block per segment: word 0 rounds the Cherenkov yield, words 1..3
+  // the fluorescence bands
   const uint4 w = philox(0u, (uint32_t)id, (uint32_t)(id >> 32), TAG_SEGMENT, p.key0, p.key1);
-  const double u = (double)w.x * (1.0 / 4294967296.0);
-  r.n = (int32_t)fl + (u < mu - fl ? 1 : 0);
-  r.cos_t = (float)(1.0 / (1.0 + g));
-  r.sin_t = (float)sqrt(s2);
+  if (cher) {
+    // refractivity at the midpoint: direct index mapping into the FP64 table and
+    // linear interpolation (Sec. 4.1), heights clamped to the table
+    const double hm = 0.5 * ((double)fz0 + (double)fz1);
+    double x = hm / p.step;
+    if (x < 0.0) x = 0.0;
+    if (x > (double)p.n_tab) x = (double)p.n_tab;
+    double fi = floor(x);
+    int64_t idx = (int64_t)fi;
+    if (idx > p.n_tab - 1) {
+      idx = p.n_tab - 1;
+      fi = (double)idx;
+    }
+    const double frac = x - fi;
+    const double delta = (1.0 - frac) * p.tab[idx] + frac * p.tab[idx + 1];
+    // threshold beta n > 1 through g = beta n - 1 = delta - eps - eps delta, eps = 1 - beta
+    const double eps = 1.0 - beta;
+    const double g = delta - eps - eps * delta;
+    if (!(g > 0.0)) {
+      r.status = 1;
+    } else {
+      const double s2 = g * (g + 2.0) / ((1.0 + g) * (1.0 + g));
+      const double z2 = (double)fq * (double)fq;
+      double mu = p.K * z2;
+      mu = mu * L;
+      mu = mu * s2;
+      mu = mu / (double)p.bunch;
+      if (!(mu < (double)(1 << kMaxRecordsPerSegmentLog2))) {
+        r.status = 2;
+        return r;
+      }
+      r.mu = mu;
+      const double fl = floor(mu);
+      const double u = (double)w.x * (1.0 / 4294967296.0);
+      r.n = (int32_t)fl + (u < mu - fl ? 1 : 0);
+      r.cos_t = (float)(1.0 / (1.0 + g));
+      r.sin_t = (float)sqrt(s2);
+    }
+  }
+  if (fluor && fdedx > 0.0f) {
+    // per band: Y_b dE/dx L / 2 (lower hemisphere only)
+    const uint32_t wb[3] = {w.y, w.z, w.w};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double mu = p.fl_yield[b] * (double)fdedx;
+      mu = mu * L;
+      mu = mu * 0.5;
+      mu = mu / (double)p.bunch;
+      if (!(mu < (double)(1 << kMaxRecordsPerSegmentLog2))) {
+        SegResult bad{0, 2, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0, {0, 0, 0}};
+        return bad;
+      }
+      const double fl = floor(mu);
+      const double u = (double)wb[b] * (1.0 / 4294967296.0);
+      r.nf[b] = (int32_t)fl + (u < mu - fl ? 1 : 0);
+    }
+  }
   // bisector of the cone axis (0,0,-1) and the track direction; the rotation
   // is M = 2 a a^T - I (Euler-Rodrigues, 180 degrees, Sec. 4.2)
   const double P0 = dx / L, P1 = dy / L, P2 = dz / L;
@@ -150,39 +152,66 @@ __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float 
 }
 
 struct Photon {
-  int32_t state, bin, tbin;
+  int32_t state, bin, tbin, fallback;
   float x, y, z, t, tau, lam, u3, ux, uy, uz;
 };
 
+// One record: emission, transport, absorption, detection. With the surrogate
+// transport every lane of the wave must call this together (`valid` marks the
+// lanes that carry a real record); the network is evaluated before any lane
+// leaves.
 template <int TRANSPORT, int DETECTOR, bool NEED_TIME>
 __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict__ s_lay,
-                                      const float2* __restrict__ s_lam, const float4 q0, const float4 q1,
-                                      const float4 q2, const float4 q3, const float4 q4, const float axz,
-                                      uint32_t k, Photon& o) {
+                                      const float2* __restrict__ s_lam, const MlpImage* __restrict__ s_img,
+                                      const float4 q0, const float4 q1, const float4 q2, const float4 q3,
+                                      const float4 q4, const float axz, const uint4 q5, uint32_t k, bool valid,
+                                      Photon& o) {
   const float sx = q0.x, sy = q0.y, sz = q0.z, cos_t = q0.w;
   const float dx = q1.x, dy = q1.y, dz = q1.z, sin_t = q1.w;
   const float ax = q2.x, ay = q2.y, az = q2.z, X0 = q2.w;
   const float dX = q3.x;
   const float core_x = q4.x, core_y = q4.y, axx = q4.z, axy = q4.w;
-  const uint4 w = philox(k, __float_as_uint(q3.y), __float_as_uint(q3.z), TAG_CHERENKOV, p.key0, p.key1);
-  const float f = u24(w.x);
-  float sphi, cphi;
-  sincospif(2.0f * u24(w.y), &sphi, &cphi);
-  const float u2 = u24(w.z);
-  const float lam = (p.spectrum == CPHOT_SPECTRUM_UNIFORM)
-                        ? p.lam_min + (p.lam_max - p.lam_min) * u2
-                        : 1.0f / (p.inv_lam_min - u2 * (p.inv_lam_min - p.inv_lam_max));
-  const float u3 = u24(w.w);
+  // record k: Cherenkov records first (k < q5.x), then the fluorescence bands
+  float f, lam, u3, ux, uy, uz;
+  if (k < q5.x) {
+    const uint4 w = philox(k, __float_as_uint(q3.y), __float_as_uint(q3.z), TAG_CHERENKOV, p.key0, p.key1);
+    f = u24(w.x);
+    float sphi, cphi;
+    sincospif(2.0f * u24(w.y), &sphi, &cphi);
+    const float u2 = u24(w.z);
+    lam = (p.spectrum == CPHOT_SPECTRUM_UNIFORM)
+              ? p.lam_min + (p.lam_max - p.lam_min) * u2
+              : 1.0f / (p.inv_lam_min - u2 * (p.inv_lam_min - p.inv_lam_max));
+    u3 = u24(w.w);
+    // photon on the cone around (0,0,-1), turned onto the track: u = 2 a (a.p) - p
+    const float plx = cphi * sin_t, ply = sphi * sin_t, plz = -cos_t;
+    const float d2 = 2.0f * fmaf(ax, plx, fmaf(ay, ply, az * plz));
+    ux = fmaf(d2, ax, -plx);
+    uy = fmaf(d2, ay, -ply);
+    uz = fmaf(d2, az, -plz);
+  } else {
+    // fluorescence (Sec. 4.2.2): isotropic in the lower hemisphere, cos(polar) uniform
+    const uint32_t band = (k < q5.y) ? 0u : ((k < q5.z) ? 1u : 2u);
+    const uint32_t kk = k - (band == 0u ? q5.x : (band == 1u ? q5.y : q5.z));
+    const uint4 w = philox(kk, __float_as_uint(q3.y), __float_as_uint(q3.z), TAG_FLUOR + band, p.key0, p.key1);
+    f = u24(w.x);
+    const float cz = 1.0f - u24(w.y);
+    float sphi, cphi;
+    sincospif(2.0f * u24(w.z), &sphi, &cphi);
+    const float sz = sqrtf((1.0f - cz) * (1.0f + cz));
+    ux = sz * cphi;
+    uy = sz * sphi;
+    uz = -cz;
+    lam = p.fl_lambda[band];
+    u3 = u24(w.w);
+  }
   o.lam = lam;
   o.u3 = u3;
   o.bin = -1;
   o.tbin = -1;
+  o.fallback = 0;
   o.t = 0.f;
   o.tau = 0.f;
-  // photon on the cone around (0,0,-1), turned onto the track: u = 2 a (a.p) - p
-  const float plx = cphi * sin_t, ply = sphi * sin_t, plz = -cos_t;
-  const float d2 = 2.0f * (ax * plx + ay * ply + az * plz);
-  const float ux = d2 * ax - plx, uy = d2 * ay - ply, uz = d2 * az - plz;
   o.ux = ux;
   o.uy = uy;
   o.uz = uz;
@@ -190,6 +219,66 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   o.x = Px;
   o.y = Py;
   o.z = Pz;
+  int kb = 0;
+  if constexpr (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT) {
+    kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
+    kb = min(max(kb, 0), p.n_lam - 1);
+  }
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED) {
+    if (!(uz < 0.f)) {
+      o.state = 1;
+      return;
+    }
+    // height above the sphere R without subtracting R: (x^2 + y^2 + z (2R + z)) / (|P - C| + R)
+    const float Rf = (float)p.earth_radius;
+    const float qz = Pz + Rf;
+    const float rq = sqrtf(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
+    const float h0 = fmaf(Px, Px, fmaf(Py, Py, Pz * (2.0f * Rf + Pz))) / (rq + Rf);
+    if (h0 < p.h_obs) {
+      o.state = 3;
+      return;
+    }
+    CurvedWalk cw;
+    curved_walk<NEED_TIME>(s_lay, s_lam[kb], p.dh, p.n_layers, p.h_obs, p.earth_radius, Px, Py, Pz, h0, ux, uy,
+                           uz, axx, axy, axz, cw);
+    o.x = (float)cw.ax;
+    o.y = (float)cw.ay;
+    o.z = (float)cw.az;
+    o.tau = cw.tau;
+    if constexpr (NEED_TIME) o.t = (cw.geo + cw.opt) * (1.0f / kCmPerNs);
+    if (!cw.arrived) {
+      o.state = 3;
+      return;
+    }
+    if (!(u3 < __expf(-cw.tau))) {
+      o.state = 2;
+      return;
+    }
+    // bins in the tangent plane at the core, in FP64
+    const double gx0 = (double)core_x - 0.5 * (double)p.nx * (double)p.cell;
+    const double gy0 = (double)core_y - 0.5 * (double)p.ny * (double)p.cell;
+    const double fxc = floor((cw.ax - gx0) / (double)p.cell), fyc = floor((cw.ay - gy0) / (double)p.cell);
+    if (!(fxc >= 0.0 && fyc >= 0.0 && fxc < (double)p.nx && fyc < (double)p.ny)) {
+      o.state = 3;
+      return;
+    }
+    o.state = 0;
+    o.bin = (int)fyc * p.nx + (int)fxc;
+    return;
+  } else {
+  float ym[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
+  bool use_mlp = false;
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_SURROGATE) {
+    const bool alive = valid && (uz < 0.f) && (Pz >= p.h_obs);
+    float xin[kMlpIn] = {Pz, -uz, atan2f(uy, ux),
+                         p.lam_min + ((float)kb + 0.5f) * ((p.lam_max - p.lam_min) / (float)p.n_lam), p.h_obs};
+    use_mlp = alive && mlp_in_domain(s_img, xin);
+    if (!use_mlp) {
+#pragma unroll
+      for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
+    }
+    mlp_forward_wave(s_img, xin, ym);
+  }
   if (!(uz < 0.f)) {
     o.state = 1;
     return;
@@ -202,53 +291,49 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   float vx, vy, vz;  // direction of the final leg
   float tau = 0.f, geo = 0.f, opt = 0.f;
   float last_delta = 0.f, last_ext = 0.f;
-  if constexpr (TRANSPORT == CPHOT_TRANSPORT_LAYERED) {
-    // Homogeneous layers (Sec. 3.4.2): straight within a layer; at a horizontal
-    // boundary the horizontal part of n u is conserved (Eq. 3.15 with a vertical
-    // normal), so layer i is crossed with sin(theta_i) = K / n_i, K = n_e sin(theta_e).
-    int i = min((int)(Pz * p.inv_dh), p.n_layers - 1);
-    const float sh = sqrtf(ux * ux + uy * uy);
-    float hx = 1.f, hy = 0.f;
-    if (sh > 0.f) {
-      const float ish = 1.0f / sh;
-      hx = ux * ish;
-      hy = uy * ish;
-    }
-    float4 L = s_lay[i];
-    const float Kc = fmaf(sh, L.x, sh);
-    int kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
-    kb = min(max(kb, 0), p.n_lam - 1);
-    const float2 sp = s_lam[kb];
-    x = Px;
-    y = Py;
-    z = Pz;
-    while (i > p.obs_layer) {
-      const float zb = (float)i * p.dh;
-      const float span = z - zb;
-      const float s = Kc * L.y;
-      const float c2 = (1.f - s) * (1.f + s);
-      const float ic = rsqrtf(c2);
-      const float path = span * ic;
-      const float adv = path * s;
-      x = fmaf(hx, adv, x);
-      y = fmaf(hy, adv, y);
-      tau = fmaf(fmaf(L.z, sp.x, L.w * sp.y), path, tau);
+  if constexpr (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT) {
+    if (TRANSPORT == CPHOT_TRANSPORT_LAYERED || !use_mlp) {
+      LayerWalk lw;
+      layer_walk<NEED_TIME, false>(s_lay, s_lam[kb], p.dh, min((int)(Pz * p.inv_dh), p.n_layers - 1),
+                                   p.obs_layer, Px, Py, Pz, ux, uy, uz, axx, axy, axz, lw);
+      x = lw.x;
+      y = lw.y;
+      z = lw.z;
+      vx = lw.vx;
+      vy = lw.vy;
+      vz = lw.vz;
+      tau = lw.tau;
+      geo = lw.geo;
+      opt = lw.opt;
+      last_delta = lw.last_delta;
+      last_ext = lw.last_ext;
+      o.fallback = (TRANSPORT == CPHOT_TRANSPORT_SURROGATE) ? 1 : 0;
+    } else {
+      // straight line to the observation level plus the predicted correction:
+      // landing (dx, dy), optical path excess e and log T; the delay after the
+      // plane front is [l (1 - u.a) + e - (dx a_x + dy a_y)] / c
+      const float s_pl = (p.h_obs - Pz) / uz;
+      // the predicted offset is along / across the photon's horizontal direction
+      const float sh = sqrtf(fmaf(ux, ux, uy * uy));
+      const float hx = sh > 0.f ? ux / sh : 1.f, hy = sh > 0.f ? uy / sh : 0.f;
+      const float odx = fmaf(ym[0], hx, -ym[1] * hy), ody = fmaf(ym[0], hy, ym[1] * hx);
+      x = fmaf(s_pl, ux, Px) + odx;
+      y = fmaf(s_pl, uy, Py) + ody;
+      z = p.h_obs;
+      vx = ux;
+      vy = uy;
+      vz = uz;
+      tau = -ym[3];
       if constexpr (NEED_TIME) {
-        const float ex = s * hx - axx, ey = s * hy - axy, ez = -c2 * ic - axz;
-        geo = fmaf(path, 0.5f * (ex * ex + ey * ey + ez * ez), geo);
-        opt = fmaf(L.x, path, opt);
+        const float gx = ux - axx, gy = uy - axy, gz = uz - axz;
+        geo = s_pl * 0.5f * (gx * gx + gy * gy + gz * gz) - (odx * axx + ody * axy);
+        opt = ym[2];
       }
-      z = zb;
-      --i;
-      L = s_lay[i];
+      const float4 L = s_lay[p.obs_layer];
+      const float2 sp = s_lam[kb];
+      last_delta = L.x;
+      last_ext = fmaf(L.z, sp.x, L.w * sp.y);
     }
-    const float s = Kc * L.y;
-    const float c = sqrtf((1.f - s) * (1.f + s));
-    vx = s * hx;
-    vy = s * hy;
-    vz = -c;
-    last_delta = L.x;
-    last_ext = fmaf(L.z, sp.x, L.w * sp.y);
   } else {
     x = Px;
     y = Py;
@@ -283,7 +368,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     }
   }
   const float ex = fmaf(s_end, vx, x), ey = fmaf(s_end, vy, y), ez = fmaf(s_end, vz, z);
-  if constexpr (TRANSPORT == CPHOT_TRANSPORT_LAYERED) {
+  if constexpr (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT) {
     tau = fmaf(last_ext, s_end, tau);
     if constexpr (NEED_TIME) {
       const float gx = vx - axx, gy = vy - axy, gz = vz - axz;
@@ -334,34 +419,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       o.tbin = tb < 0.f ? 0 : (tb >= (float)p.n_t ? p.n_t : (int)tb);
     }
   }
-}
-
-template <int BS>
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
   }
-  if (lane == 63) s_wave[wid] = x;
-  __syncthreads();
-  uint32_t pre = 0, tot = 0;
-#pragma unroll
-  for (int q = 0; q < BS / 64; ++q) {
-    const uint32_t t = s_wave[q];
-    pre += (q < wid) ? t : 0u;
-    tot += t;
-  }
-  total = tot;
-  return pre + x - v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
 }
 
 }  // namespace
@@ -369,48 +427,62 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 template <int BS, int TRANSPORT, int DETECTOR, int MODE>
 __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   constexpr bool kTime = (DETECTOR == CPHOT_DETECTOR_SPHERES) || (MODE == MODE_RECORDS);
-  constexpr bool kSort = (TRANSPORT == CPHOT_TRANSPORT_LAYERED) && (MODE != MODE_COUNTS);
+  constexpr bool kLayers = (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT);
+  constexpr bool kMlp = (TRANSPORT == CPHOT_TRANSPORT_SURROGATE);
+  constexpr bool kSort = kLayers && (MODE != MODE_COUNTS);
   // per-segment state for the record loop, one slot per segment of the tile:
   // q0 = start point, cos(theta); q1 = end - start, sin(theta); q2 = rotation
   // bisector, depth at the start; q3 = depth change, id low, id high, shower
   // (bit patterns); q4 = core x, core y, axis x, axis y; axz = axis z
   __shared__ float4 s_q0[BS], s_q1[BS], s_q2[BS], s_q3[BS], s_q4[BS];
   __shared__ float s_axz[BS];
+  __shared__ uint4 s_q5[BS];  // record boundaries: Cherenkov, + band 0, + band 1
   __shared__ uint32_t s_off[BS + 1];
   __shared__ uint32_t s_wave[BS / 64];
   __shared__ uint32_t s_src[kSort ? BS : 1];          // tile-local segment index of each slot
   __shared__ uint32_t s_bucket[kSort ? kMaxLayers + 1 : 1];
-  __shared__ float4 s_lay[TRANSPORT == CPHOT_TRANSPORT_LAYERED ? kMaxLayers : 1];
-  __shared__ float2 s_lam[TRANSPORT == CPHOT_TRANSPORT_LAYERED ? kMaxLambdaBins : 1];
+  __shared__ float4 s_lay[kLayers ? kMaxLayers : 1];
+  __shared__ float2 s_lam[kLayers ? kMaxLambdaBins : 1];
+  __shared__ uint4 s_imgw[kMlp ? sizeof(MlpImage) / 16 : 1];
+  const MlpImage* s_img = reinterpret_cast<const MlpImage*>(s_imgw);
   extern __shared__ uint32_t s_hist[];  // optional LDS grid histogram
   const int n_hist = (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_GRID && p.lds_hist) ? p.nx * p.ny : 0;
   const int tid = threadIdx.x;
 
-  if constexpr (TRANSPORT == CPHOT_TRANSPORT_LAYERED) {
+  if constexpr (kLayers) {
     for (int i = tid; i < p.n_layers; i += BS) s_lay[i] = p.layers[i];
     for (int i = tid; i < p.n_lam; i += BS) s_lam[i] = p.lambins[i];
+  }
+  if constexpr (kMlp) {
+    const uint4* src = reinterpret_cast<const uint4*>(p.mlp);
+    for (int i = tid; i < (int)(sizeof(MlpImage) / 16); i += BS) s_imgw[i] = src[i];
   }
   for (int i = tid; i < n_hist; i += BS) s_hist[i] = 0u;
   __syncthreads();
 
-  uint32_t c_in = 0, c_skip = 0, c_below = 0, c_gen = 0, c_up = 0, c_abs = 0, c_out = 0, c_bin = 0;
+  uint32_t c_in = 0, c_skip = 0, c_below = 0, c_gen = 0, c_up = 0, c_abs = 0, c_out = 0, c_bin = 0, c_fb = 0;
+  uint32_t c_fl = 0;
   const int64_t n_tiles = (p.n + BS - 1) / BS;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t i = tile * BS + tid;
     uint32_t nrec = 0;
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
     float axz = 0.f;
+    uint4 q5 = make_uint4(0u, 0u, 0u, 0u);
     int key = kMaxLayers;  // segments without records sort last
     if (i < p.n) {
       const float fx0 = p.x0[i], fy0 = p.y0[i], fz0 = p.z0[i], fx1 = p.x1[i], fy1 = p.y1[i], fz1 = p.z1[i];
       const uint64_t id = p.first_id + (uint64_t)i;
-      const SegResult r = segment_setup(p, fx0, fy0, fz0, fx1, fy1, fz1, p.beta[i], p.charge[i], id);
+      const SegResult r =
+          segment_setup(p, fx0, fy0, fz0, fx1, fy1, fz1, p.beta[i], p.charge[i], p.dedx ? p.dedx[i] : 0.0f, id);
       c_in += 1;
       c_skip += r.status == 2;
       c_below += r.status == 1;
-      nrec = (uint32_t)r.n;
+      q5 = make_uint4((uint32_t)r.n, (uint32_t)(r.n + r.nf[0]), (uint32_t)(r.n + r.nf[0] + r.nf[1]), 0u);
+      nrec = q5.z + (uint32_t)r.nf[2];
+      c_fl += nrec - (uint32_t)r.n;
       if constexpr (MODE == MODE_COUNTS) {
-        p.counts[i] = r.n;
+        p.counts[i] = (int32_t)nrec;
         if (p.expected) p.expected[i] = r.status == 0 ? r.mu : 0.0;
       } else if (nrec) {
         int sh = 0;
@@ -472,6 +544,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     s_q3[slot] = q3;
     s_q4[slot] = q4;
     s_axz[slot] = axz;
+    s_q5[slot] = q5;
     s_off[slot] = nrec;
     __syncthreads();
     uint32_t total;
@@ -481,7 +554,13 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     s_off[tid] = excl;
     if (tid == BS - 1) s_off[BS] = total;
     __syncthreads();
-    for (uint32_t j = tid; j < total; j += BS) {
+    // with the surrogate every lane of a wave runs each round (the tail lanes
+    // repeat the last record and discard it); otherwise lanes stop at `total`
+    const uint32_t rounds_end = kMlp ? ((total + BS - 1) / BS) * BS : total;
+    for (uint32_t base = 0; base + tid < rounds_end; base += BS) {
+      const uint32_t jr = base + tid;
+      const bool valid = jr < total;
+      const uint32_t j = valid ? jr : total - 1;
       // largest slot lo in [0, BS) with s_off[lo] <= j (offsets never decrease)
       int lo = 0;
 #pragma unroll
@@ -489,8 +568,9 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       const uint32_t k = j - s_off[lo];
       Photon ph;
       const float4 r3 = s_q3[lo];
-      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_q0[lo], s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], k,
-                                        ph);
+      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_q0[lo], s_q1[lo], s_q2[lo], r3, s_q4[lo],
+                                        s_axz[lo], s_q5[lo], k, valid, ph);
+      if (!valid) continue;
       if constexpr (MODE == MODE_RECORDS) {
         const uint32_t src = kSort ? s_src[lo] : (uint32_t)lo;
         const int64_t slot_out = p.rec_off[tile * BS + src] + (int64_t)k;
@@ -509,6 +589,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
         }
       } else {
         c_gen += 1;
+        c_fb += ph.fallback;
         c_up += ph.state == 1;
         c_abs += ph.state == 2;
         c_out += ph.state == 3;
@@ -520,13 +601,15 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
               atomicAdd(&s_hist[ph.bin], p.bunch);
             } else {
               const int64_t gb = (int64_t)sh * p.nx * p.ny + ph.bin;
-              if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
+              if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + gb, (double)(float)p.bunch);
+              else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
               else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + gb, p.bunch);
             }
           } else {
             const int64_t nsph = (int64_t)p.snx * p.sny;
             const int64_t gb = (int64_t)sh * nsph + ph.bin;
-            if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
+            if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + gb, (double)(float)p.bunch);
+            else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
             else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + gb, p.bunch);
             if (p.n_t > 0) atomicAdd(p.thist + gb * (p.n_t + 1) + ph.tbin, p.bunch);
           }
@@ -541,7 +624,8 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       for (int b = tid; b < n_hist; b += BS) {
         const uint32_t v = s_hist[b];
         if (v) {
-          if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + b, (unsigned long long)v);
+          if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + b, (double)v);
+          else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + b, (unsigned long long)v);
           else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + b, v);
         }
       }
@@ -549,18 +633,20 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     if (p.counters) {
       // block-level reduction: one global atomic per counter per block (same-address
       // device atomics serialise, so their number must stay small)
-      __shared__ uint32_t s_cnt[8];
-      if (tid < 8) s_cnt[tid] = 0u;
+      __shared__ uint32_t s_cnt[10];
+      if (tid < 10) s_cnt[tid] = 0u;
       __syncthreads();
-      const uint32_t v[8] = {c_in, c_skip, c_below, c_gen, c_up, c_abs, c_out, c_bin};
+      const uint32_t v[10] = {c_in, c_skip, c_below, c_gen, c_up, c_abs, c_out, c_bin, c_fb, c_fl};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < 10; ++q) {
         const uint32_t sw = wave_sum(v[q]);
         if ((tid & 63) == 0 && sw) atomicAdd(&s_cnt[q], sw);
       }
       __syncthreads();
       if (tid < 8 && s_cnt[tid]) atomicAdd(p.counters + tid, (unsigned long long)s_cnt[tid]);
       if (tid == 8 && s_cnt[7]) atomicAdd(p.counters + CPHOT_C_PHOTONS_BINNED, (unsigned long long)s_cnt[7] * p.bunch);
+      if (tid == 9 && s_cnt[8]) atomicAdd(p.counters + CPHOT_C_SURROGATE_FALLBACK, (unsigned long long)s_cnt[8]);
+      if (tid == 10 && s_cnt[9]) atomicAdd(p.counters + CPHOT_C_RECORDS_FLUORESCENCE, (unsigned long long)s_cnt[9]);
     }
   }
 }
@@ -584,12 +670,13 @@ hipError_t launch_mode(const KParams& p, int mode, int grid, size_t lds, hipStre
 
 template <int BS>
 hipError_t launch_bs(const KParams& p, int mode, int grid, size_t lds, hipStream_t s) {
-  if (p.transport == CPHOT_TRANSPORT_STRAIGHT) {
-    if (p.detector == CPHOT_DETECTOR_GRID) return launch_mode<BS, 0, 0>(p, mode, grid, lds, s);
-    return launch_mode<BS, 0, 1>(p, mode, grid, lds, s);
+  const bool g = p.detector == CPHOT_DETECTOR_GRID;
+  switch (p.transport) {
+    case CPHOT_TRANSPORT_STRAIGHT: return g ? launch_mode<BS, 0, 0>(p, mode, grid, lds, s) : launch_mode<BS, 0, 1>(p, mode, grid, lds, s);
+    case CPHOT_TRANSPORT_LAYERED: return g ? launch_mode<BS, 1, 0>(p, mode, grid, lds, s) : launch_mode<BS, 1, 1>(p, mode, grid, lds, s);
+    case CPHOT_TRANSPORT_SURROGATE: return g ? launch_mode<BS, 2, 0>(p, mode, grid, lds, s) : launch_mode<BS, 2, 1>(p, mode, grid, lds, s);
+    default: return launch_mode<BS, 3, 0>(p, mode, grid, lds, s);  // curved: grid detector only
   }
-  if (p.detector == CPHOT_DETECTOR_GRID) return launch_mode<BS, 1, 0>(p, mode, grid, lds, s);
-  return launch_mode<BS, 1, 1>(p, mode, grid, lds, s);
 }
 
 }  // namespace

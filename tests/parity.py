@@ -8,9 +8,14 @@ from oracle import oracle as O
 from paper_2405_04229_amd import cphot
 
 # Per-photon tolerances (floating point, FP32 kernel vs FP64 oracle):
-#  positions |d| <= 1e-4 max(r, 10 m) with r the distance from the core,
+#  positions |d| <= 1e-4 max(r, 10 m) + DIR_TOL H / u_z^2, with r the distance
+#  from the core; the second term is the displacement of the landing point that
+#  a direction error of DIR_TOL rad causes over a descent of H metres at
+#  vertical direction cosine u_z (the problem's own conditioning: the kernel's
+#  FP32 emission direction is asserted to lie within DIR_TOL of the oracle's),
 #  times |d| <= 1e-4 |t| + 0.01 ns, optical depth |d| <= 1e-4 tau + 1e-6.
 POS_REL, POS_FLOOR = 1e-4, 10.0
+DIR_TOL = 4e-7
 T_REL, T_ABS = 1e-4, 0.01
 TAU_REL, TAU_ABS = 1e-4, 1e-6
 # A decision taken by floating point may legitimately differ when the oracle's
@@ -82,6 +87,38 @@ def oracle_atm(atm_kw):
     return O.Atmosphere(**atm_kw)
 
 
+def near_boundary(orc, core, atm_kw, run_kw):
+    """Records of the oracle whose decisions (survival, bin, time bin, start
+    layer, wavelength bin) lie within rounding distance of their boundary, and
+    the per-record position tolerance. Returns (near, pos_tol, h_emit, layer_m, lambin_m)."""
+    surv_m = np.abs(orc["u_abs"] - np.exp(-orc["tau"]))
+    transport = run_kw.get("transport", "straight")
+    h_emit = orc["ez"]
+    if transport == "curved":
+        re = atm_kw.get("earth_radius", 6.371e6)
+        h_emit = np.sqrt(orc["ex"] ** 2 + orc["ey"] ** 2 + (orc["ez"] + re) ** 2) - re
+    r = np.hypot(orc["x"] - core[0], orc["y"] - core[1])
+    descent = np.maximum(h_emit - run_kw.get("h_obs", 2200.0), 0.0)
+    pos_tol = POS_REL * np.maximum(r, POS_FLOOR) + DIR_TOL * descent / np.maximum(orc["dz"] ** 2, 1e-12)
+    near = (surv_m < FLIP_SURV) | (orc["margin"] < pos_tol + FLIP_EDGE_REL * 10) | (orc["tmargin"] < FLIP_T)
+    lm = lbm = None
+    if transport in ("layered", "curved"):
+        dh = atm_kw["h_top"] / atm_kw["n_layers"]
+        lm = np.abs(h_emit / dh - np.round(h_emit / dh)) * dh
+        lam0, lam1 = atm_kw.get("lam_min", 300.0), atm_kw.get("lam_max", 600.0)
+        lb = (orc["lambda"] - lam0) / (lam1 - lam0) * atm_kw["n_lam"]
+        lbm = np.abs(lb - np.round(lb))
+        near |= (lm < FLIP_LAYER) | (lbm < FLIP_LAMBIN)
+    return near, pos_tol, h_emit, lm, lbm
+
+
+def flip_budget(orc, core, atm_kw, run_kw):
+    """Most bin-count differences the same photons may legitimately show: each
+    record near a decision boundary can move one bunch between two bins."""
+    near, *_ = near_boundary(orc, core, atm_kw, run_kw)
+    return 2 * run_kw.get("bunch", 1) * int(near.sum())
+
+
 def compare_records(gpu, orc, core, atm_kw, run_kw):
     """Element-by-element comparison. Returns (n_flips, report). Raises on any
     mismatch that is not a legitimate flip."""
@@ -91,20 +128,12 @@ def compare_records(gpu, orc, core, atm_kw, run_kw):
     # the same uniforms on both sides: the survival uniform is exact in FP32
     np.testing.assert_array_equal(gpu["u_abs"].astype(np.float64), orc["u_abs"])
     np.testing.assert_allclose(gpu["lambda"], orc["lambda"], rtol=2e-6)
-    np.testing.assert_allclose(np.stack([gpu["dx"], gpu["dy"], gpu["dz"]], 1),
-                               np.stack([orc["dx"], orc["dy"], orc["dz"]], 1), atol=2e-6)
-    flips = np.zeros(len(orc), dtype=bool)
-    # legitimate flips: survival, bin edges, time-bin edges, layer and wavelength-bin edges
-    surv_m = np.abs(orc["u_abs"] - np.exp(-orc["tau"]))
+    du = np.stack([gpu["dx"], gpu["dy"], gpu["dz"]], 1) - np.stack([orc["dx"], orc["dy"], orc["dz"]], 1)
+    assert np.abs(du).max() <= DIR_TOL, np.abs(du).max()
+    transport = run_kw.get("transport", "straight")
+    layered = transport in ("layered", "curved")
+    near, pos_tol, h_emit, lm, lbm = near_boundary(orc, core, atm_kw, run_kw)
     r = np.hypot(orc["x"] - core[0], orc["y"] - core[1])
-    pos_tol = POS_REL * np.maximum(r, POS_FLOOR)
-    near = (surv_m < FLIP_SURV) | (orc["margin"] < pos_tol + FLIP_EDGE_REL * 10) | (orc["tmargin"] < FLIP_T)
-    if run_kw.get("transport") == "layered":
-        dh = atm_kw["h_top"] / atm_kw["n_layers"]
-        lm = np.abs(orc["ez"] / dh - np.round(orc["ez"] / dh)) * dh
-        lb = (orc["lambda"] - atm_kw.get("lam_min", 300.0)) / (atm_kw.get("lam_max", 600.0) - atm_kw.get("lam_min", 300.0)) * atm_kw["n_lam"]
-        lbm = np.abs(lb - np.round(lb))
-        near |= (lm < FLIP_LAYER) | (lbm < FLIP_LAMBIN)
     state_diff = gpu["state"] != orc["state"]
     bin_diff = (gpu["bin"] != orc["bin"]) | (gpu["tbin"] != orc["tbin"])
     bad = (state_diff | bin_diff) & ~near
@@ -112,8 +141,10 @@ def compare_records(gpu, orc, core, atm_kw, run_kw):
                           f"{gpu[bad][:3]} vs {orc[bad][:3]}"
     flips = (state_diff | bin_diff) & near
     # continuous quantities where both sides reached the observation level
-    live = (orc["state"] != 1) & ~((orc["state"] == 3) & (orc["ez"] < run_kw.get("h_obs", 2200.0)))
-    live &= ~(near & (lm < FLIP_LAYER) if run_kw.get("transport") == "layered" else np.zeros(len(orc), bool))
+    live = (orc["state"] != 1) & ~((orc["state"] == 3) & (h_emit < run_kw.get("h_obs", 2200.0)))
+    if transport == "curved":
+        live &= orc["margin"] < 1e29      # left the top of the atmosphere: no arrival point
+    live &= ~(near & (lm < FLIP_LAYER) if layered else np.zeros(len(orc), bool))
     # a legitimate hit/miss flip moves the arrival point (sphere entry vs plane crossing)
     live &= ~bin_diff
     dpos = np.hypot(gpu["x"] - orc["x"], gpu["y"] - orc["y"])
@@ -122,7 +153,7 @@ def compare_records(gpu, orc, core, atm_kw, run_kw):
     assert np.all(dt[live] <= T_REL * np.abs(orc["t"][live]) + T_ABS), f"max time error {dt[live].max()}"
     dtau = np.abs(gpu["tau"] - orc["tau"])
     lam_edge = np.zeros(len(orc), bool)
-    if run_kw.get("transport") == "layered":
+    if layered:
         lam_edge = lbm < FLIP_LAMBIN
     ok_tau = live & ~lam_edge
     assert np.all(dtau[ok_tau] <= TAU_REL * orc["tau"][ok_tau] + TAU_ABS), f"max tau error {dtau[ok_tau].max()}"

@@ -1,0 +1,135 @@
+"""Curved-Earth transport, fluorescence emission and FP64 bins: HIP library
+against the FP64 oracle through the C ABI, on the same seeded inputs.
+
+Bars as for the planar paths: record counts bit-exact (Cherenkov and each
+fluorescence band), per-photon positions, times and optical depths within the
+tolerances of tests/parity.py, decisions identical except next to a decision
+boundary, bins equal up to those flips.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_04229_amd import cphot
+from paper_2405_04229_amd import workload as W
+from tests import cases, parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+CURVED = dict(transport="curved", detector="grid", spectrum="frank_tamm", bunch=1, h_obs=2200.0, nx=300, ny=300,
+              cell=40.0)
+
+
+def _geom(sh):
+    return np.array([[*sh.core, *sh.axis]])
+
+
+def _orc_run(run_kw, seed):
+    return O.make_run(**{**run_kw, "seed": seed})
+
+
+@pytest.mark.parametrize("zen", [0.0, 60.0, 80.0])
+def test_curved_records_match_oracle(zen):
+    sh = W.make_shower(1500, seed=31 + int(zen), xmax=500.0, zenith_deg=zen, azimuth_deg=40.0, beta="R")
+    run = {**CURVED, "cell": 40.0 if zen < 70 else 150.0, "seed": 13}
+    g = parity.device_records(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
+    o = O.trace(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 13), sh.seg, core=sh.core, axis=sh.axis)
+    flips, rep = parity.compare_records(g, o, sh.core, cases.ATMO_LAYERED, run)
+    print(rep)
+    assert (o["state"] == 0).sum() > 1000
+    assert flips <= max(3, parity.MAX_FLIP_FRACTION * len(o))
+
+
+def test_curved_bins_and_counters_match_oracle():
+    sh = W.make_shower(20_000, seed=71, xmax=600.0, zenith_deg=70.0, azimuth_deg=200.0, beta="R")
+    run = {**CURVED, "cell": 100.0, "bunch": 3, "seed": 14}
+    gb, _, gc = parity.device_run(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
+    ob, _, oc = O.propagate(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 14), sh.seg, _geom(sh), threads=8)
+    gc = gc.astype(np.uint64)
+    np.testing.assert_array_equal(gc[:4], oc[:4])
+    assert gc[3] == gc[4] + gc[5] + gc[6] + gc[7]
+    assert int(gb.sum()) == int(gc[8]) == 3 * int(gc[7])
+    assert ob.sum() > 10_000
+    assert np.abs(gb.astype(np.int64) - ob.astype(np.int64)).sum() <= max(12, 2e-4 * ob.sum())
+
+
+@pytest.mark.parametrize("transport", ["layered", "curved"])
+def test_fluorescence_counts_bit_exact(transport):
+    sh = W.make_shower(5000, seed=90, xmax=600.0, zenith_deg=50.0, beta="R", dedx=(0.1, 2.0))
+    run = {**CURVED, "transport": transport, "emission": "both", "bunch": 2, "seed": 15}
+    g = parity.device_counts(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
+    o = O.segment_counts(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 15), sh.seg)
+    np.testing.assert_array_equal(g, o["n"] + o["nf"].sum(axis=1))
+    assert o["nf"].sum() > 10_000
+    # fluorescence only: the Cherenkov part drops out, the bands stay
+    run_f = {**run, "emission": "fluorescence"}
+    gf = parity.device_counts(cases.ATMO_LAYERED, run_f, sh.seg, _geom(sh))
+    np.testing.assert_array_equal(gf, o["nf"].sum(axis=1))
+
+
+@pytest.mark.parametrize("transport", ["layered", "curved"])
+def test_fluorescence_records_match_oracle(transport):
+    sh = W.make_shower(800, seed=91, xmax=600.0, zenith_deg=40.0, azimuth_deg=75.0, beta="R", dedx=(0.1, 2.0))
+    run = {**CURVED, "transport": transport, "emission": "both", "cell": 200.0, "seed": 16}
+    g = parity.device_records(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
+    o = O.trace(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 16), sh.seg, core=sh.core, axis=sh.axis)
+    flips, rep = parity.compare_records(g, o, sh.core, cases.ATMO_LAYERED, run)
+    print(rep)
+    # the band of a fluorescence record shows in its line wavelength
+    fl = o["source"] > 0
+    want = np.asarray(O.FL_LAMBDA, dtype=np.float32)[o["source"][fl] - 1]
+    np.testing.assert_array_equal(g["lambda"][fl], want)
+    assert (o["source"] > 0).sum() > 5000 and ((o["source"] > 0) & (o["state"] == 0)).sum() > 500
+    assert flips <= max(3, parity.MAX_FLIP_FRACTION * len(o))
+
+
+def test_fluorescence_counter_and_bins():
+    sh = W.make_shower(8000, seed=92, xmax=600.0, zenith_deg=30.0, beta="R", dedx=(0.1, 2.0))
+    run = {**CURVED, "transport": "layered", "emission": "both", "cell": 100.0, "seed": 17}
+    gb, _, gc = parity.device_run(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
+    ob, _, oc = O.propagate(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 17), sh.seg, _geom(sh), threads=8)
+    sc = O.segment_counts(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 17), sh.seg)
+    assert int(gc[cphot.COUNTERS.index("records_fluorescence")]) == int(sc["nf"].sum())
+    np.testing.assert_array_equal(gc[:4].astype(np.uint64), oc[:4])
+    assert np.abs(gb.astype(np.int64) - ob.astype(np.int64)).sum() <= max(8, 2e-4 * ob.sum())
+
+
+@pytest.mark.parametrize("transport", ["layered", "curved"])
+def test_f64_bins_equal_integer_bins(transport):
+    """FP64 accumulation of whole bunch weights is exact below 2^53: the same
+    launch into double bins gives the integer bins exactly."""
+    sh = W.make_shower(30_000, seed=93, xmax=500.0, zenith_deg=35.0, beta="R")
+    run = {**CURVED, "transport": transport, "bunch": 7, "cell": 60.0, "seed": 18}
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    seg, gg, off = cphot.upload(sh.seg, _geom(sh))
+    S = cphot.make_segments(seg, gg, off)
+    out = []
+    for dtype in (torch.int64, torch.float64, torch.int32):
+        for lds in (-1, 0):
+            det = cphot.make_detector(atm, **run, lds_hist=lds)
+            bins = torch.zeros(300 * 300, dtype=dtype, device="cuda")
+            cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+            cphot.propagate(S, det, bins, None, cnt)
+            torch.cuda.synchronize()
+            out.append(bins.cpu().numpy().astype(np.float64))
+    for b in out[1:]:
+        np.testing.assert_array_equal(b, out[0])
+    assert out[0].sum() > 1e5
+
+
+def test_curved_rejects_spheres_and_missing_dedx():
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    sh = W.make_shower(100, seed=94, beta="R")
+    seg, gg, off = cphot.upload(sh.seg, _geom(sh))
+    S = cphot.make_segments(seg, gg, off)
+    bins = torch.zeros(100, dtype=torch.int64, device="cuda")
+    det = cphot.make_detector(atm, **{**cases.RUN_TELESCOPE, "transport": "curved"})
+    with pytest.raises(cphot.CphotError):
+        cphot.propagate(S, det, bins, None, None)
+    det = cphot.make_detector(atm, **{**CURVED, "transport": "layered", "emission": "both", "nx": 10, "ny": 10})
+    with pytest.raises(cphot.CphotError, match="dedx"):
+        cphot.propagate(S, det, bins, None, None)

@@ -91,8 +91,8 @@ def test_targets_by_snell_closed_form(atm):
             tau += ext[i, k] * sp / ci
         ls = (he - ho) / ct
         r_straight = (he - ho) * st / ct
-        assert y[0] == pytest.approx((r - r_straight) * math.cos(phi), abs=1e-7)
-        assert y[1] == pytest.approx((r - r_straight) * math.sin(phi), abs=1e-7)
+        assert y[0] == pytest.approx(r - r_straight, abs=1e-7)   # along the photon's azimuth
+        assert y[1] == pytest.approx(0.0, abs=1e-7)              # planar layers: no sideways offset
         assert y[2] == pytest.approx(opt - ls, rel=1e-9, abs=1e-9)
         assert y[3] == pytest.approx(-tau, rel=1e-10)
 
