@@ -1,17 +1,26 @@
 """Benchmark: photons propagated per second on one MI355X.
 
-One step = one pass of the whole photon path over one batch: cphot_propagate
+Headline step = one pass of the whole photon path over one batch: cphot_propagate
 over the telescope workload (1e6 track segments of a 20-degree gamma-like
 shower, refraction through 100 homogeneous layers with Rayleigh + aerosol
 absorption on 64 wavelength bins, bunches of 5 photons, 100 bounding spheres of
 6 m on a 150 m grid, 1 ns arrival-time histograms), bins and counters zeroed
 first. Inputs are resident in HBM before timing starts.
 
-Prints one JSON line. Extra fields: the dominant kernel's roofline position and
-the FP64 CPU oracle timed on a bounded sample on the host cores.
+The same JSON line carries:
+- roofline: the dominant kernel against the VALU issue peak;
+- cpu_baseline: the FP64 CPU oracle on the same workload on the host cores;
+- surrogate: the transport network trained on the GPU from 1e7 exact-tracer
+  photons, then run on the same workload, with its per-bin density error against
+  the exact tracer (same photons) and the straight line's for comparison;
+- batched: 256 showers of uneven size in one captured launch per step, launch
+  shape and bunch picked by the autotuner;
+- inclined (with --inclined): one 1e7-segment chunk of the large inclined
+  shower, curved Earth, Cherenkov + fluorescence, FP64 bins.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -32,38 +41,255 @@ SLOTS_PER_RECORD_BASE = 320.0
 SLOTS_PER_LAYER_CROSSING = 22.0
 SEGMENT_BYTES = 32.0
 
-def atmo_kw():
-    from paper_2405_04229_amd import workload as W
-    return dict(profile="linsley5", a=W.LINSLEY_A, b=W.LINSLEY_B, c=W.LINSLEY_C, hb=W.LINSLEY_HB_M, kappa=W.KAPPA,
-                h_top=25000.0, step=1.0, rayleigh400=2974.0, aer_tau350=0.05, aer_H=1200.0, aer_angstrom=1.0,
-                n_layers=100, n_lam=64)
+METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density error"
 
 
-RUN = dict(transport="layered", detector="spheres", spectrum="frank_tamm", bunch=5, h_obs=2200.0, snx=10, sny=10,
-           pitch=150.0, radius=6.0, n_t=512, dt=1.0, seed=2)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sh, target_s=12.0):
-    """The FP64 oracle on a contiguous sample of the same workload, all host cores."""
+def time_steps(torch, step, steps, warmup, stream):
+    """Wall time per step over `steps` after `warmup`, and the mean launch time
+    from HIP events recorded on the launch stream around each launch."""
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, float(np.mean([a.elapsed_time(b) for a, b in events]))
+
+
+def density_error(s, e, min_count=1000):
+    """Worst relative error over bins with >= min_count exact photons, and the
+    global L1 error sum|s - e| / sum e."""
+    s = np.asarray(s, dtype=np.float64).ravel()
+    e = np.asarray(e, dtype=np.float64).ravel()
+    m = e >= min_count
+    worst = float(np.max(np.abs(s[m] - e[m]) / e[m])) if m.any() else None
+    return {"worst_bin": worst, "l1": float(np.abs(s - e).sum() / max(e.sum(), 1.0)), "bins_compared": int(m.sum()),
+            "min_count": min_count}
+
+
+def cpu_baseline(sh, run, atmo, target_s=12.0):
+    """The FP64 oracle on the same workload, all host cores; whole passes are
+    repeated until about target_s of CPU work has been timed."""
     from oracle import oracle as O
-    atm = O.Atmosphere(**atmo_kw())
-    run = O.make_run(**RUN)
+    atm = O.Atmosphere(**atmo)
+    orun = O.make_run(**run)
     geom = [[*sh.core, *sh.axis]]
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = max(1, min(threads, 64))
     n = 20_000
-    while True:
+    while True:  # grow the sample until one pass takes a measurable time
         seg = {k: v[:n] for k, v in sh.seg.items()}
         t0 = time.perf_counter()
-        _, _, cnt = O.propagate(atm, run, seg, geom, threads=threads)
+        _, _, cnt = O.propagate(atm, orun, seg, geom, threads=threads)
         dt = time.perf_counter() - t0
         if dt >= target_s / 4 or n >= sh.n:
             break
         n = min(sh.n, int(n * max(2.0, target_s / max(dt, 1e-3) * 0.5)))
-    photons = float(cnt[3]) * RUN["bunch"]
-    return {"value": photons / dt, "unit": "photons/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of {sh.n} segments (same ids and random streams), {int(cnt[3])} records, "
-                      f"{dt:.1f} s"}
+    passes, total = 1, dt
+    while total < target_s and passes < 100:
+        t0 = time.perf_counter()
+        O.propagate(atm, orun, seg, geom, threads=threads)
+        total += time.perf_counter() - t0
+        passes += 1
+    photons = float(cnt[3]) * run["bunch"]
+    return {"value": photons * passes / total, "unit": "photons/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {sh.n} segments (same ids and random streams), {int(cnt[3])} records per "
+                      f"pass, {passes} passes in {total:.1f} s"}
+
+
+def mean_layer_crossings(torch, cphot, sh, geom, det, run, n=20000):
+    """Mean number of layer boundaries a record crosses, from traced records of
+    the first n segments."""
+    sample = {k: v[:n] for k, v in sh.seg.items()}
+    sg, sgg, _ = cphot.upload(sample, geom)
+    SS = cphot.make_segments(sg, sgg, None)
+    counts = torch.zeros(SS.n, dtype=torch.int32, device="cuda")
+    cphot.segment_counts(SS, det, counts)
+    offs = torch.cumsum(counts.to(torch.int64), 0) - counts.to(torch.int64)
+    tot = int(counts.sum().item())
+    rec = torch.zeros(max(tot, 1) * cphot.RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    cphot.trace_records(SS, det, offs.contiguous(), rec)
+    torch.cuda.synchronize()
+    r = cphot.records_to_numpy(rec.cpu())[:tot]
+    dh = 250.0
+    obs_layer = int(run["h_obs"] // dh)
+    zmid = 0.5 * (sample["z0"].astype(np.float64) + sample["z1"])
+    start_layer = np.minimum((zmid[r["seg"].astype(np.int64)] // dh).astype(np.int64), 99)
+    crossings = np.maximum(start_layer - obs_layer, 0)
+    return float(crossings[r["state"] != 1].mean()) if len(r) else 0.0
+
+
+def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_ms, stream):
+    """Train the transport network on the GPU, then run the telescope workload
+    through it; its bins against the exact tracer's (same photons)."""
+    sur = cphot.Surrogate(W.SURROGATE_LO, W.SURROGATE_HI, max_batch=4096, init_seed=1)
+    t0 = time.perf_counter()
+    X, Y = sur.make_training_set(atm, args.train_samples, seed=1004)
+    sur.fit_normalization(Y)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss = sur.train(X, Y, batch=4096, steps=args.train_steps, lr=3e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    loss = loss.cpu().numpy()
+    del X, Y
+    log(f"surrogate trained: {args.train_steps} steps, final loss {float(loss[-100:].mean()):.2e}")
+
+    nsph = run["snx"] * run["sny"]
+
+    def run_path(det):
+        bins = torch.zeros(nsph, dtype=torch.int64, device="cuda")
+        th = torch.zeros(nsph * (run["n_t"] + 1), dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+
+        def step(ev):
+            bins.zero_()
+            th.zero_()
+            cnt.zero_()
+            if ev is not None:
+                ev[0].record(stream)
+            cphot.propagate(S, det, bins, th, cnt, stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
+
+        ms, kern = time_steps(torch, step, args.steps, args.warmup, stream)
+        return ms, kern, bins.cpu().numpy(), cnt.cpu().numpy()
+
+    det_s = cphot.make_detector(atm, **{**run, "transport": "surrogate"}, surrogate=sur)
+    ms, kern, b_s, c_s = run_path(det_s)
+    det_l = cphot.make_detector(atm, **{**run, "transport": "straight"})
+    ms_l, _, b_l, _ = run_path(det_l)
+    photons = float(c_s[3]) * run["bunch"]
+    return {
+        "value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
+        "speedup_vs_exact": exact_ms / ms,
+        "density_error_vs_exact": density_error(b_s, exact_bins),
+        "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0),
+        "straight_line_without_correction": {"ms_per_step": ms_l,
+                                             "density_error_vs_exact": density_error(b_l, exact_bins)},
+        "network": "5-64-64-4 ReLU, bf16 weights on MFMA 16x16x32, FP32 accumulate",
+        "training": {"samples": args.train_samples, "steps": args.train_steps, "batch": 4096,
+                     "set_build_s": t1 - t0, "train_s": t2 - t1,
+                     "samples_per_s": args.train_steps * 4096 / max(t2 - t1, 1e-9),
+                     "final_loss": float(loss[-100:].mean())},
+    }
+
+
+def bench_batched(torch, cphot, W, args, stream):
+    """256 showers, segment counts log-uniform in [1e3, 1e6], zenith U[0, 60],
+    Xmax U[350, 750], each with its own 200 x 200 grid of 5 m cells, straight
+    rays; one captured launch per step with the autotuner's shape and bunch."""
+    t0 = time.perf_counter()
+    shs = W.make_batch(args.batch_showers, seed=1003, beta=args.beta)
+    log(f"batched workload generated in {time.perf_counter() - t0:.1f} s")
+    ns = len(shs)
+    n = int(sum(s.n for s in shs))
+    fields = ("x0", "y0", "z0", "x1", "y1", "z1", "beta", "charge")
+    dev = {k: torch.empty(n, dtype=torch.float32, device="cuda") for k in fields}
+    o = 0
+    for s in shs:  # per-shower copies straight into the device columns
+        for k in fields:
+            dev[k][o:o + s.n].copy_(torch.from_numpy(s.seg[k]))
+        o += s.n
+    offs = np.zeros(ns + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([s.n for s in shs])
+    geom = np.array([[s.core[0], s.core[1], *s.axis] for s in shs], dtype=np.float64)
+    del shs
+    g = torch.from_numpy(geom).cuda()
+    off = torch.from_numpy(offs).cuda()
+    S = cphot.make_segments(dev, g, off)
+    run = {**W.RUN_BATCH, "seed": 3}
+    atm = cphot.Atmosphere(**W.ATMO_STRAIGHT)
+    per = run["nx"] * run["ny"]
+    bins = torch.zeros(ns * per, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    det0 = cphot.make_detector(atm, **run)
+    t0 = time.perf_counter()
+    tune = cphot.autotune(S, det0, bins, None, cnt, bunches=[1, 2, 5], reps=2, stream=stream)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune: {tune} in {tune_s:.1f} s")
+    det = cphot.make_detector(atm, **{**run, "bunch": tune["bunch"]}, block_size=tune["block_size"],
+                              grid_blocks=tune["grid_blocks"], lds_hist=tune["lds_hist"])
+    step_g = cphot.Step(S, det, bins, None, cnt, clear=True)
+
+    def step(ev):
+        if ev is not None:
+            ev[0].record(stream)
+        step_g.launch(stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    ms, kern = time_steps(torch, step, args.steps, args.warmup, stream)
+    c = cnt.cpu().numpy()
+    photons = float(c[3]) * tune["bunch"]
+    # bunch 1 with the same shape, for the cost of the bunch choice
+    det1 = cphot.make_detector(atm, **run, block_size=tune["block_size"], grid_blocks=tune["grid_blocks"],
+                               lds_hist=tune["lds_hist"])
+    step_1 = cphot.Step(S, det1, bins, None, cnt, clear=True)
+
+    def step1(ev):
+        if ev is not None:
+            ev[0].record(stream)
+        step_1.launch(stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    ms1, _ = time_steps(torch, step1, max(3, args.steps // 2), 1, stream)
+    c1 = cnt.cpu().numpy()
+    step_g.close()
+    step_1.close()
+    return {"value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "graph_launch_ms": kern,
+            "showers": ns, "segments": n, "records_per_step": float(c[3]), "photons_per_step": photons,
+            "tuning": {**tune, "tune_s": tune_s, "bunch_candidates": [1, 2, 5]},
+            "bunch1": {"value": float(c1[3]) / (ms1 * 1e-3), "ms_per_step": ms1},
+            "workload": "256 showers, 10^U[3,6] segments each, zenith U[0,60] deg, Xmax U[350,750], "
+                        "200x200 grid of 5 m per shower, straight rays, Rayleigh; one HIP-graph launch per step"}
+
+
+def bench_inclined(torch, cphot, W, args, stream):
+    """One 1e7-segment chunk of the large inclined shower through the curved
+    atmosphere, Cherenkov + fluorescence, FP64 bins on a 1000 x 1000 grid."""
+    t0 = time.perf_counter()
+    sh = W.workload_inclined_chunk(0, beta=args.beta)
+    log(f"inclined chunk generated in {time.perf_counter() - t0:.1f} s")
+    geom = np.array([[*sh.core, *sh.axis]])
+    seg, g, off = cphot.upload(sh.seg, geom)
+    S = cphot.make_segments(seg, g, off, first_id=sh.first_id)
+    atm = cphot.Atmosphere(**W.ATMO_LAYERED)
+    run = {**W.RUN_INCLINED, "seed": 5}
+    bins = torch.zeros(run["nx"] * run["ny"], dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    t0 = time.perf_counter()
+    tune = cphot.autotune(S, cphot.make_detector(atm, **run), bins, None, cnt, reps=1, stream=stream)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune: {tune} in {tune_s:.1f} s")
+    det = cphot.make_detector(atm, **run, block_size=tune["block_size"], grid_blocks=tune["grid_blocks"],
+                              lds_hist=tune["lds_hist"], hist_window=tune["hist_window"])
+
+    def step(ev):
+        bins.zero_()
+        cnt.zero_()
+        if ev is not None:
+            ev[0].record(stream)
+        cphot.propagate(S, det, bins, None, cnt, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    ms, kern = time_steps(torch, step, max(3, args.steps // 4), 1, stream)
+    c = cnt.cpu().numpy()
+    photons = float(c[3]) * run["bunch"]
+    return {"value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
+            "segments": sh.n, "records_per_step": float(c[3]), "fluorescence_records": float(c[10]),
+            "tuning": {**tune, "tune_s": tune_s},
+            "workload": "chunk 0 of the 1e8-segment inclined shower: zenith 60 deg, Xmax 600, "
+                        "dE/dx U[0.1,2] MeV/m, curved Earth, 1000x1000 grid of 10 m, FP64 bins"}
 
 
 def main():
@@ -73,6 +299,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--beta", default="R", choices=["R", "literal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--inclined", action="store_true", help="also time one chunk of the inclined workload")
+    ap.add_argument("--train-samples", type=int, default=10_000_000)
+    ap.add_argument("--train-steps", type=int, default=20_000)
+    ap.add_argument("--batch-showers", type=int, default=256)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -95,19 +327,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
         return
+    stream = torch.cuda.current_stream()
+    run = {**W.RUN_TELESCOPE, "seed": 2}
     sh = W.workload_telescope(args.beta)
     geom = np.array([[*sh.core, *sh.axis]])
-    atm = cphot.Atmosphere(**atmo_kw())
-    det = cphot.make_detector(atm, **RUN)
+    atm = cphot.Atmosphere(**W.ATMO_LAYERED)
+    det = cphot.make_detector(atm, **run)
     seg, g, off = cphot.upload(sh.seg, geom)
     S = cphot.make_segments(seg, g, off)
-    nsph = RUN["snx"] * RUN["sny"]
+    nsph = run["snx"] * run["sny"]
     bins = torch.zeros(nsph, dtype=torch.int64, device="cuda")
-    th = torch.zeros(nsph * (RUN["n_t"] + 1), dtype=torch.int32, device="cuda")
+    th = torch.zeros(nsph * (run["n_t"] + 1), dtype=torch.int32, device="cuda")
     cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
-    stream = torch.cuda.current_stream()
 
-    def step(ev=None):
+    def step(ev):
         bins.zero_()
         th.zero_()
         cnt.zero_()
@@ -117,43 +350,15 @@ def main():
         if ev is not None:
             ev[1].record(stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(events[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    ms_per_step, kern_ms = time_steps(torch, step, args.steps, args.warmup, stream)
+    log(f"exact telescope: {ms_per_step:.3f} ms/step, kernel {kern_ms:.3f} ms")
     c = cnt.cpu().numpy()
+    exact_bins = bins.cpu().numpy()
     records = float(c[3])
-    photons = records * RUN["bunch"]
+    photons = records * run["bunch"]
     value = photons / (ms_per_step * 1e-3)
 
-    # mean layer crossings per record from a sample of traced records
-    sample = {k: v[:20000] for k, v in sh.seg.items()}
-    sg, sgg, _ = cphot.upload(sample, geom)
-    SS = cphot.make_segments(sg, sgg, None)
-    counts = torch.zeros(SS.n, dtype=torch.int32, device="cuda")
-    cphot.segment_counts(SS, det, counts)
-    offs = torch.cumsum(counts.to(torch.int64), 0) - counts.to(torch.int64)
-    tot = int(counts.sum().item())
-    rec = torch.zeros(max(tot, 1) * cphot.RECORD_BYTES, dtype=torch.uint8, device="cuda")
-    cphot.trace_records(SS, det, offs.contiguous(), rec)
-    torch.cuda.synchronize()
-    r = cphot.records_to_numpy(rec.cpu())[:tot]
-    # layer crossings of each record: from the layer of its segment's midpoint down to the observation layer
-    dh = 250.0
-    obs_layer = int(RUN["h_obs"] // dh)
-    zmid = 0.5 * (sample["z0"].astype(np.float64) + sample["z1"])
-    start_layer = np.minimum((zmid[r["seg"].astype(np.int64)] // dh).astype(np.int64), 99)
-    crossings = np.maximum(start_layer - obs_layer, 0)
-    mean_cross = float(crossings[r["state"] != 1].mean()) if len(r) else 0.0
-
+    mean_cross = mean_layer_crossings(torch, cphot, sh, geom, det, run)
     n_seg = float(sh.n)
     slots = n_seg * SLOTS_PER_SEGMENT + records * (SLOTS_PER_RECORD_BASE + SLOTS_PER_LAYER_CROSSING * mean_cross)
     achieved = slots / (kern_ms * 1e-3)
@@ -163,7 +368,7 @@ def main():
                 "algorithmic_slots_per_launch": slots, "mean_layer_crossings": mean_cross,
                 "hbm_gbps_algorithmic": n_seg * SEGMENT_BYTES / (kern_ms * 1e-3) / 1e9}
     out = {
-        "metric": "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density error",
+        "metric": METRIC,
         "value": value, "unit": "photons/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
@@ -174,8 +379,19 @@ def main():
                    "segments_per_s": n_seg / (ms_per_step * 1e-3)},
         "roofline": roofline,
     }
+    if not args.no_surrogate:
+        out["surrogate"] = bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, ms_per_step, stream)
+        log(f"surrogate: {out['surrogate']['value']:.3e} photons/s")
+    if not args.no_batched:
+        del S, seg
+        out["batched"] = bench_batched(torch, cphot, W, args, stream)
+        log(f"batched: {out['batched']['value']:.3e} photons/s")
+        torch.cuda.empty_cache()
+    if args.inclined:
+        out["inclined"] = bench_inclined(torch, cphot, W, args, stream)
+        log(f"inclined: {out['inclined']['value']:.3e} photons/s")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sh)
+        out["cpu_baseline"] = cpu_baseline(sh, run, W.ATMO_LAYERED)
     print(json.dumps(out), flush=True)
 
 

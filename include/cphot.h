@@ -174,8 +174,10 @@ typedef struct {
   double time_bin_ns;       /* width of a time bin, ns */
   int32_t block_size;       /* tuning: threads per block (0 = library choice) */
   int32_t grid_blocks;      /* tuning: blocks of the persistent grid (0 = library choice) */
-  int32_t lds_hist;         /* tuning: 1 = privatise the grid histogram in LDS, 0 = global atomics, -1 = library choice */
-  int32_t reserved1;
+  int32_t lds_hist;         /* tuning: 1 = privatise the grid histogram in LDS (the whole grid if it
+                               fits, else a window around the grid centre), 0 = global atomics only,
+                               -1 = library choice */
+  int32_t hist_window;      /* tuning: LDS window side in cells (0 = the largest that fits) */
   const cphot_surrogate* surrogate; /* SURROGATE transport: a trained network (else NULL) */
   int32_t emission;         /* CPHOT_EMIT_* bits (0 = Cherenkov) */
   int32_t reserved2;
@@ -288,6 +290,8 @@ typedef struct {
   int32_t grid_blocks;   /* 0 = one block per tile */
   int32_t lds_hist;
   int32_t bunch;
+  int32_t hist_window;   /* LDS window side in cells (0 with lds_hist 0) */
+  int32_t reserved0;
   double ms;             /* mean time of one propagation with this shape */
   double photons_per_s;  /* records generated x bunch / time */
 } cphot_tuning;

@@ -61,7 +61,7 @@ class Detector(C.Structure):
                 ("ny", C.c_int32), ("cell", C.c_double), ("snx", C.c_int32), ("sny", C.c_int32),
                 ("pitch", C.c_double), ("radius", C.c_double), ("n_time_bins", C.c_int32),
                 ("reserved0", C.c_int32), ("time_bin_ns", C.c_double), ("block_size", C.c_int32),
-                ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("reserved1", C.c_int32),
+                ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("hist_window", C.c_int32),
                 ("surrogate", C.c_void_p), ("emission", C.c_int32), ("reserved2", C.c_int32),
                 ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3)]
 
@@ -73,7 +73,8 @@ class SurrogateDesc(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32),
-                ("bunch", C.c_int32), ("ms", C.c_double), ("photons_per_s", C.c_double)]
+                ("bunch", C.c_int32), ("hist_window", C.c_int32), ("reserved0", C.c_int32), ("ms", C.c_double),
+                ("photons_per_s", C.c_double)]
 
 
 class Bins(C.Structure):
@@ -197,8 +198,8 @@ class Atmosphere:
 
 def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0,
                   h_obs=2200.0, nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0,
-                  dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, surrogate=None, emission="cherenkov",
-                  fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0)) -> Detector:
+                  dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, surrogate=None,
+                  emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0)) -> Detector:
     d = Detector()
     d.atm = atm.handle
     d.transport, d.detector, d.spectrum = TRANSPORT[transport], DETECTOR[detector], SPECTRUM[spectrum]
@@ -207,6 +208,7 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
     d.snx, d.sny, d.pitch, d.radius = int(snx), int(sny), float(pitch), float(radius)
     d.n_time_bins, d.time_bin_ns = int(n_t), float(dt)
     d.block_size, d.grid_blocks, d.lds_hist = int(block_size), int(grid_blocks), int(lds_hist)
+    d.hist_window = int(hist_window)
     d.emission = EMISSION[emission]
     d.fl_yield[:] = tuple(float(v) for v in fl_yield)
     d.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
@@ -314,8 +316,8 @@ def autotune(seg: Segments, det: Detector, bins, time_hist=None, counters=None, 
                                                   None if bc is None else bc.ctypes.data_as(C.c_void_p),
                                                   0 if bc is None else len(bc), int(reps), C.byref(t),
                                                   _stream_ptr(stream)))
-    return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, bunch=t.bunch, ms=t.ms,
-                photons_per_s=t.photons_per_s)
+    return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, hist_window=t.hist_window,
+                bunch=t.bunch, ms=t.ms, photons_per_s=t.photons_per_s)
 
 
 def segment_counts(seg: Segments, det: Detector, counts, expected=None, stream=None):

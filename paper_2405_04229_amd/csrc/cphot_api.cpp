@@ -250,24 +250,53 @@ struct LaunchShape {
   size_t lds;
 };
 
+// Launch shape. The grid histogram can be privatised in LDS: the whole grid
+// when it fits, else a window of W x W cells around the grid centre (the core),
+// where most photons of a shower land. Each block then walks a contiguous range
+// of tiles and flushes its window when the shower changes, so global atomics are
+// paid per window cell and block rather than per photon.
+constexpr size_t kLdsBudget = 64 * 1024;  // per block, static + dynamic
+
 int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchShape& s) {
   int bs = det->block_size ? det->block_size : 256;
   if (bs != 128 && bs != 256 && bs != 512) return fail(CPHOT_ERR_INVALID_ARG, "block_size must be 0, 128, 256 or 512");
+  if (det->hist_window < 0) return fail(CPHOT_ERR_INVALID_ARG, "hist_window must be >= 0");
   size_t lds = 0;
   p.lds_hist = 0;
-  if (mode == cphot::MODE_PROPAGATE && p.detector == CPHOT_DETECTOR_GRID && p.n_showers == 1) {
-    const size_t hb = (size_t)p.nx * p.ny * 4;
-    const bool fits = lds + hb <= 64 * 1024;
-    if (det->lds_hist == 1 && !fits) return fail(CPHOT_ERR_INVALID_ARG, "grid too large for an LDS histogram");
-    p.lds_hist = (det->lds_hist == 1 || (det->lds_hist < 0 && fits)) ? 1 : 0;
-    if (p.lds_hist) lds += hb;
+  p.hist_w = p.hist_h = p.hist_x0 = p.hist_y0 = 0;
+  if (mode == cphot::MODE_PROPAGATE && p.detector == CPHOT_DETECTOR_GRID && det->lds_hist != 0) {
+    const size_t stat = cphot::propagate_static_lds(p, mode, bs);
+    const size_t room = stat < kLdsBudget ? (kLdsBudget - stat) / 4 : 0;  // cells that fit
+    int w = p.nx, h = p.ny;
+    if ((size_t)w * h > room || det->hist_window > 0) {
+      int side = det->hist_window > 0 ? det->hist_window : (int)std::sqrt((double)room);
+      while (side > 0 && (size_t)side * side > room) --side;
+      w = std::min(p.nx, side);
+      h = std::min(p.ny, side);
+    }
+    const bool usable = w >= 8 && h >= 8 && (size_t)w * h <= room;
+    if (det->lds_hist == 1 && !usable) return fail(CPHOT_ERR_INVALID_ARG, "no LDS histogram window fits this launch");
+    // Library choice: the whole grid when it fits; a partial window only for
+    // straight rays, where a record costs about as much as its global atomic.
+    // Refracting transports spend far more per record and lose more to the
+    // window's lower occupancy than they save in atomics (the autotuner times both).
+    const bool whole = w == p.nx && h == p.ny;
+    const bool wanted = det->lds_hist == 1 || whole || p.transport == CPHOT_TRANSPORT_STRAIGHT;
+    if (usable && wanted) {
+      p.lds_hist = 1;
+      p.hist_w = w;
+      p.hist_h = h;
+      p.hist_x0 = (p.nx - w) / 2;
+      p.hist_y0 = (p.ny - h) / 2;
+      lds = (size_t)w * h * 4;
+    }
   }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   const int64_t tiles = (p.n + bs - 1) / bs;
   // One block per tile lets the dispatcher balance uneven tiles. With an LDS
-  // histogram a persistent grid (a few blocks per CU walking the tiles)
-  // amortises the histogram's zeroing and flush.
+  // histogram a persistent grid (a few blocks per CU, each over a contiguous
+  // range of tiles) amortises the window's zeroing and flushes.
   int64_t g = det->grid_blocks > 0 ? det->grid_blocks : (p.lds_hist ? (int64_t)cu_count(dev) * 4 : tiles);
   if (g > tiles) g = tiles;
   if (g < 1) g = 1;
@@ -572,21 +601,30 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
   for (int32_t b : bunches) {
     for (int bs : {128, 256, 512}) {
       for (int gpol = 0; gpol < 3 && rc == CPHOT_OK; ++gpol) {
-        for (int lh = 0; lh < 2 && rc == CPHOT_OK; ++lh) {
+        int tried_w[8], n_tried = 0;
+        // LDS histogram: off, then windows of the largest size that fits and of 48 / 64 / 96 cells
+        for (int hw : {-1, 0, 48, 64, 96}) {
+          if (rc != CPHOT_OK) break;
           cphot_detector d = *det;
           d.bunch = b;
           d.block_size = bs;
           d.grid_blocks = gpol == 0 ? 0 : cus * (gpol == 1 ? 2 : 4);
-          d.lds_hist = lh;
+          d.lds_hist = hw < 0 ? 0 : 1;
+          d.hist_window = hw < 0 ? 0 : hw;
           cphot::KParams p;
           if ((rc = fill_params(seg, &d, p, true, out))) break;
           if (p.n == 0) break;
           LaunchShape sh;
           if (choose_shape(&d, p, cphot::MODE_PROPAGATE, sh) != CPHOT_OK) {
-            rc = CPHOT_OK;  // shape not applicable (e.g. LDS histogram too large)
+            rc = CPHOT_OK;  // shape not applicable (e.g. no window fits)
             continue;
           }
-          if (lh == 1 && !p.lds_hist) continue;  // the histogram option does not apply here
+          if (hw >= 0) {  // skip windows that came out the same as one already timed
+            bool seen = false;
+            for (int q = 0; q < n_tried; ++q) seen = seen || tried_w[q] == p.hist_w * 65536 + p.hist_h;
+            if (seen) continue;
+            tried_w[n_tried++] = p.hist_w * 65536 + p.hist_h;
+          }
           hipError_t e = clear_outputs(out, st);
           if (e == hipSuccess) e = cphot::launch_propagate(p, cphot::MODE_PROPAGATE, sh.block, sh.grid, sh.lds, st);
           if (e == hipSuccess) e = clear_outputs(out, st);
@@ -609,7 +647,8 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
           if (pps > top.photons_per_s) {
             top.block_size = bs;
             top.grid_blocks = d.grid_blocks;
-            top.lds_hist = lh;
+            top.lds_hist = d.lds_hist;
+            top.hist_window = d.lds_hist ? p.hist_w : 0;
             top.bunch = b;
             top.ms = t;
             top.photons_per_s = pps;

@@ -77,7 +77,9 @@ struct KParams {
   // outputs
   void* bins;
   int32_t bins_u64;
-  int32_t lds_hist;
+  int32_t lds_hist;                    // grid counts privatised in an LDS window
+  int32_t hist_w, hist_h;              // window size in cells (x, y)
+  int32_t hist_x0, hist_y0;            // window origin in cells
   uint32_t* thist;
   unsigned long long* counters;
   // debug outputs
@@ -101,5 +103,7 @@ bool surrogate_ready(const cphot_surrogate* s);
 
 hipError_t launch_propagate(const KParams& p, int mode, int block_size, int grid_blocks, size_t lds_hist_bytes,
                             hipStream_t stream);
+// Static LDS bytes of the propagate kernel that `p`, `mode` and `block_size` select.
+size_t propagate_static_lds(const KParams& p, int mode, int block_size);
 
 }  // namespace cphot

@@ -153,6 +153,7 @@ __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float 
 
 struct Photon {
   int32_t state, bin, tbin, fallback;
+  int32_t ix, iy;  // grid cell
   float x, y, z, t, tau, lam, u3, ux, uy, uz;
 };
 
@@ -263,7 +264,9 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       return;
     }
     o.state = 0;
-    o.bin = (int)fyc * p.nx + (int)fxc;
+    o.ix = (int)fxc;
+    o.iy = (int)fyc;
+    o.bin = o.iy * p.nx + o.ix;
     return;
   } else {
   float ym[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
@@ -351,7 +354,11 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     const float gx0 = core_x - 0.5f * (float)p.nx * p.cell;
     const float gy0 = core_y - 0.5f * (float)p.ny * p.cell;
     const float fxc = floorf((Qx - gx0) * p.inv_cell), fyc = floorf((Qy - gy0) * p.inv_cell);
-    if (fxc >= 0.f && fyc >= 0.f && fxc < (float)p.nx && fyc < (float)p.ny) bin = (int)fyc * p.nx + (int)fxc;
+    if (fxc >= 0.f && fyc >= 0.f && fxc < (float)p.nx && fyc < (float)p.ny) {
+      o.ix = (int)fxc;
+      o.iy = (int)fyc;
+      bin = o.iy * p.nx + o.ix;
+    }
   } else {
     const float cx0 = core_x - 0.5f * (float)(p.snx - 1) * p.pitch;
     const float cy0 = core_y - 0.5f * (float)(p.sny - 1) * p.pitch;
@@ -424,6 +431,37 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
 
 }  // namespace
 
+// Shower of segment i: the largest s with offsets[s] <= i.
+__device__ __forceinline__ int shower_of(const KParams& p, int64_t i) {
+  if (p.n_showers <= 1) return 0;
+  int lo = 0, hi = p.n_showers;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (p.offsets[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Adds the LDS window of shower `sh` (record counts) to the global bins with
+// the bunch weight, and clears it. Called by the whole block.
+template <int BS>
+__device__ void flush_window(const KParams& p, uint32_t* s_hist, int sh) {
+  const int n = p.hist_w * p.hist_h;
+  const int64_t base = (int64_t)sh * p.nx * p.ny;
+  for (int b = threadIdx.x; b < n; b += BS) {
+    const uint32_t v = s_hist[b];
+    if (v) {
+      const int ly = b / p.hist_w, lx = b - ly * p.hist_w;
+      const int64_t gb = base + (int64_t)(p.hist_y0 + ly) * p.nx + (p.hist_x0 + lx);
+      const unsigned long long w = (unsigned long long)v * (unsigned long long)p.bunch;
+      if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + gb, (double)w);
+      else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, w);
+      else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + gb, (uint32_t)w);
+      s_hist[b] = 0u;
+    }
+  }
+}
+
 template <int BS, int TRANSPORT, int DETECTOR, int MODE>
 __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   constexpr bool kTime = (DETECTOR == CPHOT_DETECTOR_SPHERES) || (MODE == MODE_RECORDS);
@@ -445,8 +483,15 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   __shared__ float2 s_lam[kLayers ? kMaxLambdaBins : 1];
   __shared__ uint4 s_imgw[kMlp ? sizeof(MlpImage) / 16 : 1];
   const MlpImage* s_img = reinterpret_cast<const MlpImage*>(s_imgw);
-  extern __shared__ uint32_t s_hist[];  // optional LDS grid histogram
-  const int n_hist = (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_GRID && p.lds_hist) ? p.nx * p.ny : 0;
+  // Optional LDS window of the grid (record counts of one shower at a time).
+  // With it each block walks a contiguous range of tiles, so the window changes
+  // shower only a few times per block; records outside the window, or of another
+  // shower than the window's, go to the global bins directly.
+  extern __shared__ uint32_t s_hist[];
+  __shared__ int s_win_sh, s_tile_sh;
+  __shared__ uint32_t s_since;  // records since the last flush (keeps LDS counts below 2^32)
+  const int n_hist =
+      (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_GRID && p.lds_hist) ? p.hist_w * p.hist_h : 0;
   const int tid = threadIdx.x;
 
   if constexpr (kLayers) {
@@ -458,13 +503,37 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     for (int i = tid; i < (int)(sizeof(MlpImage) / 16); i += BS) s_imgw[i] = src[i];
   }
   for (int i = tid; i < n_hist; i += BS) s_hist[i] = 0u;
+  if (tid == 0) {
+    s_win_sh = -1;
+    s_since = 0u;
+  }
   __syncthreads();
 
   uint32_t c_in = 0, c_skip = 0, c_below = 0, c_gen = 0, c_up = 0, c_abs = 0, c_out = 0, c_bin = 0, c_fb = 0;
   uint32_t c_fl = 0;
   const int64_t n_tiles = (p.n + BS - 1) / BS;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  int64_t t_first = blockIdx.x, t_end = n_tiles, t_step = gridDim.x;
+  if (n_hist) {
+    t_first = (int64_t)blockIdx.x * n_tiles / gridDim.x;
+    t_end = ((int64_t)blockIdx.x + 1) * n_tiles / gridDim.x;
+    t_step = 1;
+  }
+  for (int64_t tile = t_first; tile < t_end; tile += t_step) {
     const int64_t i = tile * BS + tid;
+    if (n_hist) {
+      if (tid == 0) s_tile_sh = shower_of(p, tile * BS);
+      __syncthreads();
+      // per tile at most BS << 20 records: flushing at 2^31 keeps counts below 2^32
+      if (s_tile_sh != s_win_sh || s_since >= (1u << 31)) {
+        if (s_win_sh >= 0) flush_window<BS>(p, s_hist, s_win_sh);
+        __syncthreads();
+        if (tid == 0) {
+          s_win_sh = s_tile_sh;
+          s_since = 0u;
+        }
+        __syncthreads();
+      }
+    }
     uint32_t nrec = 0;
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
     float axz = 0.f;
@@ -485,15 +554,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
         p.counts[i] = (int32_t)nrec;
         if (p.expected) p.expected[i] = r.status == 0 ? r.mu : 0.0;
       } else if (nrec) {
-        int sh = 0;
-        if (p.n_showers > 1) {
-          int lo = 0, hi = p.n_showers;  // offsets[lo] <= i < offsets[hi]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (p.offsets[mid] <= i) lo = mid; else hi = mid;
-          }
-          sh = lo;
-        }
+        const int sh = shower_of(p, i);
         float X0 = 0.f, dXs = 0.f;
         if (TRANSPORT == CPHOT_TRANSPORT_STRAIGHT && p.profile == CPHOT_PROFILE_LINSLEY5) {
           X0 = depth_f(p, fz0);
@@ -552,7 +613,10 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     const uint32_t excl = block_exclusive_scan<BS>(mine, s_wave, total);
     __syncthreads();
     s_off[tid] = excl;
-    if (tid == BS - 1) s_off[BS] = total;
+    if (tid == BS - 1) {
+      s_off[BS] = total;
+      s_since += total;
+    }
     __syncthreads();
     // with the surrogate every lane of a wave runs each round (the tail lanes
     // repeat the last record and discard it); otherwise lanes stop at `total`
@@ -597,8 +661,10 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
           c_bin += 1;
           const uint32_t sh = __float_as_uint(r3.w);
           if constexpr (DETECTOR == CPHOT_DETECTOR_GRID) {
-            if (n_hist) {
-              atomicAdd(&s_hist[ph.bin], p.bunch);
+            const int lx = ph.ix - p.hist_x0, ly = ph.iy - p.hist_y0;
+            if (n_hist && (int)sh == s_win_sh && (unsigned)lx < (unsigned)p.hist_w &&
+                (unsigned)ly < (unsigned)p.hist_h) {
+              atomicAdd(&s_hist[ly * p.hist_w + lx], 1u);
             } else {
               const int64_t gb = (int64_t)sh * p.nx * p.ny + ph.bin;
               if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + gb, (double)(float)p.bunch);
@@ -621,14 +687,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   if constexpr (MODE == MODE_PROPAGATE) {
     if (n_hist) {
       __syncthreads();
-      for (int b = tid; b < n_hist; b += BS) {
-        const uint32_t v = s_hist[b];
-        if (v) {
-          if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + b, (double)v);
-          else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + b, (unsigned long long)v);
-          else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + b, v);
-        }
-      }
+      if (s_win_sh >= 0) flush_window<BS>(p, s_hist, s_win_sh);
     }
     if (p.counters) {
       // block-level reduction: one global atomic per counter per block (same-address
@@ -679,7 +738,42 @@ hipError_t launch_bs(const KParams& p, int mode, int grid, size_t lds, hipStream
   }
 }
 
+template <int BS, int T, int D, int M>
+size_t static_lds_one() {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&k_propagate<BS, T, D, M>)) != hipSuccess) return 0;
+  return a.sharedSizeBytes;
+}
+
+template <int BS, int T, int D>
+size_t static_lds_mode(int mode) {
+  switch (mode) {
+    case MODE_PROPAGATE: return static_lds_one<BS, T, D, MODE_PROPAGATE>();
+    case MODE_COUNTS: return static_lds_one<BS, T, D, MODE_COUNTS>();
+    default: return static_lds_one<BS, T, D, MODE_RECORDS>();
+  }
+}
+
+template <int BS>
+size_t static_lds_bs(const KParams& p, int mode) {
+  const bool g = p.detector == CPHOT_DETECTOR_GRID;
+  switch (p.transport) {
+    case CPHOT_TRANSPORT_STRAIGHT: return g ? static_lds_mode<BS, 0, 0>(mode) : static_lds_mode<BS, 0, 1>(mode);
+    case CPHOT_TRANSPORT_LAYERED: return g ? static_lds_mode<BS, 1, 0>(mode) : static_lds_mode<BS, 1, 1>(mode);
+    case CPHOT_TRANSPORT_SURROGATE: return g ? static_lds_mode<BS, 2, 0>(mode) : static_lds_mode<BS, 2, 1>(mode);
+    default: return static_lds_mode<BS, 3, 0>(mode);
+  }
+}
+
 }  // namespace
+
+size_t propagate_static_lds(const KParams& p, int mode, int block_size) {
+  switch (block_size) {
+    case 128: return static_lds_bs<128>(p, mode);
+    case 512: return static_lds_bs<512>(p, mode);
+    default: return static_lds_bs<256>(p, mode);
+  }
+}
 
 hipError_t launch_propagate(const KParams& p, int mode, int block_size, int grid_blocks, size_t lds_bytes,
                             hipStream_t stream) {

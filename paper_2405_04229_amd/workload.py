@@ -194,6 +194,29 @@ def concat_showers(showers):
 
 
 # ---- the five workload recipes ------------------------------------------------------
+# Plain parameter dictionaries: each side (oracle, library) builds its own objects
+# from them.
+
+_LINSLEY = dict(a=LINSLEY_A, b=LINSLEY_B, c=LINSLEY_C, hb=LINSLEY_HB_M, kappa=KAPPA)
+# straight rays, Rayleigh only, continuous wavelength (tiny vertical and batched workloads)
+ATMO_STRAIGHT = dict(profile="linsley5", h_top=25000.0, step=1.0, rayleigh400=2974.0, **_LINSLEY)
+# 100 layers of 250 m, Rayleigh + aerosol tables on 64 wavelength bins (telescope,
+# surrogate and inclined workloads; the inclined one bends them into shells)
+ATMO_LAYERED = dict(profile="linsley5", h_top=25000.0, step=1.0, rayleigh400=2974.0, aer_tau350=0.05,
+                    aer_H=1200.0, aer_angstrom=1.0, n_layers=100, n_lam=64, **_LINSLEY)
+
+RUN_TINY = dict(transport="straight", detector="grid", spectrum="uniform", bunch=1, h_obs=2200.0,
+                nx=100, ny=100, cell=10.0)
+RUN_TELESCOPE = dict(transport="layered", detector="spheres", spectrum="frank_tamm", bunch=5, h_obs=2200.0,
+                     snx=10, sny=10, pitch=150.0, radius=6.0, n_t=512, dt=1.0)
+RUN_BATCH = dict(transport="straight", detector="grid", spectrum="frank_tamm", bunch=1, h_obs=2200.0,
+                 nx=200, ny=200, cell=5.0)
+RUN_INCLINED = dict(transport="curved", detector="grid", spectrum="frank_tamm", emission="both", bunch=1,
+                    h_obs=2200.0, nx=1000, ny=1000, cell=10.0)
+# surrogate training domain: emission height, cos zenith, azimuth, wavelength, observation level
+SURROGATE_LO = (2000.0, math.cos(math.radians(60.0)), -math.pi, 300.0, 1000.0)
+SURROGATE_HI = (20000.0, 1.0, math.pi, 600.0, 3000.0)
+
 
 def workload_tiny_vertical(beta: str = "literal", n: int = 10_000) -> Shower:
     """1e4 segments, vertical, Xmax 600, straight rays to a 100 x 100 grid of 10 m at 2200 m."""

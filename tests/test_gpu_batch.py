@@ -83,8 +83,56 @@ def test_autotune_returns_equivalent_shape():
     cphot.propagate(S, det, bins, None, cnt)
     ref = bins.clone()
     tuned = cphot.make_detector(atm, **run, block_size=best["block_size"], grid_blocks=best["grid_blocks"],
-                                lds_hist=best["lds_hist"])
+                                lds_hist=best["lds_hist"], hist_window=best["hist_window"])
     bins.zero_()
     cphot.propagate(S, tuned, bins, None, cnt)
     torch.cuda.synchronize()
     assert torch.equal(bins, ref)
+
+
+@pytest.mark.parametrize("bs", [128, 256, 512])
+def test_lds_window_bins_identical_to_global_atomics(bs):
+    """Grid counts privatised in an LDS window (around each shower's core, the
+    rest global) give the same integer bins as global atomics alone, for window
+    sizes, persistent-grid sizes and block sizes, across shower boundaries
+    inside tiles and blocks."""
+    seg, offs, geom = _batch(n=20, seed=13)
+    atm = cphot.Atmosphere(**cases.ATMO_STRAIGHT)
+    run = {**RUN_BATCH, "seed": 8}
+    det, S, bins, cnt = _setup(seg, offs, geom, run, atm)
+    ref_det = cphot.make_detector(atm, **run, block_size=bs, lds_hist=0)
+    cphot.propagate(S, ref_det, bins, None, cnt)
+    torch.cuda.synchronize()
+    ref_b, ref_c = bins.clone(), cnt.clone()
+    assert int(ref_c[7]) > 10_000
+    for window in (0, 9, 16, 40):
+        for grid in (0, 7, 1024):
+            d = cphot.make_detector(atm, **run, block_size=bs, grid_blocks=grid, lds_hist=1, hist_window=window)
+            bins.zero_()
+            cnt.zero_()
+            cphot.propagate(S, d, bins, None, cnt)
+            torch.cuda.synchronize()
+            assert torch.equal(bins, ref_b), (window, grid)
+            assert torch.equal(cnt, ref_c), (window, grid)
+
+
+def test_lds_window_f64_and_large_single_grid():
+    """One shower on a grid far larger than LDS (window in the middle), FP64 and
+    u64 bins: identical to global atomics."""
+    sh = W.make_shower(20_000, seed=21, xmax=500.0, zenith_deg=45.0, azimuth_deg=10.0, beta="R")
+    g = np.array([[*sh.core, *sh.axis]])
+    atm = cphot.Atmosphere(**cases.ATMO_STRAIGHT)
+    run = {**RUN_BATCH, "nx": 700, "ny": 500, "cell": 2.0, "bunch": 3, "seed": 9}
+    seg, gg, off = cphot.upload(sh.seg, g)
+    S = cphot.make_segments(seg, gg, off)
+    out = []
+    for dtype in (torch.int64, torch.float64):
+        for lds in (0, 1):
+            d = cphot.make_detector(atm, **run, lds_hist=lds)
+            bins = torch.zeros(700 * 500, dtype=dtype, device="cuda")
+            cphot.propagate(S, d, bins, None, None)
+            torch.cuda.synchronize()
+            out.append(bins.cpu().numpy().astype(np.float64))
+    for b in out[1:]:
+        np.testing.assert_array_equal(b, out[0])
+    assert out[0].sum() > 1e5
