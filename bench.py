@@ -43,6 +43,23 @@ SEGMENT_BYTES = 32.0
 
 METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density error"
 
+# HBM bytes per launch of the exact telescope kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# scaled by a plain copy's factors (2.00, 1.00); valid only for the kernel sources they were
+# taken on (sha256 prefixes), else the roofline's traffic is reported as null.
+TRAFFIC_BYTES = 33.15e6 + 4.61e6
+TRAFFIC_SOURCES = {"cphot_kernels.hip": "e87f6e1f1717f548", "cphot_device.h": "c4233a688074585e",
+                   "cphot_internal.h": "445fcc8e0fb39e77"}
+
+
+def traffic_if_current():
+    import hashlib
+    for name, want in TRAFFIC_SOURCES.items():
+        path = os.path.join(ROOT, "paper_2405_04229_amd", "csrc", name)
+        with open(path, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != want:
+                return None
+    return TRAFFIC_BYTES
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -167,11 +184,35 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
     det_l = cphot.make_detector(atm, **{**run, "transport": "straight"})
     ms_l, _, b_l, _ = run_path(det_l)
     photons = float(c_s[3]) * run["bunch"]
+
+    def grid_density(S_, geom_, grid_run):
+        """Exact vs surrogate vs straight line on a ground grid (same photons)."""
+        out = {}
+        for name in ("layered", "surrogate", "straight"):
+            d = cphot.make_detector(atm, **{**grid_run, "transport": name},
+                                    surrogate=sur if name == "surrogate" else None)
+            b = torch.zeros(grid_run["nx"] * grid_run["ny"], dtype=torch.int64, device="cuda")
+            cphot.propagate(S_, d, b, None, None, stream=stream)
+            out[name] = b.cpu().numpy()
+        return {"surrogate": density_error(out["surrogate"], out["layered"]),
+                "straight_line": density_error(out["straight"], out["layered"]),
+                "photons": float(out["layered"].sum())}
+
+    grid_run = dict(detector="grid", spectrum="frank_tamm", bunch=5, h_obs=2200.0, nx=100, ny=100, cell=10.0,
+                    seed=2)
+    tele_grid = grid_density(S, geom, grid_run)
+    tiny = W.workload_tiny_vertical("R")
+    tg = np.array([[*tiny.core, *tiny.axis]])
+    ts, tgg, toff = cphot.upload(tiny.seg, tg)
+    tiny_grid = grid_density(cphot.make_segments(ts, tgg, toff), tg,
+                             {**W.RUN_TINY, "spectrum": "frank_tamm", "bunch": 1, "seed": 1})
     return {
         "value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
         "speedup_vs_exact": exact_ms / ms,
         "density_error_vs_exact": density_error(b_s, exact_bins),
         "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0),
+        "grid_10m_same_shower": tele_grid,
+        "tiny_vertical_shower_grid": tiny_grid,
         "straight_line_without_correction": {"ms_per_step": ms_l,
                                              "density_error_vs_exact": density_error(b_l, exact_bins)},
         "network": "5-64-64-4 ReLU, bf16 weights on MFMA 16x16x32, FP32 accumulate",
@@ -363,7 +404,8 @@ def main():
     slots = n_seg * SLOTS_PER_SEGMENT + records * (SLOTS_PER_RECORD_BASE + SLOTS_PER_LAYER_CROSSING * mean_cross)
     achieved = slots / (kern_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
-                "unit": "Tlane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": None,
+                "unit": "Tlane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": traffic_if_current(),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                 "kernel": "k_propagate<256,LAYERED,SPHERES,PROPAGATE>", "kernel_ms": kern_ms,
                 "algorithmic_slots_per_launch": slots, "mean_layer_crossings": mean_cross,
                 "hbm_gbps_algorithmic": n_seg * SEGMENT_BYTES / (kern_ms * 1e-3) / 1e9}
