@@ -458,7 +458,8 @@ static int refract_or_reflect(double* dir, const double* N, double n1, double n2
 
 /* Distance along dir from pos to the sphere of radius r about C, first
  * crossing ahead (inward when `inward`), or -1 if there is none. Written as
- * c / (-b + sqrt(b^2 - c)) where the plain root would cancel. */
+ * c / (-b + sqrt(b^2 - c)) where the plain root would cancel. A point on (or,
+ * by rounding, just inside) the sphere and moving inward crosses it at once. */
 static double to_sphere(const double* pos, const double* dir, const double* C, double r, int inward) {
   double q[3] = {pos[0] - C[0], pos[1] - C[1], pos[2] - C[2]};
   double b = dot3(q, dir);
@@ -469,7 +470,8 @@ static double to_sphere(const double* pos, const double* dir, const double* C, d
   if (disc < 0.0) return -1.0;
   double sq = sqrt(disc);
   if (inward) {
-    if (!(b < 0.0) || !(c > 0.0)) return -1.0;
+    if (!(b < 0.0)) return -1.0;
+    if (!(c > 0.0)) return 0.0;
     return c / (-b + sq);
   }
   /* outward from inside (c < 0): the positive root */
@@ -937,6 +939,60 @@ void orc_surrogate_targets(const orc_atmo* A, int64_t n, const double* X, double
     y[1] = -ox * sin(phi) + oy * cos(phi);
     y[2] = optical - s_straight;
     y[3] = -tau;
+  }
+}
+
+/* Targets of the curved-Earth surrogate (Sec. 3.3.4 shells). By the spherical
+ * symmetry a photon is started at height h_e above the Earth point below it,
+ * P = (0, 0, h_e), with local zenith angle acos(ct) and azimuth phi. The exact
+ * shell walk is compared with the straight chord from P to the same
+ * observation sphere R + h_obs:
+ *   y0 = (psi - psi_chord) (R + h_obs)   extra ground distance along the azimuth
+ *                                        (psi: central angle swept),
+ *   y1 = offset of the arrival point across the vertical plane of the start
+ *        direction (zero by symmetry),
+ *   y2 = (path length - chord length) + sum (n - 1) l   optical path excess,
+ *   y3 = -tau.
+ * A sample that does not reach the observation sphere gets NaN targets. */
+void orc_surrogate_targets_curved(const orc_atmo* A, int64_t n, const double* X, double* Y) {
+  const orc_atmo_params* p = &A->p;
+  const double Re = p->earth_radius;
+  const double C[3] = {0.0, 0.0, -Re};
+  for (int64_t j = 0; j < n; ++j) {
+    const double* x = X + 5 * j;
+    double h_e = x[0], ct = x[1], phi = x[2], lam = x[3], h_obs = x[4];
+    double st = sqrt(1.0 - ct * ct);
+    double u[3] = {st * cos(phi), st * sin(phi), -ct};
+    int kbin = (int)floor((lam - p->lam_min) / (p->lam_max - p->lam_min) * p->n_lam);
+    if (kbin < 0) kbin = 0;
+    if (kbin > p->n_lam - 1) kbin = p->n_lam - 1;
+    orc_run R;
+    memset(&R, 0, sizeof(R));
+    R.h_obs = h_obs;
+    path_state ps;
+    memset(&ps, 0, sizeof(ps));
+    ps.pos[2] = h_e;
+    for (int q = 0; q < 3; ++q) ps.dir[q] = u[q];
+    const double axis[3] = {0.0, 0.0, -1.0};
+    double* y = Y + 4 * j;
+    double P[3] = {0.0, 0.0, h_e};
+    double s_ch = to_sphere(P, u, C, Re + h_obs, 1);
+    if (!curved_walk(A, &R, kbin, axis, &ps) || !(s_ch >= 0.0)) {
+      y[0] = y[1] = y[2] = y[3] = NAN;
+      continue;
+    }
+    double q0[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
+    double q1[3] = {ps.pos[0] - C[0], ps.pos[1] - C[1], ps.pos[2] - C[2]};
+    double qs[3] = {P[0] + s_ch * u[0] - C[0], P[1] + s_ch * u[1] - C[1], P[2] + s_ch * u[2] - C[2]};
+    double c1[3] = {q0[1] * q1[2] - q0[2] * q1[1], q0[2] * q1[0] - q0[0] * q1[2], q0[0] * q1[1] - q0[1] * q1[0]};
+    double cs[3] = {q0[1] * qs[2] - q0[2] * qs[1], q0[2] * qs[0] - q0[0] * qs[2], q0[0] * qs[1] - q0[1] * qs[0]};
+    double psi = atan2(sqrt(dot3(c1, c1)), dot3(q0, q1));
+    double psi_s = atan2(sqrt(dot3(cs, cs)), dot3(q0, qs));
+    double en[3] = {-sin(phi), cos(phi), 0.0};
+    y[0] = (psi - psi_s) * (Re + h_obs);
+    y[1] = (q1[0] - qs[0]) * en[0] + (q1[1] - qs[1]) * en[1] + (q1[2] - qs[2]) * en[2];
+    y[2] = (ps.len - s_ch) + ps.opt;
+    y[3] = -ps.tau;
   }
 }
 

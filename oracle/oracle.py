@@ -116,6 +116,7 @@ def lib():
             L.orc_surrogate_inputs.argtypes = [C.c_void_p, C.c_uint64, P(C.c_double), P(C.c_double), C.c_int64,
                                                C.c_int64, P(C.c_double)]
             L.orc_surrogate_targets.argtypes = [C.c_void_p, C.c_int64, P(C.c_double), P(C.c_double)]
+            L.orc_surrogate_targets_curved.argtypes = [C.c_void_p, C.c_int64, P(C.c_double), P(C.c_double)]
             L.orc_curved_ray.argtypes = [C.c_void_p, C.c_double, P(C.c_double), P(C.c_double), P(C.c_double),
                                          P(C.c_double), C.c_int]
             L.orc_curved_ray.restype = C.c_int
@@ -304,11 +305,14 @@ def surrogate_inputs(atm: Atmosphere, seed, lo, hi, first, n):
     return X
 
 
-def surrogate_targets(atm: Atmosphere, X):
-    """Exact layered targets [n, 4] = (dx, dy, optical path excess, log T) for inputs X [n, 5]."""
+def surrogate_targets(atm: Atmosphere, X, geometry="planar"):
+    """Exact targets [n, 4] for inputs X [n, 5]: planar layers (landing offset
+    along / across the azimuth, optical path excess, log T) or curved shells
+    (extra ground distance along / across the azimuth, optical path excess, log T)."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     Y = np.zeros((X.shape[0], 4))
-    lib().orc_surrogate_targets(atm.handle, X.shape[0], _ptr(X, C.c_double), _ptr(Y, C.c_double))
+    fn = lib().orc_surrogate_targets if geometry == "planar" else lib().orc_surrogate_targets_curved
+    fn(atm.handle, X.shape[0], _ptr(X, C.c_double), _ptr(Y, C.c_double))
     return Y
 
 

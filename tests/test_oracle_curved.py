@@ -134,3 +134,15 @@ def test_curved_conservation_and_thread_invariance():
     assert int(b1.sum()) == int(c1[8]) == 2 * int(c1[7])
     sc = O.segment_counts(atm, run, sh.seg)
     assert int(c1[3]) == int(sc["n"].sum() + sc["nf"].sum())
+
+
+@pytest.mark.parametrize("zen", [0.0, 35.0, 70.0])
+def test_start_on_a_shell_boundary(zen):
+    """A photon emitted exactly on a shell boundary and moving down crosses it at
+    once: it lands where a start a micrometre higher lands."""
+    atm = _atm()
+    u = _dir(zen, 20.0)
+    ok0, end0, _ = O.curved_ray(atm, 2200.0, [0.0, 0.0, 12000.0], u)
+    ok1, end1, _ = O.curved_ray(atm, 2200.0, [0.0, 0.0, 12000.0 + 1e-6], u)
+    assert ok0 and ok1
+    np.testing.assert_allclose(end0, end1, atol=1e-5)

@@ -131,3 +131,85 @@ def test_mlp_constant_network():
     X = np.column_stack([np.linspace(lo, hi, 7) for lo, hi in zip(LO, HI)])
     y = mlp.forward(theta, X, LO, HI, mean=[10, 20, 30, 40], std=[2, 2, 2, 2])
     np.testing.assert_allclose(y, np.tile([12, 16, 31, 46], (7, 1)))
+
+
+# ---------------------------------------------------------------------------- curved shells
+
+def _chord(re, h_e, h_obs, ct):
+    """Straight chord from height h_e at local zenith cosine ct to the sphere
+    re + h_obs, in 50-digit decimal arithmetic."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    r0, r1, c = Decimal(re) + Decimal(h_e), Decimal(re) + Decimal(h_obs), Decimal(ct)
+    return float(r0 * c - (r0 * r0 * c * c - (r0 * r0 - r1 * r1)).sqrt())
+
+
+def test_curved_targets_homogeneous_medium():
+    """Shells of one refractive index bend nothing: zero extra ground distance,
+    optical path excess = (n - 1) x chord, and the optical depth is the sum of
+    each shell's extinction times the chord's length inside that shell."""
+    re = 6.371e6
+    hom = O.Atmosphere(profile="homogeneous", delta0=2e-4, h_top=25000.0, n_layers=100, n_lam=16,
+                       aer_tau350=0.1, aer_H=1500.0, earth_radius=re)
+    d, ext = hom.layer_tables()
+    assert np.ptp(d) == 0.0
+    X = O.surrogate_inputs(hom, 11, [2500.0, 0.4, -math.pi, 300.0, 1000.0], HI, 0, 300)
+    Y = O.surrogate_targets(hom, X, "curved")
+    dh = 250.0
+    for x, y in zip(X, Y):
+        h_e, ct, h_obs = x[0], x[1], x[4]
+        s = _chord(re, h_e, h_obs, ct)
+        k = int((x[3] - 300.0) / 300.0 * 16)
+        assert abs(y[0]) < 1e-6 and abs(y[1]) < 1e-6
+        assert y[2] == pytest.approx(2e-4 * s, rel=1e-7, abs=1e-7)
+        # distance along the chord from the start down to radius re + h
+        r0, s0 = re + h_e, math.sqrt(1.0 - ct * ct)
+        along = lambda h: r0 * ct - math.sqrt((re + h) ** 2 - (r0 * s0) ** 2)
+        tau = 0.0
+        for layer in range(int(h_obs // dh), min(int(h_e // dh), 99) + 1):
+            lo_, hi_ = max(layer * dh, h_obs), min((layer + 1) * dh, h_e)
+            tau += ext[layer, k] * (along(lo_) - along(hi_))
+        assert -y[3] == pytest.approx(tau, rel=1e-8)
+
+
+def test_curved_targets_flat_earth_limit(atm):
+    """With an Earth radius of 1e12 m the shells are planar layers: the curved
+    targets reduce to the planar ones."""
+    flat = O.Atmosphere(**{**cases.ATMO_LAYERED, "earth_radius": 1e12})
+    X = O.surrogate_inputs(flat, 12, LO, HI, 0, 400)
+    # keep clear of layer boundaries, where the planar and spherical walks may
+    # take a different layer sequence for the same start
+    dh = 250.0
+    m = lambda h: np.abs(h / dh - np.round(h / dh)) * dh
+    X = X[(m(X[:, 0]) > 0.05) & (m(X[:, 4]) > 0.05)]
+    Yc = O.surrogate_targets(flat, X, "curved")
+    Yp = O.surrogate_targets(flat, X, "planar")
+    # what is left of the curvature: the sphere sags by x^2 / 2R below the plane
+    # over the horizontal span x (2e-4 m at 20 km), which moves lengths by about as
+    # much; and FP64 resolves positions 1e12 m from the centre to 1.2e-4 m
+    span = (X[:, 0] - X[:, 4]) * np.sqrt(1.0 - X[:, 1] ** 2) / X[:, 1]
+    sag = span ** 2 / (2.0 * 1e12)
+    ulp = np.spacing(1e12)
+    tol = 4.0 * sag / X[:, 1] + 8.0 * ulp
+    assert np.all(np.abs(Yc[:, 0] - Yp[:, 0]) <= tol)
+    assert np.all(np.abs(Yc[:, 2] - Yp[:, 2]) <= tol)
+    assert np.median(np.abs(Yc[:, 0] - Yp[:, 0])) < 1e-6
+    np.testing.assert_allclose(Yc[:, 3], Yp[:, 3], rtol=1e-6)
+    assert np.abs(Yc[:, 1]).max() < 1e-6
+
+
+def test_curved_targets_earth_curvature_effect(atm):
+    """On the real Earth the same photon bends a little more than over planar
+    layers (the local vertical turns under it): the extra ground distance keeps
+    its sign, and the curvature correction grows with zenith angle."""
+    X = np.array([[12000.0, ct, 0.3, 405.46875, 2200.0] for ct in (0.95, 0.8, 0.6, 0.45)])
+    Yc = O.surrogate_targets(atm, X, "curved")
+    Yp = O.surrogate_targets(atm, X, "planar")
+    assert np.all(np.sign(Yc[:, 0]) == np.sign(Yp[:, 0]))
+    rel = np.abs(Yc[:, 0] - Yp[:, 0]) / np.abs(Yp[:, 0])
+    assert np.all(np.diff(rel) > 0) and rel[-1] < 0.1
+
+
+def test_curved_targets_nan_when_the_sphere_is_missed(atm):
+    X = np.array([[20000.0, 0.01, 0.0, 405.46875, 2200.0]])
+    assert np.all(np.isnan(O.surrogate_targets(atm, X, "curved")))
