@@ -15,8 +15,9 @@ The same JSON line carries:
   the exact tracer (same photons) and the straight line's for comparison;
 - batched: 256 showers of uneven size in one captured launch per step, launch
   shape and bunch picked by the autotuner;
-- inclined (with --inclined): one 1e7-segment chunk of the large inclined
-  shower, curved Earth, Cherenkov + fluorescence, FP64 bins.
+- inclined: the large inclined shower (curved Earth, Cherenkov + fluorescence,
+  FP64 bins): one 1e7-segment chunk resident in HBM, then the whole 1e8-segment
+  shower streamed from host memory in 1e7-segment chunks.
 """
 import argparse
 import json
@@ -81,14 +82,18 @@ def time_steps(torch, step, steps, warmup, stream):
 
 
 def density_error(s, e, min_count=1000):
-    """Worst relative error over bins with >= min_count exact photons, and the
-    global L1 error sum|s - e| / sum e."""
+    """Worst relative error over bins with >= min_count exact photons (and, as the
+    statistical resolution of a 1000-photon bin is itself ~1 %, over bins with
+    >= 10 x min_count), and the global L1 error sum|s - e| / sum e."""
     s = np.asarray(s, dtype=np.float64).ravel()
     e = np.asarray(e, dtype=np.float64).ravel()
-    m = e >= min_count
-    worst = float(np.max(np.abs(s[m] - e[m]) / e[m])) if m.any() else None
-    return {"worst_bin": worst, "l1": float(np.abs(s - e).sum() / max(e.sum(), 1.0)), "bins_compared": int(m.sum()),
-            "min_count": min_count}
+    out = {"l1": float(np.abs(s - e).sum() / max(e.sum(), 1.0))}
+    for key, mc in (("", min_count), ("_10x", 10 * min_count)):
+        m = e >= mc
+        out["worst_bin" + key] = float(np.max(np.abs(s[m] - e[m]) / e[m])) if m.any() else None
+        out["bins_compared" + key] = int(m.sum())
+    out["min_count"] = min_count
+    return out
 
 
 def cpu_baseline(sh, run, atmo, target_s=12.0):
@@ -198,7 +203,7 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
                 "straight_line": density_error(out["straight"], out["layered"]),
                 "photons": float(out["layered"].sum())}
 
-    grid_run = dict(detector="grid", spectrum="frank_tamm", bunch=5, h_obs=2200.0, nx=100, ny=100, cell=10.0,
+    grid_run = dict(detector="grid", spectrum="frank_tamm", bunch=1, h_obs=2200.0, nx=100, ny=100, cell=10.0,
                     seed=2)
     tele_grid = grid_density(S, geom, grid_run)
     tiny = W.workload_tiny_vertical("R")
@@ -295,8 +300,9 @@ def bench_batched(torch, cphot, W, args, stream):
 
 
 def bench_inclined(torch, cphot, W, args, stream):
-    """One 1e7-segment chunk of the large inclined shower through the curved
-    atmosphere, Cherenkov + fluorescence, FP64 bins on a 1000 x 1000 grid."""
+    """The large inclined shower through the curved atmosphere, Cherenkov +
+    fluorescence, FP64 bins on a 1000 x 1000 grid: chunk 0 (1e7 segments) resident
+    in HBM with an autotuned shape, then all chunks streamed from host memory."""
     t0 = time.perf_counter()
     sh = W.workload_inclined_chunk(0, beta=args.beta)
     log(f"inclined chunk generated in {time.perf_counter() - t0:.1f} s")
@@ -326,11 +332,33 @@ def bench_inclined(torch, cphot, W, args, stream):
     ms, kern = time_steps(torch, step, max(3, args.steps // 4), 1, stream)
     c = cnt.cpu().numpy()
     photons = float(c[3]) * run["bunch"]
-    return {"value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
-            "segments": sh.n, "records_per_step": float(c[3]), "fluorescence_records": float(c[10]),
-            "tuning": {**tune, "tune_s": tune_s},
-            "workload": "chunk 0 of the 1e8-segment inclined shower: zenith 60 deg, Xmax 600, "
-                        "dE/dx U[0.1,2] MeV/m, curved Earth, 1000x1000 grid of 10 m, FP64 bins"}
+    out = {"value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
+           "segments": sh.n, "records_per_step": float(c[3]), "fluorescence_records": float(c[10]),
+           "tuning": {**tune, "tune_s": tune_s},
+           "workload": "chunk 0 of the 1e8-segment inclined shower: zenith 60 deg, Xmax 600, "
+                       "dE/dx U[0.1,2] MeV/m, curved Earth, 1000x1000 grid of 10 m, FP64 bins, inputs in HBM"}
+    del S, seg
+    if args.inclined_chunks > 0:
+        chunks = [sh] + [W.workload_inclined_chunk(c, beta=args.beta) for c in range(1, args.inclined_chunks)]
+        streamer = cphot.Streamer(sh.n)
+        bins.zero_()
+        cnt.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for ch in chunks:
+            streamer.run(ch.seg, g, det, bins, None, cnt, first_id=ch.first_id, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        c = cnt.cpu().numpy()
+        streamer.close()
+        out["streamed"] = {"value": float(c[3]) * run["bunch"] / dt, "unit": "photons/s", "seconds": dt,
+                           "segments": int(sum(ch.n for ch in chunks)), "chunks": len(chunks),
+                           "records": float(c[3]), "fluorescence_records": float(c[10]),
+                           "photons_binned": float(c[8]),
+                           "note": "host-resident segments, pinned double-buffered copies overlapped with "
+                                   "propagation (PCIe-inclusive)"}
+        log(f"inclined streamed: {out['streamed']['value']:.3e} photons/s over {len(chunks)} chunks")
+    return out
 
 
 def main():
@@ -342,7 +370,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--inclined", action="store_true", help="also time one chunk of the inclined workload")
+    ap.add_argument("--no-inclined", action="store_true")
+    ap.add_argument("--inclined-chunks", type=int, default=10,
+                    help="chunks of 1e7 segments streamed from host memory (0: only the resident chunk)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--train-steps", type=int, default=20_000)
     ap.add_argument("--batch-showers", type=int, default=256)
@@ -429,7 +459,7 @@ def main():
         out["batched"] = bench_batched(torch, cphot, W, args, stream)
         log(f"batched: {out['batched']['value']:.3e} photons/s")
         torch.cuda.empty_cache()
-    if args.inclined:
+    if not args.no_inclined:
         out["inclined"] = bench_inclined(torch, cphot, W, args, stream)
         log(f"inclined: {out['inclined']['value']:.3e} photons/s")
     if not args.no_cpu_baseline:

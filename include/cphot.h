@@ -308,6 +308,42 @@ typedef struct {
 int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
                    const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, cphot_tuning* best, void* stream);
 
+/* ---------------------------------------------------------------- streaming from host memory
+ * A segment set too large to keep in device memory at once (the thesis feeds the
+ * photon stage chunk by chunk from the shower simulation, Sec. 5.1, 5.4) is read
+ * from host memory in chunks: each chunk is copied host -> pinned staging -> device
+ * on the streamer's own copy stream while the previous chunk propagates on the
+ * caller's stream; chunk c gets first_id + c * chunk_segments, so the photons are
+ * those of one cphot_propagate over the whole set. Bins accumulate across chunks.
+ *
+ * cphot_streamer_create allocates two device chunk buffers and two pinned host
+ * staging buffers of `chunk_segments` segments (36 B each with dE/dx) on the
+ * current device; the handle is used on that device by one host thread at a
+ * time. Errors: INVALID_ARG (chunk_segments < 1), OUT_OF_MEMORY, HIP. */
+typedef struct cphot_streamer cphot_streamer;
+
+/* Host-resident segments of one shower. */
+typedef struct {
+  const float *x0, *y0, *z0, *x1, *y1, *z1, *beta, *charge; /* host float32 [n] */
+  const float* dedx;        /* host float32 [n] or NULL */
+  int64_t n;
+  int64_t first_id;
+  const double* shower_geom; /* device float64 [5]: core x, core y, axis unit vector */
+} cphot_host_segments;
+
+int cphot_streamer_create(int64_t chunk_segments, cphot_streamer** out);
+
+/* Propagates all of `host` with `det` into `out` (accumulating), enqueueing the
+ * kernels on `stream`. Returns once the last chunk has been copied to the device
+ * and its propagation enqueued (the host arrays may then be reused); the caller
+ * synchronises `stream` before reading `out`. Argument checks as
+ * cphot_propagate, done for the whole set before the first copy. Errors:
+ * INVALID_ARG, UNSUPPORTED (several showers), HIP. */
+int cphot_streamer_run(cphot_streamer* s, const cphot_host_segments* host, const cphot_detector* det,
+                       cphot_bins* out, void* stream);
+
+void cphot_streamer_destroy(cphot_streamer* s);
+
 /* ---------------------------------------------------------------- transport surrogate
  * A network 5 -> 64 -> 64 -> 4 (ReLU hidden units, linear output, bf16 weights on
  * the matrix cores with FP32 accumulation) that maps a photon's (emission height

@@ -77,6 +77,11 @@ class Tuning(C.Structure):
                 ("photons_per_s", C.c_double)]
 
 
+class HostSegments(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in ("x0", "y0", "z0", "x1", "y1", "z1", "beta", "charge", "dedx")] + [
+        ("n", C.c_int64), ("first_id", C.c_int64), ("shower_geom", C.c_void_p)]
+
+
 class Bins(C.Structure):
     _fields_ = [("bins", C.c_void_p), ("bins_dtype", C.c_int32), ("reserved0", C.c_int32),
                 ("bins_capacity", C.c_int64), ("time_hist", C.c_void_p), ("time_capacity", C.c_int64),
@@ -132,6 +137,11 @@ def lib():
             L.cphot_autotune.argtypes = [C.POINTER(Segments), C.POINTER(Detector), C.POINTER(Bins), P, C.c_int32,
                                          C.c_int32, C.POINTER(Tuning), P]
             L.cphot_autotune.restype = C.c_int
+            L.cphot_streamer_create.argtypes = [C.c_int64, C.POINTER(C.c_void_p)]
+            L.cphot_streamer_create.restype = C.c_int
+            L.cphot_streamer_run.argtypes = [P, C.POINTER(HostSegments), C.POINTER(Detector), C.POINTER(Bins), P]
+            L.cphot_streamer_run.restype = C.c_int
+            L.cphot_streamer_destroy.argtypes = [P]
             for fn in ("create", "make_training_set", "fit_normalization", "train", "gradient", "forward",
                        "get_params", "set_params"):
                 getattr(L, "cphot_surrogate_" + fn).restype = C.c_int
@@ -280,6 +290,50 @@ def propagate(seg: Segments, det: Detector, bins, time_hist=None, counters=None,
     """Accumulates into `bins`, `time_hist` and `counters` (see make_bins)."""
     b = make_bins(bins, time_hist, counters)
     _check("cphot_propagate", lib().cphot_propagate(C.byref(seg), C.byref(det), C.byref(b), _stream_ptr(stream)))
+
+
+class Streamer:
+    """Chunked propagation of host-resident segments (cphot_streamer_*): copies of
+    chunk c + 1 overlap the propagation of chunk c."""
+
+    def __init__(self, chunk_segments: int):
+        h = C.c_void_p()
+        _check("cphot_streamer_create", lib().cphot_streamer_create(int(chunk_segments), C.byref(h)))
+        self._h = h
+
+    def run(self, seg_np: dict, geom, det: Detector, bins, time_hist=None, counters=None, first_id=0, stream=None):
+        """`seg_np`: dict of host float32 arrays (x0..charge, optional dedx); `geom`:
+        float64 CUDA tensor [1, 5]. Accumulates into the outputs."""
+        import numpy as np
+        import torch
+        cols = {}
+        hs = HostSegments()
+        n = int(np.asarray(seg_np["x0"]).shape[0])
+        for f in SEGMENT_FIELDS + ("dedx",):
+            if f == "dedx" and seg_np.get("dedx") is None:
+                continue
+            a = np.ascontiguousarray(seg_np[f], dtype=np.float32)
+            if a.shape[0] != n:
+                raise ValueError(f"segment field {f} has length {a.shape[0]}, expected {n}")
+            cols[f] = a
+            setattr(hs, f, a.ctypes.data)
+        hs.n = n
+        hs.first_id = int(first_id)
+        if not isinstance(geom, torch.Tensor) or tuple(geom.shape) != (1, 5):
+            raise ValueError("geom must be a [1, 5] float64 CUDA tensor")
+        hs.shower_geom = _dptr(geom, torch.float64, "geom")
+        b = make_bins(bins, time_hist, counters)
+        _check("cphot_streamer_run", lib().cphot_streamer_run(self._h, C.byref(hs), C.byref(det), C.byref(b),
+                                                               _stream_ptr(stream)))
+        del cols  # copied into pinned staging before run returns
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.cphot_streamer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 class Step:

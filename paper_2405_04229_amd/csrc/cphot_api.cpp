@@ -573,6 +573,122 @@ void cphot_step_destroy(cphot_step* s) {
   delete s;
 }
 
+// ---------------------------------------------------------------- streamer
+
+struct cphot_streamer {
+  int64_t chunk = 0;
+  int dev = 0;
+  float* dbuf[2] = {nullptr, nullptr};   // 9 columns of `chunk` floats each
+  float* hbuf[2] = {nullptr, nullptr};   // pinned staging, same layout
+  hipStream_t copy = nullptr;
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  hipEvent_t done[2] = {nullptr, nullptr};
+};
+
+void cphot_streamer_destroy(cphot_streamer* s) {
+  if (!s) return;
+  for (int b = 0; b < 2; ++b) {
+    if (s->done[b]) (void)hipEventSynchronize(s->done[b]);
+    if (s->copied[b]) (void)hipEventSynchronize(s->copied[b]);
+  }
+  for (int b = 0; b < 2; ++b) {
+    if (s->dbuf[b]) (void)hipFree(s->dbuf[b]);
+    if (s->hbuf[b]) (void)hipHostFree(s->hbuf[b]);
+    if (s->copied[b]) (void)hipEventDestroy(s->copied[b]);
+    if (s->done[b]) (void)hipEventDestroy(s->done[b]);
+  }
+  if (s->copy) (void)hipStreamDestroy(s->copy);
+  delete s;
+}
+
+int cphot_streamer_create(int64_t chunk_segments, cphot_streamer** out) {
+  if (!out) return fail(CPHOT_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (chunk_segments < 1 || chunk_segments > (int64_t(1) << 31))
+    return fail(CPHOT_ERR_INVALID_ARG, "chunk_segments must be in [1, 2^31]");
+  cphot_streamer* s = new cphot_streamer();
+  s->chunk = chunk_segments;
+  (void)hipGetDevice(&s->dev);
+  const size_t bytes = (size_t)chunk_segments * 9 * sizeof(float);
+  hipError_t e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    e = hipMalloc((void**)&s->dbuf[b], bytes);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->hbuf[b], bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->copied[b], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->done[b], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    cphot_streamer_destroy(s);
+    return e == hipErrorOutOfMemory ? fail(CPHOT_ERR_OUT_OF_MEMORY, "streamer buffers")
+                                    : hip_fail(e, "streamer create");
+  }
+  *out = s;
+  return CPHOT_OK;
+}
+
+int cphot_streamer_run(cphot_streamer* s, const cphot_host_segments* host, const cphot_detector* det,
+                       cphot_bins* out, void* stream) {
+  if (!s || !host || !det || !out) return fail(CPHOT_ERR_INVALID_ARG, "null argument");
+  if (host->n < 0 || host->first_id < 0) return fail(CPHOT_ERR_INVALID_ARG, "negative n or first_id");
+  if (host->n > 0 && (!host->x0 || !host->y0 || !host->z0 || !host->x1 || !host->y1 || !host->z1 ||
+                      !host->beta || !host->charge))
+    return fail(CPHOT_ERR_INVALID_ARG, "null host segment array");
+  if (!host->shower_geom) return fail(CPHOT_ERR_INVALID_ARG, "null shower geometry");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev != s->dev) return fail(CPHOT_ERR_INVALID_ARG, "streamer used on another device than it was made on");
+  const float* cols[9] = {host->x0, host->y0, host->z0, host->x1, host->y1, host->z1, host->beta, host->charge,
+                          host->dedx};
+  const int ncol = host->dedx ? 9 : 8;
+  // validate the whole run once (the same checks as a single call over the set)
+  cphot_segments whole{};
+  whole.x0 = whole.y0 = whole.z0 = whole.x1 = whole.y1 = whole.z1 = whole.beta = whole.charge = s->dbuf[0];
+  whole.dedx = host->dedx ? s->dbuf[0] : nullptr;
+  whole.n = host->n;
+  whole.first_id = host->first_id;
+  whole.n_showers = 1;
+  whole.shower_geom = host->shower_geom;
+  {
+    cphot::KParams p;
+    int rc = fill_params(&whole, det, p, true, out);
+    if (rc) return rc;
+    LaunchShape sh;
+    if ((rc = choose_shape(det, p, cphot::MODE_PROPAGATE, sh))) return rc;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t C = s->chunk;
+  for (int64_t c0 = 0, k = 0; c0 < host->n; c0 += C, ++k) {
+    const int b = (int)(k & 1);
+    const int64_t n = std::min(C, host->n - c0);
+    // staging buffer b is free once its previous copy has finished; device buffer b
+    // once the propagation that read it has finished (the copy stream waits for it)
+    hipError_t e = hipEventSynchronize(s->copied[b]);
+    if (e != hipSuccess) return hip_fail(e, "streamer wait");
+    for (int f = 0; f < ncol; ++f) std::memcpy(s->hbuf[b] + (size_t)f * C, cols[f] + c0, (size_t)n * sizeof(float));
+    e = hipStreamWaitEvent(s->copy, s->done[b], 0);
+    for (int f = 0; f < ncol && e == hipSuccess; ++f)
+      e = hipMemcpyAsync(s->dbuf[b] + (size_t)f * C, s->hbuf[b] + (size_t)f * C, (size_t)n * sizeof(float),
+                         hipMemcpyHostToDevice, s->copy);
+    if (e == hipSuccess) e = hipEventRecord(s->copied[b], s->copy);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, s->copied[b], 0);
+    if (e != hipSuccess) return hip_fail(e, "streamer copy");
+    cphot_segments seg{};
+    float* d = s->dbuf[b];
+    seg.x0 = d; seg.y0 = d + C; seg.z0 = d + 2 * C; seg.x1 = d + 3 * C; seg.y1 = d + 4 * C; seg.z1 = d + 5 * C;
+    seg.beta = d + 6 * C; seg.charge = d + 7 * C;
+    seg.dedx = host->dedx ? d + 8 * C : nullptr;
+    seg.n = n;
+    seg.first_id = host->first_id + c0;
+    seg.n_showers = 1;
+    seg.shower_geom = host->shower_geom;
+    int rc = cphot_propagate(&seg, det, out, stream);
+    if (rc) return rc;
+    e = hipEventRecord(s->done[b], st);
+    if (e != hipSuccess) return hip_fail(e, "streamer record");
+  }
+  return CPHOT_OK;
+}
+
 // ---------------------------------------------------------------- autotuner
 
 int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
