@@ -337,6 +337,48 @@ def bench_inclined(torch, cphot, W, args, stream):
            "tuning": {**tune, "tune_s": tune_s},
            "workload": "chunk 0 of the 1e8-segment inclined shower: zenith 60 deg, Xmax 600, "
                        "dE/dx U[0.1,2] MeV/m, curved Earth, 1000x1000 grid of 10 m, FP64 bins, inputs in HBM"}
+    if not args.no_surrogate:
+        # the curved-shell surrogate on the same chunk: trained on the GPU, then the
+        # same photons as the exact walk, bins compared cell by cell
+        sur = cphot.Surrogate(W.SURROGATE_CURVED_LO, W.SURROGATE_CURVED_HI, max_batch=4096, init_seed=2,
+                              geometry="curved")
+        t0 = time.perf_counter()
+        X, Y = sur.make_training_set(atm, args.train_samples, seed=1005)
+        sur.fit_normalization(Y)
+        loss = sur.train(X, Y, batch=4096, steps=2 * args.train_steps, lr=3e-3)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        del X, Y
+        exact_bins = None
+
+        def run_with(d):
+            b = torch.zeros(run["nx"] * run["ny"], dtype=torch.float64, device="cuda")
+            k = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+
+            def st(ev):
+                b.zero_()
+                k.zero_()
+                if ev is not None:
+                    ev[0].record(stream)
+                cphot.propagate(S, d, b, None, k, stream=stream)
+                if ev is not None:
+                    ev[1].record(stream)
+
+            ms_, kern_ = time_steps(torch, st, max(3, args.steps // 4), 1, stream)
+            return ms_, kern_, b.cpu().numpy(), k.cpu().numpy()
+
+        _, _, exact_bins, _ = run_with(det)
+        det_s = cphot.make_detector(atm, **{**run, "transport": "surrogate"}, surrogate=sur)
+        ms_s, kern_s, b_s, c_s = run_with(det_s)
+        out["surrogate"] = {"value": float(c_s[3]) * run["bunch"] / (ms_s * 1e-3), "unit": "photons/s",
+                            "ms_per_step": ms_s, "kernel_ms": kern_s, "speedup_vs_exact": ms / ms_s,
+                            "density_error_vs_exact": density_error(b_s, exact_bins),
+                            "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0),
+                            "training": {"samples": args.train_samples, "steps": 2 * args.train_steps,
+                                         "train_s": train_s, "final_loss": float(loss[-100:].mean().item())},
+                            "note": "fluorescence photons beyond 66 deg local zenith are traced exactly"}
+        log(f"inclined surrogate: {out['surrogate']['value']:.3e} photons/s, "
+            f"worst bin {out['surrogate']['density_error_vs_exact']['worst_bin']}")
     del S, seg
     if args.inclined_chunks > 0:
         chunks = [sh] + [W.workload_inclined_chunk(c, beta=args.beta) for c in range(1, args.inclined_chunks)]

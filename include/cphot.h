@@ -363,9 +363,21 @@ typedef struct {
   double in_lo[5];     /* domain box, inputs in the order above; cos zenith in [0, 1] */
   double in_hi[5];
   int32_t max_batch;   /* largest training batch (multiple of 64, <= 2^22) */
-  int32_t reserved0;
+  int32_t geometry;    /* CPHOT_SURROGATE_PLANAR | CPHOT_SURROGATE_CURVED */
   uint64_t init_seed;  /* He-uniform initial weights, zero biases */
 } cphot_surrogate_desc;
+
+/* Surrogate geometry. PLANAR: planar layers, as above. CURVED: spherical shells
+ * of a curved Earth (Sec. 3.3.4); zenith and height are local (angle to the
+ * radial, height above the sphere R), and the outputs, each per metre of the
+ * straight chord L to the sphere R + h_obs, are the extra ground distance
+ * (psi - psi_chord)(R + h_obs) / L of the arrival point along the photon's
+ * azimuth, the offset across it / L (zero by symmetry), the optical path excess
+ * ((path - L) + sum (n - 1) l) / L, and log T / L. A detector with SURROGATE
+ * transport and a CURVED surrogate traces like CURVED transport (ground grid
+ * only), photons outside the domain exactly. */
+#define CPHOT_SURROGATE_PLANAR 0
+#define CPHOT_SURROGATE_CURVED 1
 
 /* Allocate a surrogate on the current device. Synchronous.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP. */
@@ -378,7 +390,9 @@ void cphot_surrogate_destroy(cphot_surrogate* s);
  * inputs drawn uniformly in the domain box (emission height at or above the
  * observation level, a uniformly drawn wavelength bin) from Philox blocks with
  * counters (i low, 0 or 1, i high, 8) keyed by `seed`, targets from the exact
- * layered tracer of `atm` (which must have layers). Asynchronous.
+ * layered tracer of `atm` (which must have layers) for the surrogate's geometry
+ * (CURVED: the shell walk carried in FP64 from a start above the Earth point
+ * (0, 0), compared with the FP64 chord). Asynchronous.
  * Errors: INVALID_ARG (domain outside the atmosphere's layers or band), HIP. */
 int cphot_surrogate_make_training_set(const cphot_surrogate* s, const cphot_atmosphere* atm, int64_t first,
                                       int64_t n, uint64_t seed, float* X, float* Y, void* stream);

@@ -942,17 +942,18 @@ void orc_surrogate_targets(const orc_atmo* A, int64_t n, const double* X, double
   }
 }
 
-/* Targets of the curved-Earth surrogate (Sec. 3.3.4 shells). By the spherical
- * symmetry a photon is started at height h_e above the Earth point below it,
- * P = (0, 0, h_e), with local zenith angle acos(ct) and azimuth phi. The exact
- * shell walk is compared with the straight chord from P to the same
- * observation sphere R + h_obs:
- *   y0 = (psi - psi_chord) (R + h_obs)   extra ground distance along the azimuth
- *                                        (psi: central angle swept),
+/* Targets of the curved-Earth surrogate (Sec. 3.3.4 shells), each per metre of
+ * the straight chord L from the start to the same observation sphere R + h_obs
+ * (the absolute quantities grow with the slant distance; per metre of chord they
+ * stay of one size across zenith angles). By the spherical symmetry a photon is
+ * started at height h_e above the Earth point below it, P = (0, 0, h_e), with
+ * local zenith angle acos(ct) and azimuth phi:
+ *   y0 = (psi - psi_chord) (R + h_obs) / L   extra ground distance along the
+ *                                            azimuth (psi: central angle swept),
  *   y1 = offset of the arrival point across the vertical plane of the start
- *        direction (zero by symmetry),
- *   y2 = (path length - chord length) + sum (n - 1) l   optical path excess,
- *   y3 = -tau.
+ *        direction / L (zero by symmetry),
+ *   y2 = ((path length - L) + sum (n - 1) l) / L   optical path excess,
+ *   y3 = -tau / L.
  * A sample that does not reach the observation sphere gets NaN targets. */
 void orc_surrogate_targets_curved(const orc_atmo* A, int64_t n, const double* X, double* Y) {
   const orc_atmo_params* p = &A->p;
@@ -989,10 +990,10 @@ void orc_surrogate_targets_curved(const orc_atmo* A, int64_t n, const double* X,
     double psi = atan2(sqrt(dot3(c1, c1)), dot3(q0, q1));
     double psi_s = atan2(sqrt(dot3(cs, cs)), dot3(q0, qs));
     double en[3] = {-sin(phi), cos(phi), 0.0};
-    y[0] = (psi - psi_s) * (Re + h_obs);
-    y[1] = (q1[0] - qs[0]) * en[0] + (q1[1] - qs[1]) * en[1] + (q1[2] - qs[2]) * en[2];
-    y[2] = (ps.len - s_ch) + ps.opt;
-    y[3] = -ps.tau;
+    y[0] = (psi - psi_s) * (Re + h_obs) / s_ch;
+    y[1] = ((q1[0] - qs[0]) * en[0] + (q1[1] - qs[1]) * en[1] + (q1[2] - qs[2]) * en[2]) / s_ch;
+    y[2] = ((ps.len - s_ch) + ps.opt) / s_ch;
+    y[3] = -ps.tau / s_ch;
   }
 }
 

@@ -308,7 +308,8 @@ def surrogate_inputs(atm: Atmosphere, seed, lo, hi, first, n):
 def surrogate_targets(atm: Atmosphere, X, geometry="planar"):
     """Exact targets [n, 4] for inputs X [n, 5]: planar layers (landing offset
     along / across the azimuth, optical path excess, log T) or curved shells
-    (extra ground distance along / across the azimuth, optical path excess, log T)."""
+    (extra ground distance along / across the azimuth, optical path excess, log T,
+    each per metre of the straight chord to the observation sphere)."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     Y = np.zeros((X.shape[0], 4))
     fn = lib().orc_surrogate_targets if geometry == "planar" else lib().orc_surrogate_targets_curved

@@ -28,6 +28,7 @@ EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
 DETECTOR = {"grid": 0, "spheres": 1}
 SPECTRUM = {"uniform": 0, "frank_tamm": 1}
 BINS = {"u32": 0, "u64": 1, "f64": 2}
+GEOMETRY = {"planar": 0, "curved": 1}
 COUNTERS = ["segments_in", "segments_skipped", "segments_below_threshold", "records_generated",
             "records_upward", "records_absorbed", "records_outside", "records_binned", "photons_binned",
             "surrogate_fallback", "records_fluorescence"]
@@ -68,7 +69,7 @@ class Detector(C.Structure):
 
 class SurrogateDesc(C.Structure):
     _fields_ = [("in_lo", C.c_double * 5), ("in_hi", C.c_double * 5), ("max_batch", C.c_int32),
-                ("reserved0", C.c_int32), ("init_seed", C.c_uint64)]
+                ("geometry", C.c_int32), ("init_seed", C.c_uint64)]
 
 
 class Tuning(C.Structure):
@@ -425,11 +426,12 @@ class Surrogate:
     """Transport surrogate network (cphot_surrogate_*): training and inference
     run in the library's kernels; tensors are plain device buffers."""
 
-    def __init__(self, lo, hi, max_batch=8192, init_seed=0):
+    def __init__(self, lo, hi, max_batch=8192, init_seed=0, geometry="planar"):
         d = SurrogateDesc()
         d.in_lo[:] = tuple(float(v) for v in lo)
         d.in_hi[:] = tuple(float(v) for v in hi)
         d.max_batch, d.init_seed = int(max_batch), int(init_seed)
+        d.geometry = GEOMETRY[geometry]
         self.desc = d
         h = C.c_void_p()
         _check("cphot_surrogate_create", lib().cphot_surrogate_create(C.byref(d), C.byref(h)))

@@ -113,16 +113,19 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   if (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED &&
       det->transport != CPHOT_TRANSPORT_SURROGATE && det->transport != CPHOT_TRANSPORT_CURVED)
     return fail(CPHOT_ERR_INVALID_ARG, "unknown transport");
-  if (det->transport == CPHOT_TRANSPORT_CURVED && det->detector != CPHOT_DETECTOR_GRID)
+  if (det->transport == CPHOT_TRANSPORT_SURROGATE && !cphot::surrogate_ready(det->surrogate))
+    return fail(CPHOT_ERR_UNSUPPORTED, "surrogate transport needs a surrogate with its normalisation set");
+  const bool curved_sur = det->transport == CPHOT_TRANSPORT_SURROGATE &&
+                          cphot::surrogate_geometry(det->surrogate) == CPHOT_SURROGATE_CURVED;
+  const bool curved = det->transport == CPHOT_TRANSPORT_CURVED || curved_sur;
+  if (curved && det->detector != CPHOT_DETECTOR_GRID)
     return fail(CPHOT_ERR_UNSUPPORTED, "curved transport collects on a ground grid");
-  if (det->transport == CPHOT_TRANSPORT_CURVED && !(d.earth_radius > 1e5 && std::isfinite(d.earth_radius)))
+  if (curved && !(d.earth_radius > 1e5 && std::isfinite(d.earth_radius)))
     return fail(CPHOT_ERR_INVALID_ARG, "curved transport needs the atmosphere's earth_radius");
   if (det->emission & ~(CPHOT_EMIT_CHERENKOV | CPHOT_EMIT_FLUORESCENCE))
     return fail(CPHOT_ERR_INVALID_ARG, "unknown emission bits");
   if ((det->emission & CPHOT_EMIT_FLUORESCENCE) && seg->n > 0 && !seg->dedx)
     return fail(CPHOT_ERR_INVALID_ARG, "fluorescence needs the dedx column");
-  if (det->transport == CPHOT_TRANSPORT_SURROGATE && !cphot::surrogate_ready(det->surrogate))
-    return fail(CPHOT_ERR_UNSUPPORTED, "surrogate transport needs a surrogate with its normalisation set");
   if (det->detector != CPHOT_DETECTOR_GRID && det->detector != CPHOT_DETECTOR_SPHERES)
     return fail(CPHOT_ERR_INVALID_ARG, "unknown detector");
   if (det->spectrum != CPHOT_SPECTRUM_UNIFORM && det->spectrum != CPHOT_SPECTRUM_FRANK_TAMM)
@@ -183,7 +186,7 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   p.earth_radius = d.earth_radius;
   p.h_obs = (float)det->h_obs;
   p.X_obs = d.profile == CPHOT_PROFILE_LINSLEY5 ? (float)depth(d, det->h_obs) : 0.f;
-  p.transport = det->transport;
+  p.transport = curved_sur ? cphot::kTransportCurvedSurrogate : det->transport;
   p.detector = det->detector;
   if (det->transport != CPHOT_TRANSPORT_STRAIGHT) {
     if (d.n_layers < 1) return fail(CPHOT_ERR_INVALID_ARG, "layered transport needs an atmosphere with layers");
@@ -309,6 +312,8 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
 }  // namespace
 
 namespace cphot {
+double atmosphere_earth_radius(const cphot_atmosphere* a) { return a ? a->d.earth_radius : 0.0; }
+
 int atmosphere_layer_view(const cphot_atmosphere* a, const float4** layers, const float2** lambins, int* n_layers,
                           int* n_lam, float* dh, float* lam_min, float* lam_max) {
   if (!a || a->d.n_layers < 1) return CPHOT_ERR_INVALID_ARG;

@@ -188,6 +188,41 @@ __device__ __forceinline__ void layer_walk(const float4* __restrict__ lay, float
 // totally reflected at a boundary where the next shell's D is not positive.
 // The swept central angle is summed in FP64 and the arrival point on the
 // sphere R + h_obs is formed from it in FP64.
+// Point of the sphere R + h_obs reached after sweeping the central angle psi
+// from the emission point P in the plane of the Earth centre and the direction
+// u, moved by `across` metres normal to that plane; in FP64 (the large-radius
+// arithmetic of the curved geometry).
+__device__ __forceinline__ void curved_arrival(double Re, float h_obs, float Px, float Py, float Pz, float ux,
+                                               float uy, float uz, double psi, double across, double& ax,
+                                               double& ay, double& az) {
+  const double dqz = (double)Pz + Re;
+  const double drq = sqrt((double)Px * Px + (double)Py * Py + dqz * dqz);
+  const double dex = Px / drq, dey = Py / drq, dez = dqz / drq;
+  const double dmu = ux * dex + uy * dey + uz * dez;
+  double tx = ux - dmu * dex, ty = uy - dmu * dey, tz = uz - dmu * dez;
+  const double tn = sqrt(tx * tx + ty * ty + tz * tz);
+  if (tn > 0.0) {
+    tx /= tn;
+    ty /= tn;
+    tz /= tn;
+  } else {
+    tx = 1.0;
+    ty = 0.0;
+    tz = 0.0;
+  }
+  double sps, cps;
+  sincos(psi, &sps, &cps);
+  const double robs = Re + (double)h_obs;
+  ax = robs * (cps * dex + sps * tx);
+  ay = robs * (cps * dey + sps * ty);
+  az = robs * (cps * dez + sps * tz) - Re;
+  if (across != 0.0) {  // normal of the plane: e_r x e_t
+    ax += across * (dey * tz - dez * ty);
+    ay += across * (dez * tx - dex * tz);
+    az += across * (dex * ty - dey * tx);
+  }
+}
+
 struct CurvedWalk {
   double ax, ay, az;  // arrival point (core frame)
   float tau, geo, opt;
@@ -317,28 +352,7 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
   w.geo = geo;
   w.opt = opt;
   w.arrived = arrived;
-  // arrival point from the swept central angle, in FP64
-  const double dqz = (double)Pz + Re;
-  const double drq = sqrt((double)Px * Px + (double)Py * Py + dqz * dqz);
-  const double dex = Px / drq, dey = Py / drq, dez = dqz / drq;
-  const double dmu = ux * dex + uy * dey + uz * dez;
-  double tx = ux - dmu * dex, ty = uy - dmu * dey, tz = uz - dmu * dez;
-  const double tn = sqrt(tx * tx + ty * ty + tz * tz);
-  if (tn > 0.0) {
-    tx /= tn;
-    ty /= tn;
-    tz /= tn;
-  } else {
-    tx = 1.0;
-    ty = 0.0;
-    tz = 0.0;
-  }
-  double sps, cps;
-  sincos(psi, &sps, &cps);
-  const double robs = Re + (double)h_obs;
-  w.ax = robs * (cps * dex + sps * tx);
-  w.ay = robs * (cps * dey + sps * ty);
-  w.az = robs * (cps * dez + sps * tz) - Re;
+  curved_arrival(Re, h_obs, Px, Py, Pz, ux, uy, uz, psi, 0.0, w.ax, w.ay, w.az);
 }
 
 }  // namespace cphot

@@ -99,6 +99,10 @@ int atmosphere_layer_view(const cphot_atmosphere* atm, const float4** layers, co
                           int* n_lam, float* dh, float* lam_min, float* lam_max);
 // Inference image of a surrogate and whether its normalisation is set.
 const MlpImage* surrogate_image(const cphot_surrogate* s);
+double atmosphere_earth_radius(const cphot_atmosphere* a);
+int surrogate_geometry(const cphot_surrogate* s);
+// internal transport id: SURROGATE transport with a CURVED surrogate
+constexpr int kTransportCurvedSurrogate = 4;
 bool surrogate_ready(const cphot_surrogate* s);
 
 hipError_t launch_propagate(const KParams& p, int mode, int block_size, int grid_blocks, size_t lds_hist_bytes,

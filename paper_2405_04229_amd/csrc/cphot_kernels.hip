@@ -151,6 +151,10 @@ __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float 
   return p.opt_scale * ((b - a) - (b * b - a * a) / (2.f * t));
 }
 
+// A surrogate record outside the network's domain: its transport is redone by the
+// exact tracer in a separate pass over compacted records.
+constexpr int32_t kStateDeferred = 7;
+
 struct Photon {
   int32_t state, bin, tbin, fallback;
   int32_t ix, iy;  // grid cell
@@ -225,23 +229,72 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
     kb = min(max(kb, 0), p.n_lam - 1);
   }
-  if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED) {
-    if (!(uz < 0.f)) {
-      o.state = 1;
-      return;
-    }
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED || TRANSPORT == kTransportCurvedSurrogate) {
     // height above the sphere R without subtracting R: (x^2 + y^2 + z (2R + z)) / (|P - C| + R)
     const float Rf = (float)p.earth_radius;
     const float qz = Pz + Rf;
     const float rq = sqrtf(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
     const float h0 = fmaf(Px, Px, fmaf(Py, Py, Pz * (2.0f * Rf + Pz))) / (rq + Rf);
+    float ym[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
+    bool use_mlp = false;
+    float c0 = 0.f;  // cos of the local zenith angle (angle between -u and the upward radial)
+    if constexpr (TRANSPORT == kTransportCurvedSurrogate) {
+      const float irq = 1.0f / rq;
+      c0 = -fmaf(ux, Px * irq, fmaf(uy, Py * irq, uz * (qz * irq)));
+      const bool alive = valid && (uz < 0.f) && (h0 >= p.h_obs);
+      float xin[kMlpIn] = {h0, c0, atan2f(uy, ux),
+                           p.lam_min + ((float)kb + 0.5f) * ((p.lam_max - p.lam_min) / (float)p.n_lam), p.h_obs};
+      use_mlp = alive && mlp_in_domain(s_img, xin);
+      if (!use_mlp) {
+#pragma unroll
+        for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
+      }
+      mlp_forward_wave(s_img, xin, ym);
+    }
+    if (!(uz < 0.f)) {
+      o.state = 1;
+      return;
+    }
     if (h0 < p.h_obs) {
       o.state = 3;
       return;
     }
     CurvedWalk cw;
-    curved_walk<NEED_TIME>(s_lay, s_lam[kb], p.dh, p.n_layers, p.h_obs, p.earth_radius, Px, Py, Pz, h0, ux, uy,
-                           uz, axx, axy, axz, cw);
+    if (use_mlp) {
+      // straight chord to the sphere R + h_obs (cancellation-free root), its
+      // central angle, plus the predicted extra ground distance, offset across,
+      // optical path excess and log T (the network predicts them per metre of chord)
+      const float r0 = Rf + h0, r1 = Rf + p.h_obs;
+      const float s0 = sqrtf(fmaxf((1.0f - c0) * (1.0f + c0), 0.f));
+      const float drs = (h0 - p.h_obs) * (r0 + r1);
+      const float rc = r0 * c0;
+      const float s_ch = drs / (rc + sqrtf(fmaf(rc, rc, -drs)));
+      const float xs = s_ch * s0 / r1;
+      const float psi_s = fmaf(xs * xs * (1.0f / 6.0f), xs, xs);
+      const double psi = (double)psi_s + (double)(ym[0] * s_ch) / (double)r1;
+      curved_arrival(p.earth_radius, p.h_obs, Px, Py, Pz, ux, uy, uz, psi, (double)(ym[1] * s_ch), cw.ax, cw.ay,
+                     cw.az);
+      cw.tau = -ym[3] * s_ch;
+      cw.arrived = 1;
+      cw.geo = 0.f;
+      cw.opt = 0.f;
+      if constexpr (NEED_TIME) {
+        // delay = chord (1 - u.a) + excess - (arrival - chord end) . a
+        const float gx = ux - axx, gy = uy - axy, gz = uz - axz;
+        const double ex = (double)Px + (double)s_ch * ux, ey = (double)Py + (double)s_ch * uy,
+                     ez = (double)Pz + (double)s_ch * uz;
+        const float shift = (float)((cw.ax - ex) * axx + (cw.ay - ey) * axy + (cw.az - ez) * axz);
+        cw.geo = fmaf(s_ch * 0.5f, fmaf(gx, gx, fmaf(gy, gy, gz * gz)), -shift);
+        cw.opt = ym[2] * s_ch;
+      }
+    } else {
+      if constexpr (TRANSPORT == kTransportCurvedSurrogate) {
+        o.state = kStateDeferred;  // outside the domain: traced exactly in a compacted pass
+        return;
+      }
+      curved_walk<NEED_TIME>(s_lay, s_lam[kb], p.dh, p.n_layers, p.h_obs, p.earth_radius, Px, Py, Pz, h0, ux, uy,
+                             uz, axx, axy, axz, cw);
+    }
     o.x = (float)cw.ax;
     o.y = (float)cw.ay;
     o.z = (float)cw.az;
@@ -296,6 +349,10 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   float last_delta = 0.f, last_ext = 0.f;
   if constexpr (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT) {
     if (TRANSPORT == CPHOT_TRANSPORT_LAYERED || !use_mlp) {
+      if constexpr (TRANSPORT == CPHOT_TRANSPORT_SURROGATE) {
+        o.state = kStateDeferred;  // outside the domain: traced exactly in a compacted pass
+        return;
+      }
       LayerWalk lw;
       layer_walk<NEED_TIME, false>(s_lay, s_lam[kb], p.dh, min((int)(Pz * p.inv_dh), p.n_layers - 1),
                                    p.obs_layer, Px, Py, Pz, ux, uy, uz, axx, axy, axz, lw);
@@ -310,7 +367,6 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       opt = lw.opt;
       last_delta = lw.last_delta;
       last_ext = lw.last_ext;
-      o.fallback = (TRANSPORT == CPHOT_TRANSPORT_SURROGATE) ? 1 : 0;
     } else {
       // straight line to the observation level plus the predicted correction:
       // landing (dx, dy), optical path excess e and log T; the delay after the
@@ -466,8 +522,12 @@ template <int BS, int TRANSPORT, int DETECTOR, int MODE>
 __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   constexpr bool kTime = (DETECTOR == CPHOT_DETECTOR_SPHERES) || (MODE == MODE_RECORDS);
   constexpr bool kLayers = (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT);
-  constexpr bool kMlp = (TRANSPORT == CPHOT_TRANSPORT_SURROGATE);
+  constexpr bool kMlp = (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == kTransportCurvedSurrogate);
   constexpr bool kSort = kLayers && (MODE != MODE_COUNTS);
+  // exact transport behind a surrogate: records outside the network's domain
+  constexpr int kExact = TRANSPORT == CPHOT_TRANSPORT_SURROGATE     ? CPHOT_TRANSPORT_LAYERED
+                         : TRANSPORT == kTransportCurvedSurrogate ? CPHOT_TRANSPORT_CURVED
+                                                                   : TRANSPORT;
   // per-segment state for the record loop, one slot per segment of the tile:
   // q0 = start point, cos(theta); q1 = end - start, sin(theta); q2 = rotation
   // bisector, depth at the start; q3 = depth change, id low, id high, shower
@@ -482,6 +542,11 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   __shared__ float4 s_lay[kLayers ? kMaxLayers : 1];
   __shared__ float2 s_lam[kLayers ? kMaxLambdaBins : 1];
   __shared__ uint4 s_imgw[kMlp ? sizeof(MlpImage) / 16 : 1];
+  // compaction queue of deferred records (slot, k): at most BS enter per round and
+  // it is drained once it holds BS, so 2 BS entries suffice
+  __shared__ uint16_t s_qlo[kMlp ? 2 * BS : 1];
+  __shared__ uint32_t s_qk[kMlp ? 2 * BS : 1];
+  __shared__ uint32_t s_qn;
   const MlpImage* s_img = reinterpret_cast<const MlpImage*>(s_imgw);
   // Optional LDS window of the grid (record counts of one shower at a time).
   // With it each block walks a contiguous range of tiles, so the window changes
@@ -506,6 +571,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   if (tid == 0) {
     s_win_sh = -1;
     s_since = 0u;
+    s_qn = 0u;
   }
   __syncthreads();
 
@@ -621,20 +687,8 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     // with the surrogate every lane of a wave runs each round (the tail lanes
     // repeat the last record and discard it); otherwise lanes stop at `total`
     const uint32_t rounds_end = kMlp ? ((total + BS - 1) / BS) * BS : total;
-    for (uint32_t base = 0; base + tid < rounds_end; base += BS) {
-      const uint32_t jr = base + tid;
-      const bool valid = jr < total;
-      const uint32_t j = valid ? jr : total - 1;
-      // largest slot lo in [0, BS) with s_off[lo] <= j (offsets never decrease)
-      int lo = 0;
-#pragma unroll
-      for (int step = BS / 2; step >= 1; step >>= 1) lo += (s_off[lo + step] <= j) ? step : 0;
-      const uint32_t k = j - s_off[lo];
-      Photon ph;
-      const float4 r3 = s_q3[lo];
-      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_q0[lo], s_q1[lo], s_q2[lo], r3, s_q4[lo],
-                                        s_axz[lo], s_q5[lo], k, valid, ph);
-      if (!valid) continue;
+    // one record: a parity dump, or counters and bins
+    auto consume = [&](const Photon& ph, int lo, uint32_t k, const float4& r3) {
       if constexpr (MODE == MODE_RECORDS) {
         const uint32_t src = kSort ? s_src[lo] : (uint32_t)lo;
         const int64_t slot_out = p.rec_off[tile * BS + src] + (int64_t)k;
@@ -680,6 +734,59 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
             if (p.n_t > 0) atomicAdd(p.thist + gb * (p.n_t + 1) + ph.tbin, p.bunch);
           }
         }
+      }
+    };
+    for (uint32_t base = 0; base + tid < rounds_end; base += BS) {
+      const uint32_t jr = base + tid;
+      const bool valid = jr < total;
+      const uint32_t j = valid ? jr : total - 1;
+      // largest slot lo in [0, BS) with s_off[lo] <= j (offsets never decrease)
+      int lo = 0;
+#pragma unroll
+      for (int step = BS / 2; step >= 1; step >>= 1) lo += (s_off[lo + step] <= j) ? step : 0;
+      const uint32_t k = j - s_off[lo];
+      Photon ph;
+      const float4 r3 = s_q3[lo];
+      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_q0[lo], s_q1[lo], s_q2[lo], r3, s_q4[lo],
+                                        s_axz[lo], s_q5[lo], k, valid, ph);
+      if constexpr (kMlp) {
+        // wave-level compaction: deferred records take consecutive queue slots
+        // (ballot, prefix count of the lanes below, one LDS atomic per wave)
+        const bool push = valid && ph.state == kStateDeferred;
+        const uint64_t mask = __ballot(push);
+        if (mask) {
+          const int lane = tid & 63;
+          const int leader = __ffsll((unsigned long long)mask) - 1;
+          uint32_t wbase = 0;
+          if (lane == leader) wbase = atomicAdd(&s_qn, (uint32_t)__popcll(mask));
+          wbase = __shfl(wbase, leader, 64);
+          if (push) {
+            const uint32_t pos = wbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            s_qlo[pos] = (uint16_t)lo;
+            s_qk[pos] = k;
+          }
+        }
+        if (valid && !push) consume(ph, lo, k, r3);
+        // drain the queue with full waves once it holds a round's worth, and at the end
+        __syncthreads();
+        const uint32_t qn = s_qn;
+        if (qn >= BS || (base + BS >= rounds_end && qn > 0)) {
+          for (uint32_t q = tid; q < qn; q += BS) {
+            const int qlo = s_qlo[q];
+            const uint32_t qk = s_qk[q];
+            const float4 q3 = s_q3[qlo];
+            Photon pe;
+            trace<kExact, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3, s_q4[qlo],
+                                           s_axz[qlo], s_q5[qlo], qk, true, pe);
+            pe.fallback = 1;
+            consume(pe, qlo, qk, q3);
+          }
+          __syncthreads();
+          if (tid == 0) s_qn = 0u;
+          __syncthreads();
+        }
+      } else {
+        if (valid) consume(ph, lo, k, r3);
       }
     }
     __syncthreads();
@@ -734,7 +841,8 @@ hipError_t launch_bs(const KParams& p, int mode, int grid, size_t lds, hipStream
     case CPHOT_TRANSPORT_STRAIGHT: return g ? launch_mode<BS, 0, 0>(p, mode, grid, lds, s) : launch_mode<BS, 0, 1>(p, mode, grid, lds, s);
     case CPHOT_TRANSPORT_LAYERED: return g ? launch_mode<BS, 1, 0>(p, mode, grid, lds, s) : launch_mode<BS, 1, 1>(p, mode, grid, lds, s);
     case CPHOT_TRANSPORT_SURROGATE: return g ? launch_mode<BS, 2, 0>(p, mode, grid, lds, s) : launch_mode<BS, 2, 1>(p, mode, grid, lds, s);
-    default: return launch_mode<BS, 3, 0>(p, mode, grid, lds, s);  // curved: grid detector only
+    case CPHOT_TRANSPORT_CURVED: return launch_mode<BS, 3, 0>(p, mode, grid, lds, s);  // grid detector only
+    default: return launch_mode<BS, kTransportCurvedSurrogate, 0>(p, mode, grid, lds, s);
   }
 }
 
@@ -761,7 +869,8 @@ size_t static_lds_bs(const KParams& p, int mode) {
     case CPHOT_TRANSPORT_STRAIGHT: return g ? static_lds_mode<BS, 0, 0>(mode) : static_lds_mode<BS, 0, 1>(mode);
     case CPHOT_TRANSPORT_LAYERED: return g ? static_lds_mode<BS, 1, 0>(mode) : static_lds_mode<BS, 1, 1>(mode);
     case CPHOT_TRANSPORT_SURROGATE: return g ? static_lds_mode<BS, 2, 0>(mode) : static_lds_mode<BS, 2, 1>(mode);
-    default: return static_lds_mode<BS, 3, 0>(mode);
+    case CPHOT_TRANSPORT_CURVED: return static_lds_mode<BS, 3, 0>(mode);
+    default: return static_lds_mode<BS, kTransportCurvedSurrogate, 0>(mode);
   }
 }
 

@@ -4,7 +4,8 @@
 //
 // The surrogate replaces the layered tracer's correction to the straight line
 // (the role of the thesis's precomputed correction table, Sec. 4.4.1) by a
-// small network trained on photons the exact tracer generates.
+// small network trained on photons the exact tracer generates: over planar
+// layers, or over the spherical shells of a curved Earth (Sec. 3.3.4).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,6 +41,8 @@ struct TrainSetParams {
   float4 const* layers;
   float2 const* lambins;
   int n_layers, n_lam;
+  int geometry;  // CPHOT_SURROGATE_PLANAR | CPHOT_SURROGATE_CURVED
+  double earth_radius;
   float dh, lam_min, lam_max;
   float lo[5], hi[5];
   uint32_t key0, key1;
@@ -47,6 +50,92 @@ struct TrainSetParams {
   float* X;
   float* Y;
 };
+
+// Shell walk of the curved geometry in FP64 for training targets: the same law
+// as the propagation kernel's FP32 walk (the impact-parameter deficit
+// D = (R + h) - p carried without radius-sized subtractions, chords
+// (ha - hb)(2R + ha + hb) / (ra ca + rb cb), central angle asin(p l / (ra rb)),
+// turning inside a shell, total reflection at a boundary), in double so that
+// the targets are limited by the physics rather than by rounding. Start at
+// height h0 with local zenith cosine c0 (downward). Returns false if the ray
+// does not reach the sphere R + h_obs.
+__device__ bool shell_walk_f64(const float4* __restrict__ lay, float2 sp, double dh, int n_layers, double h_obs,
+                               double Re, double h0, double c0, double& psi, double& len, double& opt,
+                               double& tau) {
+  const double s0 = sqrt((1.0 - c0) * (1.0 + c0));
+  int i = min((int)(h0 / dh), n_layers - 1);
+  const int obs = (int)floor(h_obs / dh);
+  const double A = Re + h0;
+  const double c1 = c0 * c0 / (1.0 + s0);
+  const double d0 = (double)lay[i].x;
+  auto bracket = [&](int k) {
+    const double dk = (double)lay[k].x;
+    return c1 - s0 * (d0 - dk) / (1.0 + dk);
+  };
+  double h = h0;
+  psi = len = opt = tau = 0.0;
+  bool down = c0 > 0.0;
+  for (int iter = 0; iter < 8 * n_layers; ++iter) {
+    const double br = bracket(i);
+    const double ra = Re + h;
+    const double Da = A * br + (h - h0);
+    const double rca = sqrt(fmax(Da * (2.0 * ra - Da), 0.0));
+    const double pa = ra - Da;
+    const double ext = (double)lay[i].z * sp.x + (double)lay[i].w * sp.y;
+    double ell, dpsi;
+    bool to_top = false;
+    if (down) {
+      const double hb = (i == obs) ? h_obs : i * dh;
+      const double Db = A * br + (hb - h0);
+      if (Db > 0.0) {
+        const double rb = Re + hb;
+        const double rcb = sqrt(Db * (2.0 * rb - Db));
+        ell = (h - hb) * (2.0 * Re + h + hb) / (rca + rcb);
+        dpsi = asin(pa * ell / (ra * rb));
+        h = hb;
+      } else {
+        const double ho = (i + 1) * dh;
+        const double ro = Re + ho;
+        const double Do = A * br + (ho - h0);
+        const double rco = sqrt(fmax(Do * (2.0 * ro - Do), 0.0));
+        ell = rca + rco;
+        dpsi = atan2(rca, pa) + atan2(rco, pa);
+        h = ho;
+        down = false;
+        to_top = true;
+      }
+    } else {
+      const double ho = (i + 1) * dh;
+      const double ro = Re + ho;
+      const double Do = A * br + (ho - h0);
+      const double rco = sqrt(fmax(Do * (2.0 * ro - Do), 0.0));
+      ell = (ho - h) * (2.0 * Re + ho + h) / (rco + rca);
+      dpsi = asin(pa * ell / (ra * ro));
+      h = ho;
+      to_top = true;
+    }
+    len += ell;
+    opt += (double)lay[i].x * ell;
+    tau += ext * ell;
+    psi += dpsi;
+    if (!to_top) {
+      if (i == obs) return true;
+      if (!(A * bracket(i - 1) + (h - h0) > 0.0)) {
+        down = false;
+        continue;
+      }
+      --i;
+      continue;
+    }
+    if (i + 1 >= n_layers) return false;
+    if (!(A * bracket(i + 1) + (h - h0) > 0.0)) {
+      down = true;
+      continue;
+    }
+    ++i;
+  }
+  return false;
+}
 
 __global__ __launch_bounds__(256) void k_training_set(TrainSetParams p) {
   __shared__ float4 s_lay[kMaxLayers];
@@ -71,6 +160,33 @@ __global__ __launch_bounds__(256) void k_training_set(TrainSetParams p) {
   float sphi, cphi;
   sincosf(phi, &sphi, &cphi);
   const float ux = st * cphi, uy = st * sphi, uz = -ct;
+  float* x = p.X + 5 * j;
+  x[0] = h_e;
+  x[1] = ct;
+  x[2] = phi;
+  x[3] = lam;
+  x[4] = h_obs;
+  float* y = p.Y + 4 * j;
+  if (p.geometry == CPHOT_SURROGATE_CURVED) {
+    // by the spherical symmetry the start is above the Earth point (0, 0); the
+    // chord from there to the sphere R + h_obs, cancellation-free, in FP64
+    const double Re = p.earth_radius, he = h_e, ho = h_obs, c0 = ct;
+    const double r0 = Re + he, r1 = Re + ho, s0 = sqrt((1.0 - c0) * (1.0 + c0));
+    const double drs = (he - ho) * (r0 + r1);
+    const double s_ch = drs / (r0 * c0 + sqrt(r0 * r0 * c0 * c0 - drs));
+    const double psi_s = asin(s_ch * s0 / r1);
+    double psi, len, opt, tau;
+    if (!shell_walk_f64(s_lay, s_lam[kb], (double)p.dh, p.n_layers, ho, Re, he, c0, psi, len, opt, tau)) {
+      y[0] = y[1] = y[2] = y[3] = __builtin_nanf("");
+      return;
+    }
+    // per metre of chord: the absolute quantities grow with the slant distance
+    y[0] = (float)((psi - psi_s) * r1 / s_ch);
+    y[1] = 0.f;  // across the plane of the start direction: zero by symmetry
+    y[2] = (float)(((len - s_ch) + opt) / s_ch);
+    y[3] = (float)(-tau / s_ch);
+    return;
+  }
   const int i0 = min((int)(h_e / p.dh), p.n_layers - 1);
   const int iobs = (int)floorf(h_obs / p.dh);
   LayerWalk lw;
@@ -83,13 +199,6 @@ __global__ __launch_bounds__(256) void k_training_set(TrainSetParams p) {
   leg_excess(lw, span_last, lw.last_delta, s_lay[iobs].y, dr, gex);
   const float opt = fmaf(lw.last_delta, s_last, lw.opt);
   const float tau = fmaf(lw.last_ext, s_last, lw.tau);
-  float* x = p.X + 5 * j;
-  x[0] = h_e;
-  x[1] = ct;
-  x[2] = phi;
-  x[3] = lam;
-  x[4] = h_obs;
-  float* y = p.Y + 4 * j;
   y[0] = dr;   // along the photon's horizontal direction
   y[1] = 0.f;  // across it: zero for horizontal layers
   y[2] = gex + opt;
@@ -506,6 +615,8 @@ int cphot_surrogate_create(const cphot_surrogate_desc* desc, cphot_surrogate** o
     return sfail(CPHOT_ERR_INVALID_ARG, "cos(zenith) range must lie in [0, 1]");
   if (desc->max_batch < 64 || desc->max_batch % 64 || desc->max_batch > (1 << 22))
     return sfail(CPHOT_ERR_INVALID_ARG, "max_batch must be a positive multiple of 64 up to 2^22");
+  if (desc->geometry != CPHOT_SURROGATE_PLANAR && desc->geometry != CPHOT_SURROGATE_CURVED)
+    return sfail(CPHOT_ERR_INVALID_ARG, "unknown surrogate geometry");
   cphot_surrogate* s = new (std::nothrow) cphot_surrogate();
   if (!s) return sfail(CPHOT_ERR_OUT_OF_MEMORY, "host allocation");
   s->d = *desc;
@@ -587,6 +698,10 @@ int cphot_surrogate_make_training_set(const cphot_surrogate* s, const cphot_atmo
     return sfail(CPHOT_ERR_INVALID_ARG, "domain wavelengths must cover the atmosphere's band");
   if (s->d.in_lo[0] < s->d.in_lo[4])
     return sfail(CPHOT_ERR_INVALID_ARG, "domain emission heights must start at or above the lowest observation level");
+  p.geometry = s->d.geometry;
+  p.earth_radius = cphot::atmosphere_earth_radius(atm);
+  if (p.geometry == CPHOT_SURROGATE_CURVED && !(p.earth_radius > 1e5 && std::isfinite(p.earth_radius)))
+    return sfail(CPHOT_ERR_INVALID_ARG, "a curved surrogate needs the atmosphere's earth_radius");
   if (n == 0) return CPHOT_OK;
   for (int j = 0; j < 5; ++j) {
     p.lo[j] = (float)s->d.in_lo[j];
@@ -714,4 +829,5 @@ int cphot_surrogate_set_params(cphot_surrogate* s, const float* params, const fl
 namespace cphot {
 const MlpImage* surrogate_image(const cphot_surrogate* s) { return s ? s->img : nullptr; }
 bool surrogate_ready(const cphot_surrogate* s) { return s && s->normalised; }
+int surrogate_geometry(const cphot_surrogate* s) { return s ? s->d.geometry : CPHOT_SURROGATE_PLANAR; }
 }  // namespace cphot

@@ -216,6 +216,9 @@ RUN_INCLINED = dict(transport="curved", detector="grid", spectrum="frank_tamm", 
 # surrogate training domain: emission height, cos zenith, azimuth, wavelength, observation level
 SURROGATE_LO = (2000.0, math.cos(math.radians(60.0)), -math.pi, 300.0, 1000.0)
 SURROGATE_HI = (20000.0, 1.0, math.pi, 600.0, 3000.0)
+# curved-Earth surrogate (inclined workload): local zenith up to 66 deg, heights to 22 km
+SURROGATE_CURVED_LO = (2000.0, 0.4, -math.pi, 300.0, 1000.0)
+SURROGATE_CURVED_HI = (22000.0, 1.0, math.pi, 600.0, 3000.0)
 
 
 def workload_tiny_vertical(beta: str = "literal", n: int = 10_000) -> Shower:

@@ -1,0 +1,133 @@
+"""Curved-Earth transport surrogate on the GPU against the oracle and against the
+exact curved-shell tracer.
+
+- training targets (FP64 shell walk on the GPU) match the oracle's curved targets
+  for the same float32 inputs;
+- with a domain that excludes every photon the surrogate equals the exact curved
+  transport bit for bit (fallback path);
+- a trained network reproduces the exact per-bin photon density of an inclined
+  shower to <= 1 %.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_04229_amd import workload as W
+from tests import cases, parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_04229_amd import cphot  # noqa: E402
+
+LO, HI = cases.SURROGATE_CURVED_LO, cases.SURROGATE_CURVED_HI
+
+
+@pytest.fixture(scope="module")
+def atm():
+    return cphot.Atmosphere(**cases.ATMO_LAYERED)
+
+
+def test_curved_training_set_matches_oracle(atm):
+    sur = cphot.Surrogate(LO, HI, geometry="curved")
+    n = 20000
+    X, Y = sur.make_training_set(atm, n, seed=23, first=500)
+    X, Y = X.cpu().numpy().astype(np.float64), Y.cpu().numpy().astype(np.float64)
+    oatm = O.Atmosphere(**cases.ATMO_LAYERED)
+    Xo = O.surrogate_inputs(oatm, 23, LO, HI, 500, n)
+    np.testing.assert_allclose(X[:, [0, 4]], Xo[:, [0, 4]], rtol=2e-7)
+    np.testing.assert_array_equal(X[:, 3].astype(np.float32), Xo[:, 3].astype(np.float32))
+    assert np.all(np.isfinite(Y))
+    # targets for the very same (float32) inputs
+    Yo = O.surrogate_targets(oatm, X, "curved")
+    assert np.all(np.isfinite(Yo))
+    # per metre of chord: 1e-4 m over a chord of >= 2 km is 5e-8
+    for o, (rtol, atol) in enumerate([(1e-4, 5e-8), (0.0, 1e-12), (1e-4, 5e-8), (1e-5, 1e-11)]):
+        err = np.abs(Y[:, o] - Yo[:, o])
+        tol = rtol * np.abs(Yo[:, o]) + atol
+        assert np.all(err <= tol), (o, float((err / tol).max()))
+    # the curvature shows: the curved targets differ from the planar ones
+    Yp = O.surrogate_targets(oatm, X, "planar")
+    chord = (X[:, 0] - X[:, 4]) / X[:, 1]
+    assert np.median(np.abs(Yo[:, 0] * chord - Yp[:, 0])) > 1e-3
+
+
+def _norm(mean, std, lo, hi):
+    n = np.zeros(cphot.N_NORM, dtype=np.float32)
+    n[0:5] = lo
+    n[5:10] = hi
+    n[10:15] = 2.0 / (np.array(hi) - np.array(lo))
+    n[16:20] = mean
+    n[20:24] = std
+    return n
+
+
+def _inclined(n, seed):
+    return W.make_shower(n, seed=seed, xmax=600.0, zenith_deg=60.0, azimuth_deg=15.0, beta="R")
+
+
+def _run_grid(atm, run, sh, transport, sur=None):
+    g = np.array([[*sh.core, *sh.axis]])
+    seg, gg, off = cphot.upload(sh.seg, g)
+    S = cphot.make_segments(seg, gg, off)
+    det = cphot.make_detector(atm, **{**run, "transport": transport}, surrogate=sur)
+    bins = torch.zeros(run["nx"] * run["ny"], dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    cphot.propagate(S, det, bins, None, cnt)
+    torch.cuda.synchronize()
+    return bins.cpu().numpy(), cnt.cpu().numpy()
+
+
+def test_curved_out_of_domain_falls_back_to_exact(atm):
+    """A domain no photon reaches: every record is traced exactly, so bins and
+    counters equal the exact curved transport's bit for bit."""
+    lo = [21000.0, 0.99, -3.0, 300.0, 1000.0]
+    hi = [22000.0, 1.0, 3.0, 600.0, 1100.0]
+    sur = cphot.Surrogate(lo, hi, geometry="curved")
+    rng = np.random.default_rng(4)
+    th = rng.normal(0, 0.1, cphot.N_PARAMS).astype(np.float32)
+    sur.set_params(th, _norm([0, 0, 0, 0], [1, 1, 1, 1], lo, hi))
+    sh = _inclined(5000, 601)
+    run = {**cases.RUN_INCLINED, "emission": "cherenkov", "nx": 400, "ny": 400, "cell": 20.0, "seed": 7}
+    be, ce = _run_grid(atm, run, sh, "curved")
+    bs, cs = _run_grid(atm, run, sh, "surrogate", sur)
+    np.testing.assert_array_equal(bs, be)
+    np.testing.assert_array_equal(cs[:9], ce[:9])
+    assert 0 < cs[9] <= cs[3] - cs[4]       # every downward record above h_obs fell back
+
+
+@pytest.fixture(scope="module")
+def trained_curved(atm):
+    sur = cphot.Surrogate(LO, HI, max_batch=4096, init_seed=2, geometry="curved")
+    X, Y = sur.make_training_set(atm, 10_000_000, seed=78)
+    sur.fit_normalization(Y)
+    loss = sur.train(X, Y, batch=4096, steps=40000, lr=3e-3)
+    torch.cuda.synchronize()
+    return sur, loss.cpu().numpy()
+
+
+def test_curved_training_lowers_the_loss(trained_curved):
+    _, loss = trained_curved
+    assert np.all(np.isfinite(loss))
+    assert loss[-100:].mean() < 1e-3, loss[-100:].mean()
+
+
+def test_trained_curved_surrogate_density_within_one_percent(trained_curved, atm):
+    """Same photons through the exact shell walk and through the network: per-cell
+    photon counts on the ground grid of an inclined shower."""
+    sur, _ = trained_curved
+    sh = _inclined(400_000, 602)
+    run = {**cases.RUN_INCLINED, "emission": "cherenkov", "seed": 9}
+    be, ce = _run_grid(atm, run, sh, "curved")
+    bs, cs = _run_grid(atm, run, sh, "surrogate", sur)
+    assert cs[3] == ce[3]                    # the same records
+    assert cs[9] < 1e-2 * cs[3]              # almost none outside the domain
+    m = be >= 1000
+    assert m.sum() >= 20
+    worst = float(np.max(np.abs(bs[m].astype(np.float64) - be[m]) / be[m]))
+    l1 = float(np.abs(bs.astype(np.float64) - be).sum() / be.sum())
+    print(dict(worst=worst, l1=l1, bins=int(m.sum()), fallback=int(cs[9])))
+    assert worst <= 0.01 and l1 <= 0.01, (worst, l1)

@@ -146,8 +146,8 @@ def _chord(re, h_e, h_obs, ct):
 
 def test_curved_targets_homogeneous_medium():
     """Shells of one refractive index bend nothing: zero extra ground distance,
-    optical path excess = (n - 1) x chord, and the optical depth is the sum of
-    each shell's extinction times the chord's length inside that shell."""
+    optical path excess per metre of chord = n - 1, and the optical depth is the
+    sum of each shell's extinction times the chord's length inside that shell."""
     re = 6.371e6
     hom = O.Atmosphere(profile="homogeneous", delta0=2e-4, h_top=25000.0, n_layers=100, n_lam=16,
                        aer_tau350=0.1, aer_H=1500.0, earth_radius=re)
@@ -160,8 +160,8 @@ def test_curved_targets_homogeneous_medium():
         h_e, ct, h_obs = x[0], x[1], x[4]
         s = _chord(re, h_e, h_obs, ct)
         k = int((x[3] - 300.0) / 300.0 * 16)
-        assert abs(y[0]) < 1e-6 and abs(y[1]) < 1e-6
-        assert y[2] == pytest.approx(2e-4 * s, rel=1e-7, abs=1e-7)
+        assert abs(y[0]) < 1e-10 and abs(y[1]) < 1e-10
+        assert y[2] == pytest.approx(2e-4, rel=1e-7)
         # distance along the chord from the start down to radius re + h
         r0, s0 = re + h_e, math.sqrt(1.0 - ct * ct)
         along = lambda h: r0 * ct - math.sqrt((re + h) ** 2 - (r0 * s0) ** 2)
@@ -169,7 +169,7 @@ def test_curved_targets_homogeneous_medium():
         for layer in range(int(h_obs // dh), min(int(h_e // dh), 99) + 1):
             lo_, hi_ = max(layer * dh, h_obs), min((layer + 1) * dh, h_e)
             tau += ext[layer, k] * (along(lo_) - along(hi_))
-        assert -y[3] == pytest.approx(tau, rel=1e-8)
+        assert -y[3] * s == pytest.approx(tau, rel=1e-8)
 
 
 def test_curved_targets_flat_earth_limit(atm):
@@ -182,8 +182,8 @@ def test_curved_targets_flat_earth_limit(atm):
     dh = 250.0
     m = lambda h: np.abs(h / dh - np.round(h / dh)) * dh
     X = X[(m(X[:, 0]) > 0.05) & (m(X[:, 4]) > 0.05)]
-    Yc = O.surrogate_targets(flat, X, "curved")
-    Yp = O.surrogate_targets(flat, X, "planar")
+    Yc = O.surrogate_targets(flat, X, "curved") * ((X[:, 0] - X[:, 4]) / X[:, 1])[:, None]
+    Yp = O.surrogate_targets(flat, X, "planar")  # absolute; the chord is (h_e - h_obs) / cos in the limit
     # what is left of the curvature: the sphere sags by x^2 / 2R below the plane
     # over the horizontal span x (2e-4 m at 20 km), which moves lengths by about as
     # much; and FP64 resolves positions 1e12 m from the centre to 1.2e-4 m
@@ -203,7 +203,7 @@ def test_curved_targets_earth_curvature_effect(atm):
     layers (the local vertical turns under it): the extra ground distance keeps
     its sign, and the curvature correction grows with zenith angle."""
     X = np.array([[12000.0, ct, 0.3, 405.46875, 2200.0] for ct in (0.95, 0.8, 0.6, 0.45)])
-    Yc = O.surrogate_targets(atm, X, "curved")
+    Yc = O.surrogate_targets(atm, X, "curved") * ((X[:, 0] - X[:, 4]) / X[:, 1])[:, None]
     Yp = O.surrogate_targets(atm, X, "planar")
     assert np.all(np.sign(Yc[:, 0]) == np.sign(Yp[:, 0]))
     rel = np.abs(Yc[:, 0] - Yp[:, 0]) / np.abs(Yp[:, 0])
