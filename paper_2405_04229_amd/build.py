@@ -14,7 +14,10 @@ ARCH = os.environ.get("CPHOT_OFFLOAD_ARCH", "gfx950")
 # FMA contraction: fused operations are written out (fmaf), so one source line
 # gives the same bits in every kernel instantiation it is inlined into.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-             "-packed-fp32-ops", "-ffp-contract=off", "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
+             "-packed-fp32-ops", "-ffp-contract=off", "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+             # matrix-core results in ordinary VGPRs: no accumulator-register copies
+             # before the activations, and one register file to budget
+             "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def hipcc() -> str:

@@ -168,6 +168,7 @@ struct Photon {
 template <int TRANSPORT, int DETECTOR, bool NEED_TIME>
 __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict__ s_lay,
                                       const float2* __restrict__ s_lam, const MlpImage* __restrict__ s_img,
+                                      uint4* s_stage,
                                       const float4 q0, const float4 q1, const float4 q2, const float4 q3,
                                       const float4 q4, const float axz, const uint4 q5, uint32_t k, bool valid,
                                       Photon& o) {
@@ -249,7 +250,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
 #pragma unroll
         for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
       }
-      mlp_forward_wave(s_img, xin, ym);
+      mlp_forward_wave(s_img, xin, ym, s_stage);
     }
     if (!(uz < 0.f)) {
       o.state = 1;
@@ -333,7 +334,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
 #pragma unroll
       for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
     }
-    mlp_forward_wave(s_img, xin, ym);
+    mlp_forward_wave(s_img, xin, ym, s_stage);
   }
   if (!(uz < 0.f)) {
     o.state = 1;
@@ -547,6 +548,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   __shared__ uint16_t s_qlo[kMlp ? 2 * BS : 1];
   __shared__ uint32_t s_qk[kMlp ? 2 * BS : 1];
   __shared__ uint32_t s_qn;
+  __shared__ uint4 s_mlpx[kMlp ? BS : 1];  // per-wave staging of the network's inputs and outputs
   const MlpImage* s_img = reinterpret_cast<const MlpImage*>(s_imgw);
   // Optional LDS window of the grid (record counts of one shower at a time).
   // With it each block walks a contiguous range of tiles, so the window changes
@@ -747,8 +749,8 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       const uint32_t k = j - s_off[lo];
       Photon ph;
       const float4 r3 = s_q3[lo];
-      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_q0[lo], s_q1[lo], s_q2[lo], r3, s_q4[lo],
-                                        s_axz[lo], s_q5[lo], k, valid, ph);
+      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
+                                        s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], s_q5[lo], k, valid, ph);
       if constexpr (kMlp) {
         // wave-level compaction: deferred records take consecutive queue slots
         // (ballot, prefix count of the lanes below, one LDS atomic per wave)
@@ -776,8 +778,8 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
             const uint32_t qk = s_qk[q];
             const float4 q3 = s_q3[qlo];
             Photon pe;
-            trace<kExact, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3, s_q4[qlo],
-                                           s_axz[qlo], s_q5[qlo], qk, true, pe);
+            trace<kExact, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
+                                           s_q4[qlo], s_axz[qlo], s_q5[qlo], qk, true, pe);
             pe.fallback = 1;
             consume(pe, qlo, qk, q3);
           }

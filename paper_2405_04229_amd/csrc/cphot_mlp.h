@@ -21,7 +21,10 @@
 namespace cphot {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kMlpIn = 5;
 constexpr int kMlpHidden = 64;
@@ -56,29 +59,54 @@ __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const 
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// ReLU of two FP32 values, rounded to bf16 and packed (a in the low half). The
+// maximum with zero is taken on the bf16 bit patterns as signed 16-bit integers
+// (a negative bf16 has its sign bit set, so it compares below zero): one packed
+// integer instruction for two units. Rounding keeps the sign, so this equals
+// rounding the FP32 ReLU.
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 v = __builtin_convertvector((f32x2){a, b}, bf16x2);  // one v_cvt_pk_bf16_f32
+  const s16x2 r = __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), (s16x2){0, 0});
+  return __builtin_bit_cast(uint32_t, r);
+}
+
 // Forward pass for the 64 photons of a wave (one per lane). Must be called by
 // all 64 lanes together. x = raw inputs (h_e, cos zenith, azimuth, wavelength,
 // h_obs); y = de-standardised outputs (dx, dy, optical path excess, log T).
+// `stage` is this wave's 64 x 16 B of LDS: the inputs go through it into the
+// B-operand layout and the outputs back to one lane per photon (a write and a
+// read each instead of cross-lane shuffles).
 __device__ __forceinline__ void mlp_forward_wave(const MlpImage* __restrict__ im, const float x[kMlpIn],
-                                                 float y[kMlpOut]) {
+                                                 float y[kMlpOut], uint4* stage) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
-  float xs[kMlpIn];
-#pragma unroll
-  for (int j = 0; j < kMlpIn; ++j) xs[j] = fmaf(x[j] - im->in_lo[j], im->in_scale[j], -1.0f);
   // layer 1: B operand = scaled inputs of photon 16 nt + c in lanes g == 0
+  // (K slots 0..4; all other K slots are zero)
+  {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    float xs[kMlpIn];
+#pragma unroll
+    for (int j = 0; j < kMlpIn; ++j) xs[j] = fmaf(x[j] - im->in_lo[j], im->in_scale[j], -1.0f);
+    u32x4 w;
+    w[0] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){xs[0], xs[1]}, bf16x2));
+    w[1] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){xs[2], xs[3]}, bf16x2));
+    w[2] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){xs[4], 0.0f}, bf16x2));
+    w[3] = 0u;
+    stage[lane] = __builtin_bit_cast(uint4, w);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   bf16x8 bx[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
-#pragma unroll
-    for (int j = 0; j < kMlpIn; ++j) {
-      const float v = __shfl(xs[j], 16 * nt + c, 64);
-      bx[nt][j] = (__bf16)(g == 0 ? v : 0.0f);
-    }
-#pragma unroll
-    for (int j = kMlpIn; j < 8; ++j) bx[nt][j] = (__bf16)0.0f;
+    const uint4 v = g == 0 ? stage[16 * nt + c] : make_uint4(0u, 0u, 0u, 0u);
+    bx[nt] = __builtin_bit_cast(bf16x8, v);
   }
-  bf16x8 h1[2][4];
+  // hidden activations as bf16 pairs: slot 4 (m & 1) + r of K-tile m >> 1 is in
+  // word 2 (m & 1) + r / 2
+  u32x4 h1[2][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const bf16x8 a = im->a1[m][lane];
@@ -88,12 +116,12 @@ __device__ __forceinline__ void mlp_forward_wave(const MlpImage* __restrict__ im
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const f32x4 z = mfma16(a, bx[nt], bias);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h1[m >> 1][nt][4 * (m & 1) + r] = (__bf16)fmaxf(z[r], 0.0f);
+      h1[m >> 1][nt][2 * (m & 1)] = relu_bf16x2(z[0], z[1]);
+      h1[m >> 1][nt][2 * (m & 1) + 1] = relu_bf16x2(z[2], z[3]);
     }
   }
   // layer 2
-  bf16x8 h2[2][4];
+  u32x4 h2[2][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     f32x4 acc[4];
@@ -106,12 +134,13 @@ __device__ __forceinline__ void mlp_forward_wave(const MlpImage* __restrict__ im
     for (int kt = 0; kt < 2; ++kt) {
       const bf16x8 a = im->a2[m][kt][lane];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, h1[kt][nt], acc[nt]);
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, __builtin_bit_cast(bf16x8, h1[kt][nt]), acc[nt]);
     }
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h2[m >> 1][nt][4 * (m & 1) + r] = (__bf16)fmaxf(acc[nt][r], 0.0f);
+    for (int nt = 0; nt < 4; ++nt) {
+      h2[m >> 1][nt][2 * (m & 1)] = relu_bf16x2(acc[nt][0], acc[nt][1]);
+      h2[m >> 1][nt][2 * (m & 1) + 1] = relu_bf16x2(acc[nt][2], acc[nt][3]);
+    }
   }
   // layer 3: rows 0..3 of the output tile live in lanes g == 0
   f32x4 out[4];
@@ -124,19 +153,22 @@ __device__ __forceinline__ void mlp_forward_wave(const MlpImage* __restrict__ im
   for (int kt = 0; kt < 2; ++kt) {
     const bf16x8 a = im->a3[kt][lane];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) out[nt] = mfma16(a, h2[kt][nt], out[nt]);
+    for (int nt = 0; nt < 4; ++nt) out[nt] = mfma16(a, __builtin_bit_cast(bf16x8, h2[kt][nt]), out[nt]);
   }
-  // photon 16 g + c finds its outputs in lane c of N-tile g
+  // photon 16 nt + c finds its outputs in lane c (g == 0) of N-tile nt
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (g == 0) {
 #pragma unroll
-  for (int r = 0; r < kMlpOut; ++r) {
-    float v = 0.f;
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const float t = __shfl(out[nt][r], c, 64);
-      v = (g == nt) ? t : v;
-    }
-    y[r] = fmaf(v, im->out_std[r], im->out_mean[r]);
+    for (int nt = 0; nt < 4; ++nt) stage[16 * nt + c] = __builtin_bit_cast(uint4, out[nt]);
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const f32x4 o = __builtin_bit_cast(f32x4, stage[lane]);
+#pragma unroll
+  for (int r = 0; r < kMlpOut; ++r) y[r] = fmaf(o[r], im->out_std[r], im->out_mean[r]);
 }
 
 // True if all inputs lie in the training domain box.

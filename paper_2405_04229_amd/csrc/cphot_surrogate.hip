@@ -537,6 +537,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamParams p) {
 __global__ __launch_bounds__(256) void k_forward(const MlpImage* __restrict__ img, const float* __restrict__ X,
                                                  float* __restrict__ Y, int64_t n) {
   __shared__ __attribute__((aligned(16))) MlpImage s_img;
+  __shared__ uint4 s_stage[256];
   {
     const uint4* src = reinterpret_cast<const uint4*>(img);
     uint4* dst = reinterpret_cast<uint4*>(&s_img);
@@ -548,7 +549,7 @@ __global__ __launch_bounds__(256) void k_forward(const MlpImage* __restrict__ im
   float x[kMlpIn], y[kMlpOut];
 #pragma unroll
   for (int k = 0; k < kMlpIn; ++k) x[k] = X[5 * jj + k];
-  mlp_forward_wave(&s_img, x, y);
+  mlp_forward_wave(&s_img, x, y, s_stage + (threadIdx.x & ~63u));
   if (j < n) {
 #pragma unroll
     for (int o = 0; o < kMlpOut; ++o) Y[4 * j + o] = y[o];
