@@ -133,7 +133,11 @@ __device__ __forceinline__ void layer_walk(const float4* __restrict__ lay, float
   w.hy = hy;
   w.dr = 0.f;
   w.gex = 0.f;
-  float x = Px, y = Py, z = Pz, tau = 0.f, geo = 0.f, opt = 0.f;
+  float x = Px, y = Py, z = Pz, tau = 0.f, geo2 = 0.f, opt = 0.f;
+  // geometric delay per unit path 1 - v.a = |v - a|^2 / 2, v = (s h, -c), formed
+  // from the differences so that no near-1 quantity is subtracted; the factor
+  // 1/2 is applied once at the end
+  const float nax = -axx, nay = -axy, naz = -axz;
   while (i > obs_layer) {
     const float zb = (float)i * dh;
     const float span = z - zb;
@@ -146,8 +150,8 @@ __device__ __forceinline__ void layer_walk(const float4* __restrict__ lay, float
     y = fmaf(hy, adv, y);
     tau = fmaf(fmaf(L.z, sp.x, L.w * sp.y), path, tau);
     if constexpr (NEED_TIME) {
-      const float ex = s * hx - axx, ey = s * hy - axy, ez = -c2 * ic - axz;
-      geo = fmaf(path, 0.5f * (ex * ex + ey * ey + ez * ez), geo);
+      const float ex = fmaf(s, hx, nax), ey = fmaf(s, hy, nay), ez = fmaf(-c2, ic, naz);
+      geo2 = fmaf(path, fmaf(ex, ex, fmaf(ey, ey, ez * ez)), geo2);
     }
     if constexpr (NEED_TIME || NEED_EXCESS) opt = fmaf(L.x, path, opt);
     if constexpr (NEED_EXCESS) leg_excess(w, span, L.x, L.y, w.dr, w.gex);
@@ -165,7 +169,7 @@ __device__ __forceinline__ void layer_walk(const float4* __restrict__ lay, float
   w.vy = s * hy;
   w.vz = -c;
   w.tau = tau;
-  w.geo = geo;
+  w.geo = 0.5f * geo2;
   w.opt = opt;
   w.last_delta = L.x;
   w.last_ext = fmaf(L.z, sp.x, L.w * sp.y);
