@@ -67,6 +67,13 @@ extern "C" {
  * bins then use the arrival point's (x, y) in the tangent plane at the core
  * (the core lies at (0, 0, h_obs)). */
 #define CPHOT_TRANSPORT_CURVED 3
+/* TABLE: straight line (or chord) plus the correction interpolated bilinearly
+ * from a table precomputed with the exact tracer over emission height and cos
+ * of the zenith angle (the thesis's interpolation tracing, Sec. 4.4.1; see
+ * cphot_table_*). The table's geometry decides planar layers or curved shells
+ * (then as CURVED: ground grid only). Photons outside the table's range are
+ * traced exactly and counted in CPHOT_C_SURROGATE_FALLBACK. */
+#define CPHOT_TRANSPORT_TABLE 4
 
 /* Detectors. GRID: nx x ny square cells of `cell` metres on the observation
  * level, centred on each shower's core. SPHERES: snx x sny bounding spheres of
@@ -108,6 +115,7 @@ extern "C" {
 
 typedef struct cphot_atmosphere cphot_atmosphere;
 typedef struct cphot_surrogate cphot_surrogate;
+typedef struct cphot_table cphot_table;
 
 /* Host description of an atmosphere. All fields are read during
  * cphot_make_atmosphere only. */
@@ -183,6 +191,7 @@ typedef struct {
   int32_t reserved2;
   double fl_yield[3];       /* fluorescence photons per MeV deposited, per band */
   double fl_lambda[3];      /* band wavelengths, nm (inside the atmosphere's band) */
+  const cphot_table* table; /* TABLE transport: a correction table built for this atmosphere and h_obs */
 } cphot_detector;
 
 /* Outputs, accumulated (+=) so that chunked calls need no host work; the caller
@@ -343,6 +352,52 @@ int cphot_streamer_run(cphot_streamer* s, const cphot_host_segments* host, const
                        cphot_bins* out, void* stream);
 
 void cphot_streamer_destroy(cphot_streamer* s);
+
+/* ---------------------------------------------------------------- correction table
+ * Interpolation tracing (Sec. 4.4.1): the correction between straight-line and
+ * iterative propagation, tabulated once per atmosphere and observation level and
+ * interpolated bilinearly per photon. The exact layered result jumps where the
+ * emission height crosses a layer boundary (the start layer fixes Snell's
+ * invariant of a given direction), so heights are tabulated layer by layer, n_h
+ * nodes from each layer's bottom (h_obs for the observation layer) to its top,
+ * for the layers from h_obs up to the one containing h_hi, and never
+ * interpolated across a boundary; directions on n_c nodes uniform in tan of the
+ * (local) zenith angle from 0 to that of cos = c_lo (the corrections are smooth
+ * in tan, with a square-root cusp at the vertical in cos). Each node holds,
+ * relative to the straight path L to the
+ * observation level (planar: L = (h_e - h_obs) / cos; curved: the chord to the
+ * sphere R + h_obs): the landing offset along the photon's azimuth (planar:
+ * horizontal offset; curved: extra ground distance), the optical path excess
+ * (path - L) + sum (n - 1) l, and the Rayleigh and aerosol parts of the optical
+ * depth, sum_i R_i l_i and sum_i A_i l_i, so that tau(lambda) = R(lambda) tau_R +
+ * A(lambda) tau_A with the atmosphere's spectral factors (all in metres; over
+ * planar layers they are linear in the height within a layer, so the height
+ * interpolation is exact there). The nodes come from the exact walk carried in
+ * FP64 on the GPU. */
+typedef struct {
+  int32_t geometry;   /* CPHOT_SURROGATE_PLANAR | CPHOT_SURROGATE_CURVED */
+  int32_t n_h, n_c;   /* nodes per layer in height (>= 2) and in tan zenith (>= 2) */
+  int32_t reserved0;
+  double h_obs;       /* observation level, m (the detector's must match) */
+  double h_hi;        /* highest emission height tabulated, m (<= h_top) */
+  double c_lo;        /* lowest cos zenith tabulated, in (0, 1) */
+} cphot_table_desc;
+
+/* Build a table on the current device from `atm` (which must have layers).
+ * Synchronous. The handle owns 16 B x n_h x n_c of device memory.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP. */
+int cphot_table_create(const cphot_table_desc* desc, const cphot_atmosphere* atm, cphot_table** out);
+
+/* Release a table (NULL allowed); no enqueued work may still use it. */
+void cphot_table_destroy(cphot_table* t);
+
+/* Interpolated corrections for device float32 X [n][5] (emission height, cos
+ * zenith, azimuth (unused), wavelength, observation level (unused: the table's))
+ * into Y [n][4] = (offset along the azimuth, 0, optical path excess, log T), in
+ * metres for the straight path of each input, as the propagation applies them;
+ * rows outside the table get NaN. For checks. Asynchronous. Errors: INVALID_ARG. */
+int cphot_table_lookup(const cphot_table* t, const cphot_atmosphere* atm, const float* X, float* Y, int64_t n,
+                       void* stream);
 
 /* ---------------------------------------------------------------- transport surrogate
  * A network 5 -> 64 -> 64 -> 4 (ReLU hidden units, linear output, bf16 weights on

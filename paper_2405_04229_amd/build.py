@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcphot.so")
-SOURCES = ["cphot_api.cpp", "cphot_kernels.hip", "cphot_surrogate.hip"]
+SOURCES = ["cphot_api.cpp", "cphot_kernels.hip", "cphot_surrogate.hip", "cphot_table.hip"]
 ARCH = os.environ.get("CPHOT_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions stay off: they are avoided on this target. No implicit

@@ -23,7 +23,7 @@ ERR_CAPACITY = -5
 NCOUNTERS = 16
 
 PROFILE = {"linsley5": 0, "homogeneous": 1, "linear": 2}
-TRANSPORT = {"straight": 0, "layered": 1, "surrogate": 2, "curved": 3}
+TRANSPORT = {"straight": 0, "layered": 1, "surrogate": 2, "curved": 3, "table": 4}
 EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
 DETECTOR = {"grid": 0, "spheres": 1}
 SPECTRUM = {"uniform": 0, "frank_tamm": 1}
@@ -64,12 +64,17 @@ class Detector(C.Structure):
                 ("reserved0", C.c_int32), ("time_bin_ns", C.c_double), ("block_size", C.c_int32),
                 ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("hist_window", C.c_int32),
                 ("surrogate", C.c_void_p), ("emission", C.c_int32), ("reserved2", C.c_int32),
-                ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3)]
+                ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3), ("table", C.c_void_p)]
 
 
 class SurrogateDesc(C.Structure):
     _fields_ = [("in_lo", C.c_double * 5), ("in_hi", C.c_double * 5), ("max_batch", C.c_int32),
                 ("geometry", C.c_int32), ("init_seed", C.c_uint64)]
+
+
+class TableDesc(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("n_h", C.c_int32), ("n_c", C.c_int32), ("reserved0", C.c_int32),
+                ("h_obs", C.c_double), ("h_hi", C.c_double), ("c_lo", C.c_double)]
 
 
 class Tuning(C.Structure):
@@ -143,6 +148,11 @@ def lib():
             L.cphot_streamer_run.argtypes = [P, C.POINTER(HostSegments), C.POINTER(Detector), C.POINTER(Bins), P]
             L.cphot_streamer_run.restype = C.c_int
             L.cphot_streamer_destroy.argtypes = [P]
+            L.cphot_table_create.argtypes = [C.POINTER(TableDesc), P, C.POINTER(C.c_void_p)]
+            L.cphot_table_create.restype = C.c_int
+            L.cphot_table_destroy.argtypes = [P]
+            L.cphot_table_lookup.argtypes = [P, P, P, P, C.c_int64, P]
+            L.cphot_table_lookup.restype = C.c_int
             for fn in ("create", "make_training_set", "fit_normalization", "train", "gradient", "forward",
                        "get_params", "set_params"):
                 getattr(L, "cphot_surrogate_" + fn).restype = C.c_int
@@ -210,7 +220,8 @@ class Atmosphere:
 def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0,
                   h_obs=2200.0, nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0,
                   dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, surrogate=None,
-                  emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0)) -> Detector:
+                  emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0),
+                  table=None) -> Detector:
     d = Detector()
     d.atm = atm.handle
     d.transport, d.detector, d.spectrum = TRANSPORT[transport], DETECTOR[detector], SPECTRUM[spectrum]
@@ -225,6 +236,8 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
     d.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
     if surrogate is not None:
         d.surrogate = surrogate.handle
+    if table is not None:
+        d.table = table.handle
     d._refs = (atm, surrogate)  # keep the handles alive
     return d
 
@@ -291,6 +304,48 @@ def propagate(seg: Segments, det: Detector, bins, time_hist=None, counters=None,
     """Accumulates into `bins`, `time_hist` and `counters` (see make_bins)."""
     b = make_bins(bins, time_hist, counters)
     _check("cphot_propagate", lib().cphot_propagate(C.byref(seg), C.byref(det), C.byref(b), _stream_ptr(stream)))
+
+
+class Table:
+    """Correction table of the interpolation tracing (cphot_table_*), built on the
+    GPU from the exact walk for one atmosphere and observation level."""
+
+    def __init__(self, atm: Atmosphere, h_obs, geometry="planar", n_h=4, n_c=256, h_hi=None, c_lo=0.4):
+        """n_h: nodes per layer in height (heights are never interpolated across a
+        layer boundary); n_c: nodes in cos zenith on [c_lo, 1]."""
+        d = TableDesc()
+        d.geometry = GEOMETRY[geometry]
+        d.n_h, d.n_c = int(n_h), int(n_c)
+        d.h_obs = float(h_obs)
+        d.h_hi = float(h_hi if h_hi is not None else atm.desc.h_top)
+        d.c_lo = float(c_lo)
+        self.desc, self._atm = d, atm
+        h = C.c_void_p()
+        _check("cphot_table_create", lib().cphot_table_create(C.byref(d), atm.handle, C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def lookup(self, X, stream=None):
+        """Interpolated (offset along the azimuth, 0, optical path excess, log T) for
+        float32 CUDA X [n, 5]; NaN outside the table."""
+        import torch
+        Y = torch.empty((X.shape[0], 4), dtype=torch.float32, device="cuda")
+        _check("cphot_table_lookup", lib().cphot_table_lookup(self._h, self._atm.handle,
+                                                               C.c_void_p(_dptr(X, torch.float32, "X")),
+                                                               C.c_void_p(_dptr(Y, torch.float32, "Y")),
+                                                               int(X.shape[0]), _stream_ptr(stream)))
+        return Y
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.cphot_table_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 class Streamer:

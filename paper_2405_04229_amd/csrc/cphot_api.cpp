@@ -111,13 +111,23 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     return fail(CPHOT_ERR_INVALID_ARG, "shower_offsets required for several showers");
   if (!seg->shower_geom) return fail(CPHOT_ERR_INVALID_ARG, "shower_geom is required");
   if (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED &&
-      det->transport != CPHOT_TRANSPORT_SURROGATE && det->transport != CPHOT_TRANSPORT_CURVED)
+      det->transport != CPHOT_TRANSPORT_SURROGATE && det->transport != CPHOT_TRANSPORT_CURVED &&
+      det->transport != CPHOT_TRANSPORT_TABLE)
     return fail(CPHOT_ERR_INVALID_ARG, "unknown transport");
+  if (det->transport == CPHOT_TRANSPORT_TABLE) {
+    if (!det->table) return fail(CPHOT_ERR_INVALID_ARG, "table transport needs a correction table");
+    if (cphot::table_atmosphere(det->table) != a)
+      return fail(CPHOT_ERR_INVALID_ARG, "the correction table was built for another atmosphere");
+    if (std::fabs(cphot::table_h_obs(det->table) - det->h_obs) > 1e-6)
+      return fail(CPHOT_ERR_INVALID_ARG, "the correction table was built for another h_obs");
+  }
   if (det->transport == CPHOT_TRANSPORT_SURROGATE && !cphot::surrogate_ready(det->surrogate))
     return fail(CPHOT_ERR_UNSUPPORTED, "surrogate transport needs a surrogate with its normalisation set");
   const bool curved_sur = det->transport == CPHOT_TRANSPORT_SURROGATE &&
                           cphot::surrogate_geometry(det->surrogate) == CPHOT_SURROGATE_CURVED;
-  const bool curved = det->transport == CPHOT_TRANSPORT_CURVED || curved_sur;
+  const bool curved_tab = det->transport == CPHOT_TRANSPORT_TABLE &&
+                          cphot::table_view(det->table).geometry == CPHOT_SURROGATE_CURVED;
+  const bool curved = det->transport == CPHOT_TRANSPORT_CURVED || curved_sur || curved_tab;
   if (curved && det->detector != CPHOT_DETECTOR_GRID)
     return fail(CPHOT_ERR_UNSUPPORTED, "curved transport collects on a ground grid");
   if (curved && !(d.earth_radius > 1e5 && std::isfinite(d.earth_radius)))
@@ -186,7 +196,10 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   p.earth_radius = d.earth_radius;
   p.h_obs = (float)det->h_obs;
   p.X_obs = d.profile == CPHOT_PROFILE_LINSLEY5 ? (float)depth(d, det->h_obs) : 0.f;
-  p.transport = curved_sur ? cphot::kTransportCurvedSurrogate : det->transport;
+  p.transport = curved_sur ? cphot::kTransportCurvedSurrogate
+                : curved_tab ? cphot::kTransportCurvedTable
+                             : det->transport;
+  if (det->transport == CPHOT_TRANSPORT_TABLE) p.ctab = cphot::table_view(det->table);
   p.detector = det->detector;
   if (det->transport != CPHOT_TRANSPORT_STRAIGHT) {
     if (d.n_layers < 1) return fail(CPHOT_ERR_INVALID_ARG, "layered transport needs an atmosphere with layers");

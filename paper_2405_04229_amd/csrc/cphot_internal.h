@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/cphot.h"
+#include "cphot_table.h"
 
 namespace cphot {
 
@@ -66,6 +67,8 @@ struct KParams {
   float inv_dt;
   // surrogate transport
   const MlpImage* mlp;
+  // table transport
+  TableView ctab;  // correction table (interpolation tracing)
   // emission
   const float* dedx;
   int32_t emission;
@@ -101,9 +104,14 @@ int atmosphere_layer_view(const cphot_atmosphere* atm, const float4** layers, co
 const MlpImage* surrogate_image(const cphot_surrogate* s);
 double atmosphere_earth_radius(const cphot_atmosphere* a);
 int surrogate_geometry(const cphot_surrogate* s);
-// internal transport id: SURROGATE transport with a CURVED surrogate
-constexpr int kTransportCurvedSurrogate = 4;
 bool surrogate_ready(const cphot_surrogate* s);
+// internal transport ids: SURROGATE / TABLE transport over curved shells
+constexpr int kTransportCurvedSurrogate = 16;
+constexpr int kTransportCurvedTable = 17;
+// Correction table: device view, the atmosphere it was built from, its h_obs.
+TableView table_view(const cphot_table* t);
+const cphot_atmosphere* table_atmosphere(const cphot_table* t);
+double table_h_obs(const cphot_table* t);
 
 hipError_t launch_propagate(const KParams& p, int mode, int block_size, int grid_blocks, size_t lds_hist_bytes,
                             hipStream_t stream);

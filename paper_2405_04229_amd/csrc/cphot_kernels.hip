@@ -230,7 +230,8 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
     kb = min(max(kb, 0), p.n_lam - 1);
   }
-  if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED || TRANSPORT == kTransportCurvedSurrogate) {
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED || TRANSPORT == kTransportCurvedSurrogate ||
+                TRANSPORT == kTransportCurvedTable) {
     // height above the sphere R without subtracting R: (x^2 + y^2 + z (2R + z)) / (|P - C| + R)
     const float Rf = (float)p.earth_radius;
     const float qz = Pz + Rf;
@@ -260,6 +261,18 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       o.state = 3;
       return;
     }
+    if constexpr (TRANSPORT == kTransportCurvedTable) {
+      // correction interpolated from the table (Sec. 4.4.1), in the start shell
+      const float irq = 1.0f / rq;
+      c0 = -fmaf(ux, Px * irq, fmaf(uy, Py * irq, uz * (qz * irq)));
+      float4 v;
+      const float tz = sqrtf(fmaxf((1.0f - c0) * (1.0f + c0), 0.f)) / c0;
+      use_mlp = c0 > 0.f && table_lookup(p.ctab, min((int)(h0 / p.dh), p.n_layers - 1), h0, tz, v);
+      const float2 sp = s_lam[kb];
+      ym[0] = v.x;
+      ym[2] = v.y;
+      ym[3] = -fmaf(v.z, sp.x, v.w * sp.y);
+    }
     CurvedWalk cw;
     if (use_mlp) {
       // straight chord to the sphere R + h_obs (cancellation-free root), its
@@ -272,10 +285,12 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       const float s_ch = drs / (rc + sqrtf(fmaf(rc, rc, -drs)));
       const float xs = s_ch * s0 / r1;
       const float psi_s = fmaf(xs * xs * (1.0f / 6.0f), xs, xs);
-      const double psi = (double)psi_s + (double)(ym[0] * s_ch) / (double)r1;
-      curved_arrival(p.earth_radius, p.h_obs, Px, Py, Pz, ux, uy, uz, psi, (double)(ym[1] * s_ch), cw.ax, cw.ay,
+      // the network's outputs are per metre of chord, the table's absolute
+      const float scale = (TRANSPORT == kTransportCurvedTable) ? 1.0f : s_ch;
+      const double psi = (double)psi_s + (double)(ym[0] * scale) / (double)r1;
+      curved_arrival(p.earth_radius, p.h_obs, Px, Py, Pz, ux, uy, uz, psi, (double)(ym[1] * scale), cw.ax, cw.ay,
                      cw.az);
-      cw.tau = -ym[3] * s_ch;
+      cw.tau = -ym[3] * scale;
       cw.arrived = 1;
       cw.geo = 0.f;
       cw.opt = 0.f;
@@ -286,10 +301,10 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
                      ez = (double)Pz + (double)s_ch * uz;
         const float shift = (float)((cw.ax - ex) * axx + (cw.ay - ey) * axy + (cw.az - ez) * axz);
         cw.geo = fmaf(s_ch * 0.5f, fmaf(gx, gx, fmaf(gy, gy, gz * gz)), -shift);
-        cw.opt = ym[2] * s_ch;
+        cw.opt = ym[2] * scale;
       }
     } else {
-      if constexpr (TRANSPORT == kTransportCurvedSurrogate) {
+      if constexpr (TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable) {
         o.state = kStateDeferred;  // outside the domain: traced exactly in a compacted pass
         return;
       }
@@ -344,13 +359,23 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     o.state = 3;
     return;
   }
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_TABLE) {
+    // correction interpolated from the table (Sec. 4.4.1), in the start layer
+    float4 v;
+    const float tz = sqrtf(fmaf(ux, ux, uy * uy)) / -uz;
+    use_mlp = table_lookup(p.ctab, min((int)(Pz * p.inv_dh), p.n_layers - 1), Pz, tz, v);
+    const float2 sp = s_lam[kb];
+    ym[0] = v.x;
+    ym[2] = v.y;
+    ym[3] = -fmaf(v.z, sp.x, v.w * sp.y);
+  }
   float x, y, z;     // start of the final leg
   float vx, vy, vz;  // direction of the final leg
   float tau = 0.f, geo = 0.f, opt = 0.f;
   float last_delta = 0.f, last_ext = 0.f;
   if constexpr (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT) {
     if (TRANSPORT == CPHOT_TRANSPORT_LAYERED || !use_mlp) {
-      if constexpr (TRANSPORT == CPHOT_TRANSPORT_SURROGATE) {
+      if constexpr (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == CPHOT_TRANSPORT_TABLE) {
         o.state = kStateDeferred;  // outside the domain: traced exactly in a compacted pass
         return;
       }
@@ -524,11 +549,14 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   constexpr bool kTime = (DETECTOR == CPHOT_DETECTOR_SPHERES) || (MODE == MODE_RECORDS);
   constexpr bool kLayers = (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT);
   constexpr bool kMlp = (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == kTransportCurvedSurrogate);
+  // transports that defer some records to the exact tracer (compaction queue)
+  constexpr bool kDefer = kMlp || TRANSPORT == CPHOT_TRANSPORT_TABLE || TRANSPORT == kTransportCurvedTable;
   constexpr bool kSort = kLayers && (MODE != MODE_COUNTS);
   // exact transport behind a surrogate: records outside the network's domain
-  constexpr int kExact = TRANSPORT == CPHOT_TRANSPORT_SURROGATE     ? CPHOT_TRANSPORT_LAYERED
-                         : TRANSPORT == kTransportCurvedSurrogate ? CPHOT_TRANSPORT_CURVED
-                                                                   : TRANSPORT;
+  constexpr int kExact =
+      (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == CPHOT_TRANSPORT_TABLE)       ? CPHOT_TRANSPORT_LAYERED
+      : (TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable) ? CPHOT_TRANSPORT_CURVED
+                                                                                        : TRANSPORT;
   // per-segment state for the record loop, one slot per segment of the tile:
   // q0 = start point, cos(theta); q1 = end - start, sin(theta); q2 = rotation
   // bisector, depth at the start; q3 = depth change, id low, id high, shower
@@ -545,8 +573,8 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   __shared__ uint4 s_imgw[kMlp ? sizeof(MlpImage) / 16 : 1];
   // compaction queue of deferred records (slot, k): at most BS enter per round and
   // it is drained once it holds BS, so 2 BS entries suffice
-  __shared__ uint16_t s_qlo[kMlp ? 2 * BS : 1];
-  __shared__ uint32_t s_qk[kMlp ? 2 * BS : 1];
+  __shared__ uint16_t s_qlo[kDefer ? 2 * BS : 1];
+  __shared__ uint32_t s_qk[kDefer ? 2 * BS : 1];
   __shared__ uint32_t s_qn;
   __shared__ uint4 s_mlpx[kMlp ? BS : 1];  // per-wave staging of the network's inputs and outputs
   const MlpImage* s_img = reinterpret_cast<const MlpImage*>(s_imgw);
@@ -688,7 +716,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     __syncthreads();
     // with the surrogate every lane of a wave runs each round (the tail lanes
     // repeat the last record and discard it); otherwise lanes stop at `total`
-    const uint32_t rounds_end = kMlp ? ((total + BS - 1) / BS) * BS : total;
+    const uint32_t rounds_end = kDefer ? ((total + BS - 1) / BS) * BS : total;
     // one record: a parity dump, or counters and bins
     auto consume = [&](const Photon& ph, int lo, uint32_t k, const float4& r3) {
       if constexpr (MODE == MODE_RECORDS) {
@@ -751,7 +779,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       const float4 r3 = s_q3[lo];
       trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
                                         s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], s_q5[lo], k, valid, ph);
-      if constexpr (kMlp) {
+      if constexpr (kDefer) {
         // wave-level compaction: deferred records take consecutive queue slots
         // (ballot, prefix count of the lanes below, one LDS atomic per wave)
         const bool push = valid && ph.state == kStateDeferred;
@@ -844,6 +872,8 @@ hipError_t launch_bs(const KParams& p, int mode, int grid, size_t lds, hipStream
     case CPHOT_TRANSPORT_LAYERED: return g ? launch_mode<BS, 1, 0>(p, mode, grid, lds, s) : launch_mode<BS, 1, 1>(p, mode, grid, lds, s);
     case CPHOT_TRANSPORT_SURROGATE: return g ? launch_mode<BS, 2, 0>(p, mode, grid, lds, s) : launch_mode<BS, 2, 1>(p, mode, grid, lds, s);
     case CPHOT_TRANSPORT_CURVED: return launch_mode<BS, 3, 0>(p, mode, grid, lds, s);  // grid detector only
+    case CPHOT_TRANSPORT_TABLE: return g ? launch_mode<BS, 4, 0>(p, mode, grid, lds, s) : launch_mode<BS, 4, 1>(p, mode, grid, lds, s);
+    case kTransportCurvedTable: return launch_mode<BS, kTransportCurvedTable, 0>(p, mode, grid, lds, s);
     default: return launch_mode<BS, kTransportCurvedSurrogate, 0>(p, mode, grid, lds, s);
   }
 }
@@ -872,6 +902,8 @@ size_t static_lds_bs(const KParams& p, int mode) {
     case CPHOT_TRANSPORT_LAYERED: return g ? static_lds_mode<BS, 1, 0>(mode) : static_lds_mode<BS, 1, 1>(mode);
     case CPHOT_TRANSPORT_SURROGATE: return g ? static_lds_mode<BS, 2, 0>(mode) : static_lds_mode<BS, 2, 1>(mode);
     case CPHOT_TRANSPORT_CURVED: return static_lds_mode<BS, 3, 0>(mode);
+    case CPHOT_TRANSPORT_TABLE: return g ? static_lds_mode<BS, 4, 0>(mode) : static_lds_mode<BS, 4, 1>(mode);
+    case kTransportCurvedTable: return static_lds_mode<BS, kTransportCurvedTable, 0>(mode);
     default: return static_lds_mode<BS, kTransportCurvedSurrogate, 0>(mode);
   }
 }

@@ -17,6 +17,7 @@
 #include "cphot_device.h"
 #include "cphot_internal.h"
 #include "cphot_mlp.h"
+#include "cphot_walk64.h"
 
 namespace cphot {
 
@@ -51,92 +52,6 @@ struct TrainSetParams {
   float* Y;
 };
 
-// Shell walk of the curved geometry in FP64 for training targets: the same law
-// as the propagation kernel's FP32 walk (the impact-parameter deficit
-// D = (R + h) - p carried without radius-sized subtractions, chords
-// (ha - hb)(2R + ha + hb) / (ra ca + rb cb), central angle asin(p l / (ra rb)),
-// turning inside a shell, total reflection at a boundary), in double so that
-// the targets are limited by the physics rather than by rounding. Start at
-// height h0 with local zenith cosine c0 (downward). Returns false if the ray
-// does not reach the sphere R + h_obs.
-__device__ bool shell_walk_f64(const float4* __restrict__ lay, float2 sp, double dh, int n_layers, double h_obs,
-                               double Re, double h0, double c0, double& psi, double& len, double& opt,
-                               double& tau) {
-  const double s0 = sqrt((1.0 - c0) * (1.0 + c0));
-  int i = min((int)(h0 / dh), n_layers - 1);
-  const int obs = (int)floor(h_obs / dh);
-  const double A = Re + h0;
-  const double c1 = c0 * c0 / (1.0 + s0);
-  const double d0 = (double)lay[i].x;
-  auto bracket = [&](int k) {
-    const double dk = (double)lay[k].x;
-    return c1 - s0 * (d0 - dk) / (1.0 + dk);
-  };
-  double h = h0;
-  psi = len = opt = tau = 0.0;
-  bool down = c0 > 0.0;
-  for (int iter = 0; iter < 8 * n_layers; ++iter) {
-    const double br = bracket(i);
-    const double ra = Re + h;
-    const double Da = A * br + (h - h0);
-    const double rca = sqrt(fmax(Da * (2.0 * ra - Da), 0.0));
-    const double pa = ra - Da;
-    const double ext = (double)lay[i].z * sp.x + (double)lay[i].w * sp.y;
-    double ell, dpsi;
-    bool to_top = false;
-    if (down) {
-      const double hb = (i == obs) ? h_obs : i * dh;
-      const double Db = A * br + (hb - h0);
-      if (Db > 0.0) {
-        const double rb = Re + hb;
-        const double rcb = sqrt(Db * (2.0 * rb - Db));
-        ell = (h - hb) * (2.0 * Re + h + hb) / (rca + rcb);
-        dpsi = asin(pa * ell / (ra * rb));
-        h = hb;
-      } else {
-        const double ho = (i + 1) * dh;
-        const double ro = Re + ho;
-        const double Do = A * br + (ho - h0);
-        const double rco = sqrt(fmax(Do * (2.0 * ro - Do), 0.0));
-        ell = rca + rco;
-        dpsi = atan2(rca, pa) + atan2(rco, pa);
-        h = ho;
-        down = false;
-        to_top = true;
-      }
-    } else {
-      const double ho = (i + 1) * dh;
-      const double ro = Re + ho;
-      const double Do = A * br + (ho - h0);
-      const double rco = sqrt(fmax(Do * (2.0 * ro - Do), 0.0));
-      ell = (ho - h) * (2.0 * Re + ho + h) / (rco + rca);
-      dpsi = asin(pa * ell / (ra * ro));
-      h = ho;
-      to_top = true;
-    }
-    len += ell;
-    opt += (double)lay[i].x * ell;
-    tau += ext * ell;
-    psi += dpsi;
-    if (!to_top) {
-      if (i == obs) return true;
-      if (!(A * bracket(i - 1) + (h - h0) > 0.0)) {
-        down = false;
-        continue;
-      }
-      --i;
-      continue;
-    }
-    if (i + 1 >= n_layers) return false;
-    if (!(A * bracket(i + 1) + (h - h0) > 0.0)) {
-      down = true;
-      continue;
-    }
-    ++i;
-  }
-  return false;
-}
-
 __global__ __launch_bounds__(256) void k_training_set(TrainSetParams p) {
   __shared__ float4 s_lay[kMaxLayers];
   __shared__ float2 s_lam[kMaxLambdaBins];
@@ -169,21 +84,21 @@ __global__ __launch_bounds__(256) void k_training_set(TrainSetParams p) {
   float* y = p.Y + 4 * j;
   if (p.geometry == CPHOT_SURROGATE_CURVED) {
     // by the spherical symmetry the start is above the Earth point (0, 0); the
-    // chord from there to the sphere R + h_obs, cancellation-free, in FP64
-    const double Re = p.earth_radius, he = h_e, ho = h_obs, c0 = ct;
-    const double r0 = Re + he, r1 = Re + ho, s0 = sqrt((1.0 - c0) * (1.0 + c0));
-    const double drs = (he - ho) * (r0 + r1);
-    const double s_ch = drs / (r0 * c0 + sqrt(r0 * r0 * c0 * c0 - drs));
-    const double psi_s = asin(s_ch * s0 / r1);
-    double psi, len, opt, tau;
-    if (!shell_walk_f64(s_lay, s_lam[kb], (double)p.dh, p.n_layers, ho, Re, he, c0, psi, len, opt, tau)) {
+    // chord from there to the sphere R + h_obs, in FP64
+    const double Re = p.earth_radius, he = h_e, ho = h_obs;
+    double s_ch, psi_s;
+    chord_f64(Re, ho, he, (double)ct, s_ch, psi_s);
+    Walk64 w;
+    if (!shell_walk_f64(s_lay, (double)p.dh, p.n_layers, ho, Re, he, (double)ct, w)) {
       y[0] = y[1] = y[2] = y[3] = __builtin_nanf("");
       return;
     }
+    const float2 sp = s_lam[kb];
+    const double tau = (double)sp.x * w.tR + (double)sp.y * w.tA;
     // per metre of chord: the absolute quantities grow with the slant distance
-    y[0] = (float)((psi - psi_s) * r1 / s_ch);
+    y[0] = (float)((w.across - psi_s) * (Re + ho) / s_ch);
     y[1] = 0.f;  // across the plane of the start direction: zero by symmetry
-    y[2] = (float)(((len - s_ch) + opt) / s_ch);
+    y[2] = (float)(((w.len - s_ch) + w.opt) / s_ch);
     y[3] = (float)(-tau / s_ch);
     return;
   }

@@ -48,7 +48,8 @@ def test_library_loads_without_gpu():
 
 STRUCTS = {"cphot_atmosphere_desc": cphot.AtmosphereDesc, "cphot_segments": cphot.Segments,
            "cphot_detector": cphot.Detector, "cphot_bins": cphot.Bins, "cphot_surrogate_desc": cphot.SurrogateDesc,
-           "cphot_tuning": cphot.Tuning, "cphot_host_segments": cphot.HostSegments}
+           "cphot_tuning": cphot.Tuning, "cphot_host_segments": cphot.HostSegments,
+           "cphot_table_desc": cphot.TableDesc}
 
 
 def test_ctypes_layouts_match_header(tmp_path):
