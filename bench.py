@@ -12,7 +12,8 @@ The same JSON line carries:
 - cpu_baseline: the FP64 CPU oracle on the same workload on the host cores;
 - surrogate: the transport network trained on the GPU from 1e7 exact-tracer
   photons, then run on the same workload, with its per-bin density error against
-  the exact tracer (same photons) and the straight line's for comparison;
+  the exact tracer (same photons) and the straight line's for comparison; beside
+  it the thesis's own fast method, the interpolated correction table;
 - batched: 256 showers of uneven size in one captured launch per step, launch
   shape and bunch picked by the autotuner;
 - inclined: the large inclined shower (curved Earth, Cherenkov + fluorescence,
@@ -189,17 +190,25 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
     det_l = cphot.make_detector(atm, **{**run, "transport": "straight"})
     ms_l, _, b_l, _ = run_path(det_l)
     photons = float(c_s[3]) * run["bunch"]
+    # the thesis's own fast method: the correction interpolated from a table
+    tb = time.perf_counter()
+    tab = cphot.Table(atm, run["h_obs"], "planar", c_lo=0.4)
+    tab_build_s = time.perf_counter() - tb
+    det_t = cphot.make_detector(atm, **{**run, "transport": "table"}, table=tab)
+    ms_t, kern_t, b_t, c_t = run_path(det_t)
 
     def grid_density(S_, geom_, grid_run):
         """Exact vs surrogate vs straight line on a ground grid (same photons)."""
         out = {}
-        for name in ("layered", "surrogate", "straight"):
+        for name in ("layered", "surrogate", "straight", "table"):
             d = cphot.make_detector(atm, **{**grid_run, "transport": name},
-                                    surrogate=sur if name == "surrogate" else None)
+                                    surrogate=sur if name == "surrogate" else None,
+                                    table=tab if name == "table" else None)
             b = torch.zeros(grid_run["nx"] * grid_run["ny"], dtype=torch.int64, device="cuda")
             cphot.propagate(S_, d, b, None, None, stream=stream)
             out[name] = b.cpu().numpy()
         return {"surrogate": density_error(out["surrogate"], out["layered"]),
+                "table": density_error(out["table"], out["layered"]),
                 "straight_line": density_error(out["straight"], out["layered"]),
                 "photons": float(out["layered"].sum())}
 
@@ -220,6 +229,11 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
         "tiny_vertical_shower_grid": tiny_grid,
         "straight_line_without_correction": {"ms_per_step": ms_l,
                                              "density_error_vs_exact": density_error(b_l, exact_bins)},
+        "table": {"value": float(c_t[3]) * run["bunch"] / (ms_t * 1e-3), "unit": "photons/s", "ms_per_step": ms_t,
+                  "kernel_ms": kern_t, "speedup_vs_exact": exact_ms / ms_t,
+                  "density_error_vs_exact": density_error(b_t, exact_bins),
+                  "fallback_fraction": float(c_t[9]) / max(float(c_t[3]), 1.0), "build_s": tab_build_s,
+                  "note": "interpolation tracing (Sec. 4.4.1): 4 heights per layer x 256 tan-zenith nodes"},
         "network": "5-64-64-4 ReLU, bf16 weights on MFMA 16x16x32, FP32 accumulate",
         "training": {"samples": args.train_samples, "steps": args.train_steps, "batch": 4096,
                      "set_build_s": t1 - t0, "train_s": t2 - t1,
@@ -379,6 +393,19 @@ def bench_inclined(torch, cphot, W, args, stream):
                             "note": "fluorescence photons beyond 66 deg local zenith are traced exactly"}
         log(f"inclined surrogate: {out['surrogate']['value']:.3e} photons/s, "
             f"worst bin {out['surrogate']['density_error_vs_exact']['worst_bin']}")
+        t0 = time.perf_counter()
+        tab = cphot.Table(atm, run["h_obs"], "curved", n_c=512, c_lo=0.15)
+        tab_build_s = time.perf_counter() - t0
+        det_t = cphot.make_detector(atm, **{**run, "transport": "table"}, table=tab)
+        ms_t, kern_t, b_t, c_t = run_with(det_t)
+        out["table"] = {"value": float(c_t[3]) * run["bunch"] / (ms_t * 1e-3), "unit": "photons/s",
+                        "ms_per_step": ms_t, "kernel_ms": kern_t, "speedup_vs_exact": ms / ms_t,
+                        "density_error_vs_exact": density_error(b_t, exact_bins),
+                        "fallback_fraction": float(c_t[9]) / max(float(c_t[3]), 1.0), "build_s": tab_build_s,
+                        "note": "interpolation tracing (Sec. 4.4.1), curved shells: 4 heights per shell x 512 "
+                                "tan-zenith nodes up to 81 deg"}
+        log(f"inclined table: {out['table']['value']:.3e} photons/s, "
+            f"worst bin {out['table']['density_error_vs_exact']['worst_bin']}")
     del S, seg
     if args.inclined_chunks > 0:
         chunks = [sh] + [W.workload_inclined_chunk(c, beta=args.beta) for c in range(1, args.inclined_chunks)]
