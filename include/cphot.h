@@ -182,10 +182,11 @@ typedef struct {
   double time_bin_ns;       /* width of a time bin, ns */
   int32_t block_size;       /* tuning: threads per block (0 = library choice) */
   int32_t grid_blocks;      /* tuning: blocks of the persistent grid (0 = library choice) */
-  int32_t lds_hist;         /* tuning: 1 = privatise the grid histogram in LDS (the whole grid if it
-                               fits, else a window around the grid centre), 0 = global atomics only,
+  int32_t lds_hist;         /* tuning: 1 = privatise the counts in LDS (GRID: the whole grid if it
+                               fits, else a window around the grid centre; SPHERES: the whole sphere
+                               array, an error if it does not fit), 0 = global atomics only,
                                -1 = library choice */
-  int32_t hist_window;      /* tuning: LDS window side in cells (0 = the largest that fits) */
+  int32_t hist_window;      /* tuning: GRID LDS window side in cells (0 = the largest that fits) */
   const cphot_surrogate* surrogate; /* SURROGATE transport: a trained network (else NULL) */
   int32_t emission;         /* CPHOT_EMIT_* bits (0 = Cherenkov) */
   int32_t reserved2;

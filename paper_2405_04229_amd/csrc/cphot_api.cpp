@@ -307,13 +307,30 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
       lds = (size_t)w * h * 4;
     }
   }
+  // spheres: the whole array of sphere counts in LDS when it fits (hits cluster
+  // on the few spheres near the core, whose device atomics would serialise)
+  if (mode == cphot::MODE_PROPAGATE && p.detector == CPHOT_DETECTOR_SPHERES && det->lds_hist != 0) {
+    const size_t stat = cphot::propagate_static_lds(p, mode, bs);
+    const size_t room = stat < kLdsBudget ? (kLdsBudget - stat) / 4 : 0;
+    const size_t nsph = (size_t)p.snx * p.sny;
+    if (nsph > room) {
+      if (det->lds_hist == 1) return fail(CPHOT_ERR_INVALID_ARG, "the sphere counts do not fit in LDS");
+    } else {
+      p.lds_hist = 1;
+      p.hist_w = p.snx;
+      p.hist_h = p.sny;
+      lds = nsph * 4;
+    }
+  }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   const int64_t tiles = (p.n + bs - 1) / bs;
   // One block per tile lets the dispatcher balance uneven tiles. With an LDS
   // histogram a persistent grid (a few blocks per CU, each over a contiguous
   // range of tiles) amortises the window's zeroing and flushes.
-  int64_t g = det->grid_blocks > 0 ? det->grid_blocks : (p.lds_hist ? (int64_t)cu_count(dev) * 4 : tiles);
+  // Sphere counts are few, so their flush stays cheap at one block per tile.
+  const bool persistent = p.lds_hist && p.detector == CPHOT_DETECTOR_GRID;
+  int64_t g = det->grid_blocks > 0 ? det->grid_blocks : (persistent ? (int64_t)cu_count(dev) * 4 : tiles);
   if (g > tiles) g = tiles;
   if (g < 1) g = 1;
   s.block = bs;

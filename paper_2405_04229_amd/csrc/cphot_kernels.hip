@@ -132,14 +132,24 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
   return r;
 }
 
-// Linsley vertical depth in FP32 (g/cm^2).
+// Linsley vertical depth in FP32 (g/cm^2). The piece's constants are chosen by
+// selects over the five pieces: indexing the kernel-argument arrays with a
+// per-lane index would turn into vector loads from argument memory.
 __device__ __forceinline__ float depth_f(const KParams& p, float h) {
-  int i = 0;
+  float a = p.la[0], b = p.lb[0], ic = p.linv_c[0];
+  bool top = false;
 #pragma unroll
-  for (int j = 1; j < 5; ++j) i += (h >= p.hb[j]) ? 1 : 0;
+  for (int j = 1; j < 5; ++j) {
+    if (h >= p.hb[j]) {
+      a = p.la[j];
+      b = p.lb[j];
+      ic = p.linv_c[j];
+      top = (j == 4);
+    }
+  }
   const float hcm = h * 100.0f;
-  if (i < 4) return p.la[i] + p.lb[i] * __expf(-hcm * p.linv_c[i]);
-  return p.la[4] - p.lb[4] * hcm * p.linv_c[4];
+  if (!top) return a + b * __expf(-hcm * ic);
+  return a - b * hcm * ic;
 }
 
 // Integral of n - 1 from height lo to height hi (m), closed form per profile.
@@ -208,7 +218,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     ux = sz * cphi;
     uy = sz * sphi;
     uz = -cz;
-    lam = p.fl_lambda[band];
+    lam = band == 0u ? p.fl_lambda[0] : (band == 1u ? p.fl_lambda[1] : p.fl_lambda[2]);
     u3 = u24(w.w);
   }
   o.lam = lam;
@@ -525,16 +535,18 @@ __device__ __forceinline__ int shower_of(const KParams& p, int64_t i) {
 }
 
 // Adds the LDS window of shower `sh` (record counts) to the global bins with
-// the bunch weight, and clears it. Called by the whole block.
-template <int BS>
+// the bunch weight, and clears it. Called by the whole block. The window is a
+// rectangle of grid cells, or the whole sphere array.
+template <int BS, int DETECTOR>
 __device__ void flush_window(const KParams& p, uint32_t* s_hist, int sh) {
   const int n = p.hist_w * p.hist_h;
-  const int64_t base = (int64_t)sh * p.nx * p.ny;
+  const int row = DETECTOR == CPHOT_DETECTOR_GRID ? p.nx : p.snx;
+  const int64_t base = (int64_t)sh * row * (DETECTOR == CPHOT_DETECTOR_GRID ? p.ny : p.sny);
   for (int b = threadIdx.x; b < n; b += BS) {
     const uint32_t v = s_hist[b];
     if (v) {
       const int ly = b / p.hist_w, lx = b - ly * p.hist_w;
-      const int64_t gb = base + (int64_t)(p.hist_y0 + ly) * p.nx + (p.hist_x0 + lx);
+      const int64_t gb = base + (int64_t)(p.hist_y0 + ly) * row + (p.hist_x0 + lx);
       const unsigned long long w = (unsigned long long)v * (unsigned long long)p.bunch;
       if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + gb, (double)w);
       else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, w);
@@ -578,15 +590,16 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   __shared__ uint32_t s_qn;
   __shared__ uint4 s_mlpx[kMlp ? BS : 1];  // per-wave staging of the network's inputs and outputs
   const MlpImage* s_img = reinterpret_cast<const MlpImage*>(s_imgw);
-  // Optional LDS window of the grid (record counts of one shower at a time).
-  // With it each block walks a contiguous range of tiles, so the window changes
-  // shower only a few times per block; records outside the window, or of another
-  // shower than the window's, go to the global bins directly.
+  // Optional LDS window of the grid, or the whole sphere array (record counts of
+  // one shower at a time). With it each block walks a contiguous range of tiles,
+  // so the window changes shower only a few times per block; records outside the
+  // window, or of another shower than the window's, go to the global bins
+  // directly. Without it every hit is a device atomic, and hits on one sphere
+  // serialise on its cache line.
   extern __shared__ uint32_t s_hist[];
   __shared__ int s_win_sh, s_tile_sh;
   __shared__ uint32_t s_since;  // records since the last flush (keeps LDS counts below 2^32)
-  const int n_hist =
-      (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_GRID && p.lds_hist) ? p.hist_w * p.hist_h : 0;
+  const int n_hist = (MODE == MODE_PROPAGATE && p.lds_hist) ? p.hist_w * p.hist_h : 0;
   const int tid = threadIdx.x;
 
   if constexpr (kLayers) {
@@ -621,7 +634,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       __syncthreads();
       // per tile at most BS << 20 records: flushing at 2^31 keeps counts below 2^32
       if (s_tile_sh != s_win_sh || s_since >= (1u << 31)) {
-        if (s_win_sh >= 0) flush_window<BS>(p, s_hist, s_win_sh);
+        if (s_win_sh >= 0) flush_window<BS, DETECTOR>(p, s_hist, s_win_sh);
         __syncthreads();
         if (tid == 0) {
           s_win_sh = s_tile_sh;
@@ -758,9 +771,13 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
           } else {
             const int64_t nsph = (int64_t)p.snx * p.sny;
             const int64_t gb = (int64_t)sh * nsph + ph.bin;
-            if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + gb, (double)(float)p.bunch);
-            else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
-            else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + gb, p.bunch);
+            if (n_hist && (int)sh == s_win_sh) {
+              atomicAdd(&s_hist[ph.bin], 1u);
+            } else {
+              if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + gb, (double)(float)p.bunch);
+              else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
+              else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + gb, p.bunch);
+            }
             if (p.n_t > 0) atomicAdd(p.thist + gb * (p.n_t + 1) + ph.tbin, p.bunch);
           }
         }
@@ -824,7 +841,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   if constexpr (MODE == MODE_PROPAGATE) {
     if (n_hist) {
       __syncthreads();
-      if (s_win_sh >= 0) flush_window<BS>(p, s_hist, s_win_sh);
+      if (s_win_sh >= 0) flush_window<BS, DETECTOR>(p, s_hist, s_win_sh);
     }
     if (p.counters) {
       // block-level reduction: one global atomic per counter per block (same-address

@@ -116,6 +116,60 @@ def test_lds_window_bins_identical_to_global_atomics(bs):
             assert torch.equal(cnt, ref_c), (window, grid)
 
 
+@pytest.mark.parametrize("bs", [128, 256, 512])
+def test_lds_sphere_counts_identical_to_global_atomics(bs):
+    """Sphere counts privatised in LDS (flushed when a block's shower changes)
+    give the same bins and time histograms as global atomics alone, for u32, u64
+    and FP64 bins, several grid sizes and block sizes, across shower boundaries
+    inside tiles and blocks."""
+    seg, offs, geom = _batch(n=20, seed=17)
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    run = {**cases.RUN_TELESCOPE, "snx": 12, "sny": 9, "pitch": 20.0, "radius": 5.0, "n_t": 64, "dt": 4.0,
+           "seed": 12}
+    sg, g, off = cphot.upload(seg, geom, offs)
+    S = cphot.make_segments(sg, g, off)
+    ns, nsph = geom.shape[0], 12 * 9
+    for dtype in (torch.int32, torch.int64, torch.float64):
+        bins = torch.zeros(ns * nsph, dtype=dtype, device="cuda")
+        th = torch.zeros(ns * nsph * 65, dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(16, dtype=torch.int64, device="cuda")
+        cphot.propagate(S, cphot.make_detector(atm, **run, block_size=bs, lds_hist=0), bins, th, cnt)
+        torch.cuda.synchronize()
+        ref_b, ref_t, ref_c = bins.clone(), th.clone(), cnt.clone()
+        assert int(ref_c[7]) > 2_000
+        for grid in (0, 7, 1024):
+            bins.zero_()
+            th.zero_()
+            cnt.zero_()
+            d = cphot.make_detector(atm, **run, block_size=bs, grid_blocks=grid, lds_hist=1)
+            cphot.propagate(S, d, bins, th, cnt)
+            torch.cuda.synchronize()
+            assert torch.equal(bins, ref_b), (dtype, grid)
+            assert torch.equal(th, ref_t), (dtype, grid)
+            assert torch.equal(cnt, ref_c), (dtype, grid)
+
+
+def test_lds_sphere_counts_that_do_not_fit():
+    """A sphere array too large for LDS: an error when LDS is demanded, global
+    atomics under the library's choice, with the same bins."""
+    sh = W.make_shower(20_000, seed=22, xmax=500.0, zenith_deg=20.0, beta="R")
+    g = np.array([[*sh.core, *sh.axis]])
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    run = {**cases.RUN_TELESCOPE, "snx": 200, "sny": 200, "pitch": 2.0, "radius": 0.5, "n_t": 0, "seed": 5}
+    seg, gg, off = cphot.upload(sh.seg, g)
+    S = cphot.make_segments(seg, gg, off)
+    bins = torch.zeros(200 * 200, dtype=torch.int64, device="cuda")
+    with pytest.raises(cphot.CphotError, match="LDS"):
+        cphot.propagate(S, cphot.make_detector(atm, **run, lds_hist=1), bins)
+    out = []
+    for lds in (-1, 0):
+        bins.zero_()
+        cphot.propagate(S, cphot.make_detector(atm, **run, lds_hist=lds), bins)
+        torch.cuda.synchronize()
+        out.append(bins.clone())
+    assert torch.equal(out[0], out[1]) and int(out[0].sum()) > 1000
+
+
 def test_lds_window_f64_and_large_single_grid():
     """One shower on a grid far larger than LDS (window in the middle), FP64 and
     u64 bins: identical to global atomics."""
