@@ -272,6 +272,15 @@ struct LaunchShape {
 // of tiles and flushes its window when the shower changes, so global atomics are
 // paid per window cell and block rather than per photon.
 constexpr size_t kLdsBudget = 64 * 1024;  // per block, static + dynamic
+constexpr size_t kLdsPerCu = 160 * 1024;
+
+// LDS a block may hold while a CU still runs four waves per SIMD (the occupancy
+// the exact tracers' registers allow; kernels with more registers run fewer
+// waves and are then only more conservative): 160 KB over 16 / (BS / 64) blocks.
+size_t lds_at_four_waves(int bs) {
+  const int blocks = std::max(1, 16 / (bs / 64));
+  return kLdsPerCu / (size_t)blocks - 1024;  // margin for the allocation granule
+}
 
 int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchShape& s) {
   int bs = det->block_size ? det->block_size : 256;
@@ -279,9 +288,10 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
   if (det->hist_window < 0) return fail(CPHOT_ERR_INVALID_ARG, "hist_window must be >= 0");
   size_t lds = 0;
   p.lds_hist = 0;
-  p.hist_w = p.hist_h = p.hist_x0 = p.hist_y0 = 0;
+  p.hist_w = p.hist_h = p.hist_x0 = p.hist_y0 = p.hist_tw = 0;
+  const size_t stat =
+      (mode == cphot::MODE_PROPAGATE && det->lds_hist != 0) ? cphot::propagate_static_lds(p, mode, bs) : 0;
   if (mode == cphot::MODE_PROPAGATE && p.detector == CPHOT_DETECTOR_GRID && det->lds_hist != 0) {
-    const size_t stat = cphot::propagate_static_lds(p, mode, bs);
     const size_t room = stat < kLdsBudget ? (kLdsBudget - stat) / 4 : 0;  // cells that fit
     int w = p.nx, h = p.ny;
     if ((size_t)w * h > room || det->hist_window > 0) {
@@ -308,9 +318,12 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
     }
   }
   // spheres: the whole array of sphere counts in LDS when it fits (hits cluster
-  // on the few spheres near the core, whose device atomics would serialise)
+  // on the few spheres near the core, whose device atomics would serialise), and
+  // with it the leading time bins of every sphere, where the hits of the spheres
+  // near the core arrive (delays after the plane front of a few to tens of ns);
+  // later bins stay global. The time part takes only the LDS that leaves the
+  // occupancy the kernel's registers allow.
   if (mode == cphot::MODE_PROPAGATE && p.detector == CPHOT_DETECTOR_SPHERES && det->lds_hist != 0) {
-    const size_t stat = cphot::propagate_static_lds(p, mode, bs);
     const size_t room = stat < kLdsBudget ? (kLdsBudget - stat) / 4 : 0;
     const size_t nsph = (size_t)p.snx * p.sny;
     if (nsph > room) {
@@ -319,7 +332,12 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
       p.lds_hist = 1;
       p.hist_w = p.snx;
       p.hist_h = p.sny;
-      lds = nsph * 4;
+      const size_t cap = std::min(kLdsBudget, lds_at_four_waves(bs));
+      if (p.n_t > 0 && cap > stat + nsph * 4) {
+        const size_t tb = std::min((cap - stat) / 4 - nsph, room - nsph) / nsph;
+        p.hist_tw = (int)std::min<size_t>(tb, (size_t)p.n_t + 1);
+      }
+      lds = nsph * (1 + (size_t)p.hist_tw) * 4;
     }
   }
   int dev = 0;

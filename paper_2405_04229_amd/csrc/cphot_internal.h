@@ -83,6 +83,7 @@ struct KParams {
   int32_t lds_hist;                    // grid counts privatised in an LDS window
   int32_t hist_w, hist_h;              // window size in cells (x, y)
   int32_t hist_x0, hist_y0;            // window origin in cells
+  int32_t hist_tw;                     // spheres: leading time bins of each sphere held in LDS too
   uint32_t* thist;
   unsigned long long* counters;
   // debug outputs
@@ -116,6 +117,8 @@ double table_h_obs(const cphot_table* t);
 hipError_t launch_propagate(const KParams& p, int mode, int block_size, int grid_blocks, size_t lds_hist_bytes,
                             hipStream_t stream);
 // Static LDS bytes of the propagate kernel that `p`, `mode` and `block_size` select.
+// Static LDS bytes of the propagation kernel instance a launch would use (0 if
+// it cannot be queried).
 size_t propagate_static_lds(const KParams& p, int mode, int block_size);
 
 }  // namespace cphot

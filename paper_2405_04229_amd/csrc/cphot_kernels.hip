@@ -132,18 +132,24 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
   return r;
 }
 
-// Linsley vertical depth in FP32 (g/cm^2). The piece's constants are chosen by
-// selects over the five pieces: indexing the kernel-argument arrays with a
-// per-lane index would turn into vector loads from argument memory.
+// Uniform kernel argument forced into a scalar register: a per-lane select
+// between such values can then not be turned into a per-lane load from argument
+// memory (whose pending count would also make later rounds wait for the device
+// atomics).
+__device__ __forceinline__ float sgpr(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Linsley vertical depth in FP32 (g/cm^2); the piece's constants by selects.
 __device__ __forceinline__ float depth_f(const KParams& p, float h) {
-  float a = p.la[0], b = p.lb[0], ic = p.linv_c[0];
+  float a = sgpr(p.la[0]), b = sgpr(p.lb[0]), ic = sgpr(p.linv_c[0]);
   bool top = false;
 #pragma unroll
   for (int j = 1; j < 5; ++j) {
     if (h >= p.hb[j]) {
-      a = p.la[j];
-      b = p.lb[j];
-      ic = p.linv_c[j];
+      a = sgpr(p.la[j]);
+      b = sgpr(p.lb[j]);
+      ic = sgpr(p.linv_c[j]);
       top = (j == 4);
     }
   }
@@ -218,7 +224,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     ux = sz * cphi;
     uy = sz * sphi;
     uz = -cz;
-    lam = band == 0u ? p.fl_lambda[0] : (band == 1u ? p.fl_lambda[1] : p.fl_lambda[2]);
+    lam = band == 0u ? sgpr(p.fl_lambda[0]) : (band == 1u ? sgpr(p.fl_lambda[1]) : sgpr(p.fl_lambda[2]));
     u3 = u24(w.w);
   }
   o.lam = lam;
@@ -554,6 +560,19 @@ __device__ void flush_window(const KParams& p, uint32_t* s_hist, int sh) {
       s_hist[b] = 0u;
     }
   }
+  if constexpr (DETECTOR == CPHOT_DETECTOR_SPHERES) {
+    // leading time bins of every sphere, after the sphere counts
+    const int nt = n * p.hist_tw;
+    uint32_t* s_t = s_hist + n;
+    for (int b = threadIdx.x; b < nt; b += BS) {
+      const uint32_t v = s_t[b];
+      if (v) {
+        const int sph = b / p.hist_tw, tb = b - sph * p.hist_tw;
+        atomicAdd(p.thist + (base + sph) * (p.n_t + 1) + tb, v * (uint32_t)p.bunch);
+        s_t[b] = 0u;
+      }
+    }
+  }
 }
 
 template <int BS, int TRANSPORT, int DETECTOR, int MODE>
@@ -599,7 +618,9 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   extern __shared__ uint32_t s_hist[];
   __shared__ int s_win_sh, s_tile_sh;
   __shared__ uint32_t s_since;  // records since the last flush (keeps LDS counts below 2^32)
-  const int n_hist = (MODE == MODE_PROPAGATE && p.lds_hist) ? p.hist_w * p.hist_h : 0;
+  const int n_hist = (MODE == MODE_PROPAGATE && p.lds_hist)
+                         ? p.hist_w * p.hist_h * (DETECTOR == CPHOT_DETECTOR_SPHERES ? 1 + p.hist_tw : 1)
+                         : 0;
   const int tid = threadIdx.x;
 
   if constexpr (kLayers) {
@@ -771,14 +792,18 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
           } else {
             const int64_t nsph = (int64_t)p.snx * p.sny;
             const int64_t gb = (int64_t)sh * nsph + ph.bin;
-            if (n_hist && (int)sh == s_win_sh) {
+            const bool win = n_hist && (int)sh == s_win_sh;
+            if (win) {
               atomicAdd(&s_hist[ph.bin], 1u);
             } else {
               if (p.bins_f64) atomicAdd(reinterpret_cast<double*>(p.bins) + gb, (double)(float)p.bunch);
               else if (p.bins_u64) atomicAdd(reinterpret_cast<unsigned long long*>(p.bins) + gb, (unsigned long long)p.bunch);
               else atomicAdd(reinterpret_cast<uint32_t*>(p.bins) + gb, p.bunch);
             }
-            if (p.n_t > 0) atomicAdd(p.thist + gb * (p.n_t + 1) + ph.tbin, p.bunch);
+            if (p.n_t > 0) {
+              if (win && ph.tbin < p.hist_tw) atomicAdd(&s_hist[nsph + ph.bin * p.hist_tw + ph.tbin], 1u);
+              else atomicAdd(p.thist + gb * (p.n_t + 1) + ph.tbin, p.bunch);
+            }
           }
         }
       }

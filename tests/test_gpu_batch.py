@@ -124,7 +124,7 @@ def test_lds_sphere_counts_identical_to_global_atomics(bs):
     inside tiles and blocks."""
     seg, offs, geom = _batch(n=20, seed=17)
     atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
-    run = {**cases.RUN_TELESCOPE, "snx": 12, "sny": 9, "pitch": 20.0, "radius": 5.0, "n_t": 64, "dt": 4.0,
+    run = {**cases.RUN_TELESCOPE, "snx": 12, "sny": 9, "pitch": 20.0, "radius": 5.0, "n_t": 64, "dt": 0.1,
            "seed": 12}
     sg, g, off = cphot.upload(seg, geom, offs)
     S = cphot.make_segments(sg, g, off)
@@ -137,6 +137,9 @@ def test_lds_sphere_counts_identical_to_global_atomics(bs):
         torch.cuda.synchronize()
         ref_b, ref_t, ref_c = bins.clone(), th.clone(), cnt.clone()
         assert int(ref_c[7]) > 2_000
+        # hits inside and beyond the leading time bins held in LDS, and overflow
+        t = ref_t.view(ns * nsph, 65).sum(0).cpu().numpy()
+        assert t[:20].sum() > 0 and t[40:64].sum() > 0 and t[64] > 0, t
         for grid in (0, 7, 1024):
             bins.zero_()
             th.zero_()
