@@ -32,8 +32,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X public figures: 256 CUs, 2.4 GHz peak engine clock, 64 VALU lanes per CU per clock.
-PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
+# MI355X public figures: 256 CUs at 2.4 GHz and 157.3 TFLOP/s FP32 vector, an FMA
+# counted as two flops: 128 FP32 lane-operations per CU per clock. (The counters
+# show the exact kernel issuing more than one wave64 VALU instruction per CU per
+# clock without packed FP32, so a 64-lane ceiling would understate the peak.)
+PEAK_VALU_LANE_OPS = 256 * 128 * 2.4e9
 PEAK_HBM = 8.0e12
 
 # Algorithmic VALU lane-slots per unit of work (counted from the method's steps;
@@ -127,6 +130,17 @@ def cpu_baseline(sh, run, atmo, target_s=12.0):
                       f"pass, {passes} passes in {total:.1f} s"}
 
 
+def tuned_detector(cphot, S, atm, run, bins, th, cnt, stream, **extra):
+    """Detector with the autotuner's launch shape for this workload; the bunch
+    stays the workload's own (it defines the workload, not the launch)."""
+    det0 = cphot.make_detector(atm, **run, **extra)
+    t0 = time.perf_counter()
+    tune = cphot.autotune(S, det0, bins, th, cnt, bunches=[run["bunch"]], reps=3, stream=stream)
+    tune["tune_s"] = time.perf_counter() - t0
+    shape = {k: tune[k] for k in ("block_size", "grid_blocks", "lds_hist", "hist_window")}
+    return cphot.make_detector(atm, **run, **shape, **extra), tune
+
+
 def mean_layer_crossings(torch, cphot, sh, geom, det, run, n=20000):
     """Mean number of layer boundaries a record crosses, from traced records of
     the first n segments."""
@@ -185,16 +199,22 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
         ms, kern = time_steps(torch, step, args.steps, args.warmup, stream)
         return ms, kern, bins.cpu().numpy(), cnt.cpu().numpy()
 
-    det_s = cphot.make_detector(atm, **{**run, "transport": "surrogate"}, surrogate=sur)
+    def tuned(transport, **extra):
+        b = torch.zeros(nsph, dtype=torch.int64, device="cuda")
+        t = torch.zeros(nsph * (run["n_t"] + 1), dtype=torch.int32, device="cuda")
+        c = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+        return tuned_detector(cphot, S, atm, {**run, "transport": transport}, b, t, c, stream, **extra)
+
+    det_s, tune_s = tuned("surrogate", surrogate=sur)
     ms, kern, b_s, c_s = run_path(det_s)
-    det_l = cphot.make_detector(atm, **{**run, "transport": "straight"})
+    det_l, _ = tuned("straight")
     ms_l, _, b_l, _ = run_path(det_l)
     photons = float(c_s[3]) * run["bunch"]
     # the thesis's own fast method: the correction interpolated from a table
     tb = time.perf_counter()
     tab = cphot.Table(atm, run["h_obs"], "planar", c_lo=0.4)
     tab_build_s = time.perf_counter() - tb
-    det_t = cphot.make_detector(atm, **{**run, "transport": "table"}, table=tab)
+    det_t, tune_t = tuned("table", table=tab)
     ms_t, kern_t, b_t, c_t = run_path(det_t)
 
     def grid_density(S_, geom_, grid_run):
@@ -224,7 +244,7 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
         "value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
         "speedup_vs_exact": exact_ms / ms,
         "density_error_vs_exact": density_error(b_s, exact_bins),
-        "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0),
+        "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0), "tuning": tune_s,
         "grid_10m_same_shower": tele_grid,
         "tiny_vertical_shower_grid": tiny_grid,
         "straight_line_without_correction": {"ms_per_step": ms_l,
@@ -233,6 +253,7 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
                   "kernel_ms": kern_t, "speedup_vs_exact": exact_ms / ms_t,
                   "density_error_vs_exact": density_error(b_t, exact_bins),
                   "fallback_fraction": float(c_t[9]) / max(float(c_t[3]), 1.0), "build_s": tab_build_s,
+                  "tuning": tune_t,
                   "note": "interpolation tracing (Sec. 4.4.1): 4 heights per layer x 256 tan-zenith nodes"},
         "network": "5-64-64-4 ReLU, bf16 weights on MFMA 16x16x32, FP32 accumulate",
         "training": {"samples": args.train_samples, "steps": args.train_steps, "batch": 4096,
@@ -402,6 +423,7 @@ def bench_inclined(torch, cphot, W, args, stream):
                         "ms_per_step": ms_t, "kernel_ms": kern_t, "speedup_vs_exact": ms / ms_t,
                         "density_error_vs_exact": density_error(b_t, exact_bins),
                         "fallback_fraction": float(c_t[9]) / max(float(c_t[3]), 1.0), "build_s": tab_build_s,
+                  "tuning": tune_t,
                         "note": "interpolation tracing (Sec. 4.4.1), curved shells: 4 heights per shell x 512 "
                                 "tan-zenith nodes up to 81 deg"}
         log(f"inclined table: {out['table']['value']:.3e} photons/s, "
@@ -472,13 +494,14 @@ def main():
     sh = W.workload_telescope(args.beta)
     geom = np.array([[*sh.core, *sh.axis]])
     atm = cphot.Atmosphere(**W.ATMO_LAYERED)
-    det = cphot.make_detector(atm, **run)
     seg, g, off = cphot.upload(sh.seg, geom)
     S = cphot.make_segments(seg, g, off)
     nsph = run["snx"] * run["sny"]
     bins = torch.zeros(nsph, dtype=torch.int64, device="cuda")
     th = torch.zeros(nsph * (run["n_t"] + 1), dtype=torch.int32, device="cuda")
     cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    det, tune = tuned_detector(cphot, S, atm, run, bins, th, cnt, stream)
+    log(f"telescope autotune: {tune}")
 
     def step(ev):
         bins.zero_()
@@ -505,7 +528,8 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
                 "unit": "Tlane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": traffic_if_current(),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                "kernel": "k_propagate<256,LAYERED,SPHERES,PROPAGATE>", "kernel_ms": kern_ms,
+                "kernel": f"k_propagate<{tune['block_size']},LAYERED,SPHERES,PROPAGATE>", "kernel_ms": kern_ms,
+                "tuning": tune,
                 "algorithmic_slots_per_launch": slots, "mean_layer_crossings": mean_cross,
                 "hbm_gbps_algorithmic": n_seg * SEGMENT_BYTES / (kern_ms * 1e-3) / 1e9}
     out = {

@@ -211,6 +211,8 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     p.obs_layer = (int)std::floor(det->h_obs / (d.h_top / d.n_layers));
     p.layers = a->dev.layers;
     p.lambins = a->dev.lambins;
+    p.moments = a->dev.moments ? a->dev.moments + (size_t)p.obs_layer * d.n_layers * 5 : nullptr;
+    p.series_tmax = a->dev.moments ? a->dev.series_tmax : 0.f;
   }
   const int64_t ns = seg->n_showers;
   if (det->detector == CPHOT_DETECTOR_GRID) {
@@ -437,8 +439,9 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
   // Layer tables. Each layer's extinction per metre factorises into a height
   // part and a wavelength part: Rayleigh (X(lo) - X(hi)) / dh times 1/Lambda(lambda_k),
   // plus the aerosol column (exp(-lo/H) - exp(-hi/H)) / dh times tau_A(lambda_k).
-  std::vector<float4> lay;
+  std::vector<float4> lay, mom;
   std::vector<float2> lamb;
+  float series_tmax = 0.f;
   if (d.n_layers > 0) {
     const int L = d.n_layers, K = d.n_lambda_bins;
     const double dh = d.h_top / L;
@@ -455,6 +458,38 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
                              : 0.0;
       lay[i] = make_float4((float)dl, (float)(1.0 / (1.0 + dl)), (float)ray, (float)aer);
     }
+    // Moments for the closed-form layer sums: row (obs, j) sums over the full
+    // layers i, obs < i < j, in FP64 (e_i = (n_i - n_j) / n_i, u_i = e_i (2 - e_i)),
+    // with dh and the coefficients a1 = -1/2, a2 = 3/8, a3 = -5/16 of
+    // (1 + x)^(-1/2) folded in. The series serves photons with tan^2(zenith) up
+    // to 5.4e-3 / max|u| (at most 9), where the truncated terms stay negligible.
+    mom.assign((size_t)L * L * 5, make_float4(0.f, 0.f, 0.f, 0.f));
+    const double a1 = -0.5, a2 = 0.375, a3 = -0.3125;
+    double umax = 0.0;
+    for (int j = 1; j < L; ++j) {
+      double S[17] = {0.0};  // U1..3, EU0..2, E2U0..1, D0..2, R0..2, A0..2 (sums, without dh)
+      for (int obs = j - 1; obs >= 0; --obs) {
+        float4* r = &mom[((size_t)obs * L + j) * 5];
+        r[0] = make_float4((float)(dh * a1 * S[0]), (float)(dh * a2 * S[1]), (float)(dh * a3 * S[2]), (float)(dh * S[3]));
+        r[1] = make_float4((float)(dh * a1 * S[4]), (float)(dh * a2 * S[5]), (float)(dh * S[6]), (float)(dh * a1 * S[7]));
+        r[2] = make_float4((float)(dh * S[8]), (float)(dh * a1 * S[9]), (float)(dh * a2 * S[10]), (float)(dh * S[11]));
+        r[3] = make_float4((float)(dh * a1 * S[12]), (float)(dh * a2 * S[13]), (float)(dh * S[14]), (float)(dh * a1 * S[15]));
+        r[4] = make_float4((float)(dh * a2 * S[16]), (float)(dh * (j - obs - 1)), 0.f, 0.f);
+        // layer obs joins the sums of the rows below it
+        const int i = obs;
+        const double di = (double)lay[i].x, dj = (double)lay[j].x;
+        const double e = (di - dj) / (1.0 + di), u = e * (2.0 - e);
+        umax = std::max(umax, std::fabs(u));
+        const double Ri = (double)lay[i].z, Ai = (double)lay[i].w;
+        S[0] += u; S[1] += u * u; S[2] += u * u * u;
+        S[3] += e; S[4] += e * u; S[5] += e * u * u;
+        S[6] += e * e; S[7] += e * e * u;
+        S[8] += di; S[9] += di * u; S[10] += di * u * u;
+        S[11] += Ri; S[12] += Ri * u; S[13] += Ri * u * u;
+        S[14] += Ai; S[15] += Ai * u; S[16] += Ai * u * u;
+      }
+    }
+    series_tmax = (float)std::min(9.0, umax > 0.0 ? 5.4e-3 / umax : 9.0);
     for (int k = 0; k < K; ++k) {
       const double lam = d.lambda_min_nm + (k + 0.5) * (d.lambda_max_nm - d.lambda_min_nm) / K;
       const double r = lam / 400.0;
@@ -480,6 +515,10 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
     if ((e = hipMemcpy(a->dev.layers, lay.data(), lay.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(a->dev.lambins, lamb.data(), lamb.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup(0, "hipMemcpy(layers)", e);
+    if ((e = hipMalloc(&a->dev.moments, mom.size() * sizeof(float4))) != hipSuccess) return cleanup(0, "hipMalloc", e);
+    if ((e = hipMemcpy(a->dev.moments, mom.data(), mom.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(0, "hipMemcpy(moments)", e);
+    a->dev.series_tmax = series_tmax;
   }
   *out = a;
   return CPHOT_OK;
@@ -493,6 +532,7 @@ void cphot_destroy_atmosphere(cphot_atmosphere* a) {
   if (a->dev.delta_table) (void)hipFree(a->dev.delta_table);
   if (a->dev.layers) (void)hipFree(a->dev.layers);
   if (a->dev.lambins) (void)hipFree(a->dev.lambins);
+  if (a->dev.moments) (void)hipFree(a->dev.moments);
   (void)hipSetDevice(prev);
   delete a;
 }

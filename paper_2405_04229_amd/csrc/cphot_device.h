@@ -175,6 +175,85 @@ __device__ __forceinline__ void layer_walk(const float4* __restrict__ lay, float
   w.last_ext = fmaf(L.z, sp.x, L.w * sp.y);
 }
 
+// Closed-form layer sums for planar layers. Below the start layer j every full
+// layer i (obs < i < j, thickness dh) is crossed with 1/c_i = (1/c0) w_i,
+// w_i = (1 + t u_i)^(-1/2), t = tan^2 of the start zenith angle and
+// u_i = e_i (2 - e_i), e_i = (n_i - n_j) / n_i (Snell's law as in the crossing
+// loop). Expanding w_i in powers of t u_i turns every sum the loop accumulates
+// (travel, optical depth, optical path, geometric delay) into a polynomial in t
+// whose coefficients depend only on (obs, j): moments of the layers' refractivity
+// differences, tabulated once per atmosphere in FP64 (`mom`, five float4 per
+// start layer, dh and the series coefficients folded in):
+//   m0 = (a1 U1, a2 U2, a3 U3, EU0)   m1 = (a1 EU1, a2 EU2, E2U0, a1 E2U1)
+//   m2 = (D0, a1 D1, a2 D2, R0)       m3 = (a1 R1, a2 R2, A0, a1 A1)
+//   m4 = (a2 A2, N dh, 0, 0)
+// with U_m = dh sum u^m, EU_m = dh sum e u^m, E2U_m = dh sum e^2 u^m,
+// D_m = dh sum (n_i - 1) u^m, R_m / A_m = dh sum (Rayleigh / aerosol part) u^m,
+// N = j - obs - 1 and a1 = -1/2, a2 = 3/8, a3 = -5/16. The geometric delay is
+// expanded about the start direction v0, |v_i - a|^2 = |v0 - a|^2
+// + 2 (v0 - a).(v_i - v0) + |v_i - v0|^2, so that no near-equal lengths are
+// subtracted. With |t u| <= 5.4e-3 (the caller's bound) the truncated terms are
+// below 2e-5 m over 32 km of layers. The start layer itself is crossed straight
+// (e = 0). Outputs as layer_walk's at the top of the observation layer.
+template <bool NEED_TIME>
+__device__ __forceinline__ void layer_series(const float4* __restrict__ lay, const float4* __restrict__ mom,
+                                             float2 sp, float dh, int j, int obs_layer, float Px, float Py,
+                                             float Pz, float ux, float uy, float uz, float axx, float axy,
+                                             float axz, LayerWalk& w) {
+  const float sh = sqrtf(ux * ux + uy * uy);
+  float hx = 1.f, hy = 0.f;
+  if (sh > 0.f) {
+    const float ish = 1.0f / sh;
+    hx = ux * ish;
+    hy = uy * ish;
+  }
+  const float s0 = sh, c0 = -uz;
+  const float4* m = mom + 5 * j;
+  const float4 m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4];
+  const float4 Lj = lay[j], Lo = lay[obs_layer];
+  const float ic0 = 1.0f / c0;
+  const float tn = s0 * ic0, t = tn * tn;
+  const float span = Pz - (float)j * dh;
+  const float Ws = t * fmaf(t, fmaf(t, m0.z, m0.y), m0.x);  // dh sum (w - 1)
+  const float Wd = m4.y + Ws;                                // dh sum w
+  const float EWd = fmaf(t, fmaf(t, m1.y, m1.x), m0.w);      // dh sum e w
+  const float adv = tn * (span + (Wd - EWd));
+  w.x = fmaf(hx, adv, Px);
+  w.y = fmaf(hy, adv, Py);
+  w.z = (float)(obs_layer + 1) * dh;
+  const float Rd = fmaf(t, fmaf(t, m3.y, m3.x), m2.w);
+  const float Ad = fmaf(t, fmaf(t, m4.x, m3.w), m3.z);
+  w.tau = ic0 * fmaf(fmaf(Lj.z, sp.x, Lj.w * sp.y), span, fmaf(sp.x, Rd, sp.y * Ad));
+  w.geo = 0.f;
+  w.opt = 0.f;
+  if constexpr (NEED_TIME) {
+    const float Dd = fmaf(t, fmaf(t, m2.z, m2.y), m2.x);
+    w.opt = ic0 * fmaf(Lj.x, span, Dd);
+    const float ex = fmaf(s0, hx, -axx), ey = fmaf(s0, hy, -axy), ez = -c0 - axz;
+    const float G = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+    const float gh = fmaf(hx, ex, hy * ey);
+    const float E2Wd = fmaf(t, m1.w, m1.z);                                       // dh sum e^2 w
+    const float Qd = t * t * fmaf(t, m0.z * 0.8f, m0.y * (2.0f / 3.0f));         // dh sum (1 - w)^2 / w
+    const float inner = fmaf(G, span + Wd, fmaf(-2.0f * s0 * gh, EWd, s0 * s0 * E2Wd));
+    w.geo = 0.5f * fmaf(ic0, inner, fmaf(2.0f * ez, Ws, c0 * Qd));
+  }
+  float s, c2, e;
+  layer_angle(s0, c0, Lj.x, Lo.x, Lo.y, s, c2, e);
+  const float c = sqrtf(c2);
+  w.vx = s * hx;
+  w.vy = s * hy;
+  w.vz = -c;
+  w.last_delta = Lo.x;
+  w.last_ext = fmaf(Lo.z, sp.x, Lo.w * sp.y);
+  w.s0 = s0;
+  w.c0 = c0;
+  w.d0 = Lj.x;
+  w.hx = hx;
+  w.hy = hy;
+  w.dr = 0.f;
+  w.gex = 0.f;
+}
+
 // Curved Earth (Sec. 3.3.4): the layers are spherical shells about the Earth
 // centre. Within a shell a ray keeps its impact parameter; at a boundary the
 // vector form of Snell's law with the radial normal conserves Bouguer's

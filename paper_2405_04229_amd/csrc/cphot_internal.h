@@ -23,6 +23,10 @@ struct AtmoDevice {
   // the extinction of layer i at wavelength bin k is lay.z * lam[k].x + lay.w * lam[k].y
   float4* layers = nullptr;        // n_layers
   float2* lambins = nullptr;       // n_lam: (1 / Rayleigh length in g/cm^2, aerosol vertical depth)
+  // closed-form layer sums: [obs][j][5] float4 moments of the full layers
+  // between observation layer obs and start layer j (planar transport)
+  float4* moments = nullptr;
+  float series_tmax = 0.f;         // largest tan^2(zenith) the series may serve
 };
 
 // Everything a launch needs, passed by value as the kernel argument.
@@ -58,6 +62,8 @@ struct KParams {
   float dh, inv_dh;
   int32_t obs_layer;
   const float4* layers;
+  const float4* moments;  // rows of the observation layer's slice, by start layer
+  float series_tmax;      // 0: crossing loop only
   const float2* lambins;
   int32_t nx, ny;
   float cell, inv_cell;

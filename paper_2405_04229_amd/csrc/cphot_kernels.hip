@@ -396,8 +396,14 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
         return;
       }
       LayerWalk lw;
-      layer_walk<NEED_TIME, false>(s_lay, s_lam[kb], p.dh, min((int)(Pz * p.inv_dh), p.n_layers - 1),
-                                   p.obs_layer, Px, Py, Pz, ux, uy, uz, axx, axy, axz, lw);
+      const int j0 = min((int)(Pz * p.inv_dh), p.n_layers - 1);
+      // closed-form sums where the series holds, the crossing loop elsewhere
+      if (j0 > p.obs_layer && fmaf(ux, ux, uy * uy) <= p.series_tmax * (uz * uz))
+        layer_series<NEED_TIME>(s_lay, p.moments, s_lam[kb], p.dh, j0, p.obs_layer, Px, Py, Pz, ux, uy, uz, axx,
+                                axy, axz, lw);
+      else
+        layer_walk<NEED_TIME, false>(s_lay, s_lam[kb], p.dh, j0, p.obs_layer, Px, Py, Pz, ux, uy, uz, axx, axy,
+                                     axz, lw);
       x = lw.x;
       y = lw.y;
       z = lw.z;
