@@ -44,20 +44,25 @@ PEAK_HBM = 8.0e12
 SLOTS_PER_SEGMENT = 350.0
 SLOTS_PER_RECORD_BASE = 320.0
 SLOTS_PER_LAYER_CROSSING = 22.0
+SLOTS_PER_SERIES = 60.0  # closed-form layer sums: five Horner polynomials, delay terms, final direction
+SERIES_TAN2_MAX = 9.0    # the series bound of the standard atmospheres (tan^2 zenith <= 9)
 SEGMENT_BYTES = 32.0
 
 METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density error"
 
 # HBM bytes per launch of the exact telescope kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# scaled by a plain copy's factors (2.00, 1.00); valid only for the kernel sources they were
-# taken on (sha256 prefixes), else the roofline's traffic is reported as null.
-TRAFFIC_BYTES = 33.15e6 + 4.61e6
-TRAFFIC_SOURCES = {"cphot_kernels.hip": "e87f6e1f1717f548", "cphot_device.h": "c4233a688074585e",
-                   "cphot_internal.h": "445fcc8e0fb39e77"}
+# scaled by a plain copy's factors (2.00, 1.00); valid only for the sources and launch shape they
+# were taken on (sha256 prefixes; block size, grid, LDS counts), else reported as null.
+TRAFFIC_BYTES = 16249 * 1024 * 2.00 + 288 * 1024 * 1.00
+TRAFFIC_SOURCES = {"cphot_kernels.hip": "dc5914b9f0deff7e", "cphot_device.h": "7d0517c0cdac951a",
+                   "cphot_internal.h": "b3b6918589cbace4", "cphot_api.cpp": "702143955f7ae9af"}
+TRAFFIC_SHAPE = (512, 512, 1)
 
 
-def traffic_if_current():
+def traffic_if_current(tune):
     import hashlib
+    if (tune["block_size"], tune["grid_blocks"], tune["lds_hist"]) != TRAFFIC_SHAPE:
+        return None
     for name, want in TRAFFIC_SOURCES.items():
         path = os.path.join(ROOT, "paper_2405_04229_amd", "csrc", name)
         with open(path, "rb") as f:
@@ -141,9 +146,11 @@ def tuned_detector(cphot, S, atm, run, bins, th, cnt, stream, **extra):
     return cphot.make_detector(atm, **run, **shape, **extra), tune
 
 
-def mean_layer_crossings(torch, cphot, sh, geom, det, run, n=20000):
-    """Mean number of layer boundaries a record crosses, from traced records of
-    the first n segments."""
+def walk_profile(torch, cphot, sh, geom, det, run, n=20000):
+    """From traced records of the first n segments: the fraction of downward
+    records the closed-form layer sums serve (tan^2 zenith within the series
+    bound, start above the observation layer) and the mean number of layer
+    boundaries the others cross in the loop."""
     sample = {k: v[:n] for k, v in sh.seg.items()}
     sg, sgg, _ = cphot.upload(sample, geom)
     SS = cphot.make_segments(sg, sgg, None)
@@ -160,7 +167,13 @@ def mean_layer_crossings(torch, cphot, sh, geom, det, run, n=20000):
     zmid = 0.5 * (sample["z0"].astype(np.float64) + sample["z1"])
     start_layer = np.minimum((zmid[r["seg"].astype(np.int64)] // dh).astype(np.int64), 99)
     crossings = np.maximum(start_layer - obs_layer, 0)
-    return float(crossings[r["state"] != 1].mean()) if len(r) else 0.0
+    down = r["state"] != 1
+    tan2 = (r["dx"].astype(np.float64) ** 2 + r["dy"].astype(np.float64) ** 2) / np.maximum(
+        r["dz"].astype(np.float64) ** 2, 1e-30)
+    series = down & (crossings > 0) & (tan2 <= SERIES_TAN2_MAX)
+    loop = down & ~series
+    n_down = max(int(down.sum()), 1)
+    return float(series.sum()) / n_down, float(crossings[loop].sum()) / n_down
 
 
 def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_ms, stream):
@@ -423,7 +436,6 @@ def bench_inclined(torch, cphot, W, args, stream):
                         "ms_per_step": ms_t, "kernel_ms": kern_t, "speedup_vs_exact": ms / ms_t,
                         "density_error_vs_exact": density_error(b_t, exact_bins),
                         "fallback_fraction": float(c_t[9]) / max(float(c_t[3]), 1.0), "build_s": tab_build_s,
-                  "tuning": tune_t,
                         "note": "interpolation tracing (Sec. 4.4.1), curved shells: 4 heights per shell x 512 "
                                 "tan-zenith nodes up to 81 deg"}
         log(f"inclined table: {out['table']['value']:.3e} photons/s, "
@@ -497,16 +509,17 @@ def main():
     seg, g, off = cphot.upload(sh.seg, geom)
     S = cphot.make_segments(seg, g, off)
     nsph = run["snx"] * run["sny"]
-    bins = torch.zeros(nsph, dtype=torch.int64, device="cuda")
-    th = torch.zeros(nsph * (run["n_t"] + 1), dtype=torch.int32, device="cuda")
-    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    # the step's outputs in one buffer, cleared by one fill per step
+    nb, nc, nt = nsph * 8, cphot.NCOUNTERS * 8, nsph * (run["n_t"] + 1) * 4
+    out_buf = torch.zeros(nb + nc + nt, dtype=torch.uint8, device="cuda")
+    bins = out_buf[:nb].view(torch.int64)
+    cnt = out_buf[nb:nb + nc].view(torch.int64)
+    th = out_buf[nb + nc:].view(torch.int32)
     det, tune = tuned_detector(cphot, S, atm, run, bins, th, cnt, stream)
     log(f"telescope autotune: {tune}")
 
     def step(ev):
-        bins.zero_()
-        th.zero_()
-        cnt.zero_()
+        out_buf.zero_()
         if ev is not None:
             ev[0].record(stream)
         cphot.propagate(S, det, bins, th, cnt, stream=stream)
@@ -521,16 +534,18 @@ def main():
     photons = records * run["bunch"]
     value = photons / (ms_per_step * 1e-3)
 
-    mean_cross = mean_layer_crossings(torch, cphot, sh, geom, det, run)
+    series_frac, loop_cross = walk_profile(torch, cphot, sh, geom, det, run)
     n_seg = float(sh.n)
-    slots = n_seg * SLOTS_PER_SEGMENT + records * (SLOTS_PER_RECORD_BASE + SLOTS_PER_LAYER_CROSSING * mean_cross)
+    slots = n_seg * SLOTS_PER_SEGMENT + records * (SLOTS_PER_RECORD_BASE + SLOTS_PER_SERIES * series_frac +
+                                                   SLOTS_PER_LAYER_CROSSING * loop_cross)
     achieved = slots / (kern_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
-                "unit": "Tlane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": traffic_if_current(),
+                "unit": "Tlane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": traffic_if_current(tune),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                 "kernel": f"k_propagate<{tune['block_size']},LAYERED,SPHERES,PROPAGATE>", "kernel_ms": kern_ms,
                 "tuning": tune,
-                "algorithmic_slots_per_launch": slots, "mean_layer_crossings": mean_cross,
+                "algorithmic_slots_per_launch": slots, "series_fraction": series_frac,
+                "loop_crossings_per_record": loop_cross,
                 "hbm_gbps_algorithmic": n_seg * SEGMENT_BYTES / (kern_ms * 1e-3) / 1e9}
     out = {
         "metric": METRIC,

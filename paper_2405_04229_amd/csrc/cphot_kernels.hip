@@ -132,30 +132,29 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
   return r;
 }
 
-// Uniform kernel argument forced into a scalar register: a per-lane select
-// between such values can then not be turned into a per-lane load from argument
-// memory (whose pending count would also make later rounds wait for the device
-// atomics).
-__device__ __forceinline__ float sgpr(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+// Per-block copy in LDS of the small kernel-argument arrays that records index
+// per lane (Linsley pieces, fluorescence band wavelengths): indexing argument
+// memory per lane would become vector loads from it, and holding the values in
+// scalar registers would add to a scalar register file that is already full.
+struct KConst {
+  float4 lin[5];  // (lower bound (m), a, b, 1/c (1/cm)) per Linsley piece
+  float4 fl;      // band wavelengths (nm)
+};
+
+__device__ __forceinline__ void load_kconst(const KParams& p, KConst& k, int tid) {
+  if (tid < 5) k.lin[tid] = make_float4(p.hb[tid], p.la[tid], p.lb[tid], p.linv_c[tid]);
+  if (tid == 5) k.fl = make_float4(p.fl_lambda[0], p.fl_lambda[1], p.fl_lambda[2], 0.f);
 }
 
-// Linsley vertical depth in FP32 (g/cm^2); the piece's constants by selects.
-__device__ __forceinline__ float depth_f(const KParams& p, float h) {
-  float a = sgpr(p.la[0]), b = sgpr(p.lb[0]), ic = sgpr(p.linv_c[0]);
-  bool top = false;
+// Linsley vertical depth in FP32 (g/cm^2).
+__device__ __forceinline__ float depth_f(const KConst& k, float h) {
+  int i = 0;
 #pragma unroll
-  for (int j = 1; j < 5; ++j) {
-    if (h >= p.hb[j]) {
-      a = sgpr(p.la[j]);
-      b = sgpr(p.lb[j]);
-      ic = sgpr(p.linv_c[j]);
-      top = (j == 4);
-    }
-  }
+  for (int j = 1; j < 5; ++j) i += (h >= k.lin[j].x) ? 1 : 0;
+  const float4 c = k.lin[i];
   const float hcm = h * 100.0f;
-  if (!top) return a + b * __expf(-hcm * ic);
-  return a - b * hcm * ic;
+  if (i < 4) return c.y + c.z * __expf(-hcm * c.w);
+  return c.y - c.z * hcm * c.w;
 }
 
 // Integral of n - 1 from height lo to height hi (m), closed form per profile.
@@ -184,7 +183,7 @@ struct Photon {
 template <int TRANSPORT, int DETECTOR, bool NEED_TIME>
 __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict__ s_lay,
                                       const float2* __restrict__ s_lam, const MlpImage* __restrict__ s_img,
-                                      uint4* s_stage,
+                                      const KConst* __restrict__ s_k, uint4* s_stage,
                                       const float4 q0, const float4 q1, const float4 q2, const float4 q3,
                                       const float4 q4, const float axz, const uint4 q5, uint32_t k, bool valid,
                                       Photon& o) {
@@ -224,7 +223,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     ux = sz * cphi;
     uy = sz * sphi;
     uz = -cz;
-    lam = band == 0u ? sgpr(p.fl_lambda[0]) : (band == 1u ? sgpr(p.fl_lambda[1]) : sgpr(p.fl_lambda[2]));
+    lam = (&s_k->fl.x)[band];
     u3 = u24(w.w);
   }
   o.lam = lam;
@@ -492,7 +491,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     const float Xe = fmaf(f, dX, X0);
     float X_end = p.X_obs;
     if constexpr (DETECTOR == CPHOT_DETECTOR_SPHERES) {
-      if (p.profile == CPHOT_PROFILE_LINSLEY5) X_end = depth_f(p, ez);
+      if (p.profile == CPHOT_PROFILE_LINSLEY5) X_end = depth_f(*s_k, ez);
     }
     if (p.has_ray) {
       const float r = 400.0f / lam;
@@ -614,6 +613,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   __shared__ uint32_t s_qk[kDefer ? 2 * BS : 1];
   __shared__ uint32_t s_qn;
   __shared__ uint4 s_mlpx[kMlp ? BS : 1];  // per-wave staging of the network's inputs and outputs
+  __shared__ KConst s_k;
   const MlpImage* s_img = reinterpret_cast<const MlpImage*>(s_imgw);
   // Optional LDS window of the grid, or the whole sphere array (record counts of
   // one shower at a time). With it each block walks a contiguous range of tiles,
@@ -637,6 +637,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     const uint4* src = reinterpret_cast<const uint4*>(p.mlp);
     for (int i = tid; i < (int)(sizeof(MlpImage) / 16); i += BS) s_imgw[i] = src[i];
   }
+  load_kconst(p, s_k, tid);
   for (int i = tid; i < n_hist; i += BS) s_hist[i] = 0u;
   if (tid == 0) {
     s_win_sh = -1;
@@ -693,8 +694,8 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
         const int sh = shower_of(p, i);
         float X0 = 0.f, dXs = 0.f;
         if (TRANSPORT == CPHOT_TRANSPORT_STRAIGHT && p.profile == CPHOT_PROFILE_LINSLEY5) {
-          X0 = depth_f(p, fz0);
-          dXs = depth_f(p, fz1) - X0;
+          X0 = depth_f(s_k, fz0);
+          dXs = depth_f(s_k, fz1) - X0;
         }
         const double* g = p.geom + 5 * sh;
         q0 = make_float4(fx0, fy0, fz0, r.cos_t);
@@ -825,7 +826,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       const uint32_t k = j - s_off[lo];
       Photon ph;
       const float4 r3 = s_q3[lo];
-      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
+      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, &s_k, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
                                         s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], s_q5[lo], k, valid, ph);
       if constexpr (kDefer) {
         // wave-level compaction: deferred records take consecutive queue slots
@@ -854,7 +855,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
             const uint32_t qk = s_qk[q];
             const float4 q3 = s_q3[qlo];
             Photon pe;
-            trace<kExact, DETECTOR, kTime>(p, s_lay, s_lam, s_img, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
+            trace<kExact, DETECTOR, kTime>(p, s_lay, s_lam, s_img, &s_k, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
                                            s_q4[qlo], s_axz[qlo], s_q5[qlo], qk, true, pe);
             pe.fallback = 1;
             consume(pe, qlo, qk, q3);
