@@ -94,6 +94,26 @@ extern "C" {
 #define CPHOT_EMIT_CHERENKOV 1
 #define CPHOT_EMIT_FLUORESCENCE 2
 
+/* Data-reduction cuts for the SPHERES detector (bit set; Sec. 4.3.2 filter level 1 and
+ * Sec. 4.3.4 filter level 3, Sec. 6.2). Both are geometric bounds that never remove a
+ * photon that could reach a sphere, so bins and time histograms equal those of the
+ * same call without cuts; only the counters show the removed records.
+ * TRACK: a segment's Cherenkov records are not generated when every photon of its cone
+ *   (from any point of the segment, half-angle theta) lands farther from every sphere
+ *   than the bound: the cone's landing disc around the axis's landing point has radius
+ *   H (theta / cos^2(zeta + theta)) (H the segment's top above h_obs, zeta the track's
+ *   zenith angle), widened by the refraction bound and by r / cos of the steepest
+ *   direction. Fluorescence records are never cut (isotropic emission).
+ * PHOTON: a record whose straight line lands farther from the nearest sphere centre
+ *   than r / cos(zeta) plus the refraction bound is outside before its transport.
+ * Refraction bound: H tan(zeta) E (1 + 3 tan^2(zeta)) x 1.1 + 0.5 m, E the largest
+ *   |n_i - n_j| / n_i over the layers above the observation layer (0 for STRAIGHT).
+ *   Directions with cos(zeta) <= 0.2, or with 2.2 tan^2(zeta) E > 0.25, are never cut.
+ * Cuts act in cphot_propagate (and captured steps) only; the parity entry points
+ * (counts, records) ignore them. */
+#define CPHOT_CUT_TRACK 1
+#define CPHOT_CUT_PHOTON 2
+
 /* Bin element types of cphot_bins.bins (F64: FP64 sums of the FP32 bunch weights). */
 #define CPHOT_BINS_U32 0
 #define CPHOT_BINS_U64 1
@@ -112,6 +132,9 @@ extern "C" {
 #define CPHOT_C_PHOTONS_BINNED 8            /* records_binned x bunch size */
 #define CPHOT_C_SURROGATE_FALLBACK 9        /* records traced exactly because outside the surrogate's domain */
 #define CPHOT_C_RECORDS_FLUORESCENCE 10     /* fluorescence records among records_generated */
+#define CPHOT_C_RECORDS_CULLED_TRACK 11     /* Cherenkov records of segments removed by CPHOT_CUT_TRACK
+                                               (never generated, not in records_generated) */
+#define CPHOT_C_RECORDS_CULLED_PHOTON 12    /* records removed by CPHOT_CUT_PHOTON (among records_outside) */
 
 typedef struct cphot_atmosphere cphot_atmosphere;
 typedef struct cphot_surrogate cphot_surrogate;
@@ -189,7 +212,7 @@ typedef struct {
   int32_t hist_window;      /* tuning: GRID LDS window side in cells (0 = the largest that fits) */
   const cphot_surrogate* surrogate; /* SURROGATE transport: a trained network (else NULL) */
   int32_t emission;         /* CPHOT_EMIT_* bits (0 = Cherenkov) */
-  int32_t reserved2;
+  int32_t cuts;             /* CPHOT_CUT_* bits (SPHERES with STRAIGHT, LAYERED or TABLE transport; else 0) */
   double fl_yield[3];       /* fluorescence photons per MeV deposited, per band */
   double fl_lambda[3];      /* band wavelengths, nm (inside the atmosphere's band) */
   const cphot_table* table; /* TABLE transport: a correction table built for this atmosphere and h_obs */

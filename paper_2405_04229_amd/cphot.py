@@ -24,6 +24,7 @@ NCOUNTERS = 16
 
 PROFILE = {"linsley5": 0, "homogeneous": 1, "linear": 2}
 TRANSPORT = {"straight": 0, "layered": 1, "surrogate": 2, "curved": 3, "table": 4}
+CUTS = {"track": 1, "photon": 2}  # data-reduction bounds for spheres (never drop a possible hit)
 EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
 DETECTOR = {"grid": 0, "spheres": 1}
 SPECTRUM = {"uniform": 0, "frank_tamm": 1}
@@ -63,7 +64,7 @@ class Detector(C.Structure):
                 ("pitch", C.c_double), ("radius", C.c_double), ("n_time_bins", C.c_int32),
                 ("reserved0", C.c_int32), ("time_bin_ns", C.c_double), ("block_size", C.c_int32),
                 ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("hist_window", C.c_int32),
-                ("surrogate", C.c_void_p), ("emission", C.c_int32), ("reserved2", C.c_int32),
+                ("surrogate", C.c_void_p), ("emission", C.c_int32), ("cuts", C.c_int32),
                 ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3), ("table", C.c_void_p)]
 
 
@@ -220,7 +221,7 @@ class Atmosphere:
 def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0,
                   h_obs=2200.0, nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0,
                   dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, surrogate=None,
-                  emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0),
+                  emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0), cuts=(),
                   table=None) -> Detector:
     d = Detector()
     d.atm = atm.handle
@@ -232,6 +233,7 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
     d.block_size, d.grid_blocks, d.lds_hist = int(block_size), int(grid_blocks), int(lds_hist)
     d.hist_window = int(hist_window)
     d.emission = EMISSION[emission]
+    d.cuts = sum(CUTS[c] for c in cuts)
     d.fl_yield[:] = tuple(float(v) for v in fl_yield)
     d.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
     if surrogate is not None:

@@ -18,6 +18,7 @@ struct cphot_atmosphere {
   int64_t n_tab = 0;
   cphot::AtmoDevice dev;
   std::vector<double> layer_delta;  // host copies (FP64) for checks
+  std::vector<double> cut_e;        // per observation layer: largest |n_i - n_j| / n_i of the layers above
 };
 
 namespace {
@@ -134,6 +135,11 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     return fail(CPHOT_ERR_INVALID_ARG, "curved transport needs the atmosphere's earth_radius");
   if (det->emission & ~(CPHOT_EMIT_CHERENKOV | CPHOT_EMIT_FLUORESCENCE))
     return fail(CPHOT_ERR_INVALID_ARG, "unknown emission bits");
+  if (det->cuts & ~(CPHOT_CUT_TRACK | CPHOT_CUT_PHOTON)) return fail(CPHOT_ERR_INVALID_ARG, "unknown cut bits");
+  if (det->cuts && (det->detector != CPHOT_DETECTOR_SPHERES || curved ||
+                    (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED &&
+                     det->transport != CPHOT_TRANSPORT_TABLE)))
+    return fail(CPHOT_ERR_UNSUPPORTED, "cuts need SPHERES with STRAIGHT, LAYERED or planar TABLE transport");
   if ((det->emission & CPHOT_EMIT_FLUORESCENCE) && seg->n > 0 && !seg->dedx)
     return fail(CPHOT_ERR_INVALID_ARG, "fluorescence needs the dedx column");
   if (det->detector != CPHOT_DETECTOR_GRID && det->detector != CPHOT_DETECTOR_SPHERES)
@@ -234,6 +240,9 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
       if (det->h_obs - det->radius < lo || det->h_obs + det->radius >= hi)
         return fail(CPHOT_ERR_INVALID_ARG, "spheres must lie inside the layer containing h_obs");
     }
+    p.cuts = need_bins ? det->cuts : 0;  // the parity entry points trace every record
+    if (det->transport != CPHOT_TRANSPORT_STRAIGHT && d.n_layers > 0)
+      p.cut_e = (float)(a->cut_e[(size_t)p.obs_layer] * (1.0 + 1e-6));
     p.snx = det->snx; p.sny = det->sny;
     p.pitch = (float)det->pitch;
     p.inv_pitch = (float)(1.0 / det->pitch);
@@ -490,6 +499,15 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
       }
     }
     series_tmax = (float)std::min(9.0, umax > 0.0 ? 5.4e-3 / umax : 9.0);
+    // refraction bound of the data-reduction cuts: for the layers from obs up,
+    // |n_i - n_j| / n_i <= (max delta - min delta) / (1 + min delta)
+    a->cut_e.assign(L, 0.0);
+    double dmin = 1e300, dmax = -1e300;
+    for (int obs = L - 1; obs >= 0; --obs) {
+      dmin = std::min(dmin, (double)lay[obs].x);
+      dmax = std::max(dmax, (double)lay[obs].x);
+      a->cut_e[(size_t)obs] = (dmax - dmin) / (1.0 + dmin);
+    }
     for (int k = 0; k < K; ++k) {
       const double lam = d.lambda_min_nm + (k + 0.5) * (d.lambda_max_nm - d.lambda_min_nm) / K;
       const double r = lam / 400.0;

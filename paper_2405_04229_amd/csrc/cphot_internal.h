@@ -64,6 +64,8 @@ struct KParams {
   const float4* layers;
   const float4* moments;  // rows of the observation layer's slice, by start layer
   float series_tmax;      // 0: crossing loop only
+  int32_t cuts;           // CPHOT_CUT_* (SPHERES, propagate mode)
+  float cut_e;            // largest |n_i - n_j| / n_i above the observation layer (0 for straight rays)
   const float2* lambins;
   int32_t nx, ny;
   float cell, inv_cell;

@@ -157,6 +157,74 @@ __device__ __forceinline__ float depth_f(const KConst& k, float h) {
   return c.y - c.z * hcm * c.w;
 }
 
+// Squared horizontal distance from (qx, qy) on the observation level to the
+// nearest sphere centre of the shower's array (indices clamped to the array).
+__device__ __forceinline__ float nearest_sphere_d2(const KParams& p, float core_x, float core_y, float qx, float qy) {
+  const float cx0 = core_x - 0.5f * (float)(p.snx - 1) * p.pitch;
+  const float cy0 = core_y - 0.5f * (float)(p.sny - 1) * p.pitch;
+  const float fi = fminf(fmaxf(rintf((qx - cx0) * p.inv_pitch), 0.f), (float)(p.snx - 1));
+  const float fj = fminf(fmaxf(rintf((qy - cy0) * p.inv_pitch), 0.f), (float)(p.sny - 1));
+  const float ex = qx - fmaf(fi, p.pitch, cx0), ey = qy - fmaf(fj, p.pitch, cy0);
+  return fmaf(ex, ex, ey * ey);
+}
+
+// Data-reduction bounds (filter levels 1 and 3, Sec. 4.3.2 / 4.3.4), conservative:
+// a photon reaching a sphere of radius r crosses the observation level within
+// r / cos(final zenith) of its centre, and its crossing lies within the
+// refraction bound of its straight line's: H tan(z) E (1 + 3 tan^2 z) x 1.1 + 0.5 m,
+// E the largest |n_i - n_j| / n_i above the observation layer (|tan z_i - tan z| <=
+// tan z (E + 0.77 x) with x = 2.2 tan^2 z E <= 0.25). Directions steeper than
+// cos z = 0.2, or with x > 0.25, are never cut. `slack` covers FP32 rounding.
+__device__ __forceinline__ float cut_slack(float qx, float qy, float core_x, float core_y, float H) {
+  return 0.5f + 1e-5f * (fabsf(qx - core_x) + fabsf(qy - core_y) + H);
+}
+
+// Filter level 1: can any photon of this segment's Cherenkov cone (half-angle
+// theta, from any point of the segment) reach a sphere? The cone's straight lines
+// land within H theta / cos^2(zeta + theta) of the axis's landing point (the
+// gnomonic projection stretches arcs by at most sec^2 of the largest zenith
+// angle), the same point for every point of the segment.
+__device__ __forceinline__ bool track_may_hit(const KParams& p, float x0, float y0, float z0, float x1, float y1,
+                                              float z1, float cos_t, float sin_t, float core_x, float core_y) {
+  const float dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
+  const float L = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+  if (!(L > 0.f)) return true;
+  const float cz = -dz / L, sz = sqrtf(fmaxf((1.0f - cz) * (1.0f + cz), 0.f));
+  const float cmin = fmaf(cz, cos_t, -sz * sin_t);  // cos of the steepest cone direction
+  if (!(cmin > 0.2f)) return true;
+  const float H = fmaxf(z0, z1) - p.h_obs;
+  if (!(H > 0.f)) return true;
+  const float t2 = (1.0f - cmin * cmin) / (cmin * cmin), tmax = sqrtf(t2);
+  const float x = 2.2f * t2 * p.cut_e;
+  if (!(x <= 0.25f)) return true;
+  const float Rfp = H * (1.01f * sin_t) / (cmin * cmin);
+  const float dref = fmaf(H * tmax * p.cut_e * fmaf(3.0f, t2, 1.0f), 1.1f, 0.5f);
+  const float reff = p.radius / (cmin * sqrtf(1.0f - x));
+  const float s = (p.h_obs - z0) / dz * L;  // along the unit axis from the start point
+  const float qx = fmaf(s, dx / L, x0), qy = fmaf(s, dy / L, y0);
+  const float lim = Rfp + dref + reff + cut_slack(qx, qy, core_x, core_y, H);
+  return nearest_sphere_d2(p, core_x, core_y, qx, qy) <= lim * lim;
+}
+
+// Filter level 3: can this photon, emitted at height Pz > h_obs going down, reach
+// a sphere? Its straight line's crossing of the observation level against the
+// nearest sphere centre.
+__device__ __forceinline__ bool photon_may_hit(const KParams& p, float Px, float Py, float Pz, float ux, float uy,
+                                               float uz, float core_x, float core_y) {
+  const float c = -uz;
+  if (!(c > 0.2f)) return true;
+  const float H = Pz - p.h_obs;
+  const float t2 = fmaf(ux, ux, uy * uy) / (c * c);
+  const float x = 2.2f * t2 * p.cut_e;
+  if (!(x <= 0.25f)) return true;
+  const float dref = fmaf(H * sqrtf(t2) * p.cut_e * fmaf(3.0f, t2, 1.0f), 1.1f, 0.5f);
+  const float reff = p.radius / (c * sqrtf(1.0f - x));
+  const float s = H / c;
+  const float qx = fmaf(s, ux, Px), qy = fmaf(s, uy, Py);
+  const float lim = reff + dref + cut_slack(qx, qy, core_x, core_y, H);
+  return nearest_sphere_d2(p, core_x, core_y, qx, qy) <= lim * lim;
+}
+
 // Integral of n - 1 from height lo to height hi (m), closed form per profile.
 __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float hi, float X_lo, float X_hi) {
   if (p.profile == CPHOT_PROFILE_LINSLEY5) return p.opt_scale * (X_lo - X_hi);
@@ -166,12 +234,15 @@ __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float 
   return p.opt_scale * ((b - a) - (b * b - a * a) / (2.f * t));
 }
 
+template <int T>
+constexpr bool kMlpTransport = (T == CPHOT_TRANSPORT_SURROGATE || T == kTransportCurvedSurrogate);
+
 // A surrogate record outside the network's domain: its transport is redone by the
 // exact tracer in a separate pass over compacted records.
 constexpr int32_t kStateDeferred = 7;
 
 struct Photon {
-  int32_t state, bin, tbin, fallback;
+  int32_t state, bin, tbin, fallback, culled;
   int32_t ix, iy;  // grid cell
   float x, y, z, t, tau, lam, u3, ux, uy, uz;
 };
@@ -231,6 +302,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   o.bin = -1;
   o.tbin = -1;
   o.fallback = 0;
+  o.culled = 0;
   o.t = 0.f;
   o.tau = 0.f;
   o.ux = ux;
@@ -373,6 +445,13 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   if (Pz < p.h_obs) {
     o.state = 3;
     return;
+  }
+  if constexpr (DETECTOR == CPHOT_DETECTOR_SPHERES && !kMlpTransport<TRANSPORT>) {
+    if ((p.cuts & CPHOT_CUT_PHOTON) && !photon_may_hit(p, Px, Py, Pz, ux, uy, uz, core_x, core_y)) {
+      o.state = 3;  // filter level 3: cannot reach a sphere
+      o.culled = 1;
+      return;
+    }
   }
   if constexpr (TRANSPORT == CPHOT_TRANSPORT_TABLE) {
     // correction interpolated from the table (Sec. 4.4.1), in the start layer
@@ -647,7 +726,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
   __syncthreads();
 
   uint32_t c_in = 0, c_skip = 0, c_below = 0, c_gen = 0, c_up = 0, c_abs = 0, c_out = 0, c_bin = 0, c_fb = 0;
-  uint32_t c_fl = 0;
+  uint32_t c_fl = 0, c_cut1 = 0, c_cut3 = 0;
   const int64_t n_tiles = (p.n + BS - 1) / BS;
   int64_t t_first = blockIdx.x, t_end = n_tiles, t_step = gridDim.x;
   if (n_hist) {
@@ -679,8 +758,17 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     if (i < p.n) {
       const float fx0 = p.x0[i], fy0 = p.y0[i], fz0 = p.z0[i], fx1 = p.x1[i], fy1 = p.y1[i], fz1 = p.z1[i];
       const uint64_t id = p.first_id + (uint64_t)i;
-      const SegResult r =
+      SegResult r =
           segment_setup(p, fx0, fy0, fz0, fx1, fy1, fz1, p.beta[i], p.charge[i], p.dedx ? p.dedx[i] : 0.0f, id);
+      if constexpr (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_SPHERES && !kMlpTransport<TRANSPORT>) {
+        if ((p.cuts & CPHOT_CUT_TRACK) && r.n > 0) {
+          const double* gc = p.geom + 5 * shower_of(p, i);
+          if (!track_may_hit(p, fx0, fy0, fz0, fx1, fy1, fz1, r.cos_t, r.sin_t, (float)gc[0], (float)gc[1])) {
+            c_cut1 += (uint32_t)r.n;  // filter level 1: no photon of the cone can reach a sphere
+            r.n = 0;
+          }
+        }
+      }
       c_in += 1;
       c_skip += r.status == 2;
       c_below += r.status == 1;
@@ -779,6 +867,7 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       } else {
         c_gen += 1;
         c_fb += ph.fallback;
+        c_cut3 += ph.culled;
         c_up += ph.state == 1;
         c_abs += ph.state == 2;
         c_out += ph.state == 3;
@@ -878,12 +967,12 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
     if (p.counters) {
       // block-level reduction: one global atomic per counter per block (same-address
       // device atomics serialise, so their number must stay small)
-      __shared__ uint32_t s_cnt[10];
-      if (tid < 10) s_cnt[tid] = 0u;
+      __shared__ uint32_t s_cnt[12];
+      if (tid < 12) s_cnt[tid] = 0u;
       __syncthreads();
-      const uint32_t v[10] = {c_in, c_skip, c_below, c_gen, c_up, c_abs, c_out, c_bin, c_fb, c_fl};
+      const uint32_t v[12] = {c_in, c_skip, c_below, c_gen, c_up, c_abs, c_out, c_bin, c_fb, c_fl, c_cut1, c_cut3};
 #pragma unroll
-      for (int q = 0; q < 10; ++q) {
+      for (int q = 0; q < 12; ++q) {
         const uint32_t sw = wave_sum(v[q]);
         if ((tid & 63) == 0 && sw) atomicAdd(&s_cnt[q], sw);
       }
@@ -892,6 +981,8 @@ __global__ __launch_bounds__(BS) void k_propagate(KParams p) {
       if (tid == 8 && s_cnt[7]) atomicAdd(p.counters + CPHOT_C_PHOTONS_BINNED, (unsigned long long)s_cnt[7] * p.bunch);
       if (tid == 9 && s_cnt[8]) atomicAdd(p.counters + CPHOT_C_SURROGATE_FALLBACK, (unsigned long long)s_cnt[8]);
       if (tid == 10 && s_cnt[9]) atomicAdd(p.counters + CPHOT_C_RECORDS_FLUORESCENCE, (unsigned long long)s_cnt[9]);
+      if (tid == 11 && s_cnt[10]) atomicAdd(p.counters + CPHOT_C_RECORDS_CULLED_TRACK, (unsigned long long)s_cnt[10]);
+      if (tid == 12 && s_cnt[11]) atomicAdd(p.counters + CPHOT_C_RECORDS_CULLED_PHOTON, (unsigned long long)s_cnt[11]);
     }
   }
 }

@@ -1,0 +1,106 @@
+"""Data-reduction cuts for the telescope spheres (filter levels 1 and 3, Sec. 4.3.2,
+4.3.4, 6.2): geometric bounds that must never remove a photon that could reach a
+sphere. With the cuts on, bins and time histograms equal those of the same call
+without them bit for bit; only the counters show the removed records."""
+import numpy as np
+import pytest
+
+from paper_2405_04229_amd import workload as W
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_04229_amd import cphot  # noqa: E402
+
+C_GEN, C_UP, C_ABS, C_OUT, C_BIN = 3, 4, 5, 6, 7
+C_TRACK, C_PHOTON = 11, 12
+
+
+def _run(atm, S, ns, run, cuts, table=None):
+    nsph = run["snx"] * run["sny"]
+    n_t = run.get("n_t", 0)
+    bins = torch.zeros(ns * nsph, dtype=torch.int64, device="cuda")
+    th = torch.zeros(ns * nsph * (n_t + 1), dtype=torch.int32, device="cuda") if n_t else None
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    det = cphot.make_detector(atm, **run, cuts=cuts, table=table)
+    cphot.propagate(S, det, bins, th, cnt)
+    torch.cuda.synchronize()
+    return bins.cpu().numpy(), None if th is None else th.cpu().numpy(), cnt.cpu().numpy()
+
+
+def _check(atm, S, ns, run, table=None, expect_track=True):
+    b0, t0, c0 = _run(atm, S, ns, run, (), table)
+    assert c0[C_BIN] > 0
+    for cuts in (("track",), ("photon",), ("track", "photon")):
+        b, t, c = _run(atm, S, ns, run, cuts, table)
+        np.testing.assert_array_equal(b, b0, err_msg=str(cuts))
+        if t0 is not None:
+            np.testing.assert_array_equal(t, t0, err_msg=str(cuts))
+        assert c[C_BIN] == c0[C_BIN]
+        assert c[C_GEN] == c[C_UP] + c[C_ABS] + c[C_OUT] + c[C_BIN]
+        assert c[C_GEN] + c[C_TRACK] == c0[C_GEN]
+        if "track" in cuts and expect_track:
+            assert c[C_TRACK] > 0, cuts
+        if "photon" in cuts:
+            assert c[C_PHOTON] > 0, cuts
+        else:
+            assert c[C_PHOTON] == 0
+    return c0, c
+
+
+def _segments(sh):
+    g = np.array([[*sh.core, *sh.axis]])
+    seg, gg, off = cphot.upload(sh.seg, g)
+    return cphot.make_segments(seg, gg, off)
+
+
+def test_cuts_exact_on_the_telescope_workload():
+    """Full telescope workload (1e6 segments, 512 time bins): nothing that hits is lost."""
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    S = _segments(W.workload_telescope("R"))
+    c0, c = _check(atm, S, 1, {**cases.RUN_TELESCOPE, "seed": 21})
+    # most records of the telescope workload miss the 10 x 10 spheres; the two filters
+    # remove most of them (the last call above ran both)
+    print(dict(generated=int(c0[C_GEN]), outside=int(c0[C_OUT]), track=int(c[C_TRACK]), photon=int(c[C_PHOTON])))
+    assert c[C_TRACK] + c[C_PHOTON] > 0.5 * c0[C_OUT]
+
+
+@pytest.mark.parametrize("transport", ["straight", "layered", "table"])
+def test_cuts_exact_where_the_light_pool_clips_the_array(transport):
+    """An inclined shower whose light pool edge crosses a dense array of large
+    spheres, so that photons pass close to every bound."""
+    atm = cphot.Atmosphere(**(cases.ATMO_STRAIGHT if transport == "straight" else cases.ATMO_LAYERED))
+    sh = W.make_shower(300_000, seed=803, xmax=450.0, zenith_deg=50.0, azimuth_deg=30.0, beta="R")
+    S = _segments(sh)
+    run = {**cases.RUN_TELESCOPE, "transport": transport, "snx": 9, "sny": 7, "pitch": 40.0, "radius": 10.0,
+           "n_t": 64, "dt": 2.0, "seed": 22}
+    tab = cphot.Table(atm, run["h_obs"], "planar", h_hi=20000.0, c_lo=0.2) if transport == "table" else None
+    _check(atm, S, 1, run, table=tab)
+
+
+def test_cuts_exact_across_showers():
+    """A batch of showers with their own sphere arrays; tiles mix showers."""
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    seg, offs, geom = W.concat_showers(W.make_batch(16, seed=29, beta="R", scale=0.05))
+    sg, g, off = cphot.upload(seg, geom, offs)
+    S = cphot.make_segments(sg, g, off)
+    run = {**cases.RUN_TELESCOPE, "snx": 6, "sny": 6, "pitch": 60.0, "radius": 8.0, "n_t": 32, "dt": 2.0,
+           "seed": 23}
+    _check(atm, S, geom.shape[0], run)
+
+
+def test_cut_argument_errors():
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    S = _segments(W.make_shower(100, seed=804, beta="R"))
+    bins = torch.zeros(100 * 100, dtype=torch.int64, device="cuda")
+    with pytest.raises(cphot.CphotError, match="cuts"):  # grid detector
+        cphot.propagate(S, cphot.make_detector(atm, **{**cases.RUN_TINY, "transport": "layered"},
+                                               cuts=("photon",)), bins)
+    d = cphot.make_detector(atm, **{**cases.RUN_TELESCOPE, "n_t": 0})
+    d.cuts = 4
+    with pytest.raises(cphot.CphotError, match="cut bits"):
+        cphot.propagate(S, d, bins)
