@@ -32,6 +32,13 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
   return make_uint4(c0, c1, c2, c3);
 }
 
+// Hardware reciprocal and square root (about 1 ulp for the normal, positive
+// inputs they get here) where the correctly rounded sequences cost about ten
+// instructions; used on the per-photon planar path, whose tolerances are far
+// above an ulp.
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Random word -> uniform on [0, 1) with 24 bits (exact in FP32).
 __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }
 
@@ -200,10 +207,10 @@ __device__ __forceinline__ void layer_series(const float4* __restrict__ lay, con
                                              float2 sp, float dh, int j, int obs_layer, float Px, float Py,
                                              float Pz, float ux, float uy, float uz, float axx, float axy,
                                              float axz, LayerWalk& w) {
-  const float sh = sqrtf(ux * ux + uy * uy);
+  const float sh = sqrt_fast(ux * ux + uy * uy);
   float hx = 1.f, hy = 0.f;
   if (sh > 0.f) {
-    const float ish = 1.0f / sh;
+    const float ish = rcp_fast(sh);
     hx = ux * ish;
     hy = uy * ish;
   }
@@ -211,7 +218,7 @@ __device__ __forceinline__ void layer_series(const float4* __restrict__ lay, con
   const float4* m = mom + 5 * j;
   const float4 m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4];
   const float4 Lj = lay[j], Lo = lay[obs_layer];
-  const float ic0 = 1.0f / c0;
+  const float ic0 = rcp_fast(c0);
   const float tn = s0 * ic0, t = tn * tn;
   const float span = Pz - (float)j * dh;
   const float Ws = t * fmaf(t, fmaf(t, m0.z, m0.y), m0.x);  // dh sum (w - 1)
@@ -239,7 +246,7 @@ __device__ __forceinline__ void layer_series(const float4* __restrict__ lay, con
   }
   float s, c2, e;
   layer_angle(s0, c0, Lj.x, Lo.x, Lo.y, s, c2, e);
-  const float c = sqrtf(c2);
+  const float c = sqrt_fast(c2);
   w.vx = s * hx;
   w.vy = s * hy;
   w.vz = -c;

@@ -269,11 +269,15 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     const uint4 w = philox(k, __float_as_uint(q3.y), __float_as_uint(q3.z), TAG_CHERENKOV, p.key0, p.key1);
     f = u24(w.x);
     float sphi, cphi;
-    sincospif(2.0f * u24(w.y), &sphi, &cphi);
+    // the cone azimuth needs sin and cos only to about 2e-5: its error enters the
+    // direction times sin(theta) < 0.025; the hardware sine takes revolutions
+    const float ua = u24(w.y);
+    sphi = __builtin_amdgcn_sinf(ua);
+    cphi = __builtin_amdgcn_cosf(ua);
     const float u2 = u24(w.z);
     lam = (p.spectrum == CPHOT_SPECTRUM_UNIFORM)
               ? p.lam_min + (p.lam_max - p.lam_min) * u2
-              : 1.0f / (p.inv_lam_min - u2 * (p.inv_lam_min - p.inv_lam_max));
+              : rcp_fast(p.inv_lam_min - u2 * (p.inv_lam_min - p.inv_lam_max));
     u3 = u24(w.w);
     // photon on the cone around (0,0,-1), turned onto the track: u = 2 a (a.p) - p
     const float plx = cphi * sin_t, ply = sphi * sin_t, plz = -cos_t;
@@ -528,7 +532,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     vz = uz;
   }
   // final straight leg: crossing of the observation level
-  const float s_plane = (p.h_obs - z) / vz;
+  const float s_plane = (p.h_obs - z) * rcp_fast(vz);
   const float Qx = fmaf(s_plane, vx, x), Qy = fmaf(s_plane, vy, y);
   float s_end = s_plane;
   int32_t bin = -1;
@@ -551,7 +555,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       const float cc = qx * qx + qy * qy - p.radius * p.radius;
       const float disc = b * b - cc;
       if (disc >= 0.f) {
-        s_end = s_plane + (-b - sqrtf(disc));
+        s_end = s_plane + (-b - sqrt_fast(disc));
         bin = (int)fj * p.snx + (int)fi;
       }
     }
