@@ -187,21 +187,23 @@ __device__ __forceinline__ float cut_slack(float qx, float qy, float core_x, flo
 __device__ __forceinline__ bool track_may_hit(const KParams& p, float x0, float y0, float z0, float x1, float y1,
                                               float z1, float cos_t, float sin_t, float core_x, float core_y) {
   const float dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
-  const float L = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+  const float L = sqrt_fast(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
   if (!(L > 0.f)) return true;
-  const float cz = -dz / L, sz = sqrtf(fmaxf((1.0f - cz) * (1.0f + cz), 0.f));
+  const float iL = rcp_fast(L);
+  const float cz = -dz * iL, sz = sqrt_fast(fmaxf((1.0f - cz) * (1.0f + cz), 0.f));
   const float cmin = fmaf(cz, cos_t, -sz * sin_t);  // cos of the steepest cone direction
   if (!(cmin > 0.2f)) return true;
   const float H = fmaxf(z0, z1) - p.h_obs;
   if (!(H > 0.f)) return true;
-  const float t2 = (1.0f - cmin * cmin) / (cmin * cmin), tmax = sqrtf(t2);
+  const float ic = rcp_fast(cmin);
+  const float t2 = (1.0f - cmin * cmin) * ic * ic, tmax = sqrt_fast(t2);
   const float x = 2.2f * t2 * p.cut_e;
   if (!(x <= 0.25f)) return true;
-  const float Rfp = H * (1.01f * sin_t) / (cmin * cmin);
+  const float Rfp = H * (1.01f * sin_t) * ic * ic;
   const float dref = fmaf(H * tmax * p.cut_e * fmaf(3.0f, t2, 1.0f), 1.1f, 0.5f);
-  const float reff = p.radius / (cmin * sqrtf(1.0f - x));
-  const float s = (p.h_obs - z0) / dz * L;  // along the unit axis from the start point
-  const float qx = fmaf(s, dx / L, x0), qy = fmaf(s, dy / L, y0);
+  const float reff = p.radius * ic * rcp_fast(sqrt_fast(1.0f - x));
+  const float s = (p.h_obs - z0) * rcp_fast(dz);  // in units of the segment vector from its start
+  const float qx = fmaf(s, dx, x0), qy = fmaf(s, dy, y0);
   const float lim = Rfp + dref + reff + cut_slack(qx, qy, core_x, core_y, H);
   return nearest_sphere_d2(p, core_x, core_y, qx, qy) <= lim * lim;
 }
@@ -214,12 +216,13 @@ __device__ __forceinline__ bool photon_may_hit(const KParams& p, float Px, float
   const float c = -uz;
   if (!(c > 0.2f)) return true;
   const float H = Pz - p.h_obs;
-  const float t2 = fmaf(ux, ux, uy * uy) / (c * c);
+  const float ic = rcp_fast(c);
+  const float t2 = fmaf(ux, ux, uy * uy) * ic * ic;
   const float x = 2.2f * t2 * p.cut_e;
   if (!(x <= 0.25f)) return true;
-  const float dref = fmaf(H * sqrtf(t2) * p.cut_e * fmaf(3.0f, t2, 1.0f), 1.1f, 0.5f);
-  const float reff = p.radius / (c * sqrtf(1.0f - x));
-  const float s = H / c;
+  const float dref = fmaf(H * sqrt_fast(t2) * p.cut_e * fmaf(3.0f, t2, 1.0f), 1.1f, 0.5f);
+  const float reff = p.radius * ic * rcp_fast(sqrt_fast(1.0f - x));
+  const float s = H * ic;
   const float qx = fmaf(s, ux, Px), qy = fmaf(s, uy, Py);
   const float lim = reff + dref + cut_slack(qx, qy, core_x, core_y, H);
   return nearest_sphere_d2(p, core_x, core_y, qx, qy) <= lim * lim;
