@@ -327,14 +327,14 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
   const float Rf = (float)Re, twoR = (float)(2.0 * Re);
   // emission frame: radial e_r, tangent e_t (photon's horizontal direction), normal e_n
   const float qz = Pz + Rf;
-  const float rq = sqrtf(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
-  const float irq = 1.0f / rq;
+  const float rq = sqrt_fast(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
+  const float irq = rcp_fast(rq);
   const float erx = Px * irq, ery = Py * irq, erz = qz * irq;
   const float mu = fmaf(ux, erx, fmaf(uy, ery, uz * erz));  // cos of the angle to the upward radial
   float etx = fmaf(-mu, erx, ux), ety = fmaf(-mu, ery, uy), etz = fmaf(-mu, erz, uz);
-  const float s0 = sqrtf(fmaf(etx, etx, fmaf(ety, ety, etz * etz)));
+  const float s0 = sqrt_fast(fmaf(etx, etx, fmaf(ety, ety, etz * etz)));
   if (s0 > 0.f) {
-    const float is = 1.0f / s0;
+    const float is = rcp_fast(s0);
     etx *= is;
     ety *= is;
     etz *= is;
@@ -366,7 +366,7 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
     const float br = bracket(L.x, L.y);
     const float ra = Rf + h;
     const float Da = fmaf(A, br, h - h0);
-    const float rca = sqrtf(fmaxf(Da * (2.0f * ra - Da), 0.f));  // ra cos(angle to the radial)
+    const float rca = sqrt_fast(fmaxf(Da * (2.0f * ra - Da), 0.f));  // ra cos(angle to the radial)
     const float pa = ra - Da;                                     // impact parameter in this shell
     const float ext = fmaf(L.z, sp.x, L.w * sp.y);
     float ell, dpsi, cth;
@@ -376,20 +376,20 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
       const float Db = fmaf(A, br, hb - h0);
       if (Db > 0.f) {
         const float rb = Rf + hb;
-        const float rcb = sqrtf(Db * (2.0f * rb - Db));
-        ell = (h - hb) * (twoR + h + hb) / (rca + rcb);
-        const float x = pa * ell / (ra * rb);
+        const float rcb = sqrt_fast(Db * (2.0f * rb - Db));
+        ell = (h - hb) * (twoR + h + hb) * rcp_fast(rca + rcb);
+        const float x = pa * ell * rcp_fast(ra * rb);
         dpsi = fmaf(x * x * (1.0f / 6.0f), x, x);
-        cth = rca / ra;
+        cth = rca * rcp_fast(ra);
         h = hb;
       } else {  // the ray turns round inside the shell and leaves through its top
         const float ho = (float)(i + 1) * dh;
         const float ro = Rf + ho;
         const float Do = fmaf(A, br, ho - h0);
-        const float rco = sqrtf(fmaxf(Do * (2.0f * ro - Do), 0.f));
+        const float rco = sqrt_fast(fmaxf(Do * (2.0f * ro - Do), 0.f));
         ell = rca + rco;
         dpsi = atan2f(rca, pa) + atan2f(rco, pa);
-        cth = rca / ra;
+        cth = rca * rcp_fast(ra);
         h = ho;
         down = false;
         to_top = true;
@@ -398,17 +398,17 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
       const float ho = (float)(i + 1) * dh;
       const float ro = Rf + ho;
       const float Do = fmaf(A, br, ho - h0);
-      const float rco = sqrtf(fmaxf(Do * (2.0f * ro - Do), 0.f));
-      ell = (ho - h) * (twoR + ho + h) / (rco + rca);
-      const float x = pa * ell / (ra * ro);
+      const float rco = sqrt_fast(fmaxf(Do * (2.0f * ro - Do), 0.f));
+      ell = (ho - h) * (twoR + ho + h) * rcp_fast(rco + rca);
+      const float x = pa * ell * rcp_fast(ra * ro);
       dpsi = fmaf(x * x * (1.0f / 6.0f), x, x);
-      cth = -rca / ra;
+      cth = -rca * rcp_fast(ra);
       h = ho;
       to_top = true;
     }
     tau = fmaf(ext, ell, tau);
     if constexpr (NEED_TIME) {
-      const float sa = pa / ra;
+      const float sa = pa * rcp_fast(ra);
       float sp_, cp_;
       sincosf((float)psi, &sp_, &cp_);
       const float cphi = fmaf(cth, cp_, sa * sp_), sphi = fmaf(sa, cp_, -cth * sp_);
