@@ -53,9 +53,9 @@ METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density 
 # HBM bytes per launch of the exact telescope kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # scaled by a plain copy's factors (2.00, 1.00); valid only for the sources and launch shape they
 # were taken on (sha256 prefixes; block size, grid, LDS counts), else reported as null.
-TRAFFIC_BYTES = 16249 * 1024 * 2.00 + 288 * 1024 * 1.00
-TRAFFIC_SOURCES = {"cphot_kernels.hip": "dc5914b9f0deff7e", "cphot_device.h": "7d0517c0cdac951a",
-                   "cphot_internal.h": "b3b6918589cbace4", "cphot_api.cpp": "702143955f7ae9af"}
+TRAFFIC_BYTES = 16267.9 * 1024 * 2.00 + 144 * 1024 * 1.00
+TRAFFIC_SOURCES = {"cphot_kernels.hip": "fc06bf6dc9a9c3d8", "cphot_device.h": "e9b556d4454a60f0",
+                   "cphot_internal.h": "2c14770d0334f6fd", "cphot_api.cpp": "a740dd19a86fb902"}
 TRAFFIC_SHAPE = (512, 512, 1)
 
 
@@ -500,6 +500,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-inclined", action="store_true")
+    ap.add_argument("--no-cuts", action="store_true", help="skip the telescope step with data-reduction cuts")
+    ap.add_argument("--telescope-shape", default=None, metavar="BS,GRID,LDS",
+                    help="fixed launch shape for the exact telescope step instead of the autotuner's (profiling)")
     ap.add_argument("--inclined-chunks", type=int, default=10,
                     help="chunks of 1e7 segments streamed from host memory (0: only the resident chunk)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
@@ -541,8 +544,13 @@ def main():
     bins = out_buf[:nb].view(torch.int64)
     cnt = out_buf[nb:nb + nc].view(torch.int64)
     th = out_buf[nb + nc:].view(torch.int32)
-    det, tune = tuned_detector(cphot, S, atm, run, bins, th, cnt, stream)
-    log(f"telescope autotune: {tune}")
+    if args.telescope_shape:
+        bs_, gb_, lds_ = (int(v) for v in args.telescope_shape.split(","))
+        det = cphot.make_detector(atm, **run, block_size=bs_, grid_blocks=gb_, lds_hist=lds_)
+        tune = {"block_size": bs_, "grid_blocks": gb_, "lds_hist": lds_, "bunch": run["bunch"], "fixed": True}
+    else:
+        det, tune = tuned_detector(cphot, S, atm, run, bins, th, cnt, stream)
+    log(f"telescope shape: {tune}")
 
     def step(ev):
         out_buf.zero_()
@@ -560,9 +568,11 @@ def main():
     records = float(c[3])
     photons = records * run["bunch"]
     value = photons / (ms_per_step * 1e-3)
-    cuts = bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, exact_bins, exact_th,
-                      photons, ms_per_step)
-    log(f"telescope with cuts: {cuts['ms_per_step']:.3f} ms/step, identical bins {cuts['bins_identical']}")
+    cuts = None
+    if not args.no_cuts:
+        cuts = bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, exact_bins, exact_th,
+                          photons, ms_per_step)
+        log(f"telescope with cuts: {cuts['ms_per_step']:.3f} ms/step, identical bins {cuts['bins_identical']}")
 
     series_frac, loop_cross = walk_profile(torch, cphot, sh, geom, det, run)
     n_seg = float(sh.n)
@@ -588,8 +598,9 @@ def main():
                    "path": "exact", "records_per_step": records, "photons_per_step": photons,
                    "segments_per_s": n_seg / (ms_per_step * 1e-3)},
         "roofline": roofline,
-        "cuts": cuts,
     }
+    if cuts is not None:
+        out["cuts"] = cuts
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, ms_per_step, stream)
         log(f"surrogate: {out['surrogate']['value']:.3e} photons/s")
