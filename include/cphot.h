@@ -216,6 +216,18 @@ typedef struct {
   double fl_yield[3];       /* fluorescence photons per MeV deposited, per band */
   double fl_lambda[3];      /* band wavelengths, nm (inside the atmosphere's band) */
   const cphot_table* table; /* TABLE transport: a correction table built for this atmosphere and h_obs */
+  /* Detector efficiency (Sec. 4.3.1: mirrors, sensor): device float64 [n_lambda_bins of the
+   * atmosphere], the probability in [0, 1] that a photon of each wavelength bin that reaches the
+   * detector is recorded; a photon survives iff u < exp(-tau) x efficiency. NULL: 1. Needs an
+   * atmosphere with wavelength bins. */
+  const double* efficiency;
+  /* Pre-emission reduction (Sec. 4.3.1), device float64 [n_layers of the atmosphere] or NULL:
+   * q_i >= the detection probability exp(-tau) x efficiency of every photon emitted in layer i
+   * (cphot_reduction_table computes such a bound). A segment's expected records are multiplied by
+   * q of the layer of its lowest point before rounding, and each record survives iff
+   * u < exp(-tau) x efficiency / q: the same expected detections with fewer records generated.
+   * A q below the true probability biases the result (the caller's bound must hold). */
+  const double* reduction;
 } cphot_detector;
 
 /* Outputs, accumulated (+=) so that chunked calls need no host work; the caller
@@ -414,6 +426,19 @@ int cphot_table_create(const cphot_table_desc* desc, const cphot_atmosphere* atm
 
 /* Release a table (NULL allowed); no enqueued work may still use it. */
 void cphot_table_destroy(cphot_table* t);
+
+/* Upper bound of the detection probability per layer for the pre-emission
+ * reduction (Sec. 4.3.1): host float64 out[n_layers], out[i] = (1 + 1e-6) x
+ * max over wavelength bins k of efficiency[k] x exp(-tau_k(i)), where tau_k(i) is
+ * the vertical optical depth from the bottom of layer i down to h_obs (0 for the
+ * observation layer and below) at the bin's longest wavelength, with the smaller
+ * of the layer-average and the exact column in the observation layer. Any path
+ * from a point of layer i down to the observation level is at least that long
+ * through the same layers (planar or spherical shells, straight or refracted), so
+ * the bound holds for every photon emitted there. `efficiency` is host float64 [n_lambda_bins] or NULL (1).
+ * Errors: INVALID_ARG (atmosphere without layers, h_obs outside [0, h_top),
+ * efficiency outside [0, 1]). */
+int cphot_reduction_table(const cphot_atmosphere* atm, double h_obs, const double* efficiency, double* out);
 
 /* Interpolated corrections for device float32 X [n][5] (emission height, cos
  * zenith, azimuth (unused), wavelength, observation level (unused: the table's))

@@ -236,6 +236,10 @@ typedef struct {
   int32_t pad2;
   double fl_yield[3];   /* fluorescence photons per MeV deposited, per band */
   double fl_lambda[3];  /* band wavelengths, nm */
+  /* detector efficiency per wavelength bin of the atmosphere (NULL: 1) and the
+   * pre-emission reduction bound per layer (NULL: none), Sec. 4.3.1 */
+  const double* efficiency;
+  const double* reduction;
 } orc_run;
 
 enum { ST_BINNED = 0, ST_UPWARD = 1, ST_ABSORBED = 2, ST_OUTSIDE = 3 };
@@ -265,6 +269,7 @@ typedef struct {
   int32_t nf[3];  /* fluorescence records per band */
   int32_t pad;
   double muf[3];  /* expected fluorescence records per band */
+  double q;       /* pre-emission reduction factor (1 without reduction) */
 } orc_segment;
 
 typedef struct { double core_x, core_y, ax, ay, az; } orc_geom;
@@ -307,6 +312,22 @@ static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
   double dx = (double)x1 - (double)x0, dy = (double)y1 - (double)y0, dz = (double)z1 - (double)z0;
   double L = sqrt(dx * dx + dy * dy + dz * dz);
   if (!(L > 0.0)) { out.status = 2; return out; }
+  /* Pre-emission reduction (Sec. 4.3.1): the expected numbers of records are
+   * multiplied by an upper bound q of the detection probability of any photon
+   * the segment can emit -- the bound of the layer holding its lowest point --
+   * and every record later survives with probability (detection probability)/q,
+   * so the expected detections are unchanged while fewer records are drawn. The
+   * bound is input data (per layer), like the atmosphere's parameters. */
+  double q = 1.0;
+  if (R->reduction) {
+    double hmin = (double)z0 < (double)z1 ? (double)z0 : (double)z1;
+    double x = hmin / (A->p.h_top / A->p.n_layers);
+    if (x < 0.0) x = 0.0;
+    int64_t li = (int64_t)floor(x);
+    if (li > A->p.n_layers - 1) li = A->p.n_layers - 1;
+    q = R->reduction[li];
+  }
+  out.q = q;
   /* one Philox block per segment: word 0 rounds the Cherenkov yield, words
    * 1..3 the three fluorescence bands */
   uint32_t w[4];
@@ -331,6 +352,7 @@ static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
       /* A segment asking for 2^20 records or more (or a non-finite yield) is
        * rejected as invalid input rather than truncated. */
       if (!(mu < 1048576.0)) { memset(&out, 0, sizeof(out)); out.status = 2; return out; }
+      mu = mu * q;
       double fl = floor(mu);
       out.n = (int32_t)fl + (u32d(w[0]) < mu - fl ? 1 : 0);
       out.mu = mu; out.cos_t = 1.0 / (1.0 + g); out.sin2_t = s2;
@@ -345,6 +367,7 @@ static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
       mu = mu * 0.5;
       mu = mu / (double)R->bunch;
       if (!(mu < 1048576.0)) { memset(&out, 0, sizeof(out)); out.status = 2; return out; }
+      mu = mu * q;
       double fl = floor(mu);
       out.nf[b] = (int32_t)fl + (u32d(w[1 + b]) < mu - fl ? 1 : 0);
       out.muf[b] = mu;
@@ -541,6 +564,17 @@ static int curved_walk_rec(const orc_atmo* A, const orc_run* R, int kbin, const 
 }
 
 /* Record k of a segment: Cherenkov records first, then the fluorescence bands. */
+/* Survival threshold: the probability that a photon reaching the detector level
+ * with optical depth tau is detected (transmission exp(-tau), times the detector
+ * efficiency of its wavelength bin), over the probability q with which its
+ * record was kept at generation (Sec. 2.3.2, 4.3.1). */
+static double survival(const orc_run* R, const orc_segment* sg, double tau, int kbin) {
+  double p = exp(-tau);
+  if (R->efficiency) p = p * R->efficiency[kbin];
+  if (R->reduction) p = p / sg->q;
+  return p;
+}
+
 static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G, double K,
                          const seg_setup* st, const orc_segment* sg, uint64_t seg_id, uint32_t k,
                          orc_photon* out) {
@@ -612,7 +646,7 @@ static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G,
     double fx = (ps.pos[0] - gx0) / R->cell, fy = (ps.pos[1] - gy0) / R->cell;
     double ix = floor(fx), iy = floor(fy);
     out->margin = min4(fx - ix, ix + 1.0 - fx, fy - iy, iy + 1.0 - fy) * R->cell;
-    if (!(u3 < exp(-ps.tau))) { out->state = ST_ABSORBED; return; }
+    if (!(u3 < survival(R, sg, ps.tau, kbin))) { out->state = ST_ABSORBED; return; }
     if (!(ix >= 0 && iy >= 0 && ix < R->nx && iy < R->ny)) { out->state = ST_OUTSIDE; return; }
     out->state = ST_BINNED;
     out->bin = (int)iy * R->nx + (int)ix;
@@ -684,8 +718,9 @@ static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G,
   out->tau = ps.tau;
   out->t = (ps.geo + ps.opt) / ORC_C_M_PER_NS;
   out->margin = margin;
-  /* absorption and scattering remove the photon (Sec. 2.3.2): survival iff u < exp(-tau) */
-  if (!(u3 < exp(-ps.tau))) { out->state = ST_ABSORBED; return; }
+  /* absorption and scattering remove the photon (Sec. 2.3.2): survival iff u < exp(-tau),
+   * times the detector efficiency and over the reduction factor where set */
+  if (!(u3 < survival(R, sg, ps.tau, kbin))) { out->state = ST_ABSORBED; return; }
   if (bin < 0) { out->state = ST_OUTSIDE; return; }
   out->state = ST_BINNED;
   out->bin = bin;

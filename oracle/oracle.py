@@ -46,7 +46,7 @@ class Run(C.Structure):
                 ("snx", C.c_int32), ("sny", C.c_int32), ("pitch", C.c_double), ("radius", C.c_double),
                 ("n_t", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double),
                 ("emission", C.c_int32), ("pad2", C.c_int32), ("fl_yield", C.c_double * 3),
-                ("fl_lambda", C.c_double * 3)]
+                ("fl_lambda", C.c_double * 3), ("efficiency", C.c_void_p), ("reduction", C.c_void_p)]
 
 
 class Segments(C.Structure):
@@ -68,7 +68,7 @@ PHOTON_DTYPE = np.dtype([
 
 SEGMENT_DTYPE = np.dtype([("n", np.int32), ("status", np.int32), ("mu", np.float64),
                           ("cos_t", np.float64), ("sin2_t", np.float64), ("nf", np.int32, 3), ("pad", np.int32),
-                          ("muf", np.float64, 3)])
+                          ("muf", np.float64, 3), ("q", np.float64)])
 
 STATE = {"binned": 0, "upward": 1, "absorbed": 2, "outside": 3}
 COUNTERS = ["segments_in", "segments_skipped", "segments_below_threshold", "records_generated",
@@ -196,7 +196,10 @@ class Atmosphere:
 
 def make_run(transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0, h_obs=2200.0,
              nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0, dt=1.0,
-             emission="cherenkov", fl_yield=FL_YIELD, fl_lambda=FL_LAMBDA, **_ignored) -> Run:
+             emission="cherenkov", fl_yield=FL_YIELD, fl_lambda=FL_LAMBDA, efficiency=None, reduction=None,
+             **_ignored) -> Run:
+    """`efficiency` (per wavelength bin) and `reduction` (per layer): float64
+    arrays or None (Sec. 4.3.1)."""
     r = Run()
     r.transport, r.detector, r.spectrum = TRANSPORTS[transport], DETECTORS[detector], SPECTRA[spectrum]
     r.bunch, r.seed, r.h_obs = int(bunch), int(seed) & (2**64 - 1), float(h_obs)
@@ -206,6 +209,16 @@ def make_run(transport="straight", detector="grid", spectrum="uniform", bunch=1,
     r.emission = EMISSION[emission]
     r.fl_yield[:] = tuple(float(v) for v in fl_yield)
     r.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
+    keep = []
+    if efficiency is not None:
+        e = np.ascontiguousarray(efficiency, dtype=np.float64)
+        r.efficiency = e.ctypes.data
+        keep.append(e)
+    if reduction is not None:
+        q = np.ascontiguousarray(reduction, dtype=np.float64)
+        r.reduction = q.ctypes.data
+        keep.append(q)
+    r._keep = keep
     return r
 
 

@@ -65,7 +65,8 @@ class Detector(C.Structure):
                 ("reserved0", C.c_int32), ("time_bin_ns", C.c_double), ("block_size", C.c_int32),
                 ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("hist_window", C.c_int32),
                 ("surrogate", C.c_void_p), ("emission", C.c_int32), ("cuts", C.c_int32),
-                ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3), ("table", C.c_void_p)]
+                ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3), ("table", C.c_void_p),
+                ("efficiency", C.c_void_p), ("reduction", C.c_void_p)]
 
 
 class SurrogateDesc(C.Structure):
@@ -222,7 +223,9 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
                   h_obs=2200.0, nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0,
                   dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, surrogate=None,
                   emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0), cuts=(),
-                  table=None) -> Detector:
+                  table=None, efficiency=None, reduction=None) -> Detector:
+    """`efficiency` and `reduction`: float64 device tensors (per wavelength bin,
+    per layer) or None; see cphot_detector."""
     d = Detector()
     d.atm = atm.handle
     d.transport, d.detector, d.spectrum = TRANSPORT[transport], DETECTOR[detector], SPECTRUM[spectrum]
@@ -240,8 +243,28 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
         d.surrogate = surrogate.handle
     if table is not None:
         d.table = table.handle
-    d._refs = (atm, surrogate)  # keep the handles alive
+    if efficiency is not None or reduction is not None:
+        import torch
+        if efficiency is not None:
+            d.efficiency = _dptr(efficiency, torch.float64, "efficiency")
+        if reduction is not None:
+            d.reduction = _dptr(reduction, torch.float64, "reduction")
+    d._refs = (atm, surrogate, table, efficiency, reduction)  # keep the handles and buffers alive
     return d
+
+
+def reduction_table(atm: Atmosphere, h_obs: float, efficiency=None):
+    """Per-layer upper bound of the detection probability (cphot_reduction_table)
+    as a float64 numpy array; `efficiency`: per-wavelength-bin values or None."""
+    import numpy as np
+    n = atm.desc.n_layers
+    out = np.zeros(n, dtype=np.float64)
+    eff = None if efficiency is None else np.ascontiguousarray(efficiency, dtype=np.float64)
+    _check("cphot_reduction_table",
+           lib().cphot_reduction_table(atm.handle, C.c_double(float(h_obs)),
+                                       None if eff is None else eff.ctypes.data_as(C.c_void_p),
+                                       out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def make_segments(seg: dict, geom, offsets=None, first_id: int = 0) -> Segments:

@@ -136,6 +136,8 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   if (det->emission & ~(CPHOT_EMIT_CHERENKOV | CPHOT_EMIT_FLUORESCENCE))
     return fail(CPHOT_ERR_INVALID_ARG, "unknown emission bits");
   if (det->cuts & ~(CPHOT_CUT_TRACK | CPHOT_CUT_PHOTON)) return fail(CPHOT_ERR_INVALID_ARG, "unknown cut bits");
+  if ((det->efficiency || det->reduction) && d.n_layers < 1)
+    return fail(CPHOT_ERR_INVALID_ARG, "efficiency and reduction need an atmosphere with layers and wavelength bins");
   if (det->cuts && (det->detector != CPHOT_DETECTOR_SPHERES || curved ||
                     (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED &&
                      det->transport != CPHOT_TRANSPORT_TABLE)))
@@ -207,6 +209,15 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
                              : det->transport;
   if (det->transport == CPHOT_TRANSPORT_TABLE) p.ctab = cphot::table_view(det->table);
   p.detector = det->detector;
+  p.eff = det->efficiency;
+  p.red = det->reduction;
+  if (d.n_layers > 0) p.dh64 = d.h_top / d.n_layers;
+  if (det->efficiency || det->reduction) {  // wavelength bins and layers for straight rays too
+    p.n_layers = d.n_layers;
+    p.n_lam = d.n_lambda_bins;
+    p.dh = (float)(d.h_top / d.n_layers);
+    p.inv_dh = (float)(d.n_layers / d.h_top);
+  }
   if (det->transport != CPHOT_TRANSPORT_STRAIGHT) {
     if (d.n_layers < 1) return fail(CPHOT_ERR_INVALID_ARG, "layered transport needs an atmosphere with layers");
     if (det->transport == CPHOT_TRANSPORT_SURROGATE) p.mlp = cphot::surrogate_image(det->surrogate);
@@ -553,6 +564,53 @@ void cphot_destroy_atmosphere(cphot_atmosphere* a) {
   if (a->dev.moments) (void)hipFree(a->dev.moments);
   (void)hipSetDevice(prev);
   delete a;
+}
+
+int cphot_reduction_table(const cphot_atmosphere* a, double h_obs, const double* efficiency, double* out) {
+  if (!a || !out) return fail(CPHOT_ERR_INVALID_ARG, "null argument");
+  const cphot_atmosphere_desc& d = a->d;
+  if (d.n_layers < 1 || d.n_lambda_bins < 1) return fail(CPHOT_ERR_INVALID_ARG, "atmosphere without layers");
+  if (!(h_obs >= 0.0 && h_obs < d.h_top)) return fail(CPHOT_ERR_INVALID_ARG, "h_obs must lie in [0, h_top)");
+  const int L = d.n_layers, K = d.n_lambda_bins;
+  const double dh = d.h_top / L;
+  const int obs = (int)std::floor(h_obs / dh);
+  for (int k = 0; k < K; ++k)
+    if (efficiency && !(efficiency[k] >= 0.0 && efficiency[k] <= 1.0))
+      return fail(CPHOT_ERR_INVALID_ARG, "efficiency values must lie in [0, 1]");
+  // vertical optical depth per wavelength bin from each layer's bottom down to
+  // h_obs, accumulated upwards from the observation layer
+  std::vector<double> tau((size_t)K, 0.0);
+  for (int i = 0; i < L; ++i) {
+    double best = 0.0;
+    for (int k = 0; k < K; ++k)
+      best = std::max(best, (efficiency ? efficiency[k] : 1.0) * std::exp(-tau[(size_t)k]));
+    out[i] = best * (1.0 + 1e-6);
+    if (i >= obs) {  // the part of layer i above h_obs joins the column below layer i + 1
+      const double lo = std::max((double)i * dh, h_obs), hi = (i + 1) * dh, span = hi - lo;
+      // Rayleigh depth and aerosol column of that part: the layer averages times
+      // the span (layered transport) or the exact columns (straight rays), the
+      // smaller of the two; over a whole layer they are equal
+      const double ray_avg = d.rayleigh400 > 0.0 ? (depth(d, i * dh) - depth(d, hi)) / dh * span : 0.0;
+      const double ray_ex = d.rayleigh400 > 0.0 ? depth(d, lo) - depth(d, hi) : 0.0;
+      const double aer_avg = d.aerosol_tau350 > 0.0 ? (std::exp(-i * dh / d.aerosol_height) -
+                                                       std::exp(-hi / d.aerosol_height)) / dh * span
+                                                    : 0.0;
+      const double aer_ex = d.aerosol_tau350 > 0.0
+                                ? std::exp(-lo / d.aerosol_height) - std::exp(-hi / d.aerosol_height)
+                                : 0.0;
+      const double ray = std::min(ray_avg, ray_ex), aer = std::min(aer_avg, aer_ex);
+      for (int k = 0; k < K; ++k) {
+        // the bin's longest wavelength: the least extinction any photon of the bin sees
+        const double lam = d.lambda_min_nm + (k + 1) * (d.lambda_max_nm - d.lambda_min_nm) / K;
+        const double r = lam / 400.0;
+        const double inv_ray = d.rayleigh400 > 0.0 ? 1.0 / (d.rayleigh400 * r * r * r * r) : 0.0;
+        const double taua =
+            d.aerosol_tau350 > 0.0 ? d.aerosol_tau350 * std::pow(lam / 350.0, -d.aerosol_angstrom) : 0.0;
+        tau[(size_t)k] += ray * inv_ray + aer * taua;
+      }
+    }
+  }
+  return CPHOT_OK;
 }
 
 int cphot_propagate(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out, void* stream) {

@@ -65,6 +65,9 @@ struct KParams {
   const float4* moments;  // rows of the observation layer's slice, by start layer
   float series_tmax;      // 0: crossing loop only
   int32_t cuts;           // CPHOT_CUT_* (SPHERES, propagate mode)
+  const double* eff;      // detector efficiency per wavelength bin (NULL: 1)
+  const double* red;      // pre-emission reduction bound per layer (NULL: none)
+  double dh64;            // layer thickness in FP64 (the reduction's layer of a segment)
   float cut_e;            // largest |n_i - n_j| / n_i above the observation layer (0 for straight rays)
   const float2* lambins;
   int32_t nx, ny;

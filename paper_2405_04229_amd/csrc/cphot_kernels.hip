@@ -28,6 +28,7 @@ struct SegResult {
   float cos_t, sin_t, a0, a1, a2;
   double mu;       // expected Cherenkov records
   int32_t nf[3];   // fluorescence records per band
+  float inv_q;     // 1 / pre-emission reduction factor (1 without reduction)
 };
 
 // Per-segment yield in FP64 with IEEE basic operations only and no
@@ -37,7 +38,7 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
                                                 float fy1, float fz1, float fbeta, float fq, float fdedx,
                                                 uint64_t id) {
 #pragma clang fp contract(off)
-  SegResult r{0, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0, {0, 0, 0}};
+  SegResult r{0, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0, {0, 0, 0}, 1.f};
   const bool cher = (p.emission & CPHOT_EMIT_CHERENKOV) != 0;
   const bool fluor = (p.emission & CPHOT_EMIT_FLUORESCENCE) != 0;
   if (!__builtin_isfinite(fx0) || !__builtin_isfinite(fy0) || !__builtin_isfinite(fz0) ||
@@ -56,6 +57,18 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
   if (!(L > 0.0)) {
     r.status = 2;
     return r;
+  }
+  // pre-emission reduction (Sec. 4.3.1): the bound q of the layer holding the
+  // segment's lowest point scales every expected count before rounding
+  double q = 1.0;
+  if (p.red) {
+    const double hmin = (double)fz0 < (double)fz1 ? (double)fz0 : (double)fz1;
+    double x = hmin / p.dh64;
+    if (x < 0.0) x = 0.0;
+    int64_t li = (int64_t)floor(x);
+    if (li > p.n_layers - 1) li = p.n_layers - 1;
+    q = p.red[li];
+    r.inv_q = q > 0.0 ? (float)(1.0 / q) : 0.f;
   }
   // one Philox block per segment: word 0 rounds the Cherenkov yield, words 1..3
   // the fluorescence bands
@@ -91,6 +104,7 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
         r.status = 2;
         return r;
       }
+      mu = mu * q;
       r.mu = mu;
       const double fl = floor(mu);
       const double u = (double)w.x * (1.0 / 4294967296.0);
@@ -109,9 +123,10 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
       mu = mu * 0.5;
       mu = mu / (double)p.bunch;
       if (!(mu < (double)(1 << kMaxRecordsPerSegmentLog2))) {
-        SegResult bad{0, 2, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0, {0, 0, 0}};
+        SegResult bad{0, 2, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0, {0, 0, 0}, 1.f};
         return bad;
       }
+      mu = mu * q;
       const double fl = floor(mu);
       const double u = (double)wb[b] * (1.0 / 4294967296.0);
       r.nf[b] = (int32_t)fl + (u < mu - fl ? 1 : 0);
@@ -237,6 +252,17 @@ __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float 
   return p.opt_scale * ((b - a) - (b * b - a * a) / (2.f * t));
 }
 
+// Survival threshold of a record: exp(-tau), times the detector efficiency of
+// its wavelength bin and divided by its segment's reduction factor when set
+// (the detection probability over the probability the record was generated with).
+__device__ __forceinline__ float survival_threshold(const KParams& p, const float* __restrict__ s_eff, float tau,
+                                                    int kb, uint32_t inv_q_bits) {
+  float thr = __expf(-tau);
+  if (p.eff) thr *= s_eff[kb];
+  if (p.red) thr *= __uint_as_float(inv_q_bits);
+  return thr;
+}
+
 template <int T>
 constexpr bool kMlpTransport = (T == CPHOT_TRANSPORT_SURROGATE || T == kTransportCurvedSurrogate);
 
@@ -257,7 +283,8 @@ struct Photon {
 template <int TRANSPORT, int DETECTOR, bool NEED_TIME>
 __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict__ s_lay,
                                       const float2* __restrict__ s_lam, const MlpImage* __restrict__ s_img,
-                                      const KConst* __restrict__ s_k, uint4* s_stage,
+                                      const KConst* __restrict__ s_k, const float* __restrict__ s_eff,
+                                      uint4* s_stage,
                                       const float4 q0, const float4 q1, const float4 q2, const float4 q3,
                                       const float4 q4, const float axz, const uint4 q5, uint32_t k, bool valid,
                                       Photon& o) {
@@ -320,7 +347,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   o.y = Py;
   o.z = Pz;
   int kb = 0;
-  if constexpr (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT) {
+  if (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT || p.eff) {
     kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
     kb = min(max(kb, 0), p.n_lam - 1);
   }
@@ -414,7 +441,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       o.state = 3;
       return;
     }
-    if (!(u3 < __expf(-cw.tau))) {
+    if (!(u3 < survival_threshold(p, s_eff, cw.tau, kb, q5.w))) {
       o.state = 2;
       return;
     }
@@ -599,7 +626,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   o.z = ez;
   o.tau = tau;
   if constexpr (NEED_TIME) o.t = (geo + opt) * (1.0f / kCmPerNs);
-  if (!(u3 < __expf(-tau))) {
+  if (!(u3 < survival_threshold(p, s_eff, tau, kb, q5.w))) {
     o.state = 2;
     return;
   }
@@ -707,6 +734,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
   __shared__ uint32_t s_qn;
   __shared__ uint4 s_mlpx[kMlp ? BS : 1];  // per-wave staging of the network's inputs and outputs
   __shared__ KConst s_k;
+  __shared__ float s_eff[kMaxLambdaBins];  // detector efficiency per wavelength bin
   const MlpImage* s_img = reinterpret_cast<const MlpImage*>(s_imgw);
   // Optional LDS window of the grid, or the whole sphere array (record counts of
   // one shower at a time). With it each block walks a contiguous range of tiles,
@@ -731,6 +759,8 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
     for (int i = tid; i < (int)(sizeof(MlpImage) / 16); i += BS) s_imgw[i] = src[i];
   }
   load_kconst(p, s_k, tid);
+  if (p.eff)
+    for (int i = tid; i < p.n_lam; i += BS) s_eff[i] = (float)p.eff[i];
   for (int i = tid; i < n_hist; i += BS) s_hist[i] = 0u;
   if (tid == 0) {
     s_win_sh = -1;
@@ -786,7 +816,8 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       c_in += 1;
       c_skip += r.status == 2;
       c_below += r.status == 1;
-      q5 = make_uint4((uint32_t)r.n, (uint32_t)(r.n + r.nf[0]), (uint32_t)(r.n + r.nf[0] + r.nf[1]), 0u);
+      q5 = make_uint4((uint32_t)r.n, (uint32_t)(r.n + r.nf[0]), (uint32_t)(r.n + r.nf[0] + r.nf[1]),
+                      __float_as_uint(r.inv_q));
       nrec = q5.z + (uint32_t)r.nf[2];
       c_fl += nrec - (uint32_t)r.n;
       if constexpr (MODE == MODE_COUNTS) {
@@ -929,7 +960,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       const uint32_t k = j - s_off[lo];
       Photon ph;
       const float4 r3 = s_q3[lo];
-      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, &s_k, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
+      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
                                         s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], s_q5[lo], k, valid, ph);
       if constexpr (kDefer) {
         // wave-level compaction: deferred records take consecutive queue slots
@@ -958,7 +989,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
             const uint32_t qk = s_qk[q];
             const float4 q3 = s_q3[qlo];
             Photon pe;
-            trace<kExact, DETECTOR, kTime>(p, s_lay, s_lam, s_img, &s_k, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
+            trace<kExact, DETECTOR, kTime>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
                                            s_q4[qlo], s_axz[qlo], s_q5[qlo], qk, true, pe);
             pe.fallback = 1;
             consume(pe, qlo, qk, q3);

@@ -213,6 +213,18 @@ RUN_BATCH = dict(transport="straight", detector="grid", spectrum="frank_tamm", b
                  nx=200, ny=200, cell=5.0)
 RUN_INCLINED = dict(transport="curved", detector="grid", spectrum="frank_tamm", emission="both", bunch=1,
                     h_obs=2200.0, nx=1000, ny=1000, cell=10.0)
+
+
+def efficiency_curve(n_bins: int = 64, lam_min: float = 300.0, lam_max: float = 600.0):
+    """Synthetic detector efficiency per wavelength bin (Sec. 4.3.1 names mirror
+    reflectivity and sensor efficiency; the curves themselves are not printed):
+    a silicon-photomultiplier-like detection efficiency peaking at 0.45 near
+    420 nm with a Gaussian fall-off of 110 nm, times a mirror reflectivity of 0.9."""
+    import numpy as np
+    lam = lam_min + (np.arange(n_bins) + 0.5) * (lam_max - lam_min) / n_bins
+    return 0.9 * 0.45 * np.exp(-0.5 * ((lam - 420.0) / 110.0) ** 2)
+
+
 # surrogate training domain: emission height, cos zenith, azimuth, wavelength, observation level
 SURROGATE_LO = (2000.0, math.cos(math.radians(60.0)), -math.pi, 300.0, 1000.0)
 SURROGATE_HI = (20000.0, 1.0, math.pi, 600.0, 3000.0)

@@ -87,11 +87,14 @@ def oracle_atm(atm_kw):
     return O.Atmosphere(**atm_kw)
 
 
-def near_boundary(orc, core, atm_kw, run_kw):
+def near_boundary(orc, core, atm_kw, run_kw, surv_thr=None):
     """Records of the oracle whose decisions (survival, bin, time bin, start
     layer, wavelength bin) lie within rounding distance of their boundary, and
-    the per-record position tolerance. Returns (near, pos_tol, h_emit, layer_m, lambin_m)."""
-    surv_m = np.abs(orc["u_abs"] - np.exp(-orc["tau"]))
+    the per-record position tolerance. `surv_thr`: the survival thresholds where
+    they are not exp(-tau) (detector efficiency, pre-emission reduction).
+    Returns (near, pos_tol, h_emit, layer_m, lambin_m)."""
+    thr = np.exp(-orc["tau"]) if surv_thr is None else surv_thr
+    surv_m = np.abs(orc["u_abs"] - thr)
     transport = run_kw.get("transport", "straight")
     h_emit = orc["ez"]
     if transport == "curved":
@@ -119,7 +122,7 @@ def flip_budget(orc, core, atm_kw, run_kw):
     return 2 * run_kw.get("bunch", 1) * int(near.sum())
 
 
-def compare_records(gpu, orc, core, atm_kw, run_kw):
+def compare_records(gpu, orc, core, atm_kw, run_kw, surv_thr=None):
     """Element-by-element comparison. Returns (n_flips, report). Raises on any
     mismatch that is not a legitimate flip."""
     assert len(gpu) == len(orc), (len(gpu), len(orc))
@@ -132,7 +135,7 @@ def compare_records(gpu, orc, core, atm_kw, run_kw):
     assert np.abs(du).max() <= DIR_TOL, np.abs(du).max()
     transport = run_kw.get("transport", "straight")
     layered = transport in ("layered", "curved")
-    near, pos_tol, h_emit, lm, lbm = near_boundary(orc, core, atm_kw, run_kw)
+    near, pos_tol, h_emit, lm, lbm = near_boundary(orc, core, atm_kw, run_kw, surv_thr)
     r = np.hypot(orc["x"] - core[0], orc["y"] - core[1])
     state_diff = gpu["state"] != orc["state"]
     bin_diff = (gpu["bin"] != orc["bin"]) | (gpu["tbin"] != orc["tbin"])
