@@ -172,6 +172,40 @@ def bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, 
                     "counts the uncut step's photons"}
 
 
+def bench_reduction(torch, cphot, W, S, atm, run, out_buf, bins, th, cnt, stream, args, shape):
+    """The telescope step with a detector efficiency (synthetic SiPM-like curve
+    times a mirror), without and with the pre-emission reduction (Sec. 4.3.1):
+    fewer records generated for the same expected detections."""
+    eff = W.efficiency_curve(W.ATMO_LAYERED["n_lam"])
+    q = cphot.reduction_table(atm, run["h_obs"], eff)
+    eff_d = torch.from_numpy(eff).cuda()
+    q_d = torch.from_numpy(q).cuda()
+    res = {}
+    for name, red in (("efficiency_only", None), ("reduced", q_d)):
+        det = cphot.make_detector(atm, **run, **shape, efficiency=eff_d, reduction=red)
+
+        def step(ev, det=det):
+            out_buf.zero_()
+            if ev is not None:
+                ev[0].record(stream)
+            cphot.propagate(S, det, bins, th, cnt, stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
+
+        ms, kern = time_steps(torch, step, args.steps, args.warmup, stream)
+        c = cnt.cpu().numpy()
+        res[name] = {"ms_per_step": ms, "kernel_ms": kern, "records_generated": float(c[3]),
+                     "photons_binned": float(c[8])}
+    a, b = res["efficiency_only"], res["reduced"]
+    res["speedup"] = a["ms_per_step"] / b["ms_per_step"]
+    res["binned_ratio"] = b["photons_binned"] / max(a["photons_binned"], 1.0)
+    res["binned_sigma"] = (b["photons_binned"] - a["photons_binned"]) / max(
+        np.sqrt(a["photons_binned"] + b["photons_binned"]) * np.sqrt(run["bunch"]), 1.0)
+    res["note"] = ("synthetic detector efficiency 0.11-0.40 (SiPM-like x mirror 0.9); the reduced step draws "
+                   "each segment's records times the per-layer bound q and keeps them with probability p/q")
+    return res
+
+
 def walk_profile(torch, cphot, sh, geom, det, run, n=20000):
     """From traced records of the first n segments: the fraction of downward
     records the closed-form layer sums serve (tan^2 zenith within the series
@@ -568,6 +602,13 @@ def main():
     records = float(c[3])
     photons = records * run["bunch"]
     value = photons / (ms_per_step * 1e-3)
+    shape = {k: tune[k] for k in ("block_size", "grid_blocks", "lds_hist")}
+    reduction = None
+    if not args.no_cuts:
+        reduction = bench_reduction(torch, cphot, W, S, atm, run, out_buf, bins, th, cnt, stream, args, shape)
+        log(f"telescope with efficiency: {reduction['efficiency_only']['ms_per_step']:.3f} ms/step, "
+            f"reduced {reduction['reduced']['ms_per_step']:.3f} ms/step, binned ratio "
+            f"{reduction['binned_ratio']:.4f}")
     cuts = None
     if not args.no_cuts:
         cuts = bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, exact_bins, exact_th,
@@ -601,6 +642,8 @@ def main():
     }
     if cuts is not None:
         out["cuts"] = cuts
+    if reduction is not None:
+        out["reduction"] = reduction
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, ms_per_step, stream)
         log(f"surrogate: {out['surrogate']['value']:.3e} photons/s")

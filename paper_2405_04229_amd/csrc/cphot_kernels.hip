@@ -255,12 +255,10 @@ __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float 
 // Survival threshold of a record: exp(-tau), times the detector efficiency of
 // its wavelength bin and divided by its segment's reduction factor when set
 // (the detection probability over the probability the record was generated with).
+// Without efficiency the table holds ones, without reduction 1/q is 1: no branches.
 __device__ __forceinline__ float survival_threshold(const KParams& p, const float* __restrict__ s_eff, float tau,
                                                     int kb, uint32_t inv_q_bits) {
-  float thr = __expf(-tau);
-  if (p.eff) thr *= s_eff[kb];
-  if (p.red) thr *= __uint_as_float(inv_q_bits);
-  return thr;
+  return __expf(-tau) * (s_eff[kb] * __uint_as_float(inv_q_bits));
 }
 
 template <int T>
@@ -698,7 +696,10 @@ __device__ void flush_window(const KParams& p, uint32_t* s_hist, int sh) {
 // curved walk runs 15 % faster at four waves with a few spilled registers than
 // at three without.
 template <int T>
-constexpr int kMinWavesPerSimd = (T == kTransportCurvedTable) ? 3 : (T == CPHOT_TRANSPORT_CURVED ? 4 : 1);
+constexpr int kMinWavesPerSimd =
+    (T == kTransportCurvedTable) ? 3
+    : (T == CPHOT_TRANSPORT_CURVED || T == CPHOT_TRANSPORT_LAYERED || T == CPHOT_TRANSPORT_STRAIGHT || T == CPHOT_TRANSPORT_TABLE) ? 4
+                                                                                                                     : 1;
 
 template <int BS, int TRANSPORT, int DETECTOR, int MODE>
 __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(KParams p) {
@@ -759,8 +760,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
     for (int i = tid; i < (int)(sizeof(MlpImage) / 16); i += BS) s_imgw[i] = src[i];
   }
   load_kconst(p, s_k, tid);
-  if (p.eff)
-    for (int i = tid; i < p.n_lam; i += BS) s_eff[i] = (float)p.eff[i];
+  for (int i = tid; i < kMaxLambdaBins; i += BS) s_eff[i] = (p.eff && i < p.n_lam) ? (float)p.eff[i] : 1.0f;
   for (int i = tid; i < n_hist; i += BS) s_hist[i] = 0u;
   if (tid == 0) {
     s_win_sh = -1;
