@@ -94,6 +94,18 @@ extern "C" {
 #define CPHOT_EMIT_CHERENKOV 1
 #define CPHOT_EMIT_FLUORESCENCE 2
 
+/* Record count per segment and source from its expected value mu (Sec. 2.2.1):
+ * ROUNDED: floor(mu) + [u < mu - floor(mu)] with the segment's own random word
+ * (the mean is exact, the spread the smallest possible). POISSON: a Poisson(mu)
+ * draw by inversion in equal chunks of mean <= 64 (the first chunk with the
+ * segment's word, chunk c > 0 with Philox block (c, id low, id high, 12 + source),
+ * source 0 Cherenkov, 1 + b band b), every step an IEEE basic operation (exp(-m) by
+ * Cody-Waite reduction and a Taylor polynomial), so that counts are reproducible
+ * bit for bit on any IEEE machine. A draw of 2^20 records or more marks the segment
+ * skipped. */
+#define CPHOT_COUNTS_ROUNDED 0
+#define CPHOT_COUNTS_POISSON 1
+
 /* Data-reduction cuts for the SPHERES detector (bit set; Sec. 4.3.2 filter level 1 and
  * Sec. 4.3.4 filter level 3, Sec. 6.2). Both are geometric bounds that never remove a
  * photon that could reach a sphere, so bins and time histograms equal those of the
@@ -201,7 +213,8 @@ typedef struct {
   double pitch;             /* SPHERES spacing, m */
   double radius;            /* SPHERES radius, m */
   int32_t n_time_bins;      /* SPHERES arrival-time bins (0 = no time histograms) */
-  int32_t reserved0;
+  int32_t counts_rule;      /* CPHOT_COUNTS_ROUNDED (0): a segment's expected records mu are rounded
+                               stochastically; CPHOT_COUNTS_POISSON: drawn from Poisson(mu) */
   double time_bin_ns;       /* width of a time bin, ns */
   int32_t block_size;       /* tuning: threads per block (0 = library choice) */
   int32_t grid_blocks;      /* tuning: blocks of the persistent grid (0 = library choice) */

@@ -52,7 +52,7 @@ static double u24(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
 /* Random word -> uniform on [0,1) with 32 bits (segment count rounding). */
 static double u32d(uint32_t w) { return (double)w * (1.0 / 4294967296.0); }
 
-enum { TAG_SEGMENT = 0, TAG_CHERENKOV = 1, TAG_FLUOR = 2, TAG_TRAIN = 8 };
+enum { TAG_SEGMENT = 0, TAG_CHERENKOV = 1, TAG_FLUOR = 2, TAG_TRAIN = 8, TAG_POISSON = 12 };
 
 static void draw(uint64_t seed, uint32_t k, uint64_t seg, uint32_t tag, uint32_t out[4]) {
   uint32_t ctr[4] = {k, (uint32_t)seg, (uint32_t)(seg >> 32), tag};
@@ -230,7 +230,8 @@ typedef struct {
   double cell;          /* m */
   int32_t snx, sny;     /* sphere grid */
   double pitch, radius; /* m */
-  int32_t n_t, pad;     /* time bins per sphere (+1 overflow) */
+  int32_t n_t;          /* time bins per sphere (+1 overflow) */
+  int32_t counts_rule;  /* 0: stochastic rounding of mu, 1: Poisson(mu) */
   double dt;            /* ns */
   int32_t emission;     /* bit 0: Cherenkov, bit 1: fluorescence */
   int32_t pad2;
@@ -283,6 +284,61 @@ typedef struct {
   double cos_t, sin_t, sin2;
   double M[3][3]; /* rotation taking the cone axis (0,0,-1) onto the track direction */
 } seg_setup;
+
+/* exp(-x), 0 <= x <= 64, from IEEE basic operations only (the count decisions
+ * depend on it, so it must not vary with the C library): write x = k ln2 + r with
+ * ln2 = L1 + L2, L1 carrying 29 significant bits so that k L1 is exact (the
+ * reduction of Cody and Waite); exp(-r) = sum_{j=0}^{14} (-r)^j / j! (the first
+ * omitted term is below 2e-19 for |r| <= ln2/2); exp(-x) = 2^-k exp(-r). */
+static double exp_neg_basic(double x) {
+  static const double L1 = 0x1.62e42ffp-1;         /* ln2 rounded to 29 bits */
+  static const double L2 = -0x1.718432a1b0e26p-35; /* ln2 - L1 */
+  static const double INV_LN2 = 0x1.71547652b82fep+0;
+  static const double inv_fact[15] = {
+      1.0, 1.0, 0.5, 0x1.5555555555555p-3, 0x1.5555555555555p-5, 0x1.1111111111111p-7,
+      0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13, 0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19,
+      0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33,
+      0x1.93974a8c07c9dp-37};
+  double k = floor(x * INV_LN2 + 0.5);
+  double r = (x - k * L1) - k * L2;
+  double t = -r;
+  double sum = inv_fact[14];
+  for (int j = 13; j >= 0; --j) sum = sum * t + inv_fact[j];
+  return ldexp(sum, -(int)k);
+}
+
+/* Poisson-distributed record count with mean mu (< 2^20), the alternative to
+ * stochastic rounding (Sec. 2.2.1; a Poisson number of emissions per segment).
+ * Inversion: the smallest n with u < P(N <= n), the probabilities built as
+ * p_0 = e^-m, p_n = p_{n-1} m / n; for large means the count is a sum over equal
+ * chunks of mean m = mu / ceil(mu / 64) (sums of independent Poisson counts are
+ * Poisson), the first chunk using the segment's word w0 and chunk c > 0 word 0 of
+ * the Philox block (c, id, tag). */
+static int64_t poisson_draw(double mu, uint32_t w0, uint64_t seed, uint64_t seg_id, uint32_t tag) {
+  if (!(mu > 0.0)) return 0;
+  int64_t chunks = (int64_t)ceil(mu / 64.0);
+  double m = mu / (double)chunks;
+  double e = exp_neg_basic(m);
+  int64_t total = 0;
+  for (int64_t c = 0; c < chunks; ++c) {
+    uint32_t word = w0;
+    if (c > 0) {
+      uint32_t w[4];
+      draw(seed, (uint32_t)c, seg_id, tag, w);
+      word = w[0];
+    }
+    double u = u32d(word);
+    double p = e, F = e;
+    int64_t n = 0;
+    while (u >= F && n < 4096) {
+      n = n + 1;
+      p = p * m / (double)n;
+      F = F + p;
+    }
+    total += n;
+  }
+  return total;
+}
 
 static double frank_tamm_K(double lam_min_nm, double lam_max_nm) {
   /* integral over lambda of 2 pi alpha / lambda^2, lambda in metres */
@@ -353,8 +409,14 @@ static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
        * rejected as invalid input rather than truncated. */
       if (!(mu < 1048576.0)) { memset(&out, 0, sizeof(out)); out.status = 2; return out; }
       mu = mu * q;
-      double fl = floor(mu);
-      out.n = (int32_t)fl + (u32d(w[0]) < mu - fl ? 1 : 0);
+      if (R->counts_rule == 1) {
+        int64_t n = poisson_draw(mu, w[0], R->seed, seg_id, TAG_POISSON);
+        if (n >= 1048576) { memset(&out, 0, sizeof(out)); out.status = 2; return out; }
+        out.n = (int32_t)n;
+      } else {
+        double fl = floor(mu);
+        out.n = (int32_t)fl + (u32d(w[0]) < mu - fl ? 1 : 0);
+      }
       out.mu = mu; out.cos_t = 1.0 / (1.0 + g); out.sin2_t = s2;
     }
   }
@@ -368,8 +430,14 @@ static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
       mu = mu / (double)R->bunch;
       if (!(mu < 1048576.0)) { memset(&out, 0, sizeof(out)); out.status = 2; return out; }
       mu = mu * q;
-      double fl = floor(mu);
-      out.nf[b] = (int32_t)fl + (u32d(w[1 + b]) < mu - fl ? 1 : 0);
+      if (R->counts_rule == 1) {
+        int64_t n = poisson_draw(mu, w[1 + b], R->seed, seg_id, TAG_POISSON + 1 + (uint32_t)b);
+        if (n >= 1048576) { memset(&out, 0, sizeof(out)); out.status = 2; return out; }
+        out.nf[b] = (int32_t)n;
+      } else {
+        double fl = floor(mu);
+        out.nf[b] = (int32_t)fl + (u32d(w[1 + b]) < mu - fl ? 1 : 0);
+      }
       out.muf[b] = mu;
     }
   }
@@ -746,6 +814,10 @@ typedef struct {
 static float seg_dedx(const orc_segments* S, int64_t i) { return S->dedx ? S->dedx[i] : 0.0f; }
 
 double orc_frank_tamm_K(double lam_min, double lam_max) { return frank_tamm_K(lam_min, lam_max); }
+double orc_exp_neg(double x) { return exp_neg_basic(x); }
+int64_t orc_poisson(double mu, uint32_t w0, uint64_t seed, uint64_t seg_id, uint32_t tag) {
+  return poisson_draw(mu, w0, seed, seg_id, tag);
+}
 
 void orc_segment_counts(const orc_atmo* A, const orc_run* R, const orc_segments* S, orc_segment* out) {
   double K = frank_tamm_K(A->p.lam_min, A->p.lam_max);

@@ -44,7 +44,7 @@ class Run(C.Structure):
                 ("bunch", C.c_int32), ("seed", C.c_uint64), ("h_obs", C.c_double),
                 ("nx", C.c_int32), ("ny", C.c_int32), ("cell", C.c_double),
                 ("snx", C.c_int32), ("sny", C.c_int32), ("pitch", C.c_double), ("radius", C.c_double),
-                ("n_t", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double),
+                ("n_t", C.c_int32), ("counts_rule", C.c_int32), ("dt", C.c_double),
                 ("emission", C.c_int32), ("pad2", C.c_int32), ("fl_yield", C.c_double * 3),
                 ("fl_lambda", C.c_double * 3), ("efficiency", C.c_void_p), ("reduction", C.c_void_p)]
 
@@ -104,6 +104,10 @@ def lib():
             L.orc_layer_tables.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
             L.orc_frank_tamm_K.argtypes = [C.c_double, C.c_double]
             L.orc_frank_tamm_K.restype = C.c_double
+            L.orc_exp_neg.restype = C.c_double
+            L.orc_exp_neg.argtypes = [C.c_double]
+            L.orc_poisson.restype = C.c_int64
+            L.orc_poisson.argtypes = [C.c_double, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32]
             L.orc_segment_counts.argtypes = [C.c_void_p, P(Run), P(Segments), C.c_void_p]
             L.orc_trace.argtypes = [C.c_void_p, P(Run), P(Segments), P(Geom), C.c_void_p, C.c_int64]
             L.orc_trace.restype = C.c_int64
@@ -197,7 +201,7 @@ class Atmosphere:
 def make_run(transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0, h_obs=2200.0,
              nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0, dt=1.0,
              emission="cherenkov", fl_yield=FL_YIELD, fl_lambda=FL_LAMBDA, efficiency=None, reduction=None,
-             **_ignored) -> Run:
+             counts="rounded", **_ignored) -> Run:
     """`efficiency` (per wavelength bin) and `reduction` (per layer): float64
     arrays or None (Sec. 4.3.1)."""
     r = Run()
@@ -207,6 +211,7 @@ def make_run(transport="straight", detector="grid", spectrum="uniform", bunch=1,
     r.snx, r.sny, r.pitch, r.radius = int(snx), int(sny), float(pitch), float(radius)
     r.n_t, r.dt = int(n_t), float(dt)
     r.emission = EMISSION[emission]
+    r.counts_rule = {"rounded": 0, "poisson": 1}[counts]
     r.fl_yield[:] = tuple(float(v) for v in fl_yield)
     r.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
     keep = []
@@ -339,3 +344,13 @@ def curved_ray(atm: Atmosphere, h_obs, start, direction, cap=4096):
     m = lib().orc_curved_ray(atm.handle, float(h_obs), _ptr(P, C.c_double), _ptr(u, C.c_double),
                              _ptr(end, C.c_double), _ptr(inv, C.c_double), cap)
     return m > 0, end, inv[: min(abs(m), cap)]
+
+
+def exp_neg(x):
+    """exp(-x) of the count sampler (IEEE basic operations only), 0 <= x <= 64."""
+    return lib().orc_exp_neg(float(x))
+
+
+def poisson(mu, w0, seed=0, seg_id=0, tag=12):
+    """Poisson record count of the oracle's sampler for mean mu and first word w0."""
+    return lib().orc_poisson(float(mu), int(w0), int(seed), int(seg_id), int(tag))

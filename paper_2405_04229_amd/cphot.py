@@ -24,6 +24,7 @@ NCOUNTERS = 16
 
 PROFILE = {"linsley5": 0, "homogeneous": 1, "linear": 2}
 TRANSPORT = {"straight": 0, "layered": 1, "surrogate": 2, "curved": 3, "table": 4}
+COUNTS = {"rounded": 0, "poisson": 1}  # record count per segment from its expected value
 CUTS = {"track": 1, "photon": 2}  # data-reduction bounds for spheres (never drop a possible hit)
 EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
 DETECTOR = {"grid": 0, "spheres": 1}
@@ -62,7 +63,7 @@ class Detector(C.Structure):
                 ("bunch", C.c_int32), ("seed", C.c_uint64), ("h_obs", C.c_double), ("nx", C.c_int32),
                 ("ny", C.c_int32), ("cell", C.c_double), ("snx", C.c_int32), ("sny", C.c_int32),
                 ("pitch", C.c_double), ("radius", C.c_double), ("n_time_bins", C.c_int32),
-                ("reserved0", C.c_int32), ("time_bin_ns", C.c_double), ("block_size", C.c_int32),
+                ("counts_rule", C.c_int32), ("time_bin_ns", C.c_double), ("block_size", C.c_int32),
                 ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("hist_window", C.c_int32),
                 ("surrogate", C.c_void_p), ("emission", C.c_int32), ("cuts", C.c_int32),
                 ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3), ("table", C.c_void_p),
@@ -223,7 +224,7 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
                   h_obs=2200.0, nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0,
                   dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, surrogate=None,
                   emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0), cuts=(),
-                  table=None, efficiency=None, reduction=None) -> Detector:
+                  table=None, efficiency=None, reduction=None, counts="rounded") -> Detector:
     """`efficiency` and `reduction`: float64 device tensors (per wavelength bin,
     per layer) or None; see cphot_detector."""
     d = Detector()
@@ -237,6 +238,7 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
     d.hist_window = int(hist_window)
     d.emission = EMISSION[emission]
     d.cuts = sum(CUTS[c] for c in cuts)
+    d.counts_rule = COUNTS[counts]
     d.fl_yield[:] = tuple(float(v) for v in fl_yield)
     d.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
     if surrogate is not None:

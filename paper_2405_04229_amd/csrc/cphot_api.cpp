@@ -209,6 +209,9 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
                              : det->transport;
   if (det->transport == CPHOT_TRANSPORT_TABLE) p.ctab = cphot::table_view(det->table);
   p.detector = det->detector;
+  if (det->counts_rule != CPHOT_COUNTS_ROUNDED && det->counts_rule != CPHOT_COUNTS_POISSON)
+    return fail(CPHOT_ERR_INVALID_ARG, "unknown counts_rule");
+  p.poisson = det->counts_rule == CPHOT_COUNTS_POISSON;
   p.eff = det->efficiency;
   p.red = det->reduction;
   if (d.n_layers > 0) p.dh64 = d.h_top / d.n_layers;

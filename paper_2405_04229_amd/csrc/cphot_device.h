@@ -10,6 +10,7 @@ constexpr uint32_t TAG_SEGMENT = 0;
 constexpr uint32_t TAG_CHERENKOV = 1;
 constexpr uint32_t TAG_FLUOR = 2;  // + band (2, 3, 4)
 constexpr uint32_t TAG_TRAIN = 8;
+constexpr uint32_t TAG_POISSON = 12;  // + source (12 Cherenkov, 13..15 fluorescence bands)
 constexpr int kMaxRecordsPerSegmentLog2 = 20;
 constexpr float kCmPerNs = 0.299792458f;  // metres per ns
 
@@ -38,6 +39,63 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 // above an ulp.
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// exp(-x) for 0 <= x <= 64 from IEEE basic operations only, so that it comes out
+// bit-identical on any IEEE machine (record counts are decided by it):
+// x = k ln2 + r with ln2 split into a 29-bit head (k ln2_hi exact) and a tail
+// (Cody and Waite's reduction), exp(-r) by its Taylor series to r^14 (first omitted
+// term below 2e-19 for |r| <= ln2 / 2), then the exact scaling by 2^-k.
+__device__ inline double exp_neg_exact(double x) {
+#pragma clang fp contract(off)
+  const double kLn2Hi = 0x1.62e42ffp-1, kLn2Lo = -0x1.718432a1b0e26p-35, kInvLn2 = 0x1.71547652b82fep+0;
+  const double k = floor(x * kInvLn2 + 0.5);
+  const double r = (x - k * kLn2Hi) - k * kLn2Lo;
+  const double t = -r;
+  double q = 0x1.93974a8c07c9dp-37;  // 1/14!
+  q = q * t + 0x1.6124613a86d09p-33;
+  q = q * t + 0x1.1eed8eff8d898p-29;
+  q = q * t + 0x1.ae64567f544e4p-26;
+  q = q * t + 0x1.27e4fb7789f5cp-22;
+  q = q * t + 0x1.71de3a556c734p-19;
+  q = q * t + 0x1.a01a01a01a01ap-16;
+  q = q * t + 0x1.a01a01a01a01ap-13;
+  q = q * t + 0x1.6c16c16c16c17p-10;
+  q = q * t + 0x1.1111111111111p-7;
+  q = q * t + 0x1.5555555555555p-5;
+  q = q * t + 0x1.5555555555555p-3;
+  q = q * t + 0.5;
+  q = q * t + 1.0;
+  q = q * t + 1.0;
+  return ldexp(q, -(int)k);
+}
+
+// Poisson(mu) record count (0 <= mu < 2^20): inversion, in equal chunks of mean
+// at most 64 (a sum of independent Poisson counts is Poisson): for each chunk the
+// smallest n with u < sum_{j<=n} e^-m m^j / j!, the terms built as p <- p m / n.
+// The first chunk uses the segment's own word w0, chunk c > 0 word 0 of the Philox
+// block (c, id low, id high, tag). IEEE basic operations only (see exp_neg_exact).
+__device__ inline int64_t poisson_count(double mu, uint32_t w0, uint64_t id, uint32_t tag, uint32_t k0,
+                                        uint32_t k1) {
+#pragma clang fp contract(off)
+  if (!(mu > 0.0)) return 0;
+  const int64_t nc = (int64_t)ceil(mu / 64.0);
+  const double m = mu / (double)nc;
+  const double e = exp_neg_exact(m);
+  int64_t total = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    const uint32_t word = c == 0 ? w0 : philox((uint32_t)c, (uint32_t)id, (uint32_t)(id >> 32), tag, k0, k1).x;
+    const double u = (double)word * (1.0 / 4294967296.0);
+    double pk = e, F = e;
+    int64_t n = 0;
+    while (u >= F && n < 4096) {
+      n += 1;
+      pk = pk * m / (double)n;
+      F = F + pk;
+    }
+    total += n;
+  }
+  return total;
+}
 
 // Random word -> uniform on [0, 1) with 24 bits (exact in FP32).
 __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }

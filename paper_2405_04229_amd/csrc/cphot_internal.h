@@ -68,6 +68,7 @@ struct KParams {
   const double* eff;      // detector efficiency per wavelength bin (NULL: 1)
   const double* red;      // pre-emission reduction bound per layer (NULL: none)
   double dh64;            // layer thickness in FP64 (the reduction's layer of a segment)
+  int32_t poisson;        // record counts ~ Poisson(mu) instead of stochastic rounding
   float cut_e;            // largest |n_i - n_j| / n_i above the observation layer (0 for straight rays)
   const float2* lambins;
   int32_t nx, ny;

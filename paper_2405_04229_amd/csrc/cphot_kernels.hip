@@ -106,9 +106,19 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
       }
       mu = mu * q;
       r.mu = mu;
-      const double fl = floor(mu);
-      const double u = (double)w.x * (1.0 / 4294967296.0);
-      r.n = (int32_t)fl + (u < mu - fl ? 1 : 0);
+      if (p.poisson) {
+        const int64_t n = poisson_count(mu, w.x, id, TAG_POISSON, p.key0, p.key1);
+        if (n >= (int64_t(1) << kMaxRecordsPerSegmentLog2)) {
+          r.status = 2;
+          r.n = 0;
+          return r;
+        }
+        r.n = (int32_t)n;
+      } else {
+        const double fl = floor(mu);
+        const double u = (double)w.x * (1.0 / 4294967296.0);
+        r.n = (int32_t)fl + (u < mu - fl ? 1 : 0);
+      }
       r.cos_t = (float)(1.0 / (1.0 + g));
       r.sin_t = (float)sqrt(s2);
     }
@@ -127,9 +137,18 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
         return bad;
       }
       mu = mu * q;
-      const double fl = floor(mu);
-      const double u = (double)wb[b] * (1.0 / 4294967296.0);
-      r.nf[b] = (int32_t)fl + (u < mu - fl ? 1 : 0);
+      if (p.poisson) {
+        const int64_t n = poisson_count(mu, wb[b], id, TAG_POISSON + 1 + b, p.key0, p.key1);
+        if (n >= (int64_t(1) << kMaxRecordsPerSegmentLog2)) {
+          SegResult bad{0, 2, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0, {0, 0, 0}, 1.f};
+          return bad;
+        }
+        r.nf[b] = (int32_t)n;
+      } else {
+        const double fl = floor(mu);
+        const double u = (double)wb[b] * (1.0 / 4294967296.0);
+        r.nf[b] = (int32_t)fl + (u < mu - fl ? 1 : 0);
+      }
     }
   }
   // bisector of the cone axis (0,0,-1) and the track direction; the rotation

@@ -1,0 +1,103 @@
+"""Poisson record counts on the GPU, through the C ABI, bit-exact against the
+oracle's sampler (same words, IEEE basic operations only on both sides)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_04229_amd import workload as W
+from tests import cases, parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_04229_amd import cphot  # noqa: E402
+
+
+def _device_counts(atm, run, seg_np, geom, **kw):
+    det = cphot.make_detector(atm, **run, **kw)
+    seg, g, off = cphot.upload(seg_np, geom)
+    S = cphot.make_segments(seg, g, off)
+    counts = torch.zeros(S.n, dtype=torch.int32, device="cuda")
+    mu = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    cphot.segment_counts(S, det, counts, mu)
+    torch.cuda.synchronize()
+    return counts.cpu().numpy(), mu.cpu().numpy()
+
+
+def _oracle_total(oc):
+    return oc["n"] + oc["nf"].sum(1)
+
+
+@pytest.mark.parametrize("case", ["telescope", "large_mu", "fluorescence"])
+def test_poisson_counts_bit_exact(case):
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    oatm = O.Atmosphere(**cases.ATMO_LAYERED)
+    run = {**cases.RUN_TELESCOPE, "seed": 17}
+    sh = W.make_shower(20_000, seed=909, xmax=450.0, zenith_deg=20.0, beta="R",
+                       dedx=(0.1, 2.0) if case == "fluorescence" else None)
+    seg = dict(sh.seg)
+    if case == "large_mu":  # highly charged tracks: means in the thousands, many chunks
+        seg["charge"] = np.full(sh.n, 26.0, dtype=np.float32)
+        run = {**run, "bunch": 1}
+    if case == "fluorescence":
+        run = {**run, "emission": "both", "bunch": 1}
+    g = np.array([[*sh.core, *sh.axis]])
+    n, mu = _device_counts(atm, run, seg, g, counts="poisson")
+    oc = O.segment_counts(oatm, O.make_run(**run, counts="poisson"), seg)
+    np.testing.assert_array_equal(n, _oracle_total(oc))
+    ok = oc["status"] == 0
+    np.testing.assert_array_equal(mu[ok], oc["mu"][ok])
+    if case == "large_mu":
+        assert oc["mu"][ok].max() > 1000
+    # the Poisson rule differs from the rounding rule on the same words
+    n0, _ = _device_counts(atm, run, seg, g)
+    assert not np.array_equal(n, n0)
+
+
+def test_poisson_counts_with_reduction_and_records():
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    oatm = O.Atmosphere(**cases.ATMO_LAYERED)
+    eff = W.efficiency_curve(cases.ATMO_LAYERED["n_lam"])
+    q = cphot.reduction_table(atm, 2200.0, eff)
+    sh = W.make_shower(1500, seed=910, xmax=500.0, zenith_deg=35.0, azimuth_deg=20.0, beta="R")
+    g = np.array([[*sh.core, *sh.axis]])
+    run = dict(transport="layered", detector="grid", spectrum="frank_tamm", bunch=1, h_obs=2200.0, nx=300,
+               ny=300, cell=4.0, seed=25)
+    kw = dict(counts="poisson", efficiency=torch.from_numpy(eff).cuda(), reduction=torch.from_numpy(q).cuda())
+    n, _ = _device_counts(atm, run, sh.seg, g, **kw)
+    orun = O.make_run(**run, counts="poisson", efficiency=eff, reduction=q)
+    oc = O.segment_counts(oatm, orun, sh.seg)
+    np.testing.assert_array_equal(n, _oracle_total(oc))
+    # records of the same photons
+    det = cphot.make_detector(atm, **run, **kw)
+    seg, gg, off = cphot.upload(sh.seg, g)
+    S = cphot.make_segments(seg, gg, off)
+    counts = torch.from_numpy(n.astype(np.int32)).cuda()
+    offs = torch.cumsum(counts.to(torch.int64), 0) - counts.to(torch.int64)
+    tot = int(counts.sum().item())
+    rec = torch.zeros(max(tot, 1) * cphot.RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    cphot.trace_records(S, det, offs.contiguous(), rec)
+    torch.cuda.synchronize()
+    gr = cphot.records_to_numpy(rec.cpu())[:tot]
+    o = O.trace(oatm, orun, sh.seg, core=sh.core, axis=sh.axis)
+    k = np.clip(np.floor((o["lambda"] - 300.0) / 300.0 * 64).astype(int), 0, 63)
+    thr = np.exp(-o["tau"]) * eff[k] / oc["q"][o["seg"].astype(np.int64)]
+    flips, rep = parity.compare_records(gr, o, sh.core, cases.ATMO_LAYERED, run, surv_thr=thr)
+    print(rep)
+    assert (o["state"] == 0).sum() > 300
+    assert flips <= max(3, parity.MAX_FLIP_FRACTION * len(o))
+
+
+def test_counts_rule_argument_error():
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    sh = W.make_shower(10, seed=911, beta="R")
+    g = np.array([[*sh.core, *sh.axis]])
+    det = cphot.make_detector(atm, **cases.RUN_TELESCOPE)
+    det.counts_rule = 7
+    seg, gg, off = cphot.upload(sh.seg, g)
+    S = cphot.make_segments(seg, gg, off)
+    with pytest.raises(cphot.CphotError, match="counts_rule"):
+        cphot.segment_counts(S, det, torch.zeros(S.n, dtype=torch.int32, device="cuda"))
