@@ -83,9 +83,30 @@ extern "C" {
 #define CPHOT_DETECTOR_SPHERES 1
 
 /* Emission wavelength: UNIFORM on [lam_min, lam_max], or FRANK_TAMM with
- * dN/dlambda ~ 1/lambda^2 (Eq. 2.4). */
+ * dN/dlambda ~ 1/lambda^2 (Eq. 2.4), or DISPERSIVE: FRANK_TAMM with a refractive
+ * index that depends on the wavelength as well as the height (Sec. 2.2.1: the
+ * yield integral over wavelength and track with the Heaviside factor of the
+ * threshold, and the angle of Eq. 2.5).
+ *
+ * DISPERSIVE: n(lambda, h) - 1 = (n(h) - 1) x R(lambda) / R(lambda_ref_nm), where n(h) - 1
+ * is the atmosphere's refractivity, stated at the wavelength lambda_ref_nm, and R is the
+ * two-term dispersion formula of standard air (Ciddor, Appl. Opt. 35 (1996) 1566):
+ * R = 5792105 / (238.0185 - s^2) + 167917 / (57.362 - s^2), s = 1/lambda in 1/um.
+ * R falls with lambda above 132 nm, so n is largest at lam_min. A segment draws its
+ * records for that largest cone: mu = K z^2 L sin^2(theta_max) / bunch, with n taken at
+ * lam_min and the segment midpoint (no records, status "below threshold", when
+ * beta n(lam_min) <= 1). Each Cherenkov record samples lambda ~ 1/lambda^2, takes the
+ * angle cos(theta) = 1 / (beta n(lambda, h_mid)), and is emitted iff
+ * u < sin^2(theta) / sin^2(theta_max), with sin^2(theta) = 0 where beta n(lambda) <= 1 and
+ * u the record's survival uniform; a record not emitted has state 4 and is counted in
+ * CPHOT_C_RECORDS_NOT_EMITTED. The expected emitted records are thus the Frank-Tamm
+ * integral with the threshold, and a record is detected iff
+ * u < (sin^2(theta) / sin^2(theta_max)) x exp(-tau) x efficiency / q. The track cut
+ * (CPHOT_CUT_TRACK) uses the largest cone. Propagation (refraction, delay) uses n(h).
+ * Needs lam_min >= 150 nm and lambda_ref_nm in [150, 10^5] nm. */
 #define CPHOT_SPECTRUM_UNIFORM 0
 #define CPHOT_SPECTRUM_FRANK_TAMM 1
+#define CPHOT_SPECTRUM_DISPERSIVE 2
 
 /* Emission (bit set). CHERENKOV (Sec. 2.2.1); FLUORESCENCE (Sec. 2.2.2, 4.2.2):
  * per band b, mu_b = fl_yield[b] x dE/dx x L / 2 records (lower hemisphere
@@ -147,6 +168,9 @@ extern "C" {
 #define CPHOT_C_RECORDS_CULLED_TRACK 11     /* Cherenkov records of segments removed by CPHOT_CUT_TRACK
                                                (never generated, not in records_generated) */
 #define CPHOT_C_RECORDS_CULLED_PHOTON 12    /* records removed by CPHOT_CUT_PHOTON (among records_outside) */
+#define CPHOT_C_RECORDS_NOT_EMITTED 13      /* DISPERSIVE: records of the largest cone not emitted at
+                                               their wavelength (state 4); records_generated = upward +
+                                               absorbed + outside + binned + not_emitted */
 
 typedef struct cphot_atmosphere cphot_atmosphere;
 typedef struct cphot_surrogate cphot_surrogate;
@@ -241,6 +265,7 @@ typedef struct {
    * u < exp(-tau) x efficiency / q: the same expected detections with fewer records generated.
    * A q below the true probability biases the result (the caller's bound must hold). */
   const double* reduction;
+  double lambda_ref_nm;     /* DISPERSIVE: wavelength (nm) at which the atmosphere's n - 1 is stated */
 } cphot_detector;
 
 /* Outputs, accumulated (+=) so that chunked calls need no host work; the caller
@@ -260,7 +285,7 @@ typedef struct {
 typedef struct {
   uint64_t seg;     /* global segment id */
   uint32_t k;       /* record index within the segment */
-  int32_t state;    /* 0 binned, 1 upward, 2 absorbed, 3 outside */
+  int32_t state;    /* 0 binned, 1 upward, 2 absorbed, 3 outside, 4 not emitted (DISPERSIVE) */
   int32_t bin;      /* grid cell or sphere index, -1 if none */
   int32_t tbin;     /* time bin (SPHERES), -1 if none */
   float x, y, z;    /* arrival point (ground or sphere entry) */

@@ -220,7 +220,7 @@ void orc_layer_tables(const orc_atmo* A, double* delta_out, double* ext_out) {
 enum { TRANSPORT_STRAIGHT = 0, TRANSPORT_LAYERED = 1, TRANSPORT_CURVED = 2 };
 enum { EMIT_CHERENKOV = 1, EMIT_FLUORESCENCE = 2 };
 enum { DETECTOR_GRID = 0, DETECTOR_SPHERES = 1 };
-enum { SPECTRUM_UNIFORM = 0, SPECTRUM_FRANK_TAMM = 1 };
+enum { SPECTRUM_UNIFORM = 0, SPECTRUM_FRANK_TAMM = 1, SPECTRUM_DISPERSIVE = 2 };
 
 typedef struct {
   int32_t transport, detector, spectrum, bunch;
@@ -241,9 +241,10 @@ typedef struct {
    * pre-emission reduction bound per layer (NULL: none), Sec. 4.3.1 */
   const double* efficiency;
   const double* reduction;
+  double lambda_ref;    /* dispersive spectrum: wavelength (nm) at which the atmosphere's n - 1 holds */
 } orc_run;
 
-enum { ST_BINNED = 0, ST_UPWARD = 1, ST_ABSORBED = 2, ST_OUTSIDE = 3 };
+enum { ST_BINNED = 0, ST_UPWARD = 1, ST_ABSORBED = 2, ST_OUTSIDE = 3, ST_NOT_EMITTED = 4 };
 
 typedef struct {
   int64_t seg;
@@ -260,6 +261,7 @@ typedef struct {
   double dx, dy, dz;    /* emission direction */
   int32_t source;       /* 0 Cherenkov, 1 + b fluorescence band b */
   int32_t pad;
+  double p_emit;        /* dispersive spectrum: probability that the record is emitted (else 1) */
 } orc_photon;
 
 typedef struct {
@@ -282,6 +284,7 @@ typedef struct { double core_x, core_y, ax, ay, az; } orc_geom;
 typedef struct {
   double S[3], E[3], L, beta, z2;
   double cos_t, sin_t, sin2;
+  double delta_mid; /* n - 1 at the midpoint, at the reference wavelength (dispersive spectrum) */
   double M[3][3]; /* rotation taking the cone axis (0,0,-1) onto the track direction */
 } seg_setup;
 
@@ -340,6 +343,16 @@ static int64_t poisson_draw(double mu, uint32_t w0, uint64_t seed, uint64_t seg_
   return total;
 }
 
+/* Dispersion of air: 1e8 (n - 1) of standard air at lambda nm, the two-term
+ * formula of Ciddor (Appl. Opt. 35 (1996) 1566), wavenumber s in 1/um. Only its
+ * ratio between two wavelengths is used: n(lambda, h) - 1 = (n(h) - 1) x
+ * R(lambda) / R(lambda_ref), so the height profile keeps its own scale. */
+static double air_dispersion_sum(double lambda_nm) {
+  double s = 1000.0 / lambda_nm;
+  double s2 = s * s;
+  return 5792105.0 / (238.0185 - s2) + 167917.0 / (57.362 - s2);
+}
+
 static double frank_tamm_K(double lam_min_nm, double lam_max_nm) {
   /* integral over lambda of 2 pi alpha / lambda^2, lambda in metres */
   double l1 = lam_min_nm * 1e-9, l2 = lam_max_nm * 1e-9;
@@ -392,6 +405,14 @@ static orc_segment segment_setup(const orc_atmo* A, const orc_run* R, double K,
     /* refractivity at the segment midpoint from the 1 m table */
     double hm = 0.5 * ((double)z0 + (double)z1);
     double delta = orc_delta_table(A, hm);
+    st->delta_mid = delta;
+    /* Dispersion (Sec. 2.2.1: the threshold and the yield depend on the
+     * wavelength through n(lambda, l)): the records are drawn for the largest
+     * cone -- n at the shortest wavelength, where air refracts most -- and each
+     * record is later emitted with the ratio of its own sin^2(theta) to that
+     * cone's, which integrates the Frank-Tamm density with its Heaviside factor. */
+    if (R->spectrum == SPECTRUM_DISPERSIVE)
+      delta = delta * (air_dispersion_sum(A->p.lam_min) / air_dispersion_sum(R->lambda_ref));
     /* threshold beta n > 1, with g = beta n - 1 written through eps = 1 - beta */
     double eps = 1.0 - beta;
     double g = delta - eps - eps * delta;
@@ -636,8 +657,8 @@ static int curved_walk_rec(const orc_atmo* A, const orc_run* R, int kbin, const 
  * with optical depth tau is detected (transmission exp(-tau), times the detector
  * efficiency of its wavelength bin), over the probability q with which its
  * record was kept at generation (Sec. 2.3.2, 4.3.1). */
-static double survival(const orc_run* R, const orc_segment* sg, double tau, int kbin) {
-  double p = exp(-tau);
+static double survival(const orc_run* R, const orc_segment* sg, double tau, int kbin, double p_emit) {
+  double p = exp(-tau) * p_emit;
   if (R->efficiency) p = p * R->efficiency[kbin];
   if (R->reduction) p = p / sg->q;
   return p;
@@ -651,7 +672,7 @@ static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G,
   memset(out, 0, sizeof(*out));
   out->seg = (int64_t)seg_id; out->k = (int32_t)k; out->bin = -1; out->tbin = -1;
   uint32_t w[4];
-  double P[3], u[3], lam, u3;
+  double P[3], u[3], lam, u3, emit_p = 1.0;
   if ((int32_t)k < sg->n) {
     draw(R->seed, k, seg_id, TAG_CHERENKOV, w);
     double f = u24(w[0]);
@@ -659,8 +680,22 @@ static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G,
     if (R->spectrum == SPECTRUM_UNIFORM) lam = p->lam_min + (p->lam_max - p->lam_min) * u24(w[2]);
     else lam = 1.0 / (1.0 / p->lam_min - u24(w[2]) * (1.0 / p->lam_min - 1.0 / p->lam_max));
     u3 = u24(w[3]);
+    double cos_t = st->cos_t, sin_t = st->sin_t;
+    if (R->spectrum == SPECTRUM_DISPERSIVE) {
+      /* n(lambda, h) at the segment midpoint; the angle of Eq. 2.5 and the
+       * Frank-Tamm weight sin^2(theta) = 1 - 1/(beta n)^2 of this wavelength,
+       * zero below the threshold (the Heaviside factor) */
+      double dl = st->delta_mid * (air_dispersion_sum(lam) / air_dispersion_sum(R->lambda_ref));
+      double eps = 1.0 - st->beta;
+      double g = dl - eps - eps * dl;
+      double s2 = g > 0.0 ? g * (g + 2.0) / ((1.0 + g) * (1.0 + g)) : 0.0;
+      emit_p = s2 / st->sin2;
+      /* below the threshold the record is never emitted; its direction is then
+       * taken along the track (the cone of zero opening) */
+      if (g > 0.0) { cos_t = 1.0 / (1.0 + g); sin_t = sqrt(s2); } else { cos_t = 1.0; sin_t = 0.0; }
+    }
     /* photon on the cone around (0,0,-1) (Sec. 4.2), rotated onto the track */
-    double pl[3] = {cos(phi) * st->sin_t, sin(phi) * st->sin_t, -st->cos_t};
+    double pl[3] = {cos(phi) * sin_t, sin(phi) * sin_t, -cos_t};
     for (int i = 0; i < 3; ++i) u[i] = st->M[i][0] * pl[0] + st->M[i][1] * pl[1] + st->M[i][2] * pl[2];
     /* emission at a random point along the track (Sec. 4.2, third step) */
     for (int i = 0; i < 3; ++i) P[i] = st->S[i] + f * (st->E[i] - st->S[i]);
@@ -684,7 +719,15 @@ static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G,
   out->lambda = lam; out->u_abs = u3;
   out->ex = P[0]; out->ey = P[1]; out->ez = P[2];
   out->dx = u[0]; out->dy = u[1]; out->dz = u[2];
+  out->p_emit = emit_p;
   double axis[3] = {G->ax, G->ay, G->az};
+  /* a record of the largest cone that its wavelength does not emit */
+  if (!(u3 < emit_p)) {
+    out->state = ST_NOT_EMITTED;
+    out->x = P[0]; out->y = P[1]; out->z = P[2];
+    out->margin = 1e30; out->tmargin = 1e30;
+    return;
+  }
   /* upward photons are discarded first (Sec. 5.3.4) */
   if (!(u[2] < 0.0)) { out->state = ST_UPWARD; return; }
   double h_e = P[2];
@@ -714,7 +757,7 @@ static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G,
     double fx = (ps.pos[0] - gx0) / R->cell, fy = (ps.pos[1] - gy0) / R->cell;
     double ix = floor(fx), iy = floor(fy);
     out->margin = min4(fx - ix, ix + 1.0 - fx, fy - iy, iy + 1.0 - fy) * R->cell;
-    if (!(u3 < survival(R, sg, ps.tau, kbin))) { out->state = ST_ABSORBED; return; }
+    if (!(u3 < survival(R, sg, ps.tau, kbin, out->p_emit))) { out->state = ST_ABSORBED; return; }
     if (!(ix >= 0 && iy >= 0 && ix < R->nx && iy < R->ny)) { out->state = ST_OUTSIDE; return; }
     out->state = ST_BINNED;
     out->bin = (int)iy * R->nx + (int)ix;
@@ -788,7 +831,7 @@ static void trace_photon(const orc_atmo* A, const orc_run* R, const orc_geom* G,
   out->margin = margin;
   /* absorption and scattering remove the photon (Sec. 2.3.2): survival iff u < exp(-tau),
    * times the detector efficiency and over the reduction factor where set */
-  if (!(u3 < survival(R, sg, ps.tau, kbin))) { out->state = ST_ABSORBED; return; }
+  if (!(u3 < survival(R, sg, ps.tau, kbin, out->p_emit))) { out->state = ST_ABSORBED; return; }
   if (bin < 0) { out->state = ST_OUTSIDE; return; }
   out->state = ST_BINNED;
   out->bin = bin;
@@ -849,7 +892,7 @@ int64_t orc_trace(const orc_atmo* A, const orc_run* R, const orc_segments* S, co
 
 enum {
   C_SEG_IN = 0, C_SEG_SKIPPED, C_SEG_BELOW, C_REC_GEN, C_REC_UP, C_REC_ABS, C_REC_OUT, C_REC_BIN,
-  C_PHOT_BIN, C_SURR_FALLBACK, N_COUNTERS = 16
+  C_PHOT_BIN, C_SURR_FALLBACK, C_REC_NOT_EMITTED = 13, N_COUNTERS = 16
 };
 
 typedef struct {
@@ -883,6 +926,7 @@ static void* worker(void* vp) {
         case ST_UPWARD: W->counters[C_REC_UP] += 1; break;
         case ST_ABSORBED: W->counters[C_REC_ABS] += 1; break;
         case ST_OUTSIDE: W->counters[C_REC_OUT] += 1; break;
+        case ST_NOT_EMITTED: W->counters[C_REC_NOT_EMITTED] += 1; break;
         default:
           W->counters[C_REC_BIN] += 1;
           W->counters[C_PHOT_BIN] += (uint64_t)R->bunch;

@@ -46,7 +46,8 @@ class Run(C.Structure):
                 ("snx", C.c_int32), ("sny", C.c_int32), ("pitch", C.c_double), ("radius", C.c_double),
                 ("n_t", C.c_int32), ("counts_rule", C.c_int32), ("dt", C.c_double),
                 ("emission", C.c_int32), ("pad2", C.c_int32), ("fl_yield", C.c_double * 3),
-                ("fl_lambda", C.c_double * 3), ("efficiency", C.c_void_p), ("reduction", C.c_void_p)]
+                ("fl_lambda", C.c_double * 3), ("efficiency", C.c_void_p), ("reduction", C.c_void_p),
+                ("lambda_ref", C.c_double)]
 
 
 class Segments(C.Structure):
@@ -64,7 +65,8 @@ PHOTON_DTYPE = np.dtype([
     ("x", np.float64), ("y", np.float64), ("z", np.float64), ("t", np.float64), ("tau", np.float64),
     ("lambda", np.float64), ("u_abs", np.float64), ("margin", np.float64), ("tmargin", np.float64),
     ("ex", np.float64), ("ey", np.float64), ("ez", np.float64),
-    ("dx", np.float64), ("dy", np.float64), ("dz", np.float64), ("source", np.int32), ("pad", np.int32)])
+    ("dx", np.float64), ("dy", np.float64), ("dz", np.float64), ("source", np.int32), ("pad", np.int32),
+    ("p_emit", np.float64)])
 
 SEGMENT_DTYPE = np.dtype([("n", np.int32), ("status", np.int32), ("mu", np.float64),
                           ("cos_t", np.float64), ("sin2_t", np.float64), ("nf", np.int32, 3), ("pad", np.int32),
@@ -83,7 +85,7 @@ EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
 FL_LAMBDA = (337.0, 357.0, 391.0)
 FL_YIELD = (7.0, 5.0, 2.0)
 DETECTORS = {"grid": 0, "spheres": 1}
-SPECTRA = {"uniform": 0, "frank_tamm": 1}
+SPECTRA = {"uniform": 0, "frank_tamm": 1, "dispersive": 2}
 
 
 def lib():
@@ -201,7 +203,7 @@ class Atmosphere:
 def make_run(transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0, h_obs=2200.0,
              nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0, dt=1.0,
              emission="cherenkov", fl_yield=FL_YIELD, fl_lambda=FL_LAMBDA, efficiency=None, reduction=None,
-             counts="rounded", **_ignored) -> Run:
+             counts="rounded", lambda_ref=400.0, **_ignored) -> Run:
     """`efficiency` (per wavelength bin) and `reduction` (per layer): float64
     arrays or None (Sec. 4.3.1)."""
     r = Run()
@@ -212,6 +214,7 @@ def make_run(transport="straight", detector="grid", spectrum="uniform", bunch=1,
     r.n_t, r.dt = int(n_t), float(dt)
     r.emission = EMISSION[emission]
     r.counts_rule = {"rounded": 0, "poisson": 1}[counts]
+    r.lambda_ref = float(lambda_ref)
     r.fl_yield[:] = tuple(float(v) for v in fl_yield)
     r.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
     keep = []

@@ -28,7 +28,7 @@ COUNTS = {"rounded": 0, "poisson": 1}  # record count per segment from its expec
 CUTS = {"track": 1, "photon": 2}  # data-reduction bounds for spheres (never drop a possible hit)
 EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
 DETECTOR = {"grid": 0, "spheres": 1}
-SPECTRUM = {"uniform": 0, "frank_tamm": 1}
+SPECTRUM = {"uniform": 0, "frank_tamm": 1, "dispersive": 2}
 BINS = {"u32": 0, "u64": 1, "f64": 2}
 GEOMETRY = {"planar": 0, "curved": 1}
 COUNTERS = ["segments_in", "segments_skipped", "segments_below_threshold", "records_generated",
@@ -67,7 +67,7 @@ class Detector(C.Structure):
                 ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("hist_window", C.c_int32),
                 ("surrogate", C.c_void_p), ("emission", C.c_int32), ("cuts", C.c_int32),
                 ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3), ("table", C.c_void_p),
-                ("efficiency", C.c_void_p), ("reduction", C.c_void_p)]
+                ("efficiency", C.c_void_p), ("reduction", C.c_void_p), ("lambda_ref_nm", C.c_double)]
 
 
 class SurrogateDesc(C.Structure):
@@ -224,7 +224,7 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
                   h_obs=2200.0, nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0,
                   dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, surrogate=None,
                   emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0), cuts=(),
-                  table=None, efficiency=None, reduction=None, counts="rounded") -> Detector:
+                  table=None, efficiency=None, reduction=None, counts="rounded", lambda_ref=400.0) -> Detector:
     """`efficiency` and `reduction`: float64 device tensors (per wavelength bin,
     per layer) or None; see cphot_detector."""
     d = Detector()
@@ -239,6 +239,7 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
     d.emission = EMISSION[emission]
     d.cuts = sum(CUTS[c] for c in cuts)
     d.counts_rule = COUNTS[counts]
+    d.lambda_ref_nm = float(lambda_ref)
     d.fl_yield[:] = tuple(float(v) for v in fl_yield)
     d.fl_lambda[:] = tuple(float(v) for v in fl_lambda)
     if surrogate is not None:

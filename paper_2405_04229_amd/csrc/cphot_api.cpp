@@ -59,6 +59,14 @@ double depth(const cphot_atmosphere_desc& d, double h) {
   return d.lin_a[4] - d.lin_b[4] * hcm / d.lin_c[4];
 }
 
+// Dispersion sum of standard air, 1e8 (n - 1), at lambda nm (two-term formula of
+// Ciddor, Appl. Opt. 35 (1996) 1566; wavenumber in 1/um).
+constexpr double kDispK0 = 238.0185, kDispK1 = 5792105.0, kDispK2 = 57.362, kDispK3 = 167917.0;
+double air_dispersion(double lambda_nm) {
+  const double s = 1000.0 / lambda_nm, s2 = s * s;
+  return kDispK1 / (kDispK0 - s2) + kDispK3 / (kDispK2 - s2);
+}
+
 double density(const cphot_atmosphere_desc& d, double h) {
   const int i = linsley_layer(d, h);
   if (i < 4) return (d.lin_b[i] / d.lin_c[i]) * std::exp(-(h * 100.0) / d.lin_c[i]);
@@ -146,8 +154,13 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     return fail(CPHOT_ERR_INVALID_ARG, "fluorescence needs the dedx column");
   if (det->detector != CPHOT_DETECTOR_GRID && det->detector != CPHOT_DETECTOR_SPHERES)
     return fail(CPHOT_ERR_INVALID_ARG, "unknown detector");
-  if (det->spectrum != CPHOT_SPECTRUM_UNIFORM && det->spectrum != CPHOT_SPECTRUM_FRANK_TAMM)
+  if (det->spectrum != CPHOT_SPECTRUM_UNIFORM && det->spectrum != CPHOT_SPECTRUM_FRANK_TAMM &&
+      det->spectrum != CPHOT_SPECTRUM_DISPERSIVE)
     return fail(CPHOT_ERR_INVALID_ARG, "unknown spectrum");
+  if (det->spectrum == CPHOT_SPECTRUM_DISPERSIVE &&
+      (!(d.lambda_min_nm >= 150.0) || !(det->lambda_ref_nm >= 150.0 && det->lambda_ref_nm <= 1e5)))
+    return fail(CPHOT_ERR_INVALID_ARG, "the dispersive spectrum needs lam_min >= 150 nm and lambda_ref_nm in "
+                                       "[150, 1e5] nm");
   if (det->bunch < 1) return fail(CPHOT_ERR_INVALID_ARG, "bunch must be >= 1");
   if (!std::isfinite(det->h_obs) || det->h_obs < 0.0 || det->h_obs >= d.h_top)
     return fail(CPHOT_ERR_INVALID_ARG, "h_obs must lie in [0, h_top)");
@@ -191,6 +204,15 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   p.inv_lam_min = (float)(1.0 / d.lambda_min_nm);
   p.inv_lam_max = (float)(1.0 / d.lambda_max_nm);
   p.spectrum = det->spectrum;
+  if (det->spectrum == CPHOT_SPECTRUM_DISPERSIVE) {
+    const double rmax = air_dispersion(d.lambda_min_nm), rref = air_dispersion(det->lambda_ref_nm);
+    p.disp_dmax = rmax / rref;
+    p.disp_inv_rref = 1.0 / rref;
+    const double sm = 1000.0 / d.lambda_min_nm, s2m = sm * sm;
+    p.disp_s2m = (float)s2m;
+    p.disp_k1c = (float)(kDispK1 / (kDispK0 - s2m));
+    p.disp_k3c = (float)(kDispK3 / (kDispK2 - s2m));
+  }
   p.dedx = seg->dedx;
   p.emission = det->emission ? det->emission : CPHOT_EMIT_CHERENKOV;
   for (int b = 0; b < 3; ++b) {

@@ -54,6 +54,11 @@ struct KParams {
   float inv_ray400, aer_tau350, aer_inv_h, aer_ang;
   float lam_min, lam_max, inv_lam_min, inv_lam_max;
   int32_t spectrum;
+  // DISPERSIVE (R: the standard-air dispersion sum): R(lam_min) / R(lambda_ref) and
+  // 1 / R(lambda_ref) in FP64 (segment setup); s_min^2 = (1000 / lam_min)^2,
+  // k1 / (k0 - s_min^2) and k3 / (k2 - s_min^2) in FP32 (per-record angle)
+  double disp_dmax, disp_inv_rref;
+  float disp_s2m, disp_k1c, disp_k3c;
   // observation level quantities (FP32)
   float h_obs, X_obs, I_obs, A_obs;
   // transport / detector

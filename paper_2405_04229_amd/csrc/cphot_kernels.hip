@@ -29,6 +29,8 @@ struct SegResult {
   double mu;       // expected Cherenkov records
   int32_t nf[3];   // fluorescence records per band
   float inv_q;     // 1 / pre-emission reduction factor (1 without reduction)
+  // DISPERSIVE: g(lambda) = beta n(lambda, h_mid) - 1 = disp_gm + disp_a (R(lambda) - R(lam_min))
+  float disp_a, disp_gm;
 };
 
 // Per-segment yield in FP64 with IEEE basic operations only and no
@@ -87,14 +89,21 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
       fi = (double)idx;
     }
     const double frac = x - fi;
-    const double delta = (1.0 - frac) * p.tab[idx] + frac * p.tab[idx + 1];
-    // threshold beta n > 1 through g = beta n - 1 = delta - eps - eps delta, eps = 1 - beta
+    double delta = (1.0 - frac) * p.tab[idx] + frac * p.tab[idx + 1];
     const double eps = 1.0 - beta;
+    if (p.spectrum == CPHOT_SPECTRUM_DISPERSIVE) {
+      // records are drawn for the largest cone, n at lam_min; each record's own
+      // angle follows from its wavelength
+      r.disp_a = (float)(delta * (1.0 - eps) * p.disp_inv_rref);
+      delta = delta * p.disp_dmax;
+    }
+    // threshold beta n > 1 through g = beta n - 1 = delta - eps - eps delta, eps = 1 - beta
     const double g = delta - eps - eps * delta;
     if (!(g > 0.0)) {
       r.status = 1;
     } else {
       const double s2 = g * (g + 2.0) / ((1.0 + g) * (1.0 + g));
+      r.disp_gm = (float)g;
       const double z2 = (double)fq * (double)fq;
       double mu = p.K * z2;
       mu = mu * L;
@@ -275,6 +284,7 @@ __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float 
 // its wavelength bin and divided by its segment's reduction factor when set
 // (the detection probability over the probability the record was generated with).
 // Without efficiency the table holds ones, without reduction 1/q is 1: no branches.
+// Under the dispersive spectrum the uniform compared with it is u / p_emit.
 __device__ __forceinline__ float survival_threshold(const KParams& p, const float* __restrict__ s_eff, float tau,
                                                     int kb, uint32_t inv_q_bits) {
   return __expf(-tau) * (s_eff[kb] * __uint_as_float(inv_q_bits));
@@ -297,7 +307,7 @@ struct Photon {
 // transport every lane of the wave must call this together (`valid` marks the
 // lanes that carry a real record); the network is evaluated before any lane
 // leaves.
-template <int TRANSPORT, int DETECTOR, bool NEED_TIME>
+template <int TRANSPORT, int DETECTOR, bool NEED_TIME, bool DISP>
 __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict__ s_lay,
                                       const float2* __restrict__ s_lam, const MlpImage* __restrict__ s_img,
                                       const KConst* __restrict__ s_k, const float* __restrict__ s_eff,
@@ -305,13 +315,15 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
                                       const float4 q0, const float4 q1, const float4 q2, const float4 q3,
                                       const float4 q4, const float axz, const uint4 q5, uint32_t k, bool valid,
                                       Photon& o) {
-  const float sx = q0.x, sy = q0.y, sz = q0.z, cos_t = q0.w;
-  const float dx = q1.x, dy = q1.y, dz = q1.z, sin_t = q1.w;
+  const float sx = q0.x, sy = q0.y, sz = q0.z;
+  const float dx = q1.x, dy = q1.y, dz = q1.z;
   const float ax = q2.x, ay = q2.y, az = q2.z, X0 = q2.w;
   const float dX = q3.x;
   const float core_x = q4.x, core_y = q4.y, axx = q4.z, axy = q4.w;
   // record k: Cherenkov records first (k < q5.x), then the fluorescence bands
   float f, lam, u3, ux, uy, uz;
+  bool emitted = true;
+  float inv_pe = 1.f;
   if (k < q5.x) {
     const uint4 w = philox(k, __float_as_uint(q3.y), __float_as_uint(q3.z), TAG_CHERENKOV, p.key0, p.key1);
     f = u24(w.x);
@@ -326,6 +338,26 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
               ? p.lam_min + (p.lam_max - p.lam_min) * u2
               : rcp_fast(p.inv_lam_min - u2 * (p.inv_lam_min - p.inv_lam_max));
     u3 = u24(w.w);
+    float cos_t = q0.w, sin_t = q1.w;
+    if constexpr (DISP) {
+      // angle of this wavelength (Eq. 2.5) and the record's emission probability
+      // sin^2(theta) / sin^2(theta_max) relative to the cone it was drawn for.
+      // g = beta n - 1 is taken as its segment value at lam_min plus the change of
+      // the dispersion sum, R(lambda) - R(lam_min) = (s^2 - s_min^2) (k1 / ((k0 - s^2)
+      // (k0 - s_min^2)) + k3 / ((k2 - s^2) (k2 - s_min^2))), which FP32 resolves to
+      // about 1e-12 in g where R itself would carry 1e-10.
+      const float sg = 1000.0f * rcp_fast(lam), sg2 = sg * sg;
+      const float dR = (sg2 - p.disp_s2m) *
+                       fmaf(p.disp_k1c, rcp_fast(238.0185f - sg2), p.disp_k3c * rcp_fast(57.362f - sg2));
+      const float gm = q1.w;
+      const float g = fmaxf(fmaf(q0.w, dR, gm), 0.f);
+      const float c = rcp_fast(1.0f + g), gg = g * (g + 2.0f);
+      const float pe = (gg * (c * c)) * (((1.0f + gm) * (1.0f + gm)) * rcp_fast(gm * (gm + 2.0f)));
+      emitted = u3 < pe;
+      inv_pe = rcp_fast(pe);
+      cos_t = c;
+      sin_t = sqrt_fast(gg) * c;
+    }
     // photon on the cone around (0,0,-1), turned onto the track: u = 2 a (a.p) - p
     const float plx = cphi * sin_t, ply = sphi * sin_t, plz = -cos_t;
     const float d2 = 2.0f * fmaf(ax, plx, fmaf(ay, ply, az * plz));
@@ -350,6 +382,8 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   }
   o.lam = lam;
   o.u3 = u3;
+  // detected iff u < p_emit exp(-tau) efficiency / q: compare u / p_emit from here on
+  if constexpr (DISP) u3 = u3 * inv_pe;
   o.bin = -1;
   o.tbin = -1;
   o.fallback = 0;
@@ -363,6 +397,12 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   o.x = Px;
   o.y = Py;
   o.z = Pz;
+  if constexpr (DISP && !kMlpTransport<TRANSPORT>) {
+    if (!emitted) {  // below the threshold at its wavelength: never emitted
+      o.state = 4;
+      return;
+    }
+  }
   int kb = 0;
   if (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT || p.eff) {
     kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
@@ -381,7 +421,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     if constexpr (TRANSPORT == kTransportCurvedSurrogate) {
       const float irq = 1.0f / rq;
       c0 = -fmaf(ux, Px * irq, fmaf(uy, Py * irq, uz * (qz * irq)));
-      const bool alive = valid && (uz < 0.f) && (h0 >= p.h_obs);
+      const bool alive = valid && emitted && (uz < 0.f) && (h0 >= p.h_obs);
       float xin[kMlpIn] = {h0, c0, atan2f(uy, ux),
                            p.lam_min + ((float)kb + 0.5f) * ((p.lam_max - p.lam_min) / (float)p.n_lam), p.h_obs};
       use_mlp = alive && mlp_in_domain(s_img, xin);
@@ -390,6 +430,10 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
         for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
       }
       mlp_forward_wave(s_img, xin, ym, s_stage);
+      if (DISP && !emitted) {
+        o.state = 4;
+        return;
+      }
     }
     if (!(uz < 0.f)) {
       o.state = 1;
@@ -479,7 +523,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   float ym[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
   bool use_mlp = false;
   if constexpr (TRANSPORT == CPHOT_TRANSPORT_SURROGATE) {
-    const bool alive = valid && (uz < 0.f) && (Pz >= p.h_obs);
+    const bool alive = valid && emitted && (uz < 0.f) && (Pz >= p.h_obs);
     float xin[kMlpIn] = {Pz, -uz, atan2f(uy, ux),
                          p.lam_min + ((float)kb + 0.5f) * ((p.lam_max - p.lam_min) / (float)p.n_lam), p.h_obs};
     use_mlp = alive && mlp_in_domain(s_img, xin);
@@ -488,6 +532,10 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
     }
     mlp_forward_wave(s_img, xin, ym, s_stage);
+    if (DISP && !emitted) {
+      o.state = 4;
+      return;
+    }
   }
   if (!(uz < 0.f)) {
     o.state = 1;
@@ -720,7 +768,10 @@ constexpr int kMinWavesPerSimd =
     : (T == CPHOT_TRANSPORT_CURVED || T == CPHOT_TRANSPORT_LAYERED || T == CPHOT_TRANSPORT_STRAIGHT || T == CPHOT_TRANSPORT_TABLE) ? 4
                                                                                                                      : 1;
 
-template <int BS, int TRANSPORT, int DETECTOR, int MODE>
+// DISP: the dispersive spectrum's per-record angle and emission decision, compiled
+// only into the kernels that run it (as a runtime branch its registers cost the
+// other spectra about a tenth of their time).
+template <int BS, int TRANSPORT, int DETECTOR, int MODE, bool DISP>
 __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(KParams p) {
   constexpr bool kTime = (DETECTOR == CPHOT_DETECTOR_SPHERES) || (MODE == MODE_RECORDS);
   constexpr bool kLayers = (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT);
@@ -734,7 +785,8 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       : (TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable) ? CPHOT_TRANSPORT_CURVED
                                                                                         : TRANSPORT;
   // per-segment state for the record loop, one slot per segment of the tile:
-  // q0 = start point, cos(theta); q1 = end - start, sin(theta); q2 = rotation
+  // q0 = start point, cos(theta); q1 = end - start, sin(theta) (DISPERSIVE: the
+  // terms of beta n(lambda) - 1 in place of the angle); q2 = rotation
   // bisector, depth at the start; q3 = depth change, id low, id high, shower
   // (bit patterns); q4 = core x, core y, axis x, axis y; axz = axis z
   __shared__ float4 s_q0[BS], s_q1[BS], s_q2[BS], s_q3[BS], s_q4[BS];
@@ -850,8 +902,8 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
           dXs = depth_f(s_k, fz1) - X0;
         }
         const double* g = p.geom + 5 * sh;
-        q0 = make_float4(fx0, fy0, fz0, r.cos_t);
-        q1 = make_float4(fx1 - fx0, fy1 - fy0, fz1 - fz0, r.sin_t);
+        q0 = make_float4(fx0, fy0, fz0, DISP ? r.disp_a : r.cos_t);
+        q1 = make_float4(fx1 - fx0, fy1 - fy0, fz1 - fz0, DISP ? r.disp_gm : r.sin_t);
         q2 = make_float4(r.a0, r.a1, r.a2, X0);
         q3 = make_float4(dXs, __uint_as_float((uint32_t)id), __uint_as_float((uint32_t)(id >> 32)),
                          __uint_as_float((uint32_t)sh));
@@ -979,7 +1031,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       const uint32_t k = j - s_off[lo];
       Photon ph;
       const float4 r3 = s_q3[lo];
-      trace<TRANSPORT, DETECTOR, kTime>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
+      trace<TRANSPORT, DETECTOR, kTime, DISP>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
                                         s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], s_q5[lo], k, valid, ph);
       if constexpr (kDefer) {
         // wave-level compaction: deferred records take consecutive queue slots
@@ -1008,7 +1060,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
             const uint32_t qk = s_qk[q];
             const float4 q3 = s_q3[qlo];
             Photon pe;
-            trace<kExact, DETECTOR, kTime>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
+            trace<kExact, DETECTOR, kTime, DISP>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
                                            s_q4[qlo], s_axz[qlo], s_q5[qlo], qk, true, pe);
             pe.fallback = 1;
             consume(pe, qlo, qk, q3);
@@ -1031,12 +1083,16 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
     if (p.counters) {
       // block-level reduction: one global atomic per counter per block (same-address
       // device atomics serialise, so their number must stay small)
-      __shared__ uint32_t s_cnt[12];
-      if (tid < 12) s_cnt[tid] = 0u;
+      __shared__ uint32_t s_cnt[13];
+      if (tid < 13) s_cnt[tid] = 0u;
       __syncthreads();
-      const uint32_t v[12] = {c_in, c_skip, c_below, c_gen, c_up, c_abs, c_out, c_bin, c_fb, c_fl, c_cut1, c_cut3};
+      // every consumed record has exactly one final state; the records not emitted
+      // (state 4) are the rest, so they need no accumulator of their own
+      const uint32_t c_ne = c_gen - c_up - c_abs - c_out - c_bin;  // modulo 2^32: exact over the block
+      const uint32_t v[13] = {c_in,  c_skip, c_below, c_gen, c_up,   c_abs, c_out,
+                              c_bin, c_fb,   c_fl,    c_cut1, c_cut3, c_ne};
 #pragma unroll
-      for (int q = 0; q < 12; ++q) {
+      for (int q = 0; q < 13; ++q) {
         const uint32_t sw = wave_sum(v[q]);
         if ((tid & 63) == 0 && sw) atomicAdd(&s_cnt[q], sw);
       }
@@ -1047,24 +1103,31 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       if (tid == 10 && s_cnt[9]) atomicAdd(p.counters + CPHOT_C_RECORDS_FLUORESCENCE, (unsigned long long)s_cnt[9]);
       if (tid == 11 && s_cnt[10]) atomicAdd(p.counters + CPHOT_C_RECORDS_CULLED_TRACK, (unsigned long long)s_cnt[10]);
       if (tid == 12 && s_cnt[11]) atomicAdd(p.counters + CPHOT_C_RECORDS_CULLED_PHOTON, (unsigned long long)s_cnt[11]);
+      if (tid == 13 && s_cnt[12]) atomicAdd(p.counters + CPHOT_C_RECORDS_NOT_EMITTED, (unsigned long long)s_cnt[12]);
     }
   }
 }
 
 namespace {
 
-template <int BS, int T, int D, int M>
+template <int BS, int T, int D, int M, bool DISP>
 hipError_t launch_one(const KParams& p, int grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_propagate<BS, T, D, M>), dim3(grid), dim3(BS), lds, s, p);
+  hipLaunchKernelGGL((k_propagate<BS, T, D, M, DISP>), dim3(grid), dim3(BS), lds, s, p);
   return hipGetLastError();
 }
 
+// The count pass traces no record: one kernel serves every spectrum.
 template <int BS, int T, int D>
 hipError_t launch_mode(const KParams& p, int mode, int grid, size_t lds, hipStream_t s) {
+  const bool disp = p.spectrum == CPHOT_SPECTRUM_DISPERSIVE;
   switch (mode) {
-    case MODE_PROPAGATE: return launch_one<BS, T, D, MODE_PROPAGATE>(p, grid, lds, s);
-    case MODE_COUNTS: return launch_one<BS, T, D, MODE_COUNTS>(p, grid, lds, s);
-    default: return launch_one<BS, T, D, MODE_RECORDS>(p, grid, lds, s);
+    case MODE_PROPAGATE:
+      return disp ? launch_one<BS, T, D, MODE_PROPAGATE, true>(p, grid, lds, s)
+                  : launch_one<BS, T, D, MODE_PROPAGATE, false>(p, grid, lds, s);
+    case MODE_COUNTS: return launch_one<BS, T, D, MODE_COUNTS, false>(p, grid, lds, s);
+    default:
+      return disp ? launch_one<BS, T, D, MODE_RECORDS, true>(p, grid, lds, s)
+                  : launch_one<BS, T, D, MODE_RECORDS, false>(p, grid, lds, s);
   }
 }
 
@@ -1085,7 +1148,8 @@ hipError_t launch_bs(const KParams& p, int mode, int grid, size_t lds, hipStream
 template <int BS, int T, int D, int M>
 size_t static_lds_one() {
   hipFuncAttributes a;
-  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&k_propagate<BS, T, D, M>)) != hipSuccess) return 0;
+  // the dispersive kernels declare the same static LDS
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&k_propagate<BS, T, D, M, false>)) != hipSuccess) return 0;
   return a.sharedSizeBytes;
 }
 

@@ -91,10 +91,12 @@ def near_boundary(orc, core, atm_kw, run_kw, surv_thr=None):
     """Records of the oracle whose decisions (survival, bin, time bin, start
     layer, wavelength bin) lie within rounding distance of their boundary, and
     the per-record position tolerance. `surv_thr`: the survival thresholds where
-    they are not exp(-tau) (detector efficiency, pre-emission reduction).
+    they are not exp(-tau) (detector efficiency, pre-emission reduction); under the
+    dispersive spectrum the emission decision u < p_emit is one more boundary.
     Returns (near, pos_tol, h_emit, layer_m, lambin_m)."""
-    thr = np.exp(-orc["tau"]) if surv_thr is None else surv_thr
-    surv_m = np.abs(orc["u_abs"] - thr)
+    p_emit = orc["p_emit"]  # 1 except under the dispersive spectrum
+    thr = np.exp(-orc["tau"]) * p_emit if surv_thr is None else surv_thr
+    surv_m = np.minimum(np.abs(orc["u_abs"] - thr), np.abs(orc["u_abs"] - p_emit))
     transport = run_kw.get("transport", "straight")
     h_emit = orc["ez"]
     if transport == "curved":
@@ -131,8 +133,12 @@ def compare_records(gpu, orc, core, atm_kw, run_kw, surv_thr=None):
     # the same uniforms on both sides: the survival uniform is exact in FP32
     np.testing.assert_array_equal(gpu["u_abs"].astype(np.float64), orc["u_abs"])
     np.testing.assert_allclose(gpu["lambda"], orc["lambda"], rtol=2e-6)
+    # directions of records never emitted (dispersive spectrum, state 4 in the
+    # oracle) are not compared: next to the threshold the cone's opening is
+    # ill-conditioned and such a record carries no photon
     du = np.stack([gpu["dx"], gpu["dy"], gpu["dz"]], 1) - np.stack([orc["dx"], orc["dy"], orc["dz"]], 1)
-    assert np.abs(du).max() <= DIR_TOL, np.abs(du).max()
+    du = du[orc["state"] != 4]
+    assert du.size == 0 or np.abs(du).max() <= DIR_TOL, np.abs(du).max()
     transport = run_kw.get("transport", "straight")
     layered = transport in ("layered", "curved")
     near, pos_tol, h_emit, lm, lbm = near_boundary(orc, core, atm_kw, run_kw, surv_thr)
@@ -144,12 +150,13 @@ def compare_records(gpu, orc, core, atm_kw, run_kw, surv_thr=None):
                           f"{gpu[bad][:3]} vs {orc[bad][:3]}"
     flips = (state_diff | bin_diff) & near
     # continuous quantities where both sides reached the observation level
-    live = (orc["state"] != 1) & ~((orc["state"] == 3) & (h_emit < run_kw.get("h_obs", 2200.0)))
+    live = (orc["state"] != 1) & (orc["state"] != 4) & ~((orc["state"] == 3) & (h_emit < run_kw.get("h_obs", 2200.0)))
     if transport == "curved":
         live &= orc["margin"] < 1e29      # left the top of the atmosphere: no arrival point
     live &= ~(near & (lm < FLIP_LAYER) if layered else np.zeros(len(orc), bool))
     # a legitimate hit/miss flip moves the arrival point (sphere entry vs plane crossing)
     live &= ~bin_diff
+    live &= gpu["state"] != 4  # an emission flip: one side stopped at the emission point
     dpos = np.hypot(gpu["x"] - orc["x"], gpu["y"] - orc["y"])
     assert np.all(dpos[live] <= pos_tol[live]), f"max position error {np.max(dpos[live] / pos_tol[live])} of tolerance"
     dt = np.abs(gpu["t"] - orc["t"])

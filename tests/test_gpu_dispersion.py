@@ -1,0 +1,142 @@
+"""Dispersive spectrum (Sec. 2.2.1, Eq. 2.5) on the GPU, through the C ABI, against
+the oracle on the same seeded inputs: counts bit-exact, records at parity
+(emission decisions identical except next to u = p_emit), bins and counters."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from oracle import oracle as O
+from paper_2405_04229_amd import workload as W
+from tests import cases, parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_04229_amd import cphot  # noqa: E402
+
+ATMO = cases.ATMO_LAYERED
+
+
+def _geom(sh):
+    return np.array([[*sh.core, *sh.axis]])
+
+
+def _near_threshold(sh, seed):
+    """The shower's segments with beta moved to the threshold of a wavelength spread
+    over the band: beta (1 + delta(h_mid) D) = 1 with D uniform in [0.975, 1.035]
+    (D = (n(lambda) - 1) / (n(400 nm) - 1) spans about 0.98 to 1.03 over 300-600 nm)."""
+    oatm = O.Atmosphere(**ATMO)
+    seg = dict(sh.seg)
+    hm = 0.5 * (seg["z0"].astype(np.float64) + seg["z1"])
+    delta = oatm.delta_table(hm)
+    D = np.random.default_rng(seed).uniform(0.975, 1.035, len(hm))
+    seg["beta"] = (1.0 / (1.0 + delta * D)).astype(np.float32)
+    return seg
+
+
+@pytest.mark.parametrize("counts", ["rounded", "poisson"])
+@pytest.mark.parametrize("near", [False, True])
+def test_counts_bit_exact(counts, near):
+    sh = W.make_shower(20_000, seed=920, xmax=450.0, zenith_deg=20.0, beta="R")
+    seg = _near_threshold(sh, 1) if near else sh.seg
+    run = {**cases.RUN_TELESCOPE, "spectrum": "dispersive", "lambda_ref": 400.0, "counts": counts, "seed": 12}
+    g, mu = parity.device_counts(ATMO, run, seg, _geom(sh), with_mu=True)
+    o = O.segment_counts(parity.oracle_atm(ATMO), O.make_run(**run), seg)
+    np.testing.assert_array_equal(g, o["n"])
+    omu = np.where(o["status"] == 0, o["mu"], 0.0)
+    np.testing.assert_array_equal(mu.view(np.uint64), omu.view(np.uint64))
+    if near:
+        assert (o["status"] == 1).sum() > 500  # below the threshold even at lam_min
+
+
+@pytest.mark.parametrize("transport,near", [("layered", False), ("layered", True), ("straight", True),
+                                            ("curved", True)])
+def test_records_match_oracle(transport, near):
+    sh = W.make_shower(2500, seed=921, xmax=500.0, zenith_deg=30.0, azimuth_deg=60.0, beta="R")
+    seg = _near_threshold(sh, 2) if near else sh.seg
+    run = dict(transport=transport, detector="grid", spectrum="dispersive", lambda_ref=400.0, bunch=1,
+               h_obs=2200.0, nx=300, ny=300, cell=40.0 if transport == "curved" else 4.0, seed=26)
+    g = parity.device_records(ATMO, run, seg, _geom(sh))
+    o = O.trace(parity.oracle_atm(ATMO), O.make_run(**run), seg, core=sh.core, axis=sh.axis)
+    flips, rep = parity.compare_records(g, o, sh.core, ATMO, run)
+    print(rep, np.bincount(o["state"], minlength=5))
+    ne = o["state"] == 4
+    assert ne.sum() > (0.2 if near else 0.01) * len(o)
+    assert (o["state"] == 0).sum() > 300
+    assert flips <= max(3, parity.MAX_FLIP_FRACTION * len(o))
+    # emission decisions: identical except next to u = p_emit
+    d = (g["state"] == 4) != ne
+    assert not (d & (np.abs(o["u_abs"] - o["p_emit"]) > parity.FLIP_SURV)).any()
+
+
+def test_bins_counters_and_cuts_telescope():
+    """Telescope spheres with layered transport: counters conserved with the not-
+    emitted records, bins at parity with the oracle, and the track and photon cuts
+    (the track cut takes the largest cone) leave the bins unchanged."""
+    sh = W.make_shower(40_000, seed=922, xmax=400.0, zenith_deg=20.0, beta="R")
+    seg = dict(sh.seg)
+    run = {**cases.RUN_TELESCOPE, "pitch": 40.0, "spectrum": "dispersive", "lambda_ref": 400.0, "seed": 27}
+    gb, gt, gc = parity.device_run(ATMO, run, seg, _geom(sh))
+    ob, ot, oc = O.propagate(parity.oracle_atm(ATMO), O.make_run(**run), seg, _geom(sh), threads=8)
+    gc = gc.astype(np.uint64)
+    np.testing.assert_array_equal(gc[:4], oc[:4])
+    assert gc[13] > 0 and abs(int(gc[13]) - int(oc[13])) <= 5
+    assert gc[3] == gc[4] + gc[5] + gc[6] + gc[7] + gc[13]
+    assert np.abs(gb.astype(np.int64) - ob.astype(np.int64)).sum() <= max(10, 2e-4 * ob.sum())
+    assert np.abs(gt.astype(np.int64) - ot.astype(np.int64)).sum() <= max(20, 4e-4 * ot.sum())
+    cb, ct, cc = parity.device_run(ATMO, {**run, "cuts": ("track", "photon")}, seg, _geom(sh))
+    np.testing.assert_array_equal(cb, gb)
+    np.testing.assert_array_equal(ct, gt)
+    assert cc[11] + cc[12] > 0
+
+
+def test_surrogate_fallback_keeps_the_emission_decision():
+    """A surrogate whose domain holds no photon: every emitted record is traced
+    exactly, so the bins equal the layered transport's, with the emission decision
+    taken before the network's wave-wide evaluation."""
+    lo = [2000.0, 0.5, -math.pi, 300.0, 2500.0]
+    hi = [20000.0, 1.0, math.pi, 600.0, 3000.0]
+    sur = cphot.Surrogate(lo, hi)
+    theta = mlp.init(9).astype(np.float32)
+    norm = np.zeros(cphot.N_NORM, dtype=np.float32)
+    norm[0:5], norm[5:10] = lo, hi
+    norm[10:15] = 2.0 / (np.array(hi) - np.array(lo))
+    norm[20:24] = 1.0
+    sur.set_params(theta, norm)
+    sh = W.make_shower(5000, seed=923, xmax=400.0, zenith_deg=20.0, beta="R")
+    run = {**cases.RUN_TELESCOPE, "pitch": 40.0, "spectrum": "dispersive", "lambda_ref": 400.0, "seed": 28}
+    be, te, ce = parity.device_run(ATMO, run, sh.seg, _geom(sh))
+    atm = cphot.Atmosphere(**ATMO)
+    det = cphot.make_detector(atm, **{**run, "transport": "surrogate"}, surrogate=sur)
+    seg, gg, off = cphot.upload(sh.seg, _geom(sh))
+    S = cphot.make_segments(seg, gg, off)
+    bins = torch.zeros(100, dtype=torch.int64, device="cuda")
+    th = torch.zeros(100 * 513, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    cphot.propagate(S, det, bins, th, cnt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(bins.cpu().numpy(), be.ravel())
+    np.testing.assert_array_equal(th.cpu().numpy(), te.ravel())
+    c = cnt.cpu().numpy()
+    np.testing.assert_array_equal(c[:9], ce[:9])
+    assert c[13] == ce[13] > 0
+
+
+def test_dispersive_argument_errors():
+    atm = cphot.Atmosphere(**ATMO)
+    sh = W.make_shower(10, seed=924, beta="R")
+    seg, gg, off = cphot.upload(sh.seg, _geom(sh))
+    S = cphot.make_segments(seg, gg, off)
+    c = torch.zeros(S.n, dtype=torch.int32, device="cuda")
+    det = cphot.make_detector(atm, **{**cases.RUN_TELESCOPE, "spectrum": "dispersive"}, lambda_ref=100.0)
+    with pytest.raises(cphot.CphotError, match="dispersive"):
+        cphot.segment_counts(S, det, c)
+    atm2 = cphot.Atmosphere(**{**ATMO, "lam_min": 120.0})
+    det = cphot.make_detector(atm2, **{**cases.RUN_TELESCOPE, "spectrum": "dispersive"})
+    with pytest.raises(cphot.CphotError, match="dispersive"):
+        cphot.segment_counts(S, det, c)
