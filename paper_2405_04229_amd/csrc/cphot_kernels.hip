@@ -35,7 +35,9 @@ struct SegResult {
 
 // Per-segment yield in FP64 with IEEE basic operations only and no
 // contraction, in the fixed order that makes the record count reproducible
-// bit for bit on any IEEE machine.
+// bit for bit on any IEEE machine. EXT: Poisson counts and the dispersive
+// spectrum are compiled in (kernels without them never see those settings).
+template <bool EXT>
 __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, float fy0, float fz0, float fx1,
                                                 float fy1, float fz1, float fbeta, float fq, float fdedx,
                                                 uint64_t id) {
@@ -91,7 +93,7 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
     const double frac = x - fi;
     double delta = (1.0 - frac) * p.tab[idx] + frac * p.tab[idx + 1];
     const double eps = 1.0 - beta;
-    if (p.spectrum == CPHOT_SPECTRUM_DISPERSIVE) {
+    if (EXT && p.spectrum == CPHOT_SPECTRUM_DISPERSIVE) {
       // records are drawn for the largest cone, n at lam_min; each record's own
       // angle follows from its wavelength
       r.disp_a = (float)(delta * (1.0 - eps) * p.disp_inv_rref);
@@ -115,7 +117,7 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
       }
       mu = mu * q;
       r.mu = mu;
-      if (p.poisson) {
+      if (EXT && p.poisson) {
         const int64_t n = poisson_count(mu, w.x, id, TAG_POISSON, p.key0, p.key1);
         if (n >= (int64_t(1) << kMaxRecordsPerSegmentLog2)) {
           r.status = 2;
@@ -146,7 +148,7 @@ __device__ __forceinline__ SegResult segment_setup(const KParams& p, float fx0, 
         return bad;
       }
       mu = mu * q;
-      if (p.poisson) {
+      if (EXT && p.poisson) {
         const int64_t n = poisson_count(mu, wb[b], id, TAG_POISSON + 1 + b, p.key0, p.key1);
         if (n >= (int64_t(1) << kMaxRecordsPerSegmentLog2)) {
           SegResult bad{0, 2, 0.f, 0.f, 0.f, 0.f, 0.f, 0.0, {0, 0, 0}, 1.f};
@@ -307,7 +309,7 @@ struct Photon {
 // transport every lane of the wave must call this together (`valid` marks the
 // lanes that carry a real record); the network is evaluated before any lane
 // leaves.
-template <int TRANSPORT, int DETECTOR, bool NEED_TIME, bool DISP>
+template <int TRANSPORT, int DETECTOR, bool NEED_TIME, bool EXT>
 __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict__ s_lay,
                                       const float2* __restrict__ s_lam, const MlpImage* __restrict__ s_img,
                                       const KConst* __restrict__ s_k, const float* __restrict__ s_eff,
@@ -339,7 +341,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
               : rcp_fast(p.inv_lam_min - u2 * (p.inv_lam_min - p.inv_lam_max));
     u3 = u24(w.w);
     float cos_t = q0.w, sin_t = q1.w;
-    if constexpr (DISP) {
+    if (EXT && p.spectrum == CPHOT_SPECTRUM_DISPERSIVE) {
       // angle of this wavelength (Eq. 2.5) and the record's emission probability
       // sin^2(theta) / sin^2(theta_max) relative to the cone it was drawn for.
       // g = beta n - 1 is taken as its segment value at lam_min plus the change of
@@ -383,7 +385,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   o.lam = lam;
   o.u3 = u3;
   // detected iff u < p_emit exp(-tau) efficiency / q: compare u / p_emit from here on
-  if constexpr (DISP) u3 = u3 * inv_pe;
+  if constexpr (EXT) u3 = u3 * inv_pe;
   o.bin = -1;
   o.tbin = -1;
   o.fallback = 0;
@@ -397,7 +399,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   o.x = Px;
   o.y = Py;
   o.z = Pz;
-  if constexpr (DISP && !kMlpTransport<TRANSPORT>) {
+  if constexpr (EXT && !kMlpTransport<TRANSPORT>) {
     if (!emitted) {  // below the threshold at its wavelength: never emitted
       o.state = 4;
       return;
@@ -430,7 +432,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
         for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
       }
       mlp_forward_wave(s_img, xin, ym, s_stage);
-      if (DISP && !emitted) {
+      if (EXT && !emitted) {
         o.state = 4;
         return;
       }
@@ -532,7 +534,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
     }
     mlp_forward_wave(s_img, xin, ym, s_stage);
-    if (DISP && !emitted) {
+    if (EXT && !emitted) {
       o.state = 4;
       return;
     }
@@ -768,10 +770,11 @@ constexpr int kMinWavesPerSimd =
     : (T == CPHOT_TRANSPORT_CURVED || T == CPHOT_TRANSPORT_LAYERED || T == CPHOT_TRANSPORT_STRAIGHT || T == CPHOT_TRANSPORT_TABLE) ? 4
                                                                                                                      : 1;
 
-// DISP: the dispersive spectrum's per-record angle and emission decision, compiled
-// only into the kernels that run it (as a runtime branch its registers cost the
-// other spectra about a tenth of their time).
-template <int BS, int TRANSPORT, int DETECTOR, int MODE, bool DISP>
+// EXT: Poisson record counts and the dispersive spectrum (its per-record angle and
+// emission decision), compiled only into the kernels that run them: as runtime
+// branches their registers cost the default path spills and about a tenth of its
+// time.
+template <int BS, int TRANSPORT, int DETECTOR, int MODE, bool EXT>
 __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(KParams p) {
   constexpr bool kTime = (DETECTOR == CPHOT_DETECTOR_SPHERES) || (MODE == MODE_RECORDS);
   constexpr bool kLayers = (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT);
@@ -874,7 +877,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       const float fx0 = p.x0[i], fy0 = p.y0[i], fz0 = p.z0[i], fx1 = p.x1[i], fy1 = p.y1[i], fz1 = p.z1[i];
       const uint64_t id = p.first_id + (uint64_t)i;
       SegResult r =
-          segment_setup(p, fx0, fy0, fz0, fx1, fy1, fz1, p.beta[i], p.charge[i], p.dedx ? p.dedx[i] : 0.0f, id);
+          segment_setup<EXT>(p, fx0, fy0, fz0, fx1, fy1, fz1, p.beta[i], p.charge[i], p.dedx ? p.dedx[i] : 0.0f, id);
       if constexpr (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_SPHERES && !kMlpTransport<TRANSPORT>) {
         if ((p.cuts & CPHOT_CUT_TRACK) && r.n > 0) {
           const double* gc = p.geom + 5 * shower_of(p, i);
@@ -902,8 +905,9 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
           dXs = depth_f(s_k, fz1) - X0;
         }
         const double* g = p.geom + 5 * sh;
-        q0 = make_float4(fx0, fy0, fz0, DISP ? r.disp_a : r.cos_t);
-        q1 = make_float4(fx1 - fx0, fy1 - fy0, fz1 - fz0, DISP ? r.disp_gm : r.sin_t);
+        const bool disp = EXT && p.spectrum == CPHOT_SPECTRUM_DISPERSIVE;
+        q0 = make_float4(fx0, fy0, fz0, disp ? r.disp_a : r.cos_t);
+        q1 = make_float4(fx1 - fx0, fy1 - fy0, fz1 - fz0, disp ? r.disp_gm : r.sin_t);
         q2 = make_float4(r.a0, r.a1, r.a2, X0);
         q3 = make_float4(dXs, __uint_as_float((uint32_t)id), __uint_as_float((uint32_t)(id >> 32)),
                          __uint_as_float((uint32_t)sh));
@@ -1031,7 +1035,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       const uint32_t k = j - s_off[lo];
       Photon ph;
       const float4 r3 = s_q3[lo];
-      trace<TRANSPORT, DETECTOR, kTime, DISP>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
+      trace<TRANSPORT, DETECTOR, kTime, EXT>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
                                         s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], s_q5[lo], k, valid, ph);
       if constexpr (kDefer) {
         // wave-level compaction: deferred records take consecutive queue slots
@@ -1060,7 +1064,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
             const uint32_t qk = s_qk[q];
             const float4 q3 = s_q3[qlo];
             Photon pe;
-            trace<kExact, DETECTOR, kTime, DISP>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
+            trace<kExact, DETECTOR, kTime, EXT>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
                                            s_q4[qlo], s_axz[qlo], s_q5[qlo], qk, true, pe);
             pe.fallback = 1;
             consume(pe, qlo, qk, q3);
@@ -1110,24 +1114,24 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
 
 namespace {
 
-template <int BS, int T, int D, int M, bool DISP>
+template <int BS, int T, int D, int M, bool EXT>
 hipError_t launch_one(const KParams& p, int grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_propagate<BS, T, D, M, DISP>), dim3(grid), dim3(BS), lds, s, p);
+  hipLaunchKernelGGL((k_propagate<BS, T, D, M, EXT>), dim3(grid), dim3(BS), lds, s, p);
   return hipGetLastError();
 }
 
-// The count pass traces no record: one kernel serves every spectrum.
+template <int BS, int T, int D, int M>
+hipError_t launch_ext(const KParams& p, int grid, size_t lds, hipStream_t s) {
+  const bool ext = p.poisson || p.spectrum == CPHOT_SPECTRUM_DISPERSIVE;
+  return ext ? launch_one<BS, T, D, M, true>(p, grid, lds, s) : launch_one<BS, T, D, M, false>(p, grid, lds, s);
+}
+
 template <int BS, int T, int D>
 hipError_t launch_mode(const KParams& p, int mode, int grid, size_t lds, hipStream_t s) {
-  const bool disp = p.spectrum == CPHOT_SPECTRUM_DISPERSIVE;
   switch (mode) {
-    case MODE_PROPAGATE:
-      return disp ? launch_one<BS, T, D, MODE_PROPAGATE, true>(p, grid, lds, s)
-                  : launch_one<BS, T, D, MODE_PROPAGATE, false>(p, grid, lds, s);
-    case MODE_COUNTS: return launch_one<BS, T, D, MODE_COUNTS, false>(p, grid, lds, s);
-    default:
-      return disp ? launch_one<BS, T, D, MODE_RECORDS, true>(p, grid, lds, s)
-                  : launch_one<BS, T, D, MODE_RECORDS, false>(p, grid, lds, s);
+    case MODE_PROPAGATE: return launch_ext<BS, T, D, MODE_PROPAGATE>(p, grid, lds, s);
+    case MODE_COUNTS: return launch_ext<BS, T, D, MODE_COUNTS>(p, grid, lds, s);
+    default: return launch_ext<BS, T, D, MODE_RECORDS>(p, grid, lds, s);
   }
 }
 
@@ -1148,7 +1152,7 @@ hipError_t launch_bs(const KParams& p, int mode, int grid, size_t lds, hipStream
 template <int BS, int T, int D, int M>
 size_t static_lds_one() {
   hipFuncAttributes a;
-  // the dispersive kernels declare the same static LDS
+  // the EXT kernels declare the same static LDS
   if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&k_propagate<BS, T, D, M, false>)) != hipSuccess) return 0;
   return a.sharedSizeBytes;
 }
