@@ -53,9 +53,9 @@ METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density 
 # HBM bytes per launch of the exact telescope kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # scaled by a plain copy's factors (2.00, 1.00); valid only for the sources and launch shape they
 # were taken on (sha256 prefixes; block size, grid, LDS counts), else reported as null.
-TRAFFIC_BYTES = 16267.9 * 1024 * 2.00 + 144 * 1024 * 1.00
-TRAFFIC_SOURCES = {"cphot_kernels.hip": "fc06bf6dc9a9c3d8", "cphot_device.h": "e9b556d4454a60f0",
-                   "cphot_internal.h": "2c14770d0334f6fd", "cphot_api.cpp": "a740dd19a86fb902"}
+TRAFFIC_BYTES = 16270.0 * 1024 * 2.00 + 144.0 * 1024 * 1.00
+TRAFFIC_SOURCES = {"cphot_kernels.hip": "3d4b26c4fd8431b7", "cphot_device.h": "412f1e9c31f153d6",
+                   "cphot_internal.h": "e7ff53602758d13b", "cphot_api.cpp": "b4a406efd9866946"}
 TRAFFIC_SHAPE = (512, 512, 1)
 
 
