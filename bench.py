@@ -535,8 +535,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-inclined", action="store_true")
     ap.add_argument("--no-cuts", action="store_true", help="skip the telescope step with data-reduction cuts")
-    ap.add_argument("--telescope-shape", default=None, metavar="BS,GRID,LDS",
-                    help="fixed launch shape for the exact telescope step instead of the autotuner's (profiling)")
+    ap.add_argument("--telescope-shape", default="512,512,1", metavar="BS,GRID,LDS|auto",
+                    help="launch shape of the exact telescope step: the profiled shape (default; the HBM "
+                         "traffic figure holds for it) or 'auto' for the autotuner's pick")
     ap.add_argument("--inclined-chunks", type=int, default=10,
                     help="chunks of 1e7 segments streamed from host memory (0: only the resident chunk)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
@@ -578,7 +579,7 @@ def main():
     bins = out_buf[:nb].view(torch.int64)
     cnt = out_buf[nb:nb + nc].view(torch.int64)
     th = out_buf[nb + nc:].view(torch.int32)
-    if args.telescope_shape:
+    if args.telescope_shape != "auto":
         bs_, gb_, lds_ = (int(v) for v in args.telescope_shape.split(","))
         det = cphot.make_detector(atm, **run, block_size=bs_, grid_blocks=gb_, lds_hist=lds_)
         tune = {"block_size": bs_, "grid_blocks": gb_, "lds_hist": lds_, "bunch": run["bunch"], "fixed": True}
