@@ -140,3 +140,32 @@ def test_dispersive_argument_errors():
     det = cphot.make_detector(atm2, **{**cases.RUN_TELESCOPE, "spectrum": "dispersive"})
     with pytest.raises(cphot.CphotError, match="dispersive"):
         cphot.segment_counts(S, det, c)
+
+
+def test_records_sampled_at_full_telescope_size():
+    """Sampled slices of the 1e6-segment telescope workload under the dispersive
+    spectrum, traced one by one by the oracle with the slices' global ids."""
+    sh = W.workload_telescope("R")
+    run = {**cases.RUN_TELESCOPE, "spectrum": "dispersive", "lambda_ref": 400.0, "seed": 2}
+    for start in (0, 333_333, 999_900):
+        sl = slice(start, start + 100)
+        seg = {k: v[sl] for k, v in sh.seg.items()}
+        g = parity.device_records(ATMO, run, seg, _geom(sh), first_id=start)
+        o = O.trace(parity.oracle_atm(ATMO), O.make_run(**run), seg, core=sh.core, axis=sh.axis, first_id=start)
+        flips, rep = parity.compare_records(g, o, sh.core, ATMO, run)
+        assert flips <= 3
+        assert (o["state"] == 4).any()
+
+
+@pytest.mark.parametrize("n", [0, 1, 257])
+def test_dispersive_ragged_and_empty(n):
+    sh = W.make_shower(max(n, 1), seed=925, xmax=450.0, zenith_deg=20.0, beta="R")
+    seg = {k: v[:n] for k, v in sh.seg.items()}
+    run = dict(transport="layered", detector="grid", spectrum="dispersive", lambda_ref=400.0, bunch=1,
+               h_obs=2200.0, nx=100, ny=100, cell=10.0, seed=29)
+    g = parity.device_counts(ATMO, run, seg, _geom(sh))
+    o = O.segment_counts(parity.oracle_atm(ATMO), O.make_run(**run), seg)
+    np.testing.assert_array_equal(g, o["n"])
+    gb, _, gc = parity.device_run(ATMO, run, seg, _geom(sh))
+    assert int(gc[0]) == n
+    assert gc[3] == gc[4] + gc[5] + gc[6] + gc[7] + gc[13]

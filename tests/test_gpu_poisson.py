@@ -101,3 +101,28 @@ def test_counts_rule_argument_error():
     S = cphot.make_segments(seg, gg, off)
     with pytest.raises(cphot.CphotError, match="counts_rule"):
         cphot.segment_counts(S, det, torch.zeros(S.n, dtype=torch.int32, device="cuda"))
+
+
+def test_poisson_counts_full_telescope_size():
+    """All 1e6 segments of the telescope workload in the benchmark's configuration,
+    Poisson rule: counts and mu bit-identical to the oracle's."""
+    sh = W.workload_telescope("R")
+    run = {**cases.RUN_TELESCOPE, "seed": 2}
+    g, mu = parity.device_counts(cases.ATMO_LAYERED, {**run, "counts": "poisson"}, sh.seg,
+                                 np.array([[*sh.core, *sh.axis]]), with_mu=True)
+    o = O.segment_counts(O.Atmosphere(**cases.ATMO_LAYERED), O.make_run(**run, counts="poisson"), sh.seg)
+    np.testing.assert_array_equal(g, o["n"])
+    omu = np.where(o["status"] == 0, o["mu"], 0.0)
+    np.testing.assert_array_equal(mu.view(np.uint64), omu.view(np.uint64))
+    assert g.sum() > 1e7
+
+
+@pytest.mark.parametrize("n", [0, 1, 255, 257])
+def test_poisson_counts_ragged_and_empty(n):
+    sh = W.workload_tiny_vertical("R", n=max(n, 1))
+    seg = {k: v[:n] for k, v in sh.seg.items()}
+    run = {**cases.RUN_TINY, "spectrum": "frank_tamm", "counts": "poisson", "seed": 4}
+    g = parity.device_counts(cases.ATMO_STRAIGHT, run, seg, np.array([[*sh.core, *sh.axis]]))
+    o = O.segment_counts(O.Atmosphere(**cases.ATMO_STRAIGHT), O.make_run(**run), seg)
+    assert len(g) == n
+    np.testing.assert_array_equal(g, o["n"])
