@@ -153,7 +153,8 @@ extern "C" {
 #define CPHOT_BINS_F64 2
 
 /* Counter slots (uint64) of cphot_bins.counters. After a call,
- * records_generated = records_upward + records_absorbed + records_outside + records_binned. */
+ * records_generated = records_upward + records_absorbed + records_outside + records_binned
+ * + records_not_emitted (the last is zero except under CPHOT_SPECTRUM_DISPERSIVE). */
 #define CPHOT_C_SEGMENTS_IN 0
 #define CPHOT_C_SEGMENTS_SKIPPED 1          /* non-finite, zero length, beta outside (0,1) */
 #define CPHOT_C_SEGMENTS_BELOW_THRESHOLD 2  /* beta n <= 1 (Sec. 2.2.1) */
