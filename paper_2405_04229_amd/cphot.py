@@ -225,8 +225,12 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
                   dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, surrogate=None,
                   emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0), cuts=(),
                   table=None, efficiency=None, reduction=None, counts="rounded", lambda_ref=400.0) -> Detector:
-    """`efficiency` and `reduction`: float64 device tensors (per wavelength bin,
-    per layer) or None; see cphot_detector."""
+    """Fields of cphot_detector by name. `spectrum`: "uniform", "frank_tamm" or
+    "dispersive" (with `lambda_ref`, the wavelength in nm at which the
+    atmosphere's n - 1 holds); `counts`: "rounded" (stochastic rounding of each
+    segment's expected records) or "poisson"; `cuts`: any of "track", "photon";
+    `efficiency` and `reduction`: float64 device tensors (per wavelength bin,
+    per layer) or None."""
     d = Detector()
     d.atm = atm.handle
     d.transport, d.detector, d.spectrum = TRANSPORT[transport], DETECTOR[detector], SPECTRUM[spectrum]
