@@ -169,3 +169,40 @@ def test_dispersive_ragged_and_empty(n):
     gb, _, gc = parity.device_run(ATMO, run, seg, _geom(sh))
     assert int(gc[0]) == n
     assert gc[3] == gc[4] + gc[5] + gc[6] + gc[7] + gc[13]
+
+
+def _table_run(atm, run, sh, transport, **kw):
+    g = _geom(sh)
+    seg, gg, off = cphot.upload(sh.seg, g)
+    S = cphot.make_segments(seg, gg, off)
+    det = cphot.make_detector(atm, **{**run, "transport": transport}, **kw)
+    per = run["nx"] * run["ny"] if run.get("detector", "grid") == "grid" else run["snx"] * run["sny"]
+    bins = torch.zeros(per, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    cphot.propagate(S, det, bins, None, cnt)
+    torch.cuda.synchronize()
+    return bins.cpu().numpy(), cnt.cpu().numpy()
+
+
+@pytest.mark.parametrize("geometry", ["planar", "curved"])
+def test_table_transport_keeps_the_emission_decision(geometry):
+    """The emission decision precedes transport: with the interpolation table the
+    same records are emitted as with the exact walk, and a table that holds no
+    photon (everything traced exactly) gives the exact walk's bins bit for bit."""
+    atm = cphot.Atmosphere(**ATMO)
+    exact = "layered" if geometry == "planar" else "curved"
+    sh = W.make_shower(4000, seed=926, xmax=450.0, zenith_deg=20.0 if geometry == "planar" else 60.0, beta="R")
+    run = dict(detector="grid", spectrum="dispersive", lambda_ref=400.0, bunch=1, h_obs=2200.0, nx=200, ny=200,
+               cell=10.0 if geometry == "planar" else 40.0, seed=30)
+    be, ce = _table_run(atm, run, sh, exact)
+    empty = cphot.Table(atm, 2200.0, geometry, n_h=8, n_c=8, h_hi=2250.0, c_lo=0.99)
+    b0, c0 = _table_run(atm, run, sh, "table", table=empty)
+    np.testing.assert_array_equal(b0, be)
+    np.testing.assert_array_equal(c0[:9], ce[:9])
+    assert c0[13] == ce[13] > 0
+    tab = cphot.Table(atm, 2200.0, geometry, h_hi=20000.0 if geometry == "planar" else 22000.0,
+                      c_lo=0.4 if geometry == "planar" else 0.3)
+    bt, ct = _table_run(atm, run, sh, "table", table=tab)
+    assert ct[3] == ce[3] and ct[13] == ce[13]
+    assert ct[3] == ct[4] + ct[5] + ct[6] + ct[7] + ct[13]
+    assert abs(int(ct[7]) - int(ce[7])) <= 1e-3 * ce[7] + 10
