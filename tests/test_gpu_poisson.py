@@ -126,3 +126,23 @@ def test_poisson_counts_ragged_and_empty(n):
     o = O.segment_counts(O.Atmosphere(**cases.ATMO_STRAIGHT), O.make_run(**run), seg)
     assert len(g) == n
     np.testing.assert_array_equal(g, o["n"])
+
+
+def test_poisson_counts_near_the_record_limit():
+    """Means from 1e4 up to just under 2^20 records (up to ~16,000 chunks per
+    segment) agree bit for bit; a mean or a draw at or above 2^20 is rejected the
+    same way on both sides."""
+    sh = W.make_shower(64, seed=927, xmax=450.0, zenith_deg=20.0, beta="R")
+    run = {**cases.RUN_TELESCOPE, "bunch": 1, "counts": "poisson", "seed": 5}
+    oatm = O.Atmosphere(**cases.ATMO_LAYERED)
+    base = O.segment_counts(oatm, O.make_run(**{**run, "counts": "rounded"}), sh.seg)
+    ok = base["status"] == 0
+    seg = {k: v[ok] for k, v in sh.seg.items()}
+    mu1 = base["mu"][ok]
+    target = np.geomspace(1e4, 1.2e6, len(mu1))
+    seg["charge"] = np.sqrt(target / mu1).astype(np.float32)
+    g = parity.device_counts(cases.ATMO_LAYERED, run, seg, np.array([[*sh.core, *sh.axis]]))
+    o = O.segment_counts(oatm, O.make_run(**run), seg)
+    np.testing.assert_array_equal(g, o["n"])
+    assert o["mu"][o["status"] == 0].max() > 9e5
+    assert (o["status"] == 2).sum() >= 2  # means of 2^20 or more
