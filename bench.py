@@ -547,7 +547,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (scale for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: the photon path needs no collectives and this build "
+        print("bench.py runs on exactly one GPU: the photon path needs no collectives and the benchmark "
               "measures one MI355X; multi-GPU figures are not produced.", file=sys.stderr)
         sys.exit(2)
 

@@ -1012,7 +1012,7 @@ int orc_layered_ray(const orc_atmo* A, const double* P, const double* u, double 
 /* ------------------------------------------------------------------------- */
 /* Transport surrogate: training inputs and exact targets                     */
 /* ------------------------------------------------------------------------- */
-/* The MLP surrogate of this build replaces the layered tracer's correction to
+/* The MLP transport surrogate replaces the layered tracer's correction to
  * the straight line, the role the thesis gives to its precomputed correction
  * table (Sec. 4.4.1: the difference between the straight-line and the
  * iterative propagation). Inputs per photon: emission height h_e (m), cos of the
