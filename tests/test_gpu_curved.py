@@ -133,3 +133,24 @@ def test_curved_rejects_spheres_and_missing_dedx():
     det = cphot.make_detector(atm, **{**CURVED, "transport": "layered", "emission": "both", "nx": 10, "ny": 10})
     with pytest.raises(cphot.CphotError, match="dedx"):
         cphot.propagate(S, det, bins, None, None)
+
+
+def test_inclined_chunk_at_full_size():
+    """The benchmark's inclined chunk (1e7 segments, curved Earth, Cherenkov and
+    fluorescence): record counts of every segment bit-exact, and sampled slices
+    traced record by record with their global segment ids."""
+    sh = W.workload_inclined_chunk(0)
+    run = {**W.RUN_INCLINED, "seed": 3}
+    g = parity.device_counts(cases.ATMO_LAYERED, run, sh.seg, _geom(sh), first_id=sh.first_id)
+    o = O.segment_counts(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 3), sh.seg, first_id=sh.first_id)
+    np.testing.assert_array_equal(g, o["n"] + o["nf"].sum(1))
+    assert g.sum() > 5e8
+    for start in (0, 4_321_987, 9_999_900):
+        sl = slice(start, start + 100)
+        seg = {k: v[sl] for k, v in sh.seg.items()}
+        gr = parity.device_records(cases.ATMO_LAYERED, run, seg, _geom(sh), first_id=sh.first_id + start)
+        orr = O.trace(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 3), seg, core=sh.core, axis=sh.axis,
+                      first_id=sh.first_id + start)
+        flips, rep = parity.compare_records(gr, orr, sh.core, cases.ATMO_LAYERED, run)
+        assert flips <= 3, rep
+        assert (orr["source"] > 0).any()
