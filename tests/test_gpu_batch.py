@@ -193,3 +193,26 @@ def test_lds_window_f64_and_large_single_grid():
     for b in out[1:]:
         np.testing.assert_array_equal(b, out[0])
     assert out[0].sum() > 1e5
+
+
+@pytest.mark.parametrize("bunch", [1, 5])
+def test_batched_workload_at_full_size(bunch):
+    """The benchmark's batch (256 showers, 3.3e7 segments): every segment's record
+    count bit-exact, and slices of three showers traced record by record with
+    their global segment ids and their own geometry."""
+    seg, offs, geom = W.concat_showers(W.make_batch(256, seed=1003, beta="R"))
+    run = {**RUN_BATCH, "bunch": bunch, "seed": 3}
+    # counts depend on the segments only: one shower's geometry serves the whole set
+    g = parity.device_counts(cases.ATMO_STRAIGHT, run, seg, geom[:1])
+    o = O.segment_counts(parity.oracle_atm(cases.ATMO_STRAIGHT), O.make_run(**run), seg)
+    np.testing.assert_array_equal(g, o["n"])
+    assert len(g) > 3e7
+    atm = parity.oracle_atm(cases.ATMO_STRAIGHT)
+    for s in (0, 131, 255):
+        start = int(offs[s]) + (int(offs[s + 1]) - int(offs[s])) // 2
+        sl = slice(start, min(start + 100, int(offs[s + 1])))
+        part = {k: v[sl] for k, v in seg.items()}
+        gr = parity.device_records(cases.ATMO_STRAIGHT, run, part, geom[s:s + 1], first_id=start)
+        orr = O.trace(atm, O.make_run(**run), part, core=geom[s, :2], axis=geom[s, 2:5], first_id=start)
+        flips, rep = parity.compare_records(gr, orr, geom[s, :2], cases.ATMO_STRAIGHT, run)
+        assert flips <= 3, rep
