@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define CPHOT_ABI_VERSION 1
+#define CPHOT_ABI_VERSION 2
 #define CPHOT_NCOUNTERS 16
 
 #define CPHOT_OK 0

@@ -104,6 +104,7 @@ RECORD_BYTES = 64
 
 _lock = threading.Lock()
 _lib = None
+ABI_VERSION = 2  # CPHOT_ABI_VERSION of include/cphot.h that the ctypes structs below mirror
 
 
 def lib():
@@ -116,6 +117,9 @@ def lib():
             L = C.CDLL(LIB_PATH)
             P = C.c_void_p
             L.cphot_version.restype = C.c_int
+            if L.cphot_version() != ABI_VERSION:
+                raise RuntimeError(f"libcphot.so has ABI version {L.cphot_version()}, this binding's structs are "
+                                   f"version {ABI_VERSION}: rebuild with __graft_entry__.build()")
             L.cphot_status_string.argtypes = [C.c_int]
             L.cphot_status_string.restype = C.c_char_p
             L.cphot_last_error.restype = C.c_char_p

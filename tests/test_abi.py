@@ -42,7 +42,9 @@ def test_library_loads_without_gpu():
     if not os.path.exists(cphot.LIB_PATH):
         pytest.skip("libcphot.so not built")
     L = cphot.lib()
-    assert L.cphot_version() == 1
+    assert L.cphot_version() == cphot.ABI_VERSION
+    header = open(os.path.join(os.path.dirname(__file__), "..", "include", "cphot.h")).read()
+    assert int(re.search(r"#define CPHOT_ABI_VERSION (\d+)", header).group(1)) == cphot.ABI_VERSION
     assert L.cphot_status_string(-1) == b"invalid argument"
 
 
