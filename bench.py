@@ -55,7 +55,7 @@ METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density 
 # were taken on (sha256 prefixes; block size, grid, LDS counts), else reported as null.
 TRAFFIC_BYTES = 16270.0 * 1024 * 2.00 + 144.0 * 1024 * 1.00
 TRAFFIC_SOURCES = {"cphot_kernels.hip": "3d4b26c4fd8431b7", "cphot_device.h": "412f1e9c31f153d6",
-                   "cphot_internal.h": "e7ff53602758d13b", "cphot_api.cpp": "b4a406efd9866946"}
+                   "cphot_internal.h": "e7ff53602758d13b", "cphot_api.cpp": "5fd5435c41b40305"}
 TRAFFIC_SHAPE = (512, 512, 1)
 
 

@@ -392,6 +392,28 @@ typedef struct {
 int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
                    const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, cphot_tuning* best, void* stream);
 
+/* cphot_autotune behind a cache of results keyed by a configuration signature:
+ * the device (architecture name and compute-unit count), the ABI version, the
+ * atmosphere's profile, layer and wavelength-bin counts, every detector setting
+ * except the launch shape (transport, detector kind and geometry, spectrum,
+ * emission, counts rule, cuts, bunch, time bins, which optional tables are set),
+ * the segment and shower counts, the bunch candidates and `reps`. A signature
+ * seen before returns its stored result (`*hit` = 1, nothing launched, `out`
+ * untouched); otherwise cphot_autotune runs and its result is stored (`*hit` =
+ * 0). The cache lives in process memory; with `cache_path` (may be NULL) it is
+ * also a text file, read on the first call that names it and appended to after
+ * each new tuning, so that later processes on the same kind of device skip the
+ * search. `hit` may be NULL. The stored shape is a timing result: it holds for
+ * inputs of the same sizes, not for the same data only. Synchronous on a miss.
+ * Errors: as cphot_autotune; INVALID_ARG when the file cannot be appended to. */
+int cphot_autotune_cached(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
+                          const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, const char* cache_path,
+                          cphot_tuning* best, int32_t* hit, void* stream);
+
+/* Forget every cached tuning result of this process (files are not touched; a
+ * file named again is read again). */
+void cphot_autotune_cache_clear(void);
+
 /* ---------------------------------------------------------------- streaming from host memory
  * A segment set too large to keep in device memory at once (the thesis feeds the
  * photon stage chunk by chunk from the shower simulation, Sec. 5.1, 5.4) is read

@@ -150,6 +150,12 @@ def lib():
             L.cphot_autotune.argtypes = [C.POINTER(Segments), C.POINTER(Detector), C.POINTER(Bins), P, C.c_int32,
                                          C.c_int32, C.POINTER(Tuning), P]
             L.cphot_autotune.restype = C.c_int
+            L.cphot_autotune_cached.argtypes = [C.POINTER(Segments), C.POINTER(Detector), C.POINTER(Bins), P,
+                                                C.c_int32, C.c_int32, C.c_char_p, C.POINTER(Tuning),
+                                                C.POINTER(C.c_int32), P]
+            L.cphot_autotune_cached.restype = C.c_int
+            L.cphot_autotune_cache_clear.argtypes = []
+            L.cphot_autotune_cache_clear.restype = None
             L.cphot_streamer_create.argtypes = [C.c_int64, C.POINTER(C.c_void_p)]
             L.cphot_streamer_create.restype = C.c_int
             L.cphot_streamer_run.argtypes = [P, C.POINTER(HostSegments), C.POINTER(Detector), C.POINTER(Bins), P]
@@ -451,19 +457,34 @@ class Step:
         self.close()
 
 
-def autotune(seg: Segments, det: Detector, bins, time_hist=None, counters=None, bunches=None, reps=3, stream=None):
+def autotune(seg: Segments, det: Detector, bins, time_hist=None, counters=None, bunches=None, reps=3, stream=None,
+             cache=False, cache_path=None):
     """Fastest launch shape (and bunch among `bunches`) for these inputs; the
-    outputs are overwritten by the trials."""
+    outputs are overwritten by the trials. With `cache` (or a `cache_path`),
+    cphot_autotune_cached: a configuration tuned before in this process (or
+    recorded in the file) returns its stored result, with "cached": True."""
     import numpy as np
     b = make_bins(bins, time_hist, counters)
     t = Tuning()
     bc = None if not bunches else np.ascontiguousarray(bunches, dtype=np.int32)
-    _check("cphot_autotune", lib().cphot_autotune(C.byref(seg), C.byref(det), C.byref(b),
-                                                  None if bc is None else bc.ctypes.data_as(C.c_void_p),
-                                                  0 if bc is None else len(bc), int(reps), C.byref(t),
-                                                  _stream_ptr(stream)))
+    bp = None if bc is None else bc.ctypes.data_as(C.c_void_p)
+    nb = 0 if bc is None else len(bc)
+    hit = C.c_int32(0)
+    if cache or cache_path:
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check("cphot_autotune_cached", lib().cphot_autotune_cached(C.byref(seg), C.byref(det), C.byref(b), bp, nb,
+                                                                    int(reps), path, C.byref(t), C.byref(hit),
+                                                                    _stream_ptr(stream)))
+    else:
+        _check("cphot_autotune", lib().cphot_autotune(C.byref(seg), C.byref(det), C.byref(b), bp, nb, int(reps),
+                                                      C.byref(t), _stream_ptr(stream)))
     return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, hist_window=t.hist_window,
-                bunch=t.bunch, ms=t.ms, photons_per_s=t.photons_per_s)
+                bunch=t.bunch, ms=t.ms, photons_per_s=t.photons_per_s, cached=bool(hit.value))
+
+
+def autotune_cache_clear():
+    """Forget the tuning results cached in this process."""
+    lib().cphot_autotune_cache_clear()
 
 
 def segment_counts(seg: Segments, det: Detector, counts, expected=None, stream=None):

@@ -975,3 +975,114 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
 }
 
 }  // extern "C"
+
+namespace {
+
+// Process-wide cache of tuning results by configuration signature, optionally
+// mirrored in text files (one "signature|fields" line per entry).
+struct TuneCache {
+  std::mutex mu;
+  std::vector<std::pair<std::string, cphot_tuning>> entries;
+  std::vector<std::string> files_read;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
+// Everything the best launch shape can depend on, except the launch shape itself:
+// device, atmosphere layout, detector settings, segment and shower counts, the
+// candidate bunches and the number of timed launches.
+std::string tune_signature(const cphot_segments* seg, const cphot_detector* det, const int32_t* bunches,
+                           int32_t n_bunch, int32_t reps) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  std::string name = "unknown";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) name = prop.gcnArchName;
+  const cphot_atmosphere_desc& a = det->atm->d;
+  char buf[1024];
+  std::snprintf(buf, sizeof(buf),
+                "abi%d;%s;cu%d;atm%d,%d,%d,%.9g,%.9g,%.9g;t%d;d%d;s%d;e%d;c%d;cuts%d;b%d;h%.9g;g%d,%d,%.9g;"
+                "sp%d,%d,%.9g,%.9g;nt%d,%.9g;eff%d;red%d;sur%d;tab%d;n%lld;ns%lld;reps%d;bunches",
+                CPHOT_ABI_VERSION, name.c_str(), cu_count(dev), a.profile, a.n_layers, a.n_lambda_bins, a.h_top,
+                a.lambda_min_nm, a.lambda_max_nm, det->transport, det->detector, det->spectrum, det->emission,
+                det->counts_rule, det->cuts, det->bunch, det->h_obs, det->nx, det->ny, det->cell, det->snx,
+                det->sny, det->pitch, det->radius, det->n_time_bins, det->time_bin_ns, det->efficiency != nullptr,
+                det->reduction != nullptr, det->surrogate != nullptr, det->table != nullptr, (long long)seg->n,
+                (long long)seg->n_showers, reps);
+  std::string sig = buf;
+  for (int i = 0; i < n_bunch; ++i) sig += "," + std::to_string(bunches[i]);
+  return sig;
+}
+
+void read_tune_file(TuneCache& c, const char* path) {
+  for (const std::string& f : c.files_read)
+    if (f == path) return;
+  c.files_read.push_back(path);
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return;  // no file yet
+  char line[2048];
+  while (std::fgets(line, sizeof(line), fp)) {
+    char* bar = std::strchr(line, '|');
+    if (!bar) continue;
+    *bar = 0;
+    cphot_tuning t{};
+    if (std::sscanf(bar + 1, "%d %d %d %d %d %lf %lf", &t.block_size, &t.grid_blocks, &t.lds_hist, &t.bunch,
+                    &t.hist_window, &t.ms, &t.photons_per_s) != 7)
+      continue;
+    bool have = false;
+    for (auto& e : c.entries) have = have || e.first == line;
+    if (!have) c.entries.emplace_back(line, t);
+  }
+  std::fclose(fp);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cphot_autotune_cached(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
+                          const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, const char* cache_path,
+                          cphot_tuning* best, int32_t* hit, void* stream) {
+  if (!seg || !det || !det->atm || !out || !best) return fail(CPHOT_ERR_INVALID_ARG, "null argument");
+  if (n_bunch < 0 || (n_bunch > 0 && !bunch_candidates)) return fail(CPHOT_ERR_INVALID_ARG, "bad bunch list");
+  const std::string sig = tune_signature(seg, det, bunch_candidates, n_bunch, reps);
+  if (sig.find('|') != std::string::npos || sig.find('\n') != std::string::npos)
+    return fail(CPHOT_ERR_INVALID_ARG, "device name unusable in a cache signature");
+  TuneCache& c = tune_cache();
+  {
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (cache_path) read_tune_file(c, cache_path);
+    for (auto& e : c.entries)
+      if (e.first == sig) {
+        *best = e.second;
+        if (hit) *hit = 1;
+        return CPHOT_OK;
+      }
+  }
+  cphot_tuning t{};
+  const int rc = cphot_autotune(seg, det, out, bunch_candidates, n_bunch, reps, &t, stream);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(c.mu);
+  c.entries.emplace_back(sig, t);
+  if (cache_path) {
+    FILE* fp = std::fopen(cache_path, "a");
+    if (!fp) return fail(CPHOT_ERR_INVALID_ARG, std::string("cannot append to the tuning cache ") + cache_path);
+    std::fprintf(fp, "%s|%d %d %d %d %d %.17g %.17g\n", sig.c_str(), t.block_size, t.grid_blocks, t.lds_hist,
+                 t.bunch, t.hist_window, t.ms, t.photons_per_s);
+    std::fclose(fp);
+  }
+  *best = t;
+  if (hit) *hit = 0;
+  return CPHOT_OK;
+}
+
+void cphot_autotune_cache_clear(void) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  c.entries.clear();
+  c.files_read.clear();
+}
+
+}  // extern "C"

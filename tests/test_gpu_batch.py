@@ -216,3 +216,25 @@ def test_batched_workload_at_full_size(bunch):
         orr = O.trace(atm, O.make_run(**run), part, core=geom[s, :2], axis=geom[s, 2:5], first_id=start)
         flips, rep = parity.compare_records(gr, orr, geom[s, :2], cases.ATMO_STRAIGHT, run)
         assert flips <= 3, rep
+
+
+def test_autotune_cache_in_memory_and_file(tmp_path):
+    seg, offs, geom = _batch(n=4, scale=0.02, seed=13)
+    atm = cphot.Atmosphere(**cases.ATMO_STRAIGHT)
+    run = {**RUN_BATCH, "seed": 6}
+    det, S, bins, cnt = _setup(seg, offs, geom, run, atm)
+    path = tmp_path / "tuning.txt"
+    cphot.autotune_cache_clear()
+    a = cphot.autotune(S, det, bins, None, cnt, bunches=[1, 2], reps=1, cache_path=path)
+    assert not a["cached"]
+    b = cphot.autotune(S, det, bins, None, cnt, bunches=[1, 2], reps=1, cache_path=path)
+    assert b == {**a, "cached": True}
+    c = cphot.autotune(S, det, bins, None, cnt, bunches=[1], reps=1, cache_path=path)  # another signature
+    assert not c["cached"]
+    assert len(path.read_text().splitlines()) == 2
+    cphot.autotune_cache_clear()  # as a new process would: the file answers
+    d = cphot.autotune(S, det, bins, None, cnt, bunches=[1, 2], reps=1, cache_path=path)
+    assert d == {**a, "cached": True}
+    assert cphot.autotune(S, det, bins, None, cnt, bunches=[1, 2], reps=1, cache=True)["cached"]
+    cphot.autotune_cache_clear()
+    assert not cphot.autotune(S, det, bins, None, cnt, bunches=[1, 2], reps=1, cache=True)["cached"]
