@@ -206,6 +206,34 @@ def bench_reduction(torch, cphot, W, S, atm, run, out_buf, bins, th, cnt, stream
     return res
 
 
+def bench_emission_options(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, shape, exact):
+    """The telescope step with Poisson record counts and with the dispersive
+    spectrum (n - 1 stated at 400 nm): the kernels that carry these options,
+    their time beside the default step's and the photons they bin."""
+    res = {}
+    for name, extra in (("poisson_counts", {"counts": "poisson"}),
+                        ("dispersive", {"spectrum": "dispersive", "lambda_ref": 400.0})):
+        det = cphot.make_detector(atm, **{**run, **extra}, **shape)
+
+        def step(ev, det=det):
+            out_buf.zero_()
+            if ev is not None:
+                ev[0].record(stream)
+            cphot.propagate(S, det, bins, th, cnt, stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
+
+        ms, kern = time_steps(torch, step, args.steps, args.warmup, stream)
+        c = cnt.cpu().numpy()
+        res[name] = {"ms_per_step": ms, "kernel_ms": kern, "vs_default_step": ms / exact["ms_per_step"],
+                     "records_generated": float(c[3]), "records_not_emitted": float(c[13]),
+                     "photons_binned": float(c[8]), "binned_vs_default": float(c[8]) / max(exact["binned"], 1.0)}
+    res["note"] = ("same workload and launch shape as the default step; Poisson counts keep the expected "
+                   "records, the dispersive spectrum draws records for the largest cone and emits each "
+                   "with sin^2(theta(lambda)) / sin^2(theta_max)")
+    return res
+
+
 def walk_profile(torch, cphot, sh, geom, det, run, n=20000):
     """From traced records of the first n segments: the fraction of downward
     records the closed-form layer sums serve (tan^2 zenith within the series
@@ -610,6 +638,12 @@ def main():
         log(f"telescope with efficiency: {reduction['efficiency_only']['ms_per_step']:.3f} ms/step, "
             f"reduced {reduction['reduced']['ms_per_step']:.3f} ms/step, binned ratio "
             f"{reduction['binned_ratio']:.4f}")
+    emission = None
+    if not args.no_cuts:
+        emission = bench_emission_options(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, shape,
+                                          {"ms_per_step": ms_per_step, "binned": float(c[8])})
+        log(f"telescope with Poisson counts: {emission['poisson_counts']['ms_per_step']:.3f} ms/step, "
+            f"dispersive: {emission['dispersive']['ms_per_step']:.3f} ms/step")
     cuts = None
     if not args.no_cuts:
         cuts = bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, exact_bins, exact_th,
@@ -645,6 +679,8 @@ def main():
         out["cuts"] = cuts
     if reduction is not None:
         out["reduction"] = reduction
+    if emission is not None:
+        out["emission_options"] = emission
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, ms_per_step, stream)
         log(f"surrogate: {out['surrogate']['value']:.3e} photons/s")
