@@ -206,3 +206,38 @@ def test_table_transport_keeps_the_emission_decision(geometry):
     assert ct[3] == ce[3] and ct[13] == ce[13]
     assert ct[3] == ct[4] + ct[5] + ct[6] + ct[7] + ct[13]
     assert abs(int(ct[7]) - int(ce[7])) <= 1e-3 * ce[7] + 10
+
+
+def test_records_with_efficiency_and_reduction():
+    """Dispersive emission with a detector efficiency and the pre-emission
+    reduction: a record is detected iff u < p_emit exp(-tau) efficiency / q."""
+    atm = cphot.Atmosphere(**ATMO)
+    eff = W.efficiency_curve(ATMO["n_lam"])
+    q = cphot.reduction_table(atm, 2200.0, eff)
+    sh = W.make_shower(2000, seed=928, xmax=500.0, zenith_deg=30.0, azimuth_deg=50.0, beta="R")
+    seg = _near_threshold(sh, 3)
+    run = dict(transport="layered", detector="grid", spectrum="dispersive", lambda_ref=400.0, bunch=1,
+               h_obs=2200.0, nx=300, ny=300, cell=4.0, seed=31)
+    dev = dict(efficiency=torch.from_numpy(eff).cuda(), reduction=torch.from_numpy(q).cuda())
+    det = cphot.make_detector(atm, **run, **dev)
+    sg, gg, off = cphot.upload(seg, _geom(sh))
+    S = cphot.make_segments(sg, gg, off)
+    counts = torch.zeros(S.n, dtype=torch.int32, device="cuda")
+    cphot.segment_counts(S, det, counts)
+    offs = torch.cumsum(counts.to(torch.int64), 0) - counts.to(torch.int64)
+    tot = int(counts.sum().item())
+    rec = torch.zeros(max(tot, 1) * cphot.RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    cphot.trace_records(S, det, offs.contiguous(), rec)
+    torch.cuda.synchronize()
+    g = cphot.records_to_numpy(rec.cpu())[:tot]
+    oatm = parity.oracle_atm(ATMO)
+    orun = O.make_run(**run, efficiency=eff, reduction=q)
+    oc = O.segment_counts(oatm, orun, seg)
+    np.testing.assert_array_equal(counts.cpu().numpy(), oc["n"])
+    o = O.trace(oatm, orun, seg, core=sh.core, axis=sh.axis)
+    k = np.clip(np.floor((o["lambda"] - 300.0) / 300.0 * ATMO["n_lam"]).astype(int), 0, ATMO["n_lam"] - 1)
+    thr = np.exp(-o["tau"]) * eff[k] / oc["q"][o["seg"].astype(np.int64)] * o["p_emit"]
+    flips, rep = parity.compare_records(g, o, sh.core, ATMO, run, surv_thr=thr)
+    print(rep, np.bincount(o["state"], minlength=5))
+    assert (o["state"] == 4).sum() > 0.2 * len(o) and (o["state"] == 0).sum() > 100
+    assert flips <= max(3, parity.MAX_FLIP_FRACTION * len(o))
