@@ -8,7 +8,10 @@ W3 [64, 4], b3 [4] (4804 values; W[in, out]).
 With quantize=True the forward pass rounds what the GPU kernels feed to its bf16
 matrix cores (scaled inputs, weights, hidden activations) to bf16 and computes
 everything else in FP64: the same network the kernels evaluate, without their
-FP32 summation order.
+FP32 summation order. The backward pass then also rounds the operands the
+training kernel feeds to its matrix cores: the output error dL/dy and the
+back-propagated errors of both hidden layers (bias gradients are the sums of
+those rounded errors).
 """
 import numpy as np
 
@@ -69,14 +72,14 @@ def loss_and_grad(theta, X, Y, lo, hi, mean, std, quantize=True):
     n = X.shape[0]
     r = f["yh"] - t
     loss = float(np.mean(r * r))
-    dy = 2.0 * r / (n * 4)
+    dy = q(2.0 * r / (n * 4))
     g = {}
     g["W3"] = f["h2"].T @ dy
     g["b3"] = dy.sum(0)
-    dz2 = (dy @ q(P["W3"]).T) * (f["z2"] > 0)
+    dz2 = q((dy @ q(P["W3"]).T) * (f["z2"] > 0))
     g["W2"] = f["h1"].T @ dz2
     g["b2"] = dz2.sum(0)
-    dz1 = (dz2 @ q(P["W2"]).T) * (f["z1"] > 0)
+    dz1 = q((dz2 @ q(P["W2"]).T) * (f["z1"] > 0))
     g["W1"] = f["xh"].T @ dz1
     g["b1"] = dz1.sum(0)
     return loss, pack(g)

@@ -115,7 +115,8 @@ def test_gradient_matches_fp64_backprop(atm):
         k = int(np.prod(shape))
         a, b = g[o:o + k], go[o:o + k]
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
-        assert rel < 2e-2, (name, rel)
+        print(name, rel)
+        assert rel < 1e-2, (name, rel)
         o += k
     cos = g @ go / (np.linalg.norm(g) * np.linalg.norm(go))
     assert cos > 0.9995
