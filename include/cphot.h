@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define CPHOT_ABI_VERSION 2
+#define CPHOT_ABI_VERSION 3
 #define CPHOT_NCOUNTERS 16
 
 #define CPHOT_OK 0
@@ -65,8 +65,16 @@ extern "C" {
  * (0, 0, -earth_radius) (Sec. 3.3.4, spherical model), refraction at every
  * shell boundary, arrival on the sphere of radius earth_radius + h_obs; GRID
  * bins then use the arrival point's (x, y) in the tangent plane at the core
- * (the core lies at (0, 0, h_obs)). */
+ * (the core lies at (0, 0, h_obs)). A downward ray whose straight line stays
+ * well clear of grazing (D_obs / G_j <= 0.1 and t <= the atmosphere's bound, see
+ * cphot_device.h) takes the closed-form shell sums: the straight chord and its
+ * central angle formed directly, the refraction terms from shell moments
+ * tabulated per atmosphere (the same sums as the walk, truncation below 5e-4 m
+ * and 1e-6 in optical depth). Other rays are gathered per block into full waves
+ * and walked shell by shell. CURVED_WALK: the shell-by-shell walk for every ray
+ * (the thesis's iterative tracing; same results within rounding). */
 #define CPHOT_TRANSPORT_CURVED 3
+#define CPHOT_TRANSPORT_CURVED_WALK 5
 /* TABLE: straight line (or chord) plus the correction interpolated bilinearly
  * from a table precomputed with the exact tracer over emission height and cos
  * of the zenith angle (the thesis's interpolation tracing, Sec. 4.4.1; see
@@ -205,8 +213,8 @@ typedef struct {
 /* Track segments, structure of arrays, float32 device arrays of length n. The
  * caller owns them. A segment starts at (x0,y0,z0) and ends at (x1,y1,z1), the
  * particle moving with speed beta (in units of c) and charge `charge` (in
- * units of e). Segment i carries the global id first_id + i, which keys its
- * random streams: the same id always yields the same photons. */
+ * units of e). Segment i carries the global id first_id + i * id_stride, which
+ * keys its random streams: the same id always yields the same photons. */
 typedef struct {
   const float* x0; const float* y0; const float* z0;
   const float* x1; const float* y1; const float* z1;
@@ -215,7 +223,9 @@ typedef struct {
   int64_t n;                      /* number of segments (0 is allowed) */
   int64_t first_id;               /* global id of segment 0 */
   int32_t n_showers;              /* >= 1 */
-  int32_t reserved0;
+  int32_t id_stride;              /* segment i has the global id first_id + i * id_stride (0 means 1):
+                                     a strided subset of a larger set keeps its segments' ids, and with
+                                     them their photons */
   const int64_t* shower_offsets;  /* device int64 [n_showers + 1], ascending, [0] = 0, [n_showers] = n;
                                      may be NULL when n_showers == 1 */
   const double* shower_geom;      /* device float64 [n_showers * 5]: core x, core y (m, on the
@@ -257,14 +267,16 @@ typedef struct {
   /* Detector efficiency (Sec. 4.3.1: mirrors, sensor): device float64 [n_lambda_bins of the
    * atmosphere], the probability in [0, 1] that a photon of each wavelength bin that reaches the
    * detector is recorded; a photon survives iff u < exp(-tau) x efficiency. NULL: 1. Needs an
-   * atmosphere with wavelength bins. */
+   * atmosphere with wavelength bins. The array must hold exactly n_lambda_bins values: the
+   * kernels read one per bin and cannot check the length (the Python binding does). */
   const double* efficiency;
   /* Pre-emission reduction (Sec. 4.3.1), device float64 [n_layers of the atmosphere] or NULL:
    * q_i >= the detection probability exp(-tau) x efficiency of every photon emitted in layer i
    * (cphot_reduction_table computes such a bound). A segment's expected records are multiplied by
    * q of the layer of its lowest point before rounding, and each record survives iff
    * u < exp(-tau) x efficiency / q: the same expected detections with fewer records generated.
-   * A q below the true probability biases the result (the caller's bound must hold). */
+   * A q below the true probability biases the result (the caller's bound must hold). The array
+   * must hold exactly n_layers values (read per layer, unchecked by the kernels). */
   const double* reduction;
   double lambda_ref_nm;     /* DISPERSIVE: wavelength (nm) at which the atmosphere's n - 1 is stated */
 } cphot_detector;

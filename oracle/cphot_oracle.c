@@ -852,7 +852,12 @@ typedef struct {
   int64_t n;
   int64_t first_id;
   const float* dedx;  /* MeV/m, may be NULL (no fluorescence) */
+  int64_t id_stride;  /* segment i has the global id first_id + i * id_stride (0 means 1) */
 } orc_segments;
+
+static uint64_t seg_id_of(const orc_segments* S, int64_t i) {
+  return (uint64_t)(S->first_id + i * (S->id_stride > 0 ? S->id_stride : 1));
+}
 
 static float seg_dedx(const orc_segments* S, int64_t i) { return S->dedx ? S->dedx[i] : 0.0f; }
 
@@ -867,7 +872,7 @@ void orc_segment_counts(const orc_atmo* A, const orc_run* R, const orc_segments*
   for (int64_t i = 0; i < S->n; ++i) {
     seg_setup st;
     out[i] = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
-                           S->beta[i], S->charge[i], seg_dedx(S, i), (uint64_t)(S->first_id + i), &st);
+                           S->beta[i], S->charge[i], seg_dedx(S, i), seg_id_of(S, i), &st);
   }
 }
 
@@ -880,10 +885,10 @@ int64_t orc_trace(const orc_atmo* A, const orc_run* R, const orc_segments* S, co
   for (int64_t i = 0; i < S->n; ++i) {
     seg_setup st;
     orc_segment sg = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
-                                   S->beta[i], S->charge[i], seg_dedx(S, i), (uint64_t)(S->first_id + i), &st);
+                                   S->beta[i], S->charge[i], seg_dedx(S, i), seg_id_of(S, i), &st);
     int32_t nrec = segment_records(&sg);
     for (int32_t k = 0; k < nrec; ++k) {
-      if (m < cap) trace_photon(A, R, G, K, &st, &sg, (uint64_t)(S->first_id + i), (uint32_t)k, &out[m]);
+      if (m < cap) trace_photon(A, R, G, K, &st, &sg, seg_id_of(S, i), (uint32_t)k, &out[m]);
       ++m;
     }
   }
@@ -911,7 +916,7 @@ static void* worker(void* vp) {
   for (int64_t i = W->begin; i < W->end; ++i) {
     while (W->offsets && i >= W->offsets[sh + 1]) ++sh;
     seg_setup st;
-    uint64_t sid = (uint64_t)(S->first_id + i);
+    uint64_t sid = seg_id_of(S, i);
     orc_segment sg = segment_setup(A, R, K, S->x0[i], S->y0[i], S->z0[i], S->x1[i], S->y1[i], S->z1[i],
                                    S->beta[i], S->charge[i], seg_dedx(S, i), sid, &st);
     W->counters[C_SEG_IN] += 1;

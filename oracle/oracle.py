@@ -52,7 +52,7 @@ class Run(C.Structure):
 
 class Segments(C.Structure):
     _fields_ = [(f, C.POINTER(C.c_float)) for f in ("x0", "y0", "z0", "x1", "y1", "z1", "beta", "charge")] + \
-               [("n", C.c_int64), ("first_id", C.c_int64), ("dedx", C.POINTER(C.c_float))]
+               [("n", C.c_int64), ("first_id", C.c_int64), ("dedx", C.POINTER(C.c_float)), ("id_stride", C.c_int64)]
 
 
 class Geom(C.Structure):
@@ -230,7 +230,7 @@ def make_run(transport="straight", detector="grid", spectrum="uniform", bunch=1,
     return r
 
 
-def _segments(seg: dict, first_id: int):
+def _segments(seg: dict, first_id: int, id_stride: int = 1):
     arrs = {k: np.ascontiguousarray(seg[k], dtype=np.float32) for k in
             ("x0", "y0", "z0", "x1", "y1", "z1", "beta", "charge")}
     s = Segments()
@@ -238,6 +238,7 @@ def _segments(seg: dict, first_id: int):
         setattr(s, k, _ptr(v, C.c_float))
     s.n = int(arrs["x0"].shape[0])
     s.first_id = int(first_id)
+    s.id_stride = int(id_stride)
     if seg.get("dedx") is not None:
         arrs["dedx"] = np.ascontiguousarray(seg["dedx"], dtype=np.float32)
         s.dedx = _ptr(arrs["dedx"], C.c_float)
@@ -255,17 +256,18 @@ def frank_tamm_K(lam_min=300.0, lam_max=600.0) -> float:
     return lib().orc_frank_tamm_K(lam_min, lam_max)
 
 
-def segment_counts(atm: Atmosphere, run: Run, seg: dict, first_id: int = 0) -> np.ndarray:
-    s, keep = _segments(seg, first_id)
+def segment_counts(atm: Atmosphere, run: Run, seg: dict, first_id: int = 0, id_stride: int = 1) -> np.ndarray:
+    s, keep = _segments(seg, first_id, id_stride)
     out = np.zeros(s.n, dtype=SEGMENT_DTYPE)
     lib().orc_segment_counts(atm.handle, C.byref(run), C.byref(s), out.ctypes.data_as(C.c_void_p))
     return out
 
 
 def trace(atm: Atmosphere, run: Run, seg: dict, core=(0.0, 0.0), axis=(0.0, 0.0, -1.0),
-          first_id: int = 0) -> np.ndarray:
-    """Every photon record of the given segments, in (segment, k) order."""
-    s, keep = _segments(seg, first_id)
+          first_id: int = 0, id_stride: int = 1) -> np.ndarray:
+    """Every photon record of the given segments, in (segment, k) order; segment i
+    has the global id first_id + i * id_stride."""
+    s, keep = _segments(seg, first_id, id_stride)
     g = _geom(core, axis)
     cap = 1024
     while True:
@@ -277,12 +279,12 @@ def trace(atm: Atmosphere, run: Run, seg: dict, core=(0.0, 0.0), axis=(0.0, 0.0,
 
 
 def propagate(atm: Atmosphere, run: Run, seg: dict, geoms, offsets=None, first_id: int = 0,
-              threads: int = 1):
+              threads: int = 1, id_stride: int = 1):
     """Bins, time histograms and counters for a batch of showers.
 
     geoms: sequence of (core_x, core_y, axis_x, axis_y, axis_z), one per shower;
     offsets: int64 [n_showers + 1] segment offsets (None for one shower)."""
-    s, keep = _segments(seg, first_id)
+    s, keep = _segments(seg, first_id, id_stride)
     geoms = np.atleast_2d(np.asarray(geoms, dtype=np.float64))
     ns = geoms.shape[0]
     G = (Geom * ns)()

@@ -23,7 +23,7 @@ ERR_CAPACITY = -5
 NCOUNTERS = 16
 
 PROFILE = {"linsley5": 0, "homogeneous": 1, "linear": 2}
-TRANSPORT = {"straight": 0, "layered": 1, "surrogate": 2, "curved": 3, "table": 4}
+TRANSPORT = {"straight": 0, "layered": 1, "surrogate": 2, "curved": 3, "table": 4, "curved_walk": 5}
 COUNTS = {"rounded": 0, "poisson": 1}  # record count per segment from its expected value
 CUTS = {"track": 1, "photon": 2}  # data-reduction bounds for spheres (never drop a possible hit)
 EMISSION = {"cherenkov": 1, "fluorescence": 2, "both": 3}
@@ -54,7 +54,7 @@ class AtmosphereDesc(C.Structure):
 
 class Segments(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in ("x0", "y0", "z0", "x1", "y1", "z1", "beta", "charge")] + \
-               [("n", C.c_int64), ("first_id", C.c_int64), ("n_showers", C.c_int32), ("reserved0", C.c_int32),
+               [("n", C.c_int64), ("first_id", C.c_int64), ("n_showers", C.c_int32), ("id_stride", C.c_int32),
                 ("shower_offsets", C.c_void_p), ("shower_geom", C.c_void_p), ("dedx", C.c_void_p)]
 
 
@@ -104,7 +104,7 @@ RECORD_BYTES = 64
 
 _lock = threading.Lock()
 _lib = None
-ABI_VERSION = 2  # CPHOT_ABI_VERSION of include/cphot.h that the ctypes structs below mirror
+ABI_VERSION = 3  # CPHOT_ABI_VERSION of include/cphot.h that the ctypes structs below mirror
 
 
 def lib():
@@ -262,9 +262,14 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
         d.table = table.handle
     if efficiency is not None or reduction is not None:
         import torch
+        # the kernels read one value per wavelength bin / per layer of the atmosphere
         if efficiency is not None:
+            if efficiency.numel() != atm.desc.n_lambda_bins:
+                raise ValueError(f"efficiency needs {atm.desc.n_lambda_bins} values (one per wavelength bin)")
             d.efficiency = _dptr(efficiency, torch.float64, "efficiency")
         if reduction is not None:
+            if reduction.numel() != atm.desc.n_layers:
+                raise ValueError(f"reduction needs {atm.desc.n_layers} values (one per layer)")
             d.reduction = _dptr(reduction, torch.float64, "reduction")
     d._refs = (atm, surrogate, table, efficiency, reduction)  # keep the handles and buffers alive
     return d
@@ -284,9 +289,10 @@ def reduction_table(atm: Atmosphere, h_obs: float, efficiency=None):
     return out
 
 
-def make_segments(seg: dict, geom, offsets=None, first_id: int = 0) -> Segments:
+def make_segments(seg: dict, geom, offsets=None, first_id: int = 0, id_stride: int = 1) -> Segments:
     """`seg`: dict of float32 CUDA tensors x0..z1, beta, charge; `geom`: float64 CUDA
-    tensor [n_showers, 5]; `offsets`: int64 CUDA tensor [n_showers + 1] or None."""
+    tensor [n_showers, 5]; `offsets`: int64 CUDA tensor [n_showers + 1] or None.
+    Segment i carries the global id first_id + i * id_stride."""
     import torch
     s = Segments()
     n = int(seg["x0"].shape[0])
@@ -297,6 +303,9 @@ def make_segments(seg: dict, geom, offsets=None, first_id: int = 0) -> Segments:
         setattr(s, f, _dptr(t, torch.float32, f))
     s.n = n
     s.first_id = int(first_id)
+    if int(id_stride) < 1 or int(id_stride) >= 2**31:
+        raise ValueError("id_stride must be in [1, 2^31)")
+    s.id_stride = int(id_stride)
     ns = int(geom.shape[0])
     s.n_showers = ns
     s.shower_geom = _dptr(geom, torch.float64, "geom")

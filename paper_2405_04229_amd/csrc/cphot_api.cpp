@@ -112,6 +112,7 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   const cphot_atmosphere_desc& d = a->d;
   if (seg->n < 0) return fail(CPHOT_ERR_INVALID_ARG, "negative segment count");
   if (seg->first_id < 0) return fail(CPHOT_ERR_INVALID_ARG, "negative first_id");
+  if (seg->id_stride < 0) return fail(CPHOT_ERR_INVALID_ARG, "negative id_stride");
   if (seg->n > 0 && (!seg->x0 || !seg->y0 || !seg->z0 || !seg->x1 || !seg->y1 || !seg->z1 || !seg->beta ||
                      !seg->charge))
     return fail(CPHOT_ERR_INVALID_ARG, "null segment array");
@@ -121,7 +122,7 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   if (!seg->shower_geom) return fail(CPHOT_ERR_INVALID_ARG, "shower_geom is required");
   if (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED &&
       det->transport != CPHOT_TRANSPORT_SURROGATE && det->transport != CPHOT_TRANSPORT_CURVED &&
-      det->transport != CPHOT_TRANSPORT_TABLE)
+      det->transport != CPHOT_TRANSPORT_TABLE && det->transport != CPHOT_TRANSPORT_CURVED_WALK)
     return fail(CPHOT_ERR_INVALID_ARG, "unknown transport");
   if (det->transport == CPHOT_TRANSPORT_TABLE) {
     if (!det->table) return fail(CPHOT_ERR_INVALID_ARG, "table transport needs a correction table");
@@ -136,7 +137,8 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
                           cphot::surrogate_geometry(det->surrogate) == CPHOT_SURROGATE_CURVED;
   const bool curved_tab = det->transport == CPHOT_TRANSPORT_TABLE &&
                           cphot::table_view(det->table).geometry == CPHOT_SURROGATE_CURVED;
-  const bool curved = det->transport == CPHOT_TRANSPORT_CURVED || curved_sur || curved_tab;
+  const bool curved = det->transport == CPHOT_TRANSPORT_CURVED || det->transport == CPHOT_TRANSPORT_CURVED_WALK ||
+                      curved_sur || curved_tab;
   if (curved && det->detector != CPHOT_DETECTOR_GRID)
     return fail(CPHOT_ERR_UNSUPPORTED, "curved transport collects on a ground grid");
   if (curved && !(d.earth_radius > 1e5 && std::isfinite(d.earth_radius)))
@@ -171,6 +173,7 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   p.beta = seg->beta; p.charge = seg->charge;
   p.n = seg->n;
   p.first_id = (uint64_t)seg->first_id;
+  p.id_stride = seg->id_stride > 0 ? (uint64_t)seg->id_stride : 1u;
   p.n_showers = seg->n_showers;
   p.offsets = seg->shower_offsets;
   p.geom = seg->shower_geom;
@@ -255,6 +258,11 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     p.lambins = a->dev.lambins;
     p.moments = a->dev.moments ? a->dev.moments + (size_t)p.obs_layer * d.n_layers * 5 : nullptr;
     p.series_tmax = a->dev.moments ? a->dev.series_tmax : 0.f;
+    if (det->transport == CPHOT_TRANSPORT_CURVED && a->dev.shells) {
+      p.shells = a->dev.shells + (size_t)p.obs_layer * d.n_layers * cphot::kShellRow;
+      p.shell_tmax = a->dev.shell_tmax;
+      p.shell_rho = (float)cphot::kShellRhoMax;
+    }
   }
   const int64_t ns = seg->n_showers;
   if (det->detector == CPHOT_DETECTOR_GRID) {
@@ -306,6 +314,64 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     p.counters = out->counters;
   }
   return CPHOT_OK;
+}
+
+// Moments of the closed-form shell sums (curved Earth; cphot_device.h, curved_series).
+// Row (obs, j) sums over the full shells i, obs < i < j, in FP64: for each weight w
+// and pair (k, m), a_km sum_i w_i u_i^k (D'_{i+1}^m - D'_i^m) with
+// e_i = (n_i - n_j) / n_i, u_i = e_i (2 - e_i), D'_i = (b_j^2 - b_i^2) / (2 R dh)
+// = (j - i) (1 + (i + j) dh / (2 R)), a_km = binom(1/2, k + m) binom(k + m, k) (-1)^m.
+// Weights (one 16-float group each, entry q for pair q): Rayleigh and aerosol parts of
+// the extinction, R^2 e_i / (b_i b_{i+1}), R^2 / (b_i b_{i+1}) (k >= 1), 1 (k >= 1), n_i - 1.
+// Returns the largest |u| over all pairs (it bounds the series' t).
+double shell_moments(const std::vector<float4>& lay, int L, double dh, double Re, std::vector<float>& rows) {
+  static const int kKM[cphot::kShellTerms][2] = {{0, 1}, {0, 2}, {0, 3}, {0, 4}, {0, 5}, {1, 1}, {1, 2}, {1, 3},
+                                                 {1, 4}, {1, 5}, {2, 1}, {2, 2}, {2, 3}, {3, 1}, {3, 2}};
+  double acoef[cphot::kShellTerms];
+  for (int q = 0; q < cphot::kShellTerms; ++q) {
+    const int k = kKM[q][0], m = kKM[q][1], n = k + m;
+    double bh = 1.0;  // binom(1/2, n)
+    for (int i = 0; i < n; ++i) bh *= (0.5 - i) / (i + 1);
+    double bk = 1.0;  // binom(n, k)
+    for (int i = 0; i < k; ++i) bk *= (double)(n - i) / (i + 1);
+    acoef[q] = bh * bk * ((m & 1) ? -1.0 : 1.0);
+  }
+  rows.assign((size_t)L * L * cphot::kShellRow, 0.f);
+  const double R2 = Re * Re;
+  double umax = 0.0;
+  for (int j = 1; j < L; ++j) {
+    double S[6][cphot::kShellTerms] = {{0.0}};
+    const double dj = (double)lay[j].x;
+    for (int obs = j - 1; obs >= 0; --obs) {
+      float* r = &rows[((size_t)obs * L + j) * cphot::kShellRow];
+      for (int q = 0; q < cphot::kShellTerms; ++q) {
+        r[q] = (float)(acoef[q] * S[0][q]);
+        r[16 + q] = (float)(acoef[q] * S[1][q]);
+        r[32 + q] = (float)(acoef[q] * S[2][q]);
+        r[80 + q] = (float)(acoef[q] * S[5][q]);
+        if (q >= 5) {  // k >= 1 only: the straight line's part is formed directly
+          r[48 + q] = (float)(acoef[q] * S[3][q]);
+          r[64 + q] = (float)(acoef[q] * S[4][q]);
+        }
+      }
+      // shell i = obs joins the sums of the rows below it
+      const int i = obs;
+      const double di = (double)lay[i].x;
+      const double e = (di - dj) / (1.0 + di), u = e * (2.0 - e);
+      umax = std::max(umax, std::fabs(u));
+      const double bi = Re + i * dh, bi1 = Re + (i + 1) * dh;
+      const double w[6] = {(double)lay[i].z, (double)lay[i].w, R2 * e / (bi * bi1), R2 / (bi * bi1), 1.0, di};
+      const double D0 = (double)(j - i) * (1.0 + (i + j) * dh / (2.0 * Re));
+      const double D1 = (double)(j - i - 1) * (1.0 + (i + 1 + j) * dh / (2.0 * Re));
+      for (int q = 0; q < cphot::kShellTerms; ++q) {
+        const int k = kKM[q][0], m = kKM[q][1];
+        const double diff = std::pow(D1, m) - std::pow(D0, m);
+        const double f = std::pow(u, k) * diff;
+        for (int c = 0; c < 6; ++c) S[c][q] += w[c] * f;
+      }
+    }
+  }
+  return umax;
 }
 
 struct LaunchShape {
@@ -486,7 +552,8 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
   // plus the aerosol column (exp(-lo/H) - exp(-hi/H)) / dh times tau_A(lambda_k).
   std::vector<float4> lay, mom;
   std::vector<float2> lamb;
-  float series_tmax = 0.f;
+  std::vector<float> shells;
+  float series_tmax = 0.f, shell_tmax = 0.f;
   if (d.n_layers > 0) {
     const int L = d.n_layers, K = d.n_lambda_bins;
     const double dh = d.h_top / L;
@@ -535,6 +602,10 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
       }
     }
     series_tmax = (float)std::min(9.0, umax > 0.0 ? 5.4e-3 / umax : 9.0);
+    if (finite_pos(d.earth_radius) && d.earth_radius > 1e5) {
+      const double umax_c = shell_moments(lay, L, dh, d.earth_radius, shells);
+      shell_tmax = (float)std::min(25.0, umax_c > 0.0 ? 1.4e-2 / umax_c : 25.0);
+    }
     // refraction bound of the data-reduction cuts: for the layers from obs up,
     // |n_i - n_j| / n_i <= (max delta - min delta) / (1 + min delta)
     a->cut_e.assign(L, 0.0);
@@ -573,6 +644,14 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
     if ((e = hipMemcpy(a->dev.moments, mom.data(), mom.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup(0, "hipMemcpy(moments)", e);
     a->dev.series_tmax = series_tmax;
+    if (!shells.empty()) {
+      if ((e = hipMalloc(&a->dev.shells, shells.size() * sizeof(float))) != hipSuccess)
+        return cleanup(0, "hipMalloc", e);
+      if ((e = hipMemcpy(a->dev.shells, shells.data(), shells.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+          hipSuccess)
+        return cleanup(0, "hipMemcpy(shells)", e);
+      a->dev.shell_tmax = shell_tmax;
+    }
   }
   *out = a;
   return CPHOT_OK;
@@ -587,6 +666,7 @@ void cphot_destroy_atmosphere(cphot_atmosphere* a) {
   if (a->dev.layers) (void)hipFree(a->dev.layers);
   if (a->dev.lambins) (void)hipFree(a->dev.lambins);
   if (a->dev.moments) (void)hipFree(a->dev.moments);
+  if (a->dev.shells) (void)hipFree(a->dev.shells);
   (void)hipSetDevice(prev);
   delete a;
 }

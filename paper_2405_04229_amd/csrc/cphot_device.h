@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cphot_internal.h"
+
 namespace cphot {
 
 constexpr uint32_t TAG_SEGMENT = 0;
@@ -510,6 +512,182 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
   w.opt = opt;
   w.arrived = arrived;
   curved_arrival(Re, h_obs, Px, Py, Pz, ux, uy, uz, psi, 0.0, w.ax, w.ay, w.az);
+}
+
+// Closed-form shell sums for a downward ray over spherical shells (Sec. 3.3.4;
+// the evaluation of the shell walk's sums without one step per shell, as the
+// planar layer sums above).
+//
+// With p the impact parameter in the start shell j (radius r0 = R + h0 there,
+// local zenith cosine c0), Bouguer's invariant gives p_i^2 = p^2 (1 - u_i) in
+// shell i, u_i = e_i (2 - e_i), e_i = (n_i - n_j) / n_i. With G(r) = r^2 - p^2
+// (the straight line's squared distance from its perigee) the chord of shell i
+// between radii ra > rb is sqrt(G(ra) + p^2 u_i) - sqrt(G(rb) + p^2 u_i). For the
+// full shells between the observation shell and j, write G(b) = G_j - D(b),
+// D(b) = b_j^2 - b^2 (b_j the start shell's lower radius), and expand
+// sqrt(G_j - D + p^2 u) = sqrt(G_j) (1 - x + y)^(1/2) in x = D / G_j (curvature)
+// and y = t u, t = p^2 / G_j (refraction; t is tan^2 of the straight line's
+// zenith angle at b_j): every weighted sum of chords sum_i w_i l_i becomes
+// sqrt(G_j) sum_km a_km t^k G_j^-m T_km(w), with shell moments
+// T_km(w) = sum_i w_i u_i^k (D_{i+1}^m - D_i^m) tabulated per (observation
+// shell, start shell) in FP64, the coefficients a_km = binom(1/2, k + m)
+// binom(k + m, k) (-1)^m folded in and D scaled by S = 2 R dh. Weights: the
+// Rayleigh and aerosol extinction parts (optical depth), the central angle per
+// metre of chord R^2 / (b_i b_{i+1}) (its refraction part, k >= 1) and
+// R^2 e_i / (b_i b_{i+1}) (the change of p), the path length (k >= 1) and n - 1
+// (the delay). The straight line itself is never expanded: its chord L_s from r0
+// to the observation sphere and its central angle asin(s0 L_s / r_obs) are
+// formed directly, and the series add only the refraction terms to them. The
+// partial start shell (straight, u = 0) and the partial observation shell
+// (chord with p_obs, and its difference to the straight chord) are formed
+// directly without subtracting near-equal lengths.
+//
+// Terms: k = 0 and 1 to m = 5, k = 2 to m = 3, k = 3 to m = 2 (15 pairs). The
+// series serves rays with D_obs / G_j <= rho_max (0.1) and t <= t_max (the
+// atmosphere's bound, t u_max <= 1.4e-2): there the omitted terms stay below
+// 5e-4 m in path and arrival point and 1e-6 in optical depth (checked against
+// the shell-by-shell chords in FP64). Other rays return false (the shell walk
+// traces them). The delay uses the identity sum l_i (1 - v_i . a) = L - a.(E - P)
+// split into the straight line's part L_s |u - a|^2 / 2, the path excess and the
+// shift of the arrival point along the sphere.
+// (kShellTerms, kShellRow and the row layout: cphot_internal.h)
+
+// s += v . (b0, b1, b2, b3)
+__device__ __forceinline__ float shell_acc4(float4 v, float b0, float b1, float b2, float b3, float s) {
+  return fmaf(v.w, b3, fmaf(v.z, b2, fmaf(v.y, b1, fmaf(v.x, b0, s))));
+}
+
+template <bool NEED_TIME>
+__device__ __forceinline__ bool curved_series(const float4* __restrict__ lay, const float* __restrict__ rows,
+                                              float2 sp, float dh, int n_layers, int obs, float h_obs, double Re,
+                                              float rho_max, float t_max, float Px, float Py, float Pz, float h0,
+                                              float ux, float uy, float uz, float axx, float axy, float axz,
+                                              CurvedWalk& w) {
+  const float Rf = (float)Re, twoR = (float)(2.0 * Re);
+  const float qz = Pz + Rf;
+  const float rq = sqrt_fast(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
+  const float irq = rcp_fast(rq);
+  const float erx = Px * irq, ery = Py * irq, erz = qz * irq;
+  const float mu = fmaf(ux, erx, fmaf(uy, ery, uz * erz));
+  const float c0 = -mu;
+  if (!(c0 > 0.f)) return false;
+  const float etx0 = fmaf(-mu, erx, ux), ety0 = fmaf(-mu, ery, uy), etz0 = fmaf(-mu, erz, uz);
+  const float s0 = sqrt_fast(fmaf(etx0, etx0, fmaf(ety0, ety0, etz0 * etz0)));
+  const int j = min((int)(h0 / dh), n_layers - 1);
+  const float r0 = Rf + h0;
+  const float rc0 = r0 * c0, p = r0 * s0;
+  const float G0 = rc0 * rc0;
+  const float robs = Rf + h_obs;
+  // straight chord from r0 to the observation sphere
+  const float dO = (h0 - h_obs) * (twoR + h0 + h_obs);
+  const float Gobs = G0 - dO;
+  if (!(Gobs > 0.f)) return false;
+  const float Ls = dO * rcp_fast(rc0 + sqrt_fast(Gobs));
+  const float4 Lj = lay[j];
+  const float extj = fmaf(Lj.z, sp.x, Lj.w * sp.y);
+  float tau, dpsi = 0.f, dL = 0.f, opt = 0.f;
+  if (j <= obs) {
+    tau = extj * Ls;
+    if constexpr (NEED_TIME) opt = Lj.x * Ls;
+  } else {
+    const float hj = (float)j * dh, ho1 = (float)(obs + 1) * dh;
+    const float dJ = (h0 - hj) * (twoR + h0 + hj);           // r0^2 - b_j^2
+    const float Gj = G0 - dJ;
+    const float DO = (hj - h_obs) * (twoR + hj + h_obs);     // b_j^2 - r_obs^2
+    const float iG = rcp_fast(Gj);
+    const float t = (p * p) * iG;
+    if (!(DO * iG <= rho_max && t <= t_max)) return false;
+    const float sG = sqrt_fast(Gj);
+    const float gam = (twoR * dh) * iG;
+    // basis sqrt(G_j) t^k gam^m of the 15 terms, taken four at a time against the
+    // rows' float4 groups (few live registers): q = 0..4 (k 0, m 1..5), 5..9 (k 1,
+    // m 1..5), 10..12 (k 2, m 1..3), 13..14 (k 3, m 1..2)
+    const float g1 = sG * gam, g2 = g1 * gam, g3 = g2 * gam, g4 = g3 * gam, g5 = g4 * gam;
+    const float t2 = t * t, t3 = t2 * t;
+    const float* r = rows + (size_t)j * kShellRow;
+    const float4* r4 = reinterpret_cast<const float4*>(r);
+    float sR = 0.f, sA = 0.f, sPe = 0.f, sP1 = 0.f, sL = 0.f, sD = 0.f;
+    {
+      const float b0 = g1, b1 = g2, b2 = g3, b3 = g4;
+      sR = shell_acc4(r4[0], b0, b1, b2, b3, sR);
+      sA = shell_acc4(r4[4], b0, b1, b2, b3, sA);
+      sPe = shell_acc4(r4[8], b0, b1, b2, b3, sPe);
+      if constexpr (NEED_TIME) sD = shell_acc4(r4[20], b0, b1, b2, b3, sD);
+    }
+    // the groups' loads stay with their products: hoisting all of them would hold
+    // 64 (96 with the delay) table values at once
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const float b0 = g5, b1 = t * g1, b2 = t * g2, b3 = t * g3;
+      sR = shell_acc4(r4[1], b0, b1, b2, b3, sR);
+      sA = shell_acc4(r4[5], b0, b1, b2, b3, sA);
+      sPe = shell_acc4(r4[9], b0, b1, b2, b3, sPe);
+      sP1 = shell_acc4(r4[13], b0, b1, b2, b3, sP1);
+      if constexpr (NEED_TIME) {
+        sL = shell_acc4(r4[17], b0, b1, b2, b3, sL);
+        sD = shell_acc4(r4[21], b0, b1, b2, b3, sD);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const float b0 = t * g4, b1 = t * g5, b2 = t2 * g1, b3 = t2 * g2;
+      sR = shell_acc4(r4[2], b0, b1, b2, b3, sR);
+      sA = shell_acc4(r4[6], b0, b1, b2, b3, sA);
+      sPe = shell_acc4(r4[10], b0, b1, b2, b3, sPe);
+      sP1 = shell_acc4(r4[14], b0, b1, b2, b3, sP1);
+      if constexpr (NEED_TIME) {
+        sL = shell_acc4(r4[18], b0, b1, b2, b3, sL);
+        sD = shell_acc4(r4[22], b0, b1, b2, b3, sD);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const float b0 = t2 * g3, b1 = t3 * g1, b2 = t3 * g2;  // the groups' fourth entries are zero
+      sR = shell_acc4(r4[3], b0, b1, b2, 0.f, sR);
+      sA = shell_acc4(r4[7], b0, b1, b2, 0.f, sA);
+      sPe = shell_acc4(r4[11], b0, b1, b2, 0.f, sPe);
+      sP1 = shell_acc4(r4[15], b0, b1, b2, 0.f, sP1);
+      if constexpr (NEED_TIME) {
+        sL = shell_acc4(r4[19], b0, b1, b2, 0.f, sL);
+        sD = shell_acc4(r4[23], b0, b1, b2, 0.f, sD);
+      }
+    }
+    // partial start shell (straight: u = 0 there) and partial observation shell
+    const float lS = dJ * rcp_fast(rc0 + sG);
+    const float4 Lo = lay[obs];
+    const float eO = (Lo.x - Lj.x) * Lo.y;
+    const float dd = (p * p) * (eO * (2.0f - eO));
+    const float num = (ho1 - h_obs) * (twoR + ho1 + h_obs);  // b_{obs+1}^2 - r_obs^2
+    const float A0 = Gj - (hj - ho1) * (twoR + hj + ho1), B0 = Gj - DO;
+    const float qA = sqrt_fast(A0 + dd), qA0 = sqrt_fast(A0), qB = sqrt_fast(B0 + dd), qB0 = sqrt_fast(B0);
+    const float lO = num * rcp_fast(qA + qB), lOs = num * rcp_fast(qA0 + qB0);
+    const float dlO = -dd * (lO + lOs) * rcp_fast((qA + qA0) * (qB + qB0));  // lO - lOs
+    tau = fmaf(extj, lS, fmaf(sp.x, sR, fmaf(sp.y, sA, fmaf(Lo.z, sp.x, Lo.w * sp.y) * lO)));
+    dpsi = p * ((sP1 - sPe) * rcp_fast(Rf * Rf) + (dlO - eO * lO) * rcp_fast((Rf + ho1) * robs));
+    if constexpr (NEED_TIME) {
+      dL = sL + dlO;
+      opt = fmaf(Lj.x, lS, fmaf(Lo.x, lO, sD));
+    }
+  }
+  // straight central angle asin(s0 Ls / r_obs) (x <= 0.02: three terms)
+  const float x = s0 * Ls * rcp_fast(robs), x2 = x * x;
+  const float psi_s = x * fmaf(x2, fmaf(x2, 0.075f, 1.0f / 6.0f), 1.0f);
+  w.tau = tau;
+  w.opt = opt;
+  w.geo = 0.f;
+  if constexpr (NEED_TIME) {
+    // delay: L_s |u - a|^2 / 2 + (L - L_s) - dpsi a.dE/dpsi at the straight arrival point
+    const float is = s0 > 0.f ? rcp_fast(s0) : 0.f;
+    const float etx = s0 > 0.f ? etx0 * is : 1.f, ety = s0 > 0.f ? ety0 * is : 0.f, etz = s0 > 0.f ? etz0 * is : 0.f;
+    const float a_r = fmaf(axx, erx, fmaf(axy, ery, axz * erz)), a_t = fmaf(axx, etx, fmaf(axy, ety, axz * etz));
+    const float gx = ux - axx, gy = uy - axy, gz = uz - axz;
+    const float ps2 = psi_s * psi_s;  // |psi| <= 0.02: two terms each
+    const float sps = psi_s * fmaf(ps2, -1.0f / 6.0f, 1.0f), cps = fmaf(ps2, -0.5f, 1.0f);
+    w.geo = fmaf(0.5f * Ls, fmaf(gx, gx, fmaf(gy, gy, gz * gz)), dL) - dpsi * robs * fmaf(a_t, cps, -a_r * sps);
+  }
+  w.arrived = 1;
+  curved_arrival(Re, h_obs, Px, Py, Pz, ux, uy, uz, (double)psi_s + (double)dpsi, 0.0, w.ax, w.ay, w.az);
+  return true;
 }
 
 }  // namespace cphot

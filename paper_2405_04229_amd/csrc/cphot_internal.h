@@ -16,6 +16,17 @@ struct MlpImage;
 constexpr int kMaxLayers = 128;
 constexpr int kMaxLambdaBins = 64;
 
+// Closed-form shell sums (curved Earth, curved_series in cphot_device.h): 15 (k, m)
+// pairs of the double series, one row of shell moments per (observation shell,
+// start shell), one 16-float group per weight (16-byte aligned), entry q of a group
+// for pair q (q = 0..4: k 0, m 1..5; 5..9: k 1, m 1..5; 10..12: k 2, m 1..3; 13, 14:
+// k 3, m 1..2; entry 15 zero): [0, 16) Rayleigh, [16, 32) aerosol, [32, 48)
+// R^2 e / (b b'), [48, 64) R^2 / (b b') (k >= 1: entries 0..4 zero), [64, 80) path
+// (k >= 1), [80, 96) n - 1.
+constexpr int kShellTerms = 15;
+constexpr int kShellRow = 96;
+constexpr double kShellRhoMax = 0.1;  // largest D_obs / G_j the series serves
+
 // Device-side tables owned by an atmosphere handle.
 struct AtmoDevice {
   double* delta_table = nullptr;   // n_tab + 1 entries, FP64 (per-segment yield)
@@ -27,6 +38,9 @@ struct AtmoDevice {
   // between observation layer obs and start layer j (planar transport)
   float4* moments = nullptr;
   float series_tmax = 0.f;         // largest tan^2(zenith) the series may serve
+  // closed-form shell sums (curved Earth): [obs][j][kShellRow] floats of shell moments
+  float* shells = nullptr;
+  float shell_tmax = 0.f;          // largest t = tan^2 of the straight zenith at b_j the series may serve
 };
 
 // Everything a launch needs, passed by value as the kernel argument.
@@ -35,6 +49,7 @@ struct KParams {
   const float *x0, *y0, *z0, *x1, *y1, *z1, *beta, *charge;
   int64_t n;
   uint64_t first_id;
+  uint64_t id_stride;  // global id of segment i: first_id + i * id_stride
   int32_t n_showers;
   const int64_t* offsets;
   const double* geom;
@@ -69,6 +84,8 @@ struct KParams {
   const float4* layers;
   const float4* moments;  // rows of the observation layer's slice, by start layer
   float series_tmax;      // 0: crossing loop only
+  const float* shells;    // curved: shell-moment rows of the observation shell's slice, by start shell
+  float shell_tmax, shell_rho;  // curved series domain (0: shell walk only)
   int32_t cuts;           // CPHOT_CUT_* (SPHERES, propagate mode)
   const double* eff;      // detector efficiency per wavelength bin (NULL: 1)
   const double* red;      // pre-emission reduction bound per layer (NULL: none)
@@ -126,6 +143,8 @@ bool surrogate_ready(const cphot_surrogate* s);
 // internal transport ids: SURROGATE / TABLE transport over curved shells
 constexpr int kTransportCurvedSurrogate = 16;
 constexpr int kTransportCurvedTable = 17;
+// the shell walk for every photon (CPHOT_TRANSPORT_CURVED_WALK)
+constexpr int kTransportCurvedWalk = CPHOT_TRANSPORT_CURVED_WALK;
 // Correction table: device view, the atmosphere it was built from, its h_obs.
 TableView table_view(const cphot_table* t);
 const cphot_atmosphere* table_atmosphere(const cphot_table* t);

@@ -410,8 +410,8 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     kb = (int)((lam - p.lam_min) * ((float)p.n_lam / (p.lam_max - p.lam_min)));
     kb = min(max(kb, 0), p.n_lam - 1);
   }
-  if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED || TRANSPORT == kTransportCurvedSurrogate ||
-                TRANSPORT == kTransportCurvedTable) {
+  if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED || TRANSPORT == kTransportCurvedWalk ||
+                TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable) {
     // height above the sphere R without subtracting R: (x^2 + y^2 + z (2R + z)) / (|P - C| + R)
     const float Rf = (float)p.earth_radius;
     const float qz = Pz + Rf;
@@ -492,8 +492,18 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
         o.state = kStateDeferred;  // outside the domain: traced exactly in a compacted pass
         return;
       }
-      curved_walk<NEED_TIME>(s_lay, s_lam[kb], p.dh, p.n_layers, p.h_obs, p.earth_radius, Px, Py, Pz, h0, ux, uy,
-                             uz, axx, axy, axz, cw);
+      if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED) {
+        // closed-form shell sums; rays outside their domain are walked in a compacted pass
+        if (!curved_series<NEED_TIME>(s_lay, p.shells, s_lam[kb], p.dh, p.n_layers, p.obs_layer, p.h_obs,
+                                      p.earth_radius, p.shell_rho, p.shell_tmax, Px, Py, Pz, h0, ux, uy, uz, axx,
+                                      axy, axz, cw)) {
+          o.state = kStateDeferred;
+          return;
+        }
+      } else {
+        curved_walk<NEED_TIME>(s_lay, s_lam[kb], p.dh, p.n_layers, p.h_obs, p.earth_radius, Px, Py, Pz, h0, ux, uy,
+                               uz, axx, axy, axz, cw);
+      }
     }
     o.x = (float)cw.ax;
     o.y = (float)cw.ay;
@@ -766,8 +776,10 @@ __device__ void flush_window(const KParams& p, uint32_t* s_hist, int sh) {
 // at three without.
 template <int T>
 constexpr int kMinWavesPerSimd =
-    (T == kTransportCurvedTable) ? 3
-    : (T == CPHOT_TRANSPORT_CURVED || T == CPHOT_TRANSPORT_LAYERED || T == CPHOT_TRANSPORT_STRAIGHT || T == CPHOT_TRANSPORT_TABLE) ? 4
+    (T == kTransportCurvedTable || T == CPHOT_TRANSPORT_CURVED) ? 3
+    : (T == kTransportCurvedWalk || T == CPHOT_TRANSPORT_LAYERED ||
+       T == CPHOT_TRANSPORT_STRAIGHT || T == CPHOT_TRANSPORT_TABLE)
+        ? 4
                                                                                                                      : 1;
 
 // EXT: Poisson record counts and the dispersive spectrum (its per-record angle and
@@ -780,13 +792,16 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
   constexpr bool kLayers = (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT);
   constexpr bool kMlp = (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == kTransportCurvedSurrogate);
   // transports that defer some records to the exact tracer (compaction queue)
-  constexpr bool kDefer = kMlp || TRANSPORT == CPHOT_TRANSPORT_TABLE || TRANSPORT == kTransportCurvedTable;
+  constexpr bool kDefer = kMlp || TRANSPORT == CPHOT_TRANSPORT_TABLE || TRANSPORT == kTransportCurvedTable ||
+                          TRANSPORT == CPHOT_TRANSPORT_CURVED;
   constexpr bool kSort = kLayers && (MODE != MODE_COUNTS);
   // exact transport behind a surrogate: records outside the network's domain
   constexpr int kExact =
       (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == CPHOT_TRANSPORT_TABLE)       ? CPHOT_TRANSPORT_LAYERED
-      : (TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable) ? CPHOT_TRANSPORT_CURVED
-                                                                                        : TRANSPORT;
+      : (TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable ||
+         TRANSPORT == CPHOT_TRANSPORT_CURVED)
+          ? kTransportCurvedWalk
+          : TRANSPORT;
   // per-segment state for the record loop, one slot per segment of the tile:
   // q0 = start point, cos(theta); q1 = end - start, sin(theta) (DISPERSIVE: the
   // terms of beta n(lambda) - 1 in place of the angle); q2 = rotation
@@ -875,7 +890,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
     int key = kMaxLayers;  // segments without records sort last
     if (i < p.n) {
       const float fx0 = p.x0[i], fy0 = p.y0[i], fz0 = p.z0[i], fx1 = p.x1[i], fy1 = p.y1[i], fz1 = p.z1[i];
-      const uint64_t id = p.first_id + (uint64_t)i;
+      const uint64_t id = p.first_id + (uint64_t)i * p.id_stride;
       SegResult r =
           segment_setup<EXT>(p, fx0, fy0, fz0, fx1, fy1, fz1, p.beta[i], p.charge[i], p.dedx ? p.dedx[i] : 0.0f, id);
       if constexpr (MODE == MODE_PROPAGATE && DETECTOR == CPHOT_DETECTOR_SPHERES && !kMlpTransport<TRANSPORT>) {
@@ -1143,6 +1158,7 @@ hipError_t launch_bs(const KParams& p, int mode, int grid, size_t lds, hipStream
     case CPHOT_TRANSPORT_LAYERED: return g ? launch_mode<BS, 1, 0>(p, mode, grid, lds, s) : launch_mode<BS, 1, 1>(p, mode, grid, lds, s);
     case CPHOT_TRANSPORT_SURROGATE: return g ? launch_mode<BS, 2, 0>(p, mode, grid, lds, s) : launch_mode<BS, 2, 1>(p, mode, grid, lds, s);
     case CPHOT_TRANSPORT_CURVED: return launch_mode<BS, 3, 0>(p, mode, grid, lds, s);  // grid detector only
+    case kTransportCurvedWalk: return launch_mode<BS, kTransportCurvedWalk, 0>(p, mode, grid, lds, s);
     case CPHOT_TRANSPORT_TABLE: return g ? launch_mode<BS, 4, 0>(p, mode, grid, lds, s) : launch_mode<BS, 4, 1>(p, mode, grid, lds, s);
     case kTransportCurvedTable: return launch_mode<BS, kTransportCurvedTable, 0>(p, mode, grid, lds, s);
     default: return launch_mode<BS, kTransportCurvedSurrogate, 0>(p, mode, grid, lds, s);
@@ -1174,6 +1190,7 @@ size_t static_lds_bs(const KParams& p, int mode) {
     case CPHOT_TRANSPORT_LAYERED: return g ? static_lds_mode<BS, 1, 0>(mode) : static_lds_mode<BS, 1, 1>(mode);
     case CPHOT_TRANSPORT_SURROGATE: return g ? static_lds_mode<BS, 2, 0>(mode) : static_lds_mode<BS, 2, 1>(mode);
     case CPHOT_TRANSPORT_CURVED: return static_lds_mode<BS, 3, 0>(mode);
+    case kTransportCurvedWalk: return static_lds_mode<BS, kTransportCurvedWalk, 0>(mode);
     case CPHOT_TRANSPORT_TABLE: return g ? static_lds_mode<BS, 4, 0>(mode) : static_lds_mode<BS, 4, 1>(mode);
     case kTransportCurvedTable: return static_lds_mode<BS, kTransportCurvedTable, 0>(mode);
     default: return static_lds_mode<BS, kTransportCurvedSurrogate, 0>(mode);

@@ -172,9 +172,10 @@ struct TrainWeights {  // bf16 operand layouts for the training kernel (k-contig
 };
 
 // Builds the training layouts and the inference image from the FP32 master
-// weights and the normalisation; also advances the step counter.
+// weights and the normalisation (at creation, after new parameters or a new
+// normalisation; a training step updates its own entries, see k_adam).
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ m, const float* __restrict__ norm,
-                                             TrainWeights* tw, MlpImage* im, int* step, int advance) {
+                                             TrainWeights* tw, MlpImage* im) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int T = gridDim.x * 256;
   for (int e = t; e < 64 * 32; e += T) {
@@ -224,9 +225,37 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ m, const
     im->out_mean[t] = norm[16 + t];
     im->out_std[t] = norm[20 + t];
   }
-  if (t == 0) {
-    im->pad0 = 0.f;
-    if (advance) *step += 1;
+  if (t == 0) im->pad0 = 0.f;
+}
+
+// Writes the bf16 copies of parameter i (new FP32 value v) into every slot of the
+// training layouts and the inference image that holds it: the inverse of k_pack's
+// index maps, so that one Adam thread refreshes its own parameter and a training
+// step needs no separate packing pass. Slots that hold zero padding are untouched.
+__device__ __forceinline__ void scatter_param(int i, float v, TrainWeights* tw, MlpImage* im) {
+  const __bf16 b = (__bf16)v;
+  if (i < kOffB1) {  // W1[k][o]
+    const int k = i / 64, o = i % 64;
+    tw->w1t[o][k] = b;
+    im->a1[o / 16][o % 16][k] = b;  // lane c (g = 0) of M-tile o / 16, K slot k
+  } else if (i < kOffW2) {
+    im->b1[i - kOffB1] = v;
+  } else if (i < kOffB2) {  // W2[a][c2]: K slot (kt, g, ii) of unit a, column c2
+    const int e = i - kOffW2, a = e / 64, c2 = e % 64;
+    tw->w2t[c2][a] = b;
+    tw->w2[a][c2] = b;
+    const int kt = (a / 16) >> 1, ii = 4 * ((a / 16) & 1) + (a & 3), g = (a % 16) >> 2;
+    im->a2[c2 / 16][kt][16 * g + c2 % 16][ii] = b;
+  } else if (i < kOffW3) {
+    im->b2[i - kOffB2] = v;
+  } else if (i < kOffB3) {  // W3[in][o]
+    const int e = i - kOffW3, in = e / 4, o = e % 4;
+    tw->w3t[o][in] = b;
+    tw->w3[in][o] = b;
+    const int kt = (in / 16) >> 1, ii = 4 * ((in / 16) & 1) + (in & 3), g = (in % 16) >> 2;
+    im->a3[kt][16 * g + o][ii] = b;
+  } else {
+    im->b3[i - kOffB3] = v;
   }
 }
 
@@ -409,7 +438,9 @@ struct AdamParams {
   float* master;
   float* m1;
   float* m2;
-  const int* step;
+  TrainWeights* tw;  // bf16 layouts refreshed with each updated parameter
+  MlpImage* img;
+  int t;             // Adam steps done before this one
   int total_steps;
   float lr;
   float* grad_out;   // may be null
@@ -421,7 +452,7 @@ struct AdamParams {
 
 __global__ __launch_bounds__(256) void k_adam(AdamParams p) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const int t = *p.step;  // steps done before this one
+  const int t = p.t;
   if (i < kMlpParams) {
     float gsum = 0.f;
     for (int b = 0; b < p.blocks; ++b) gsum += p.partial[(size_t)b * kMlpParams + i];
@@ -437,7 +468,9 @@ __global__ __launch_bounds__(256) void k_adam(AdamParams p) {
       p.m2[i] = m2;
       const float mh = m1 / (1.f - powf(b1, tt));
       const float vh = m2 / (1.f - powf(b2, tt));
-      p.master[i] -= lr * mh / (sqrtf(vh) + eps);
+      const float w = p.master[i] - lr * mh / (sqrtf(vh) + eps);
+      p.master[i] = w;
+      scatter_param(i, w, p.tw, p.img);
     }
   }
   if (i == 0 && p.loss_out) {
@@ -487,7 +520,7 @@ struct cphot_surrogate {
   float* norm = nullptr;
   float* partial = nullptr;
   float* loss_partial = nullptr;
-  int* step = nullptr;
+  int steps_done = 0;  // Adam steps enqueued so far (bias correction)
   double* sums = nullptr;
   cphot::TrainWeights* tw = nullptr;
   cphot::MlpImage* img = nullptr;
@@ -512,8 +545,8 @@ double init_uniform(uint64_t& s) {
   return (double)(z >> 11) * (1.0 / 9007199254740992.0);
 }
 
-hipError_t pack(cphot_surrogate* s, hipStream_t st, int advance) {
-  hipLaunchKernelGGL(cphot::k_pack, dim3(16), dim3(256), 0, st, s->master, s->norm, s->tw, s->img, s->step, advance);
+hipError_t pack(cphot_surrogate* s, hipStream_t st) {
+  hipLaunchKernelGGL(cphot::k_pack, dim3(16), dim3(256), 0, st, s->master, s->norm, s->tw, s->img);
   return hipGetLastError();
 }
 
@@ -550,7 +583,6 @@ int cphot_surrogate_create(const cphot_surrogate_desc* desc, cphot_surrogate** o
   if ((e = hipMalloc(&s->partial, (size_t)s->max_blocks * cphot::kMlpParams * 4)) != hipSuccess)
     return fail_free(e, "hipMalloc");
   if ((e = hipMalloc(&s->loss_partial, (size_t)s->max_blocks * 4)) != hipSuccess) return fail_free(e, "hipMalloc");
-  if ((e = hipMalloc(&s->step, sizeof(int))) != hipSuccess) return fail_free(e, "hipMalloc");
   if ((e = hipMalloc(&s->sums, 8 * sizeof(double))) != hipSuccess) return fail_free(e, "hipMalloc");
   if ((e = hipMalloc(&s->tw, sizeof(cphot::TrainWeights))) != hipSuccess) return fail_free(e, "hipMalloc");
   if ((e = hipMalloc(&s->img, sizeof(cphot::MlpImage))) != hipSuccess) return fail_free(e, "hipMalloc");
@@ -572,14 +604,12 @@ int cphot_surrogate_create(const cphot_surrogate_desc* desc, cphot_surrogate** o
   }
   for (int o = 0; o < 4; ++o) nrm[20 + o] = 1.f;
   std::vector<float> zeros(cphot::kMlpParams, 0.f);
-  const int zero_step = 0;
   if ((e = hipMemcpy(s->master, w.data(), w.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(s->m1, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(s->m2, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(s->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(s->step, &zero_step, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      (e = hipMemcpy(s->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
     return fail_free(e, "hipMemcpy");
-  if ((e = pack(s, nullptr, 0)) != hipSuccess) return fail_free(e, "pack");
+  if ((e = pack(s, nullptr)) != hipSuccess) return fail_free(e, "pack");
   if ((e = hipDeviceSynchronize()) != hipSuccess) return fail_free(e, "synchronize");
   *out = s;
   return CPHOT_OK;
@@ -591,7 +621,7 @@ void cphot_surrogate_destroy(cphot_surrogate* s) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(s->device);
   for (void* ptr : {(void*)s->master, (void*)s->m1, (void*)s->m2, (void*)s->norm, (void*)s->partial,
-                    (void*)s->loss_partial, (void*)s->step, (void*)s->sums, (void*)s->tw, (void*)s->img})
+                    (void*)s->loss_partial, (void*)s->sums, (void*)s->tw, (void*)s->img})
     if (ptr) (void)hipFree(ptr);
   (void)hipSetDevice(prev);
   delete s;
@@ -618,6 +648,14 @@ int cphot_surrogate_make_training_set(const cphot_surrogate* s, const cphot_atmo
   p.earth_radius = cphot::atmosphere_earth_radius(atm);
   if (p.geometry == CPHOT_SURROGATE_CURVED && !(p.earth_radius > 1e5 && std::isfinite(p.earth_radius)))
     return sfail(CPHOT_ERR_INVALID_ARG, "a curved surrogate needs the atmosphere's earth_radius");
+  if (p.geometry == CPHOT_SURROGATE_CURVED) {
+    // every ray of the box must meet the observation sphere on its straight chord (the
+    // targets are per metre of that chord): (R + h_e,max) sin(zenith_max) < R + h_obs,min
+    const double c = s->d.in_lo[1], sz = std::sqrt(std::max(0.0, (1.0 - c) * (1.0 + c)));
+    if (!((p.earth_radius + s->d.in_hi[0]) * sz < p.earth_radius + s->d.in_lo[4]))
+      return sfail(CPHOT_ERR_INVALID_ARG, "curved domain box reaches rays that miss the observation sphere: "
+                                          "raise the lowest cos zenith or lower the highest emission height");
+  }
   if (n == 0) return CPHOT_OK;
   for (int j = 0; j < 5; ++j) {
     p.lo[j] = (float)s->d.in_lo[j];
@@ -641,7 +679,7 @@ int cphot_surrogate_fit_normalization(cphot_surrogate* s, const float* Y, int64_
   const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
   hipLaunchKernelGGL(cphot::k_output_sums, dim3(blocks), dim3(256), 0, st, Y, n, s->sums);
   hipLaunchKernelGGL(cphot::k_output_norm, dim3(1), dim3(64), 0, st, (const double*)s->sums, n, s->norm);
-  hipError_t e = pack(s, st, 0);
+  hipError_t e = pack(s, st);
   if (e != hipSuccess) return shfail(e, "normalisation");
   s->normalised = true;
   return CPHOT_OK;
@@ -671,7 +709,9 @@ static int run_steps(cphot_surrogate* s, const float* X, const float* Y, int64_t
     ap.master = s->master;
     ap.m1 = s->m1;
     ap.m2 = s->m2;
-    ap.step = s->step;
+    ap.tw = s->tw;
+    ap.img = s->img;
+    ap.t = s->steps_done;
     ap.total_steps = total_steps;
     ap.lr = lr;
     ap.grad_out = grad_out;
@@ -680,10 +720,7 @@ static int run_steps(cphot_surrogate* s, const float* X, const float* Y, int64_t
     ap.batch = batch;
     ap.update = update;
     hipLaunchKernelGGL(cphot::k_adam, dim3((cphot::kMlpParams + 255) / 256), dim3(256), 0, st, ap);
-    if (update) {
-      hipError_t e = pack(s, st, 1);
-      if (e != hipSuccess) return shfail(e, "pack");
-    }
+    if (update) ++s->steps_done;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return shfail(e, "training step");
   }
@@ -735,7 +772,7 @@ int cphot_surrogate_set_params(cphot_surrogate* s, const float* params, const fl
     e = hipMemcpy(s->norm, norm, cphot::kMlpNorm * 4, hipMemcpyHostToDevice);
     s->normalised = true;
   }
-  if (e == hipSuccess) e = pack(s, nullptr, 0);
+  if (e == hipSuccess) e = pack(s, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   return e == hipSuccess ? CPHOT_OK : shfail(e, "set params");
 }

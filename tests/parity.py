@@ -28,12 +28,12 @@ FLIP_SURV, FLIP_EDGE_REL, FLIP_T, FLIP_LAYER, FLIP_LAMBIN = 2e-5, 1e-4, 0.02, 5e
 MAX_FLIP_FRACTION = 3e-4
 
 
-def device_run(atm_kw, run_kw, seg_np, geom, offsets=None, first_id=0, counters=True):
+def device_run(atm_kw, run_kw, seg_np, geom, offsets=None, first_id=0, counters=True, id_stride=1):
     import torch
     atm = cphot.Atmosphere(**atm_kw)
     det = cphot.make_detector(atm, **run_kw)
     seg, g, off = cphot.upload(seg_np, geom, offsets)
-    S = cphot.make_segments(seg, g, off, first_id=first_id)
+    S = cphot.make_segments(seg, g, off, first_id=first_id, id_stride=id_stride)
     ns = g.shape[0]
     if run_kw.get("detector", "grid") == "grid":
         per = run_kw.get("nx", 100) * run_kw.get("ny", 100)
@@ -52,12 +52,12 @@ def device_run(atm_kw, run_kw, seg_np, geom, offsets=None, first_id=0, counters=
     return out
 
 
-def device_counts(atm_kw, run_kw, seg_np, geom, first_id=0, with_mu=False):
+def device_counts(atm_kw, run_kw, seg_np, geom, first_id=0, with_mu=False, id_stride=1):
     import torch
     atm = cphot.Atmosphere(**atm_kw)
     det = cphot.make_detector(atm, **run_kw)
     seg, g, off = cphot.upload(seg_np, geom)
-    S = cphot.make_segments(seg, g, off, first_id=first_id)
+    S = cphot.make_segments(seg, g, off, first_id=first_id, id_stride=id_stride)
     counts = torch.zeros(S.n, dtype=torch.int32, device="cuda")
     mu = torch.zeros(S.n, dtype=torch.float64, device="cuda") if with_mu else None
     cphot.segment_counts(S, det, counts, mu)
@@ -67,12 +67,12 @@ def device_counts(atm_kw, run_kw, seg_np, geom, first_id=0, with_mu=False):
     return counts.cpu().numpy()
 
 
-def device_records(atm_kw, run_kw, seg_np, geom, first_id=0):
+def device_records(atm_kw, run_kw, seg_np, geom, first_id=0, id_stride=1):
     import torch
     atm = cphot.Atmosphere(**atm_kw)
     det = cphot.make_detector(atm, **run_kw)
     seg, g, off = cphot.upload(seg_np, geom)
-    S = cphot.make_segments(seg, g, off, first_id=first_id)
+    S = cphot.make_segments(seg, g, off, first_id=first_id, id_stride=id_stride)
     counts = torch.zeros(S.n, dtype=torch.int32, device="cuda")
     cphot.segment_counts(S, det, counts)
     offs = torch.cumsum(counts.to(torch.int64), 0) - counts.to(torch.int64)
@@ -98,6 +98,8 @@ def near_boundary(orc, core, atm_kw, run_kw, surv_thr=None):
     thr = np.exp(-orc["tau"]) * p_emit if surv_thr is None else surv_thr
     surv_m = np.minimum(np.abs(orc["u_abs"] - thr), np.abs(orc["u_abs"] - p_emit))
     transport = run_kw.get("transport", "straight")
+    if transport == "curved_walk":  # the same shells, walked shell by shell
+        transport = "curved"
     h_emit = orc["ez"]
     if transport == "curved":
         re = atm_kw.get("earth_radius", 6.371e6)
@@ -140,6 +142,8 @@ def compare_records(gpu, orc, core, atm_kw, run_kw, surv_thr=None):
     du = du[orc["state"] != 4]
     assert du.size == 0 or np.abs(du).max() <= DIR_TOL, np.abs(du).max()
     transport = run_kw.get("transport", "straight")
+    if transport == "curved_walk":
+        transport = "curved"
     layered = transport in ("layered", "curved")
     near, pos_tol, h_emit, lm, lbm = near_boundary(orc, core, atm_kw, run_kw, surv_thr)
     r = np.hypot(orc["x"] - core[0], orc["y"] - core[1])

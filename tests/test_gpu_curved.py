@@ -29,13 +29,19 @@ def _geom(sh):
 
 
 def _orc_run(run_kw, seed):
-    return O.make_run(**{**run_kw, "seed": seed})
+    # the oracle walks the shells one by one for either library transport
+    tr = "curved" if run_kw.get("transport") == "curved_walk" else run_kw.get("transport", "straight")
+    return O.make_run(**{**run_kw, "transport": tr, "seed": seed})
 
 
+@pytest.mark.parametrize("transport", ["curved", "curved_walk"])
 @pytest.mark.parametrize("zen", [0.0, 60.0, 80.0])
-def test_curved_records_match_oracle(zen):
+def test_curved_records_match_oracle(zen, transport):
+    """Closed-form shell sums (with the shell walk for the rays outside their
+    domain) and the shell walk for every ray, each record against the oracle's
+    shell-by-shell FP64 walk."""
     sh = W.make_shower(1500, seed=31 + int(zen), xmax=500.0, zenith_deg=zen, azimuth_deg=40.0, beta="R")
-    run = {**CURVED, "cell": 40.0 if zen < 70 else 150.0, "seed": 13}
+    run = {**CURVED, "transport": transport, "cell": 40.0 if zen < 70 else 150.0, "seed": 13}
     g = parity.device_records(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
     o = O.trace(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 13), sh.seg, core=sh.core, axis=sh.axis)
     flips, rep = parity.compare_records(g, o, sh.core, cases.ATMO_LAYERED, run)
@@ -71,7 +77,7 @@ def test_fluorescence_counts_bit_exact(transport):
     np.testing.assert_array_equal(gf, o["nf"].sum(axis=1))
 
 
-@pytest.mark.parametrize("transport", ["layered", "curved"])
+@pytest.mark.parametrize("transport", ["layered", "curved", "curved_walk"])
 def test_fluorescence_records_match_oracle(transport):
     sh = W.make_shower(800, seed=91, xmax=600.0, zenith_deg=40.0, azimuth_deg=75.0, beta="R", dedx=(0.1, 2.0))
     run = {**CURVED, "transport": transport, "emission": "both", "cell": 200.0, "seed": 16}
@@ -154,3 +160,78 @@ def test_inclined_chunk_at_full_size():
         flips, rep = parity.compare_records(gr, orr, sh.core, cases.ATMO_LAYERED, run)
         assert flips <= 3, rep
         assert (orr["source"] > 0).any()
+
+
+@pytest.mark.parametrize("zen", [30.0, 60.0, 75.0])
+def test_shell_series_serves_most_rays_and_equals_walk(zen):
+    """The closed-form shell sums against the shell walk on the same records
+    (Cherenkov and fluorescence, FP64 grid): the series serve the rays clear of
+    grazing, the rest go through the compacted walk (counted as fallbacks), and
+    the two transports give the same arrival points, optical depths and times
+    within the parity tolerances, and the same bins up to decision flips."""
+    sh = W.make_shower(3000, seed=95 + int(zen), xmax=600.0, zenith_deg=zen, azimuth_deg=110.0, beta="R",
+                       dedx=(0.1, 2.0))
+    run = {**CURVED, "emission": "both", "cell": 50.0, "seed": 19}
+    gs = parity.device_records(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
+    gw = parity.device_records(cases.ATMO_LAYERED, {**run, "transport": "curved_walk"}, sh.seg, _geom(sh))
+    assert len(gs) == len(gw) and len(gs) > 50_000
+    both = (gs["state"] != 1) & (gw["state"] != 1)
+    d = np.hypot(gs["x"][both].astype(np.float64) - gw["x"][both], gs["y"][both].astype(np.float64) - gw["y"][both])
+    r = np.hypot(gw["x"][both].astype(np.float64) - sh.core[0], gw["y"][both].astype(np.float64) - sh.core[1])
+    assert np.all(d <= 1e-4 * np.maximum(r, 10.0) + 0.05), d.max()
+    tau_w = gw["tau"][both].astype(np.float64)
+    assert np.all(np.abs(gs["tau"][both] - tau_w) <= 1e-4 * tau_w + 1e-6)
+    t_w = gw["t"][both].astype(np.float64)
+    assert np.all(np.abs(gs["t"][both] - t_w) <= 1e-4 * np.abs(t_w) + 0.01)
+    assert (gs["state"] != gw["state"]).mean() < 1e-3
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    seg, gg, off = cphot.upload(sh.seg, _geom(sh))
+    S = cphot.make_segments(seg, gg, off)
+    out = {}
+    for tr in ("curved", "curved_walk"):
+        bins = torch.zeros(300 * 300, dtype=torch.float64, device="cuda")
+        cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+        cphot.propagate(S, cphot.make_detector(atm, **{**run, "transport": tr}), bins, None, cnt)
+        torch.cuda.synchronize()
+        out[tr] = (bins.cpu().numpy(), cnt.cpu().numpy())
+    (bs, cs), (bw, cw) = out["curved"], out["curved_walk"]
+    np.testing.assert_array_equal(cs[:4], cw[:4])
+    assert cs[3] == cs[4] + cs[5] + cs[6] + cs[7]
+    fb = cs[cphot.COUNTERS.index("surrogate_fallback")] / cs[3]
+    print(f"zenith {zen}: {cs[3]} records, {fb:.3f} walked, max offset {d.max():.3e} m")
+    assert 0.0 < fb < 0.2
+    assert cw[cphot.COUNTERS.index("surrogate_fallback")] == 0
+    assert np.abs(bs - bw).sum() <= max(6, 2e-4 * bw.sum())
+
+
+def test_inclined_subset_every_1000th_segment():
+    """The deterministic subset of the inclined chunk on which the CPU baseline is
+    timed (global segment ids = 0 mod 1000, passed with id_stride 1000 so that each
+    segment keeps its id and photons): counts of every segment bit-exact, counters
+    and FP64-grid bins against the oracle up to decision flips, and the first
+    segments' records one by one."""
+    sh = W.workload_inclined_chunk(0)
+    sub = {k: v[::1000] for k, v in sh.seg.items()}
+    run = {**W.RUN_INCLINED, "seed": 5}
+    orun = _orc_run(run, 5)
+    oatm = parity.oracle_atm(cases.ATMO_LAYERED)
+    g = parity.device_counts(cases.ATMO_LAYERED, run, sub, _geom(sh), first_id=sh.first_id, id_stride=1000)
+    o = O.segment_counts(oatm, orun, sub, first_id=sh.first_id, id_stride=1000)
+    np.testing.assert_array_equal(g, o["n"] + o["nf"].sum(1))
+    gb, _, gc = parity.device_run(cases.ATMO_LAYERED, run, sub, _geom(sh), first_id=sh.first_id, id_stride=1000)
+    ob, _, oc = O.propagate(oatm, orun, sub, _geom(sh), first_id=sh.first_id, threads=8, id_stride=1000)
+    gc = gc.astype(np.uint64)
+    np.testing.assert_array_equal(gc[:4], oc[:4])
+    assert gc[3] == gc[4] + gc[5] + gc[6] + gc[7] and gc[3] > 600_000
+    assert ob.sum() > 200_000
+    # every record of the subset: differences only next to a decision boundary, and
+    # the bins differ by at most the records that flipped
+    gr = parity.device_records(cases.ATMO_LAYERED, run, sub, _geom(sh), first_id=sh.first_id, id_stride=1000)
+    orr = O.trace(oatm, orun, sub, core=sh.core, axis=sh.axis, first_id=sh.first_id, id_stride=1000)
+    np.testing.assert_array_equal(gr["seg"], orr["seg"])
+    flips, rep = parity.compare_records(gr, orr, sh.core, cases.ATMO_LAYERED, run)
+    print(rep)
+    assert flips <= max(3, parity.MAX_FLIP_FRACTION * len(orr))
+    diff = int(np.abs(gb.astype(np.int64) - ob.astype(np.int64)).sum())
+    print(f"subset: {len(orr)} records, {flips} flips, bin L1 difference {diff} of {int(ob.sum())}")
+    assert diff <= 2 * flips
