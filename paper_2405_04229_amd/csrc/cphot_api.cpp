@@ -258,7 +258,9 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     p.lambins = a->dev.lambins;
     p.moments = a->dev.moments ? a->dev.moments + (size_t)p.obs_layer * d.n_layers * 5 : nullptr;
     p.series_tmax = a->dev.moments ? a->dev.series_tmax : 0.f;
-    if (det->transport == CPHOT_TRANSPORT_CURVED && a->dev.shells) {
+    // closed-form shell sums: the curved exact transport, and the exact tracer
+    // behind the curved surrogate and table
+    if ((det->transport == CPHOT_TRANSPORT_CURVED || curved_sur || curved_tab) && a->dev.shells) {
       p.shells = a->dev.shells + (size_t)p.obs_layer * d.n_layers * cphot::kShellRow;
       p.shell_tmax = a->dev.shell_tmax;
       p.shell_rho = (float)cphot::kShellRhoMax;

@@ -145,6 +145,10 @@ constexpr int kTransportCurvedSurrogate = 16;
 constexpr int kTransportCurvedTable = 17;
 // the shell walk for every photon (CPHOT_TRANSPORT_CURVED_WALK)
 constexpr int kTransportCurvedWalk = CPHOT_TRANSPORT_CURVED_WALK;
+// the closed-form shell sums, the shell walk in place for rays outside their
+// domain: the exact tracer behind the curved surrogate and table (their deferred
+// records are already compacted, so nothing is deferred a second time)
+constexpr int kTransportCurvedExact = 18;
 // Correction table: device view, the atmosphere it was built from, its h_obs.
 TableView table_view(const cphot_table* t);
 const cphot_atmosphere* table_atmosphere(const cphot_table* t);

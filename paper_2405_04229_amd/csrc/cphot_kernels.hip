@@ -411,7 +411,8 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     kb = min(max(kb, 0), p.n_lam - 1);
   }
   if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED || TRANSPORT == kTransportCurvedWalk ||
-                TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable) {
+                TRANSPORT == kTransportCurvedExact || TRANSPORT == kTransportCurvedSurrogate ||
+                TRANSPORT == kTransportCurvedTable) {
     // height above the sphere R without subtracting R: (x^2 + y^2 + z (2R + z)) / (|P - C| + R)
     const float Rf = (float)p.earth_radius;
     const float qz = Pz + Rf;
@@ -492,13 +493,19 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
         o.state = kStateDeferred;  // outside the domain: traced exactly in a compacted pass
         return;
       }
-      if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED) {
-        // closed-form shell sums; rays outside their domain are walked in a compacted pass
+      if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED || TRANSPORT == kTransportCurvedExact) {
+        // closed-form shell sums; rays outside their domain are walked, in a
+        // compacted pass (CURVED) or in place (records that are compacted already)
         if (!curved_series<NEED_TIME>(s_lay, p.shells, s_lam[kb], p.dh, p.n_layers, p.obs_layer, p.h_obs,
                                       p.earth_radius, p.shell_rho, p.shell_tmax, Px, Py, Pz, h0, ux, uy, uz, axx,
                                       axy, axz, cw)) {
-          o.state = kStateDeferred;
-          return;
+          if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED) {
+            o.state = kStateDeferred;
+            return;
+          } else {
+            curved_walk<NEED_TIME>(s_lay, s_lam[kb], p.dh, p.n_layers, p.h_obs, p.earth_radius, Px, Py, Pz, h0,
+                                   ux, uy, uz, axx, axy, axz, cw);
+          }
         }
       } else {
         curved_walk<NEED_TIME>(s_lay, s_lam[kb], p.dh, p.n_layers, p.h_obs, p.earth_radius, Px, Py, Pz, h0, ux, uy,
@@ -798,10 +805,9 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
   // exact transport behind a surrogate: records outside the network's domain
   constexpr int kExact =
       (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == CPHOT_TRANSPORT_TABLE)       ? CPHOT_TRANSPORT_LAYERED
-      : (TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable ||
-         TRANSPORT == CPHOT_TRANSPORT_CURVED)
-          ? kTransportCurvedWalk
-          : TRANSPORT;
+      : (TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable) ? kTransportCurvedExact
+      : (TRANSPORT == CPHOT_TRANSPORT_CURVED)                                               ? kTransportCurvedWalk
+                                                                                            : TRANSPORT;
   // per-segment state for the record loop, one slot per segment of the tile:
   // q0 = start point, cos(theta); q1 = end - start, sin(theta) (DISPERSIVE: the
   // terms of beta n(lambda) - 1 in place of the angle); q2 = rotation
