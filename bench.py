@@ -1,26 +1,33 @@
 """Benchmark: photons propagated per second on one MI355X.
 
 Headline step = one pass of the whole photon path over one batch: cphot_propagate
-over the telescope workload (1e6 track segments of a 20-degree gamma-like
-shower, refraction through 100 homogeneous layers with Rayleigh + aerosol
-absorption on 64 wavelength bins, bunches of 5 photons, 100 bounding spheres of
-6 m on a 150 m grid, 1 ns arrival-time histograms), bins and counters zeroed
-first. Inputs are resident in HBM before timing starts.
+over the resident chunk of the large inclined shower (1e7 track segments of a
+60-degree shower, curved Earth, Cherenkov emission plus isotropic fluorescence in
+three bands, FP64 bins on a 1000 x 1000 ground grid of 10 m), exact transport
+(closed-form shell sums, the shell walk where they do not hold), bins and
+counters zeroed first. Inputs are resident in HBM before timing starts.
 
 The same JSON line carries:
-- roofline: the dominant kernel against the VALU issue peak;
-- cpu_baseline: the FP64 CPU oracle on the same workload on the host cores;
-- surrogate: the transport network trained on the GPU from 1e7 exact-tracer
-  photons, then run on the same workload, with its per-bin density error against
-  the exact tracer (same photons) and the straight line's for comparison; beside
-  it the thesis's own fast method, the interpolated correction table;
+- roofline: the headline kernel against the VALU issue peak, with the algorithmic
+  work of the iterative shell method and, from the kept profile, the instructions
+  the kernel actually issues;
+- cpu_baseline: the FP64 CPU oracle on the deterministic subset of the same chunk
+  (global segment ids = 0 mod 1000), one thread and all host cores, beside the
+  GPU's run of that subset and its error per output against the oracle;
+- inclined: beside the headline, the plain shell walk (the iterative tracer), the
+  transport network trained on the GPU (same photons, bins compared cell by
+  cell), the interpolated correction table, and the whole 1e8-segment shower
+  streamed from host memory;
+- telescope: the refracting telescope workload (1e6 segments, bunches of 5, 100
+  bounding spheres with 1 ns time histograms) with its own roofline, the
+  data-reduction cuts, detector efficiency with pre-emission reduction, Poisson
+  counts, the dispersive spectrum, the planar network and table;
 - batched: 256 showers of uneven size in one captured launch per step, launch
-  shape and bunch picked by the autotuner;
-- inclined: the large inclined shower (curved Earth, Cherenkov + fluorescence,
-  FP64 bins): one 1e7-segment chunk resident in HBM, then the whole 1e8-segment
-  shower streamed from host memory in 1e7-segment chunks.
+  shape picked by the autotuner among the bunch sizes whose bins stay within 1 %
+  of bunch 1.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -33,42 +40,52 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X public figures: 256 CUs at 2.4 GHz and 157.3 TFLOP/s FP32 vector, an FMA
-# counted as two flops: 128 FP32 lane-operations per CU per clock. (The counters
-# show the exact kernel issuing more than one wave64 VALU instruction per CU per
-# clock without packed FP32, so a 64-lane ceiling would understate the peak.)
+# counted as two flops: 128 FP32 lane-operations per CU per clock (the published
+# peak; it needs two wave64 VALU instructions per CU per clock). One wave64 VALU
+# instruction per CU per clock is 64 lane-operations: reported beside it.
 PEAK_VALU_LANE_OPS = 256 * 128 * 2.4e9
+PEAK_WAVE64_ISSUE = 256 * 64 * 2.4e9
 PEAK_HBM = 8.0e12
 
-# Algorithmic VALU lane-slots per unit of work (counted from the method's steps;
-# 32-bit multiplies and transcendentals weighted 4 as quarter-rate operations).
+# Algorithmic VALU lane-slots per unit of work, counted from the method's steps
+# (32-bit multiplies and transcendentals weighted 4 as quarter-rate operations):
+# a segment's FP64 yield, Philox word and rotation bisector; a record's Philox
+# block, uniforms, cone, rotation, final leg, detector test and exp(-tau); one
+# layer or shell crossing of the iterative refraction (Sec. 3.4.2: chord, Snell
+# update, optical depth, delay terms); the FP64 arrival point on the observation
+# sphere of the curved geometry (about 20 FP64 operations, weight 2).
 SLOTS_PER_SEGMENT = 350.0
 SLOTS_PER_RECORD_BASE = 320.0
-SLOTS_PER_LAYER_CROSSING = 22.0
-SLOTS_PER_SERIES = 60.0  # closed-form layer sums: five Horner polynomials, delay terms, final direction
-SERIES_TAN2_MAX = 9.0    # the series bound of the standard atmospheres (tan^2 zenith <= 9)
+SLOTS_PER_CROSSING = 24.0
+SLOTS_FP64_ARRIVAL = 40.0
 SEGMENT_BYTES = 32.0
+SEGMENT_BYTES_DEDX = 36.0
 
 METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density error"
 
-# HBM bytes per launch of the exact telescope kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# scaled by a plain copy's factors (2.00, 1.00); valid only for the sources and launch shape they
-# were taken on (sha256 prefixes; block size, grid, LDS counts), else reported as null.
-TRAFFIC_BYTES = 16270.0 * 1024 * 2.00 + 144.0 * 1024 * 1.00
-TRAFFIC_SOURCES = {"cphot_kernels.hip": "3d4b26c4fd8431b7", "cphot_device.h": "412f1e9c31f153d6",
-                   "cphot_internal.h": "e7ff53602758d13b", "cphot_api.cpp": "5fd5435c41b40305"}
-TRAFFIC_SHAPE = (512, 512, 1)
+# Measured facts of a kernel at one launch shape, from rocprofv3 (VALU instructions
+# issued per launch; HBM bytes per launch = FETCH_SIZE and WRITE_SIZE scaled by a
+# plain copy's factors), valid only for the sources and shape they were taken on
+# (sha256 prefixes of the kernel sources), else reported as null.
+KERNEL_SOURCES = ("cphot_kernels.hip", "cphot_device.h", "cphot_internal.h", "cphot_mlp.h")
+MEASURED = {}
 
 
-def traffic_if_current(tune):
-    import hashlib
-    if (tune["block_size"], tune["grid_blocks"], tune["lds_hist"]) != TRAFFIC_SHAPE:
+def sources_sha():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_04229_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_if_current(key, tune):
+    m = MEASURED.get(key)
+    if not m or m["sha"] != sources_sha():
         return None
-    for name, want in TRAFFIC_SOURCES.items():
-        path = os.path.join(ROOT, "paper_2405_04229_amd", "csrc", name)
-        with open(path, "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest()[:16] != want:
-                return None
-    return TRAFFIC_BYTES
+    if (tune["block_size"], tune["grid_blocks"], tune["lds_hist"]) != tuple(m["shape"]):
+        return None
+    return m
 
 
 def log(msg):
@@ -92,7 +109,7 @@ def time_steps(torch, step, steps, warmup, stream):
 
 def density_error(s, e, min_count=1000):
     """Worst relative error over bins with >= min_count exact photons (and, as the
-    statistical resolution of a 1000-photon bin is itself ~1 %, over bins with
+    statistical resolution of a 1000-photon bin is itself ~3 %, over bins with
     >= 10 x min_count), and the global L1 error sum|s - e| / sum e."""
     s = np.asarray(s, dtype=np.float64).ravel()
     e = np.asarray(e, dtype=np.float64).ravel()
@@ -102,48 +119,352 @@ def density_error(s, e, min_count=1000):
         out["worst_bin" + key] = float(np.max(np.abs(s[m] - e[m]) / e[m])) if m.any() else None
         out["bins_compared" + key] = int(m.sum())
     out["min_count"] = min_count
+    out["within_1pct"] = bool(out["l1"] <= 0.01 and (out["worst_bin"] is None or out["worst_bin"] <= 0.01))
     return out
 
 
-def cpu_baseline(sh, run, atmo, target_s=12.0):
-    """The FP64 oracle on the same workload, all host cores; whole passes are
-    repeated until about target_s of CPU work has been timed."""
-    from oracle import oracle as O
-    atm = O.Atmosphere(**atmo)
-    orun = O.make_run(**run)
-    geom = [[*sh.core, *sh.axis]]
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    threads = max(1, min(threads, 64))
-    n = 20_000
-    while True:  # grow the sample until one pass takes a measurable time
-        seg = {k: v[:n] for k, v in sh.seg.items()}
-        t0 = time.perf_counter()
-        _, _, cnt = O.propagate(atm, orun, seg, geom, threads=threads)
-        dt = time.perf_counter() - t0
-        if dt >= target_s / 4 or n >= sh.n:
-            break
-        n = min(sh.n, int(n * max(2.0, target_s / max(dt, 1e-3) * 0.5)))
-    passes, total = 1, dt
-    while total < target_s and passes < 100:
-        t0 = time.perf_counter()
-        O.propagate(atm, orun, seg, geom, threads=threads)
-        total += time.perf_counter() - t0
-        passes += 1
-    photons = float(cnt[3]) * run["bunch"]
-    return {"value": photons * passes / total, "unit": "photons/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of {sh.n} segments (same ids and random streams), {int(cnt[3])} records per "
-                      f"pass, {passes} passes in {total:.1f} s"}
+def radial_height(x, y, z, R=6.371e6):
+    x, y, z = (np.asarray(a, dtype=np.float64) for a in (x, y, z))
+    return (x * x + y * y + z * (2 * R + z)) / (np.sqrt(x * x + y * y + (z + R) ** 2) + R)
 
 
-def tuned_detector(cphot, S, atm, run, bins, th, cnt, stream, **extra):
+def traced_records(torch, cphot, seg_np, geom, det, first_id=0, id_stride=1):
+    sg, sgg, _ = cphot.upload(seg_np, geom)
+    SS = cphot.make_segments(sg, sgg, None, first_id=first_id, id_stride=id_stride)
+    counts = torch.zeros(SS.n, dtype=torch.int32, device="cuda")
+    cphot.segment_counts(SS, det, counts)
+    offs = torch.cumsum(counts.to(torch.int64), 0) - counts.to(torch.int64)
+    tot = int(counts.sum().item())
+    rec = torch.zeros(max(tot, 1) * cphot.RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    cphot.trace_records(SS, det, offs.contiguous(), rec)
+    torch.cuda.synchronize()
+    return cphot.records_to_numpy(rec.cpu())[:tot]
+
+
+def crossing_profile(torch, cphot, seg_np, geom, det, h_obs, dh, n_layers, curved, n=20000):
+    """Mean number of layer (planar) or shell (curved) boundaries a record's ray
+    crosses on its way down to the observation level, over the records of the
+    first n segments (upward records and those emitted below h_obs cross none):
+    the iterative method's work per record."""
+    sample = {k: v[:n] for k, v in seg_np.items()}
+    r = traced_records(torch, cphot, sample, geom, det)
+    s = r["seg"].astype(np.int64)
+    xm = 0.5 * (sample["x0"].astype(np.float64) + sample["x1"])
+    ym = 0.5 * (sample["y0"].astype(np.float64) + sample["y1"])
+    zm = 0.5 * (sample["z0"].astype(np.float64) + sample["z1"])
+    h = radial_height(xm, ym, zm) if curved else zm
+    start = np.minimum((h[s] // dh).astype(np.int64), n_layers - 1)
+    obs = int(h_obs // dh)
+    down = r["state"] != 1
+    cross = np.where(down, np.maximum(start - obs, 0), 0)
+    return float(cross.mean()) if len(cross) else 0.0, len(r)
+
+
+def tuned_detector(cphot, S, atm, run, bins, th, cnt, stream, reps=3, **extra):
     """Detector with the autotuner's launch shape for this workload; the bunch
     stays the workload's own (it defines the workload, not the launch)."""
     det0 = cphot.make_detector(atm, **run, **extra)
     t0 = time.perf_counter()
-    tune = cphot.autotune(S, det0, bins, th, cnt, bunches=[run["bunch"]], reps=3, stream=stream)
+    tune = cphot.autotune(S, det0, bins, th, cnt, bunches=[run["bunch"]], reps=reps, stream=stream)
     tune["tune_s"] = time.perf_counter() - t0
     shape = {k: tune[k] for k in ("block_size", "grid_blocks", "lds_hist", "hist_window")}
     return cphot.make_detector(atm, **run, **shape, **extra), tune
+
+
+def roofline_entry(kernel, kern_ms, n_seg, seg_bytes, records, crossings, fp64_arrival, tune, key):
+    """Achieved algorithmic lane-operations per second of one launch against the
+    VALU peak; with a current profile, the issued VALU lane-instructions too."""
+    per_record = SLOTS_PER_RECORD_BASE + SLOTS_PER_CROSSING * crossings + (SLOTS_FP64_ARRIVAL if fp64_arrival else 0.0)
+    slots = n_seg * SLOTS_PER_SEGMENT + records * per_record
+    achieved = slots / (kern_ms * 1e-3)
+    m = measured_if_current(key, tune)
+    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "Tlane-ops/s",
+           "frac": achieved / PEAK_VALU_LANE_OPS, "frac_vs_wave64_issue": achieved / PEAK_WAVE64_ISSUE,
+           "traffic": m["hbm_bytes"] if m else None,
+           "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's)",
+           "kernel": kernel, "kernel_ms": kern_ms, "tuning": tune,
+           "algorithmic_slots_per_launch": slots, "slots_per_record": per_record,
+           "crossings_per_record": crossings,
+           "algorithmic_hbm_bytes": n_seg * seg_bytes,
+           "hbm_gbps_algorithmic": n_seg * seg_bytes / (kern_ms * 1e-3) / 1e9,
+           "model": "segment 350 slots; record 320 + 24 per layer/shell crossing of the iterative method"
+                    + (" + 40 for the FP64 arrival" if fp64_arrival else "")}
+    if m:
+        issued = m["valu_insts"] * 64.0
+        out["isa"] = {"valu_lane_instructions_per_launch": issued,
+                      "valu_lane_instructions_per_record": issued / max(records, 1.0),
+                      "achieved": issued / (kern_ms * 1e-3) / 1e12,
+                      "frac": issued / (kern_ms * 1e-3) / PEAK_VALU_LANE_OPS,
+                      "frac_vs_wave64_issue": issued / (kern_ms * 1e-3) / PEAK_WAVE64_ISSUE,
+                      "profile": m["profile"]}
+    return out
+
+
+# ------------------------------------------------------------------------------ inclined shower
+
+def run_path(torch, cphot, S, det, nbins, stream, steps, warmup, dtype):
+    bins = torch.zeros(nbins, dtype=dtype, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+
+    def step(ev):
+        bins.zero_()
+        cnt.zero_()
+        if ev is not None:
+            ev[0].record(stream)
+        cphot.propagate(S, det, bins, None, cnt, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    ms, kern = time_steps(torch, step, steps, warmup, stream)
+    return ms, kern, bins.cpu().numpy(), cnt.cpu().numpy()
+
+
+def bench_inclined(torch, cphot, W, args, stream):
+    """The resident chunk through the curved shells: the exact step (headline),
+    its roofline, then the plain walk, the network, the table and the streamed shower."""
+    t0 = time.perf_counter()
+    sh = W.workload_inclined_chunk(0, beta=args.beta)
+    log(f"inclined chunk generated in {time.perf_counter() - t0:.1f} s")
+    geom = np.array([[*sh.core, *sh.axis]])
+    seg, g, off = cphot.upload(sh.seg, geom)
+    S = cphot.make_segments(seg, g, off, first_id=sh.first_id)
+    atm = cphot.Atmosphere(**W.ATMO_LAYERED)
+    run = {**W.RUN_INCLINED, "seed": 5}
+    nb = run["nx"] * run["ny"]
+    bins = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    det, tune = tuned_detector(cphot, S, atm, run, bins, None, cnt, stream, reps=2)
+    log(f"inclined autotune: {tune}")
+    steps = max(5, args.steps // 2)
+    ms, kern, exact_bins, c = run_path(torch, cphot, S, det, nb, stream, steps, args.warmup, torch.float64)
+    records = float(c[3])
+    photons = records * run["bunch"]
+    log(f"inclined exact: {ms:.3f} ms/step, kernel {kern:.3f} ms, {records:.4g} records")
+    dh = W.ATMO_LAYERED["h_top"] / W.ATMO_LAYERED["n_layers"]
+    cross, _ = crossing_profile(torch, cphot, sh.seg, geom, det, run["h_obs"], dh, W.ATMO_LAYERED["n_layers"], True)
+    roof = roofline_entry(f"k_propagate<{tune['block_size']},CURVED,GRID,PROPAGATE>", kern, float(sh.n),
+                          SEGMENT_BYTES_DEDX, records, cross, True, tune, "inclined_curved")
+    head = {"value": photons / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": kern, "records": records,
+            "photons": photons, "segments": sh.n, "fluorescence_records": float(c[10]),
+            "records_walked": float(c[9]), "photons_binned": float(c[8]), "tuning": tune}
+    extra = {}
+    # the plain exact tracer: every ray walked shell by shell (Sec. 3.4.2 over shells)
+    det_w, tune_w = tuned_detector(cphot, S, atm, {**run, "transport": "curved_walk"}, bins, None, cnt, stream, reps=1)
+    ms_w, kern_w, b_w, c_w = run_path(torch, cphot, S, det_w, nb, stream, max(3, steps // 2), 1, torch.float64)
+    extra["walk"] = {"value": float(c_w[3]) * run["bunch"] / (ms_w * 1e-3), "unit": "photons/s", "ms_per_step": ms_w,
+                     "kernel_ms": kern_w, "tuning": tune_w, "bins_identical_to_headline": bool(
+                         np.array_equal(b_w, exact_bins)),
+                     "bins_diff_l1": float(np.abs(b_w - exact_bins).sum()),
+                     "note": "the iterative tracer: every ray walked shell by shell"}
+    log(f"inclined walk: {ms_w:.3f} ms/step")
+    if not args.no_surrogate:
+        sur = cphot.Surrogate(W.SURROGATE_CURVED_LO, W.SURROGATE_CURVED_HI, max_batch=4096, init_seed=2,
+                              geometry="curved")
+        t0 = time.perf_counter()
+        X, Y = sur.make_training_set(atm, args.train_samples, seed=1005)
+        sur.fit_normalization(Y)
+        loss = sur.train(X, Y, batch=4096, steps=2 * args.train_steps, lr=3e-3)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        del X, Y
+        det_s, tune_s = tuned_detector(cphot, S, atm, {**run, "transport": "surrogate"}, bins, None, cnt, stream,
+                                       reps=1, surrogate=sur)
+        ms_s, kern_s, b_s, c_s = run_path(torch, cphot, S, det_s, nb, stream, max(3, steps // 2), 1, torch.float64)
+        extra["surrogate"] = {
+            "value": float(c_s[3]) * run["bunch"] / (ms_s * 1e-3), "unit": "photons/s", "ms_per_step": ms_s,
+            "kernel_ms": kern_s, "speedup_vs_exact": ms / ms_s, "speedup_vs_walk": ms_w / ms_s,
+            "density_error_vs_exact": density_error(b_s, exact_bins),
+            "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0), "tuning": tune_s,
+            "training": {"samples": args.train_samples, "steps": 2 * args.train_steps, "train_s": train_s,
+                         "final_loss": float(loss[-100:].mean().item())},
+            "domain": {"lo": list(W.SURROGATE_CURVED_LO), "hi": list(W.SURROGATE_CURVED_HI)}}
+        log(f"inclined surrogate: {extra['surrogate']['value']:.3e} photons/s, "
+            f"worst bin {extra['surrogate']['density_error_vs_exact']['worst_bin']}")
+        sur.close()
+    t0 = time.perf_counter()
+    tab = cphot.Table(atm, run["h_obs"], "curved", n_c=512, c_lo=0.15)
+    tab_build_s = time.perf_counter() - t0
+    det_t, tune_t = tuned_detector(cphot, S, atm, {**run, "transport": "table"}, bins, None, cnt, stream, reps=1,
+                                   table=tab)
+    ms_t, kern_t, b_t, c_t = run_path(torch, cphot, S, det_t, nb, stream, max(3, steps // 2), 1, torch.float64)
+    extra["table"] = {"value": float(c_t[3]) * run["bunch"] / (ms_t * 1e-3), "unit": "photons/s", "ms_per_step": ms_t,
+                      "kernel_ms": kern_t, "speedup_vs_exact": ms / ms_t, "speedup_vs_walk": ms_w / ms_t,
+                      "density_error_vs_exact": density_error(b_t, exact_bins),
+                      "fallback_fraction": float(c_t[9]) / max(float(c_t[3]), 1.0), "build_s": tab_build_s,
+                      "tuning": tune_t,
+                      "note": "interpolation tracing (Sec. 4.4.1), curved shells: 4 heights per shell x 512 "
+                              "tan-zenith nodes up to 81 deg"}
+    log(f"inclined table: {extra['table']['value']:.3e} photons/s")
+    if args.inclined_chunks > 0:
+        chunks = [sh] + [W.workload_inclined_chunk(k, beta=args.beta) for k in range(1, args.inclined_chunks)]
+        streamer = cphot.Streamer(sh.n)
+        bins.zero_()
+        cnt.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for ch in chunks:
+            streamer.run(ch.seg, g, det, bins, None, cnt, first_id=ch.first_id, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cs = cnt.cpu().numpy()
+        streamer.close()
+        extra["streamed"] = {"value": float(cs[3]) * run["bunch"] / dt, "unit": "photons/s", "seconds": dt,
+                             "segments": int(sum(ch.n for ch in chunks)), "chunks": len(chunks),
+                             "records": float(cs[3]), "fluorescence_records": float(cs[10]),
+                             "photons_binned": float(cs[8]),
+                             "note": "host-resident segments, pinned double-buffered copies overlapped with "
+                                     "propagation (PCIe-inclusive)"}
+        log(f"inclined streamed: {extra['streamed']['value']:.3e} photons/s over {len(chunks)} chunks")
+        del chunks
+    ctx = {"sh": sh, "geom": geom, "det": det, "run": run, "atm": atm}
+    return head, roof, extra, ctx
+
+
+# ------------------------------------------------------------------------------ CPU baseline
+
+def output_errors(gpu, orc, core, h_obs, dh, curved, lam_range=(300.0, 600.0), n_lam=64):
+    """Largest differences of the GPU's records from the oracle's on the outputs
+    both sides compute, over records that reached the observation level with the
+    same decisions (state, bin) and start away from a layer boundary."""
+    assert len(gpu) == len(orc)
+    same = (gpu["state"] == orc["state"]) & (gpu["bin"] == orc["bin"])
+    arrived = (orc["state"] == 0) | (orc["state"] == 2)
+    h_e = radial_height(orc["ex"], orc["ey"], orc["ez"]) if curved else orc["ez"]
+    away = np.abs(h_e / dh - np.round(h_e / dh)) * dh > 5e-3
+    # a wavelength next to an absorption-bin edge may fall into the neighbouring bin
+    lb = (orc["lambda"] - lam_range[0]) / (lam_range[1] - lam_range[0]) * n_lam
+    away &= np.abs(lb - np.round(lb)) > 1e-4
+    live = same & arrived & away
+    r = np.hypot(orc["x"] - core[0], orc["y"] - core[1])
+    dpos = np.hypot(gpu["x"] - orc["x"], gpu["y"] - orc["y"])
+    dt = np.abs(gpu["t"] - orc["t"])
+    dtau = np.abs(gpu["tau"] - orc["tau"])
+    ddir = np.max(np.abs(np.stack([gpu["dx"] - orc["dx"], gpu["dy"] - orc["dy"], gpu["dz"] - orc["dz"]], 1)), 1)
+    L = live
+
+    def mx(a):
+        return float(a.max()) if a.size else 0.0
+    return {"records": int(len(orc)), "records_compared": int(L.sum()),
+            "decision_flips": int((~same).sum()),
+            "position_abs_m": mx(dpos[L]), "position_rel": mx(dpos[L] / np.maximum(r[L], 10.0)),
+            "time_abs_ns": mx(dt[L]), "time_rel": mx(dt[L] / np.maximum(np.abs(orc["t"][L]), 1e-9)),
+            "tau_abs": mx(dtau[L]), "tau_rel": mx(dtau[L] / np.maximum(orc["tau"][L], 1e-12)),
+            "direction_abs": mx(ddir), "wavelength_rel": mx(np.abs(gpu["lambda"] - orc["lambda"]) / orc["lambda"]),
+            "survival_uniform_identical": bool(np.array_equal(gpu["u_abs"].astype(np.float64), orc["u_abs"]))}
+
+
+def cpu_baseline(torch, cphot, W, ctx, target_s=12.0):
+    """The FP64 oracle on the deterministic subset of the inclined chunk (segment
+    ids = 0 mod 1000): one thread, then all host cores; the GPU runs the same
+    subset for parity (bins, counts, expected counts, every record's outputs)."""
+    from oracle import oracle as O
+    sh, geom, det, run = ctx["sh"], ctx["geom"], ctx["det"], ctx["run"]
+    stride = 1000
+    sub = {k: np.ascontiguousarray(v[::stride]) for k, v in sh.seg.items()}
+    oatm = O.Atmosphere(**W.ATMO_LAYERED)
+    orun = O.make_run(**run)
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(threads, 64))
+    t0 = time.perf_counter()
+    ob, _, oc = O.propagate(oatm, orun, sub, geom, first_id=sh.first_id, threads=1, id_stride=stride)
+    t1 = time.perf_counter() - t0
+    photons = float(oc[3]) * run["bunch"]
+    passes, total = 0, 0.0
+    while total < target_s and passes < 200:
+        t0 = time.perf_counter()
+        O.propagate(oatm, orun, sub, geom, first_id=sh.first_id, threads=threads, id_stride=stride)
+        total += time.perf_counter() - t0
+        passes += 1
+    out = {"value": photons * passes / total, "unit": "photons/s", "cores": threads, "kind": "oracle",
+           "per_core": photons / t1, "single_thread_s": t1,
+           "sample": f"segments with global id = 0 mod {stride} of the 1e7-segment inclined chunk ({len(sub['x0'])} "
+                     f"segments, the same ids and random streams as in the full launch), {int(oc[3])} records per "
+                     f"pass; one thread {t1:.2f} s, {threads} threads {passes} passes in {total:.1f} s"}
+    # the GPU on the same subset
+    seg, g, off = cphot.upload(sub, geom)
+    S = cphot.make_segments(seg, g, off, first_id=sh.first_id, id_stride=stride)
+    bins = torch.zeros(run["nx"] * run["ny"], dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    cphot.propagate(S, det, bins, None, cnt)
+    counts = torch.zeros(S.n, dtype=torch.int32, device="cuda")
+    mu = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    cphot.segment_counts(S, det, counts, mu)
+    torch.cuda.synchronize()
+    gb, gc = bins.cpu().numpy(), cnt.cpu().numpy().astype(np.uint64)
+    osc = O.segment_counts(oatm, orun, sub, first_id=sh.first_id, id_stride=stride)
+    grec = traced_records(torch, cphot, sub, geom, det, first_id=sh.first_id, id_stride=stride)
+    orec = O.trace(oatm, orun, sub, core=sh.core, axis=sh.axis, first_id=sh.first_id, id_stride=stride)
+    dh = W.ATMO_LAYERED["h_top"] / W.ATMO_LAYERED["n_layers"]
+    errs = output_errors(grec, orec, sh.core, run["h_obs"], dh, True, n_lam=W.ATMO_LAYERED["n_lam"])
+    ob0 = ob[0].astype(np.float64)
+    errs.update({"records_generated_equal": bool(gc[3] == oc[3]),
+                 "fluorescence_records_equal": bool(int(gc[10]) == int(osc["nf"].sum())),
+                 "counts_identical": bool(np.array_equal(counts.cpu().numpy(), osc["n"] + osc["nf"].sum(1))),
+                 "expected_count_max_abs_diff": float(np.max(np.abs(mu.cpu().numpy() - osc["mu"]))),
+                 "bins_l1_diff": float(np.abs(gb - ob0).sum()), "bins_photons": float(ob0.sum()),
+                 "bins_cells_differing": int((gb != ob0).sum())})
+    out["gpu_subset_parity"] = errs
+    return out
+
+
+# ------------------------------------------------------------------------------ telescope
+
+def bench_telescope(torch, cphot, W, args, stream):
+    run = {**W.RUN_TELESCOPE, "seed": 2}
+    sh = W.workload_telescope(args.beta)
+    geom = np.array([[*sh.core, *sh.axis]])
+    atm = cphot.Atmosphere(**W.ATMO_LAYERED)
+    seg, g, off = cphot.upload(sh.seg, geom)
+    S = cphot.make_segments(seg, g, off)
+    nsph = run["snx"] * run["sny"]
+    # the step's outputs in one buffer, cleared by one fill per step
+    nb, nc, nt = nsph * 8, cphot.NCOUNTERS * 8, nsph * (run["n_t"] + 1) * 4
+    out_buf = torch.zeros(nb + nc + nt, dtype=torch.uint8, device="cuda")
+    bins = out_buf[:nb].view(torch.int64)
+    cnt = out_buf[nb:nb + nc].view(torch.int64)
+    th = out_buf[nb + nc:].view(torch.int32)
+    if args.telescope_shape != "auto":
+        bs_, gb_, lds_ = (int(v) for v in args.telescope_shape.split(","))
+        det = cphot.make_detector(atm, **run, block_size=bs_, grid_blocks=gb_, lds_hist=lds_)
+        tune = {"block_size": bs_, "grid_blocks": gb_, "lds_hist": lds_, "bunch": run["bunch"], "fixed": True}
+    else:
+        det, tune = tuned_detector(cphot, S, atm, run, bins, th, cnt, stream)
+
+    def step(ev):
+        out_buf.zero_()
+        if ev is not None:
+            ev[0].record(stream)
+        cphot.propagate(S, det, bins, th, cnt, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    ms, kern = time_steps(torch, step, args.steps, args.warmup, stream)
+    log(f"exact telescope: {ms:.3f} ms/step, kernel {kern:.3f} ms")
+    c = cnt.cpu().numpy()
+    exact_bins = bins.cpu().numpy()
+    exact_th = th.cpu().numpy()
+    records = float(c[3])
+    photons = records * run["bunch"]
+    dh = W.ATMO_LAYERED["h_top"] / W.ATMO_LAYERED["n_layers"]
+    cross, _ = crossing_profile(torch, cphot, sh.seg, geom, det, run["h_obs"], dh, W.ATMO_LAYERED["n_layers"], False)
+    res = {"value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
+           "records_per_step": records, "photons_per_step": photons, "segments_per_s": sh.n / (ms * 1e-3),
+           "workload": f"1e6 segments, zenith 20 deg, Xmax 400, beta variant {args.beta}, 100 layers x 64 "
+                       "wavelength bins, bunch 5, 10x10 spheres r=6 m pitch 150 m, 512 x 1 ns time bins",
+           "roofline": roofline_entry(f"k_propagate<{tune['block_size']},LAYERED,SPHERES,PROPAGATE>", kern,
+                                      float(sh.n), SEGMENT_BYTES, records, cross, False, tune, "telescope_layered")}
+    shape = {k: tune[k] for k in ("block_size", "grid_blocks", "lds_hist")}
+    if not args.no_cuts:
+        res["reduction"] = bench_reduction(torch, cphot, W, S, atm, run, out_buf, bins, th, cnt, stream, args, shape)
+        res["emission_options"] = bench_emission_options(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream,
+                                                         args, shape, {"ms_per_step": ms, "binned": float(c[8])})
+        res["cuts"] = bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, exact_bins,
+                                 exact_th, photons, ms)
+        log(f"telescope with cuts: {res['cuts']['ms_per_step']:.3f} ms/step")
+    if not args.no_surrogate:
+        res["surrogate"] = bench_surrogate(torch, cphot, W, args, atm, S, run, exact_bins, ms, stream)
+        log(f"telescope surrogate: {res['surrogate']['value']:.3e} photons/s")
+    return res
 
 
 def bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, exact_bins, exact_th, photons,
@@ -234,39 +555,9 @@ def bench_emission_options(torch, cphot, S, atm, run, out_buf, bins, th, cnt, st
     return res
 
 
-def walk_profile(torch, cphot, sh, geom, det, run, n=20000):
-    """From traced records of the first n segments: the fraction of downward
-    records the closed-form layer sums serve (tan^2 zenith within the series
-    bound, start above the observation layer) and the mean number of layer
-    boundaries the others cross in the loop."""
-    sample = {k: v[:n] for k, v in sh.seg.items()}
-    sg, sgg, _ = cphot.upload(sample, geom)
-    SS = cphot.make_segments(sg, sgg, None)
-    counts = torch.zeros(SS.n, dtype=torch.int32, device="cuda")
-    cphot.segment_counts(SS, det, counts)
-    offs = torch.cumsum(counts.to(torch.int64), 0) - counts.to(torch.int64)
-    tot = int(counts.sum().item())
-    rec = torch.zeros(max(tot, 1) * cphot.RECORD_BYTES, dtype=torch.uint8, device="cuda")
-    cphot.trace_records(SS, det, offs.contiguous(), rec)
-    torch.cuda.synchronize()
-    r = cphot.records_to_numpy(rec.cpu())[:tot]
-    dh = 250.0
-    obs_layer = int(run["h_obs"] // dh)
-    zmid = 0.5 * (sample["z0"].astype(np.float64) + sample["z1"])
-    start_layer = np.minimum((zmid[r["seg"].astype(np.int64)] // dh).astype(np.int64), 99)
-    crossings = np.maximum(start_layer - obs_layer, 0)
-    down = r["state"] != 1
-    tan2 = (r["dx"].astype(np.float64) ** 2 + r["dy"].astype(np.float64) ** 2) / np.maximum(
-        r["dz"].astype(np.float64) ** 2, 1e-30)
-    series = down & (crossings > 0) & (tan2 <= SERIES_TAN2_MAX)
-    loop = down & ~series
-    n_down = max(int(down.sum()), 1)
-    return float(series.sum()) / n_down, float(crossings[loop].sum()) / n_down
-
-
-def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_ms, stream):
-    """Train the transport network on the GPU, then run the telescope workload
-    through it; its bins against the exact tracer's (same photons)."""
+def bench_surrogate(torch, cphot, W, args, atm, S, run, exact_bins, exact_ms, stream):
+    """Train the planar transport network on the GPU, then run the telescope
+    workload through it; its bins against the exact tracer's (same photons)."""
     sur = cphot.Surrogate(W.SURROGATE_LO, W.SURROGATE_HI, max_batch=4096, init_seed=1)
     t0 = time.perf_counter()
     X, Y = sur.make_training_set(atm, args.train_samples, seed=1004)
@@ -278,11 +569,9 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
     t2 = time.perf_counter()
     loss = loss.cpu().numpy()
     del X, Y
-    log(f"surrogate trained: {args.train_steps} steps, final loss {float(loss[-100:].mean()):.2e}")
-
     nsph = run["snx"] * run["sny"]
 
-    def run_path(det):
+    def run_spheres(det):
         bins = torch.zeros(nsph, dtype=torch.int64, device="cuda")
         th = torch.zeros(nsph * (run["n_t"] + 1), dtype=torch.int32, device="cuda")
         cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
@@ -307,19 +596,18 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
         return tuned_detector(cphot, S, atm, {**run, "transport": transport}, b, t, c, stream, **extra)
 
     det_s, tune_s = tuned("surrogate", surrogate=sur)
-    ms, kern, b_s, c_s = run_path(det_s)
+    ms, kern, b_s, c_s = run_spheres(det_s)
     det_l, _ = tuned("straight")
-    ms_l, _, b_l, _ = run_path(det_l)
+    ms_l, _, b_l, _ = run_spheres(det_l)
     photons = float(c_s[3]) * run["bunch"]
-    # the thesis's own fast method: the correction interpolated from a table
     tb = time.perf_counter()
     tab = cphot.Table(atm, run["h_obs"], "planar", c_lo=0.4)
     tab_build_s = time.perf_counter() - tb
     det_t, tune_t = tuned("table", table=tab)
-    ms_t, kern_t, b_t, c_t = run_path(det_t)
+    ms_t, kern_t, b_t, c_t = run_spheres(det_t)
 
-    def grid_density(S_, geom_, grid_run):
-        """Exact vs surrogate vs straight line on a ground grid (same photons)."""
+    def grid_density(S_, grid_run):
+        """Exact vs network vs straight line vs table on a ground grid (same photons)."""
         out = {}
         for name in ("layered", "surrogate", "straight", "table"):
             d = cphot.make_detector(atm, **{**grid_run, "transport": name},
@@ -333,20 +621,20 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
                 "straight_line": density_error(out["straight"], out["layered"]),
                 "photons": float(out["layered"].sum())}
 
-    grid_run = dict(detector="grid", spectrum="frank_tamm", bunch=1, h_obs=2200.0, nx=100, ny=100, cell=10.0,
-                    seed=2)
-    tele_grid = grid_density(S, geom, grid_run)
+    # the 10 m grid of the same shower: hundreds of bins above 1000 photons
+    tele_grid = grid_density(S, dict(detector="grid", spectrum="frank_tamm", bunch=1, h_obs=2200.0, nx=100, ny=100,
+                                     cell=10.0, seed=2))
     tiny = W.workload_tiny_vertical("R")
     tg = np.array([[*tiny.core, *tiny.axis]])
     ts, tgg, toff = cphot.upload(tiny.seg, tg)
-    tiny_grid = grid_density(cphot.make_segments(ts, tgg, toff), tg,
+    tiny_grid = grid_density(cphot.make_segments(ts, tgg, toff),
                              {**W.RUN_TINY, "spectrum": "frank_tamm", "bunch": 1, "seed": 1})
-    return {
+    res = {
         "value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
         "speedup_vs_exact": exact_ms / ms,
-        "density_error_vs_exact": density_error(b_s, exact_bins),
+        "density_error_vs_exact_spheres": density_error(b_s, exact_bins),
+        "density_error_vs_exact_grid_10m": tele_grid,
         "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0), "tuning": tune_s,
-        "grid_10m_same_shower": tele_grid,
         "tiny_vertical_shower_grid": tiny_grid,
         "straight_line_without_correction": {"ms_per_step": ms_l,
                                              "density_error_vs_exact": density_error(b_l, exact_bins)},
@@ -362,12 +650,18 @@ def bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, exact_
                      "samples_per_s": args.train_steps * 4096 / max(t2 - t1, 1e-9),
                      "final_loss": float(loss[-100:].mean())},
     }
+    sur.close()
+    tab.close()
+    return res
 
+
+# ------------------------------------------------------------------------------ batched
 
 def bench_batched(torch, cphot, W, args, stream):
     """256 showers, segment counts log-uniform in [1e3, 1e6], zenith U[0, 60],
     Xmax U[350, 750], each with its own 200 x 200 grid of 5 m cells, straight
-    rays; one captured launch per step with the autotuner's shape and bunch."""
+    rays; one captured launch per step with the autotuner's shape, the bunch
+    chosen among those whose bins stay within 1 % of bunch 1."""
     t0 = time.perf_counter()
     shs = W.make_batch(args.batch_showers, seed=1003, beta=args.beta)
     log(f"batched workload generated in {time.perf_counter() - t0:.1f} s")
@@ -394,7 +688,8 @@ def bench_batched(torch, cphot, W, args, stream):
     cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
     det0 = cphot.make_detector(atm, **run)
     t0 = time.perf_counter()
-    tune = cphot.autotune(S, det0, bins, None, cnt, bunches=[1, 2, 5], reps=2, stream=stream)
+    tune = cphot.autotune_accuracy(S, det0, bins, None, cnt, bunches=[1, 2, 5], reps=2, max_error=0.01,
+                                   min_count=1000.0, stream=stream)
     tune_s = time.perf_counter() - t0
     log(f"autotune: {tune} in {tune_s:.1f} s")
     det = cphot.make_detector(atm, **{**run, "bunch": tune["bunch"]}, block_size=tune["block_size"],
@@ -411,146 +706,35 @@ def bench_batched(torch, cphot, W, args, stream):
     ms, kern = time_steps(torch, step, args.steps, args.warmup, stream)
     c = cnt.cpu().numpy()
     photons = float(c[3]) * tune["bunch"]
-    # bunch 1 with the same shape, for the cost of the bunch choice
-    det1 = cphot.make_detector(atm, **run, block_size=tune["block_size"], grid_blocks=tune["grid_blocks"],
-                               lds_hist=tune["lds_hist"])
-    step_1 = cphot.Step(S, det1, bins, None, cnt, clear=True)
+    res = {"value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "graph_launch_ms": kern,
+           "showers": ns, "segments": n, "records_per_step": float(c[3]), "photons_per_step": photons,
+           "tuning": {**tune, "tune_s": tune_s, "bunch_candidates": [1, 2, 5]},
+           "workload": "256 showers, 10^U[3,6] segments each, zenith U[0,60] deg, Xmax U[350,750], "
+                       "200x200 grid of 5 m per shower, straight rays, Rayleigh; one HIP-graph launch per step"}
+    if tune["bunch"] == 1:
+        # the rate the rejected bunch of 5 would give, with the same shape, labelled as such
+        det5 = cphot.make_detector(atm, **{**run, "bunch": 5}, block_size=tune["block_size"],
+                                   grid_blocks=tune["grid_blocks"], lds_hist=tune["lds_hist"])
+        step_5 = cphot.Step(S, det5, bins, None, cnt, clear=True)
 
-    def step1(ev):
-        if ev is not None:
-            ev[0].record(stream)
-        step_1.launch(stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
+        def step5(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            step_5.launch(stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
 
-    ms1, _ = time_steps(torch, step1, max(3, args.steps // 2), 1, stream)
-    c1 = cnt.cpu().numpy()
+        ms5, _ = time_steps(torch, step5, max(3, args.steps // 2), 1, stream)
+        c5 = cnt.cpu().numpy()
+        res["bunch5_rejected"] = {"value": float(c5[3]) * 5 / (ms5 * 1e-3), "ms_per_step": ms5,
+                                  "worst_bin_vs_bunch1": tune["bin_errors"].get(5),
+                                  "note": "coarser statistics: per-shower bins beyond 1 % of bunch 1"}
+        step_5.close()
     step_g.close()
-    step_1.close()
-    return {"value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "graph_launch_ms": kern,
-            "showers": ns, "segments": n, "records_per_step": float(c[3]), "photons_per_step": photons,
-            "tuning": {**tune, "tune_s": tune_s, "bunch_candidates": [1, 2, 5]},
-            "bunch1": {"value": float(c1[3]) / (ms1 * 1e-3), "ms_per_step": ms1},
-            "workload": "256 showers, 10^U[3,6] segments each, zenith U[0,60] deg, Xmax U[350,750], "
-                        "200x200 grid of 5 m per shower, straight rays, Rayleigh; one HIP-graph launch per step"}
+    return res
 
 
-def bench_inclined(torch, cphot, W, args, stream):
-    """The large inclined shower through the curved atmosphere, Cherenkov +
-    fluorescence, FP64 bins on a 1000 x 1000 grid: chunk 0 (1e7 segments) resident
-    in HBM with an autotuned shape, then all chunks streamed from host memory."""
-    t0 = time.perf_counter()
-    sh = W.workload_inclined_chunk(0, beta=args.beta)
-    log(f"inclined chunk generated in {time.perf_counter() - t0:.1f} s")
-    geom = np.array([[*sh.core, *sh.axis]])
-    seg, g, off = cphot.upload(sh.seg, geom)
-    S = cphot.make_segments(seg, g, off, first_id=sh.first_id)
-    atm = cphot.Atmosphere(**W.ATMO_LAYERED)
-    run = {**W.RUN_INCLINED, "seed": 5}
-    bins = torch.zeros(run["nx"] * run["ny"], dtype=torch.float64, device="cuda")
-    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
-    t0 = time.perf_counter()
-    tune = cphot.autotune(S, cphot.make_detector(atm, **run), bins, None, cnt, reps=1, stream=stream)
-    tune_s = time.perf_counter() - t0
-    log(f"autotune: {tune} in {tune_s:.1f} s")
-    det = cphot.make_detector(atm, **run, block_size=tune["block_size"], grid_blocks=tune["grid_blocks"],
-                              lds_hist=tune["lds_hist"], hist_window=tune["hist_window"])
-
-    def step(ev):
-        bins.zero_()
-        cnt.zero_()
-        if ev is not None:
-            ev[0].record(stream)
-        cphot.propagate(S, det, bins, None, cnt, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
-
-    ms, kern = time_steps(torch, step, max(3, args.steps // 4), 1, stream)
-    c = cnt.cpu().numpy()
-    photons = float(c[3]) * run["bunch"]
-    out = {"value": photons / (ms * 1e-3), "unit": "photons/s", "ms_per_step": ms, "kernel_ms": kern,
-           "segments": sh.n, "records_per_step": float(c[3]), "fluorescence_records": float(c[10]),
-           "tuning": {**tune, "tune_s": tune_s},
-           "workload": "chunk 0 of the 1e8-segment inclined shower: zenith 60 deg, Xmax 600, "
-                       "dE/dx U[0.1,2] MeV/m, curved Earth, 1000x1000 grid of 10 m, FP64 bins, inputs in HBM"}
-    if not args.no_surrogate:
-        # the curved-shell surrogate on the same chunk: trained on the GPU, then the
-        # same photons as the exact walk, bins compared cell by cell
-        sur = cphot.Surrogate(W.SURROGATE_CURVED_LO, W.SURROGATE_CURVED_HI, max_batch=4096, init_seed=2,
-                              geometry="curved")
-        t0 = time.perf_counter()
-        X, Y = sur.make_training_set(atm, args.train_samples, seed=1005)
-        sur.fit_normalization(Y)
-        loss = sur.train(X, Y, batch=4096, steps=2 * args.train_steps, lr=3e-3)
-        torch.cuda.synchronize()
-        train_s = time.perf_counter() - t0
-        del X, Y
-        exact_bins = None
-
-        def run_with(d):
-            b = torch.zeros(run["nx"] * run["ny"], dtype=torch.float64, device="cuda")
-            k = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
-
-            def st(ev):
-                b.zero_()
-                k.zero_()
-                if ev is not None:
-                    ev[0].record(stream)
-                cphot.propagate(S, d, b, None, k, stream=stream)
-                if ev is not None:
-                    ev[1].record(stream)
-
-            ms_, kern_ = time_steps(torch, st, max(3, args.steps // 4), 1, stream)
-            return ms_, kern_, b.cpu().numpy(), k.cpu().numpy()
-
-        _, _, exact_bins, _ = run_with(det)
-        det_s = cphot.make_detector(atm, **{**run, "transport": "surrogate"}, surrogate=sur)
-        ms_s, kern_s, b_s, c_s = run_with(det_s)
-        out["surrogate"] = {"value": float(c_s[3]) * run["bunch"] / (ms_s * 1e-3), "unit": "photons/s",
-                            "ms_per_step": ms_s, "kernel_ms": kern_s, "speedup_vs_exact": ms / ms_s,
-                            "density_error_vs_exact": density_error(b_s, exact_bins),
-                            "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0),
-                            "training": {"samples": args.train_samples, "steps": 2 * args.train_steps,
-                                         "train_s": train_s, "final_loss": float(loss[-100:].mean().item())},
-                            "note": "fluorescence photons beyond 66 deg local zenith are traced exactly"}
-        log(f"inclined surrogate: {out['surrogate']['value']:.3e} photons/s, "
-            f"worst bin {out['surrogate']['density_error_vs_exact']['worst_bin']}")
-        t0 = time.perf_counter()
-        tab = cphot.Table(atm, run["h_obs"], "curved", n_c=512, c_lo=0.15)
-        tab_build_s = time.perf_counter() - t0
-        det_t = cphot.make_detector(atm, **{**run, "transport": "table"}, table=tab)
-        ms_t, kern_t, b_t, c_t = run_with(det_t)
-        out["table"] = {"value": float(c_t[3]) * run["bunch"] / (ms_t * 1e-3), "unit": "photons/s",
-                        "ms_per_step": ms_t, "kernel_ms": kern_t, "speedup_vs_exact": ms / ms_t,
-                        "density_error_vs_exact": density_error(b_t, exact_bins),
-                        "fallback_fraction": float(c_t[9]) / max(float(c_t[3]), 1.0), "build_s": tab_build_s,
-                        "note": "interpolation tracing (Sec. 4.4.1), curved shells: 4 heights per shell x 512 "
-                                "tan-zenith nodes up to 81 deg"}
-        log(f"inclined table: {out['table']['value']:.3e} photons/s, "
-            f"worst bin {out['table']['density_error_vs_exact']['worst_bin']}")
-    del S, seg
-    if args.inclined_chunks > 0:
-        chunks = [sh] + [W.workload_inclined_chunk(c, beta=args.beta) for c in range(1, args.inclined_chunks)]
-        streamer = cphot.Streamer(sh.n)
-        bins.zero_()
-        cnt.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for ch in chunks:
-            streamer.run(ch.seg, g, det, bins, None, cnt, first_id=ch.first_id, stream=stream)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        c = cnt.cpu().numpy()
-        streamer.close()
-        out["streamed"] = {"value": float(c[3]) * run["bunch"] / dt, "unit": "photons/s", "seconds": dt,
-                           "segments": int(sum(ch.n for ch in chunks)), "chunks": len(chunks),
-                           "records": float(c[3]), "fluorescence_records": float(c[10]),
-                           "photons_binned": float(c[8]),
-                           "note": "host-resident segments, pinned double-buffered copies overlapped with "
-                                   "propagation (PCIe-inclusive)"}
-        log(f"inclined streamed: {out['streamed']['value']:.3e} photons/s over {len(chunks)} chunks")
-    return out
-
+# ------------------------------------------------------------------------------ main
 
 def main():
     ap = argparse.ArgumentParser()
@@ -561,11 +745,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-inclined", action="store_true")
-    ap.add_argument("--no-cuts", action="store_true", help="skip the telescope step with data-reduction cuts")
+    ap.add_argument("--no-telescope", action="store_true")
+    ap.add_argument("--no-cuts", action="store_true", help="skip the telescope steps with cuts, reduction and options")
     ap.add_argument("--telescope-shape", default="512,512,1", metavar="BS,GRID,LDS|auto",
-                    help="launch shape of the exact telescope step: the profiled shape (default; the HBM "
-                         "traffic figure holds for it) or 'auto' for the autotuner's pick")
+                    help="launch shape of the exact telescope step: a fixed shape (default) or 'auto'")
     ap.add_argument("--inclined-chunks", type=int, default=10,
                     help="chunks of 1e7 segments streamed from host memory (0: only the resident chunk)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
@@ -594,106 +777,34 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
         return
     stream = torch.cuda.current_stream()
-    run = {**W.RUN_TELESCOPE, "seed": 2}
-    sh = W.workload_telescope(args.beta)
-    geom = np.array([[*sh.core, *sh.axis]])
-    atm = cphot.Atmosphere(**W.ATMO_LAYERED)
-    seg, g, off = cphot.upload(sh.seg, geom)
-    S = cphot.make_segments(seg, g, off)
-    nsph = run["snx"] * run["sny"]
-    # the step's outputs in one buffer, cleared by one fill per step
-    nb, nc, nt = nsph * 8, cphot.NCOUNTERS * 8, nsph * (run["n_t"] + 1) * 4
-    out_buf = torch.zeros(nb + nc + nt, dtype=torch.uint8, device="cuda")
-    bins = out_buf[:nb].view(torch.int64)
-    cnt = out_buf[nb:nb + nc].view(torch.int64)
-    th = out_buf[nb + nc:].view(torch.int32)
-    if args.telescope_shape != "auto":
-        bs_, gb_, lds_ = (int(v) for v in args.telescope_shape.split(","))
-        det = cphot.make_detector(atm, **run, block_size=bs_, grid_blocks=gb_, lds_hist=lds_)
-        tune = {"block_size": bs_, "grid_blocks": gb_, "lds_hist": lds_, "bunch": run["bunch"], "fixed": True}
-    else:
-        det, tune = tuned_detector(cphot, S, atm, run, bins, th, cnt, stream)
-    log(f"telescope shape: {tune}")
-
-    def step(ev):
-        out_buf.zero_()
-        if ev is not None:
-            ev[0].record(stream)
-        cphot.propagate(S, det, bins, th, cnt, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
-
-    ms_per_step, kern_ms = time_steps(torch, step, args.steps, args.warmup, stream)
-    log(f"exact telescope: {ms_per_step:.3f} ms/step, kernel {kern_ms:.3f} ms")
-    c = cnt.cpu().numpy()
-    exact_bins = bins.cpu().numpy()
-    exact_th = th.cpu().numpy()
-    records = float(c[3])
-    photons = records * run["bunch"]
-    value = photons / (ms_per_step * 1e-3)
-    shape = {k: tune[k] for k in ("block_size", "grid_blocks", "lds_hist")}
-    reduction = None
-    if not args.no_cuts:
-        reduction = bench_reduction(torch, cphot, W, S, atm, run, out_buf, bins, th, cnt, stream, args, shape)
-        log(f"telescope with efficiency: {reduction['efficiency_only']['ms_per_step']:.3f} ms/step, "
-            f"reduced {reduction['reduced']['ms_per_step']:.3f} ms/step, binned ratio "
-            f"{reduction['binned_ratio']:.4f}")
-    emission = None
-    if not args.no_cuts:
-        emission = bench_emission_options(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, shape,
-                                          {"ms_per_step": ms_per_step, "binned": float(c[8])})
-        log(f"telescope with Poisson counts: {emission['poisson_counts']['ms_per_step']:.3f} ms/step, "
-            f"dispersive: {emission['dispersive']['ms_per_step']:.3f} ms/step")
-    cuts = None
-    if not args.no_cuts:
-        cuts = bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, exact_bins, exact_th,
-                          photons, ms_per_step)
-        log(f"telescope with cuts: {cuts['ms_per_step']:.3f} ms/step, identical bins {cuts['bins_identical']}")
-
-    series_frac, loop_cross = walk_profile(torch, cphot, sh, geom, det, run)
-    n_seg = float(sh.n)
-    slots = n_seg * SLOTS_PER_SEGMENT + records * (SLOTS_PER_RECORD_BASE + SLOTS_PER_SERIES * series_frac +
-                                                   SLOTS_PER_LAYER_CROSSING * loop_cross)
-    achieved = slots / (kern_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
-                "unit": "Tlane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": traffic_if_current(tune),
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                "kernel": f"k_propagate<{tune['block_size']},LAYERED,SPHERES,PROPAGATE>", "kernel_ms": kern_ms,
-                "tuning": tune,
-                "algorithmic_slots_per_launch": slots, "series_fraction": series_frac,
-                "loop_crossings_per_record": loop_cross,
-                "hbm_gbps_algorithmic": n_seg * SEGMENT_BYTES / (kern_ms * 1e-3) / 1e9}
+    head, roof, inclined, ctx = bench_inclined(torch, cphot, W, args, stream)
     out = {
         "metric": METRIC,
-        "value": value, "unit": "photons/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"telescope: 1e6 segments, zenith 20 deg, Xmax 400, beta variant {args.beta}, "
-                               "100 layers x 64 wavelength bins, bunch 5, 10x10 spheres r=6 m pitch 150 m, "
-                               "512 x 1 ns time bins",
-                   "path": "exact", "records_per_step": records, "photons_per_step": photons,
-                   "segments_per_s": n_seg / (ms_per_step * 1e-3)},
-        "roofline": roofline,
+        "value": head["value"], "unit": "photons/s", "n_gpus": 1, "steps": max(5, args.steps // 2),
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "large inclined shower, resident chunk: 1e7 segments of a 60-degree shower "
+                               f"(Xmax 600, beta variant {args.beta}), curved Earth (100 shells of 250 m), "
+                               "Cherenkov + fluorescence (3 bands, dE/dx U[0.1,2] MeV/m), 64 wavelength bins, "
+                               "1000x1000 grid of 10 m, FP64 bins",
+                   "path": "exact (closed-form shell sums, shell walk beyond them)",
+                   "records_per_step": head["records"], "photons_per_step": head["photons"],
+                   "segments_per_s": head["segments"] / (head["ms_per_step"] * 1e-3),
+                   "kernel_ms": head["kernel_ms"], "tuning": head["tuning"]},
+        "roofline": roof,
+        "inclined": inclined,
     }
-    if cuts is not None:
-        out["cuts"] = cuts
-    if reduction is not None:
-        out["reduction"] = reduction
-    if emission is not None:
-        out["emission_options"] = emission
-    if not args.no_surrogate:
-        out["surrogate"] = bench_surrogate(torch, cphot, W, args, atm, S, geom, run, exact_bins, ms_per_step, stream)
-        log(f"surrogate: {out['surrogate']['value']:.3e} photons/s")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(torch, cphot, W, ctx)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3e} photons/s on {out['cpu_baseline']['cores']} cores")
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_telescope:
+        out["telescope"] = bench_telescope(torch, cphot, W, args, stream)
+        torch.cuda.empty_cache()
     if not args.no_batched:
-        del S, seg
         out["batched"] = bench_batched(torch, cphot, W, args, stream)
         log(f"batched: {out['batched']['value']:.3e} photons/s")
-        torch.cuda.empty_cache()
-    if not args.no_inclined:
-        out["inclined"] = bench_inclined(torch, cphot, W, args, stream)
-        log(f"inclined: {out['inclined']['value']:.3e} photons/s")
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sh, run, W.ATMO_LAYERED)
     print(json.dumps(out), flush=True)
 
 

@@ -404,6 +404,22 @@ typedef struct {
 int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
                    const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, cphot_tuning* best, void* stream);
 
+/* cphot_autotune with an accuracy constraint on the bunch size. A bunch of b
+ * photons moves b photons at once, so bins are coarser draws of the same density
+ * (the thesis weighs bunch size against statistical resolution, Sec. 5.3.2). Each
+ * candidate b is run once with the detector's own launch shape and its bins are
+ * compared cell by cell with those of bunch 1 (the finest statistics):
+ * err_b = max over cells with at least `min_count` bunch-1 photons of
+ * |n_b - n_1| / n_1 (0 for b = 1). Only candidates with err_b <= max_error are
+ * handed to cphot_autotune (bunch 1 always is), which picks the fastest shape
+ * and bunch among them. `bin_errors` (may be NULL) receives err_b per candidate,
+ * in the order given. Outputs are overwritten; synchronous on `stream`.
+ * Errors: INVALID_ARG (no candidates, a candidate < 1, max_error < 0,
+ * min_count < 1, no bins), HIP. */
+int cphot_autotune_accuracy(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
+                            const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, double max_error,
+                            double min_count, double* bin_errors, cphot_tuning* best, void* stream);
+
 /* cphot_autotune behind a cache of results keyed by a configuration signature:
  * the device (architecture name and compute-unit count), the ABI version, the
  * atmosphere's profile, layer and wavelength-bin counts, every detector setting

@@ -154,6 +154,10 @@ def lib():
                                                 C.c_int32, C.c_int32, C.c_char_p, C.POINTER(Tuning),
                                                 C.POINTER(C.c_int32), P]
             L.cphot_autotune_cached.restype = C.c_int
+            L.cphot_autotune_accuracy.argtypes = [C.POINTER(Segments), C.POINTER(Detector), C.POINTER(Bins), P,
+                                                  C.c_int32, C.c_int32, C.c_double, C.c_double, P,
+                                                  C.POINTER(Tuning), P]
+            L.cphot_autotune_accuracy.restype = C.c_int
             L.cphot_autotune_cache_clear.argtypes = []
             L.cphot_autotune_cache_clear.restype = None
             L.cphot_streamer_create.argtypes = [C.c_int64, C.POINTER(C.c_void_p)]
@@ -489,6 +493,26 @@ def autotune(seg: Segments, det: Detector, bins, time_hist=None, counters=None, 
                                                       C.byref(t), _stream_ptr(stream)))
     return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, hist_window=t.hist_window,
                 bunch=t.bunch, ms=t.ms, photons_per_s=t.photons_per_s, cached=bool(hit.value))
+
+
+def autotune_accuracy(seg: Segments, det: Detector, bins, time_hist=None, counters=None, bunches=(1,), reps=3,
+                      max_error=0.01, min_count=1000.0, stream=None):
+    """cphot_autotune over the bunch sizes whose bins stay within max_error of the
+    bunch-1 bins (cells with >= min_count photons); "bin_errors" holds each
+    candidate's error, in the order of `bunches`."""
+    import numpy as np
+    b = make_bins(bins, time_hist, counters)
+    t = Tuning()
+    bc = np.ascontiguousarray(bunches, dtype=np.int32)
+    errs = np.zeros(len(bc), dtype=np.float64)
+    _check("cphot_autotune_accuracy",
+           lib().cphot_autotune_accuracy(C.byref(seg), C.byref(det), C.byref(b), bc.ctypes.data_as(C.c_void_p),
+                                         len(bc), int(reps), float(max_error), float(min_count),
+                                         errs.ctypes.data_as(C.c_void_p), C.byref(t), _stream_ptr(stream)))
+    return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, hist_window=t.hist_window,
+                bunch=t.bunch, ms=t.ms, photons_per_s=t.photons_per_s,
+                bin_errors={int(k): float(e) for k, e in zip(bc, errs)}, max_error=float(max_error),
+                min_count=float(min_count))
 
 
 def autotune_cache_clear():

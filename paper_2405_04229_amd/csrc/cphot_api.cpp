@@ -1167,4 +1167,60 @@ void cphot_autotune_cache_clear(void) {
   c.files_read.clear();
 }
 
+
+int cphot_autotune_accuracy(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
+                            const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, double max_error,
+                            double min_count, double* bin_errors, cphot_tuning* best, void* stream) {
+  if (!seg || !det || !out || !best) return fail(CPHOT_ERR_INVALID_ARG, "null argument");
+  if (n_bunch < 1 || !bunch_candidates) return fail(CPHOT_ERR_INVALID_ARG, "need at least one bunch candidate");
+  if (!(max_error >= 0.0) || !(min_count >= 1.0) || !std::isfinite(max_error) || !std::isfinite(min_count))
+    return fail(CPHOT_ERR_INVALID_ARG, "max_error must be >= 0 and min_count >= 1");
+  if (!out->bins) return fail(CPHOT_ERR_INVALID_ARG, "the bunch check compares bins: bins required");
+  for (int i = 0; i < n_bunch; ++i)
+    if (bunch_candidates[i] < 1) return fail(CPHOT_ERR_INVALID_ARG, "bunch candidates must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  // bins of one propagation with bunch b, as doubles on the host
+  const int64_t nb = out->bins_capacity;
+  auto bins_of = [&](int32_t b, std::vector<double>& h) -> int {
+    cphot_detector d = *det;
+    d.bunch = b;
+    hipError_t ce = clear_outputs(out, st);
+    if (ce != hipSuccess) return hip_fail(ce, "bunch check clear");
+    int rc = cphot_propagate(seg, &d, out, st);
+    if (rc) return rc;
+    h.assign((size_t)nb, 0.0);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "bunch check");
+    if (out->bins_dtype == CPHOT_BINS_F64) {
+      e = hipMemcpy(h.data(), out->bins, (size_t)nb * 8, hipMemcpyDeviceToHost);
+    } else if (out->bins_dtype == CPHOT_BINS_U64) {
+      std::vector<unsigned long long> t((size_t)nb);
+      e = hipMemcpy(t.data(), out->bins, (size_t)nb * 8, hipMemcpyDeviceToHost);
+      for (int64_t i = 0; i < nb; ++i) h[(size_t)i] = (double)t[(size_t)i];
+    } else {
+      std::vector<uint32_t> t((size_t)nb);
+      e = hipMemcpy(t.data(), out->bins, (size_t)nb * 4, hipMemcpyDeviceToHost);
+      for (int64_t i = 0; i < nb; ++i) h[(size_t)i] = (double)t[(size_t)i];
+    }
+    return e == hipSuccess ? CPHOT_OK : hip_fail(e, "bunch check copy");
+  };
+  std::vector<double> ref, cur;
+  int rc = bins_of(1, ref);
+  if (rc) return rc;
+  std::vector<int32_t> ok;
+  for (int i = 0; i < n_bunch; ++i) {
+    const int32_t b = bunch_candidates[i];
+    double err = 0.0;
+    if (b != 1) {
+      if ((rc = bins_of(b, cur))) return rc;
+      for (size_t c = 0; c < ref.size(); ++c)
+        if (ref[c] >= min_count) err = std::max(err, std::fabs(cur[c] - ref[c]) / ref[c]);
+    }
+    if (bin_errors) bin_errors[i] = err;
+    if (err <= max_error) ok.push_back(b);
+  }
+  if (ok.empty()) ok.push_back(1);  // the finest statistics are the reference: always admissible
+  return cphot_autotune(seg, det, out, ok.data(), (int32_t)ok.size(), reps, best, stream);
+}
+
 }  // extern "C"

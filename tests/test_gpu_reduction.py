@@ -137,7 +137,14 @@ def test_efficiency_and_reduction_argument_errors():
     seg, gg, off = cphot.upload(sh.seg, g)
     S = cphot.make_segments(seg, gg, off)
     bins = torch.zeros(100 * 100, dtype=torch.int64, device="cuda")
+    # the binding checks the lengths the kernels read (one value per wavelength bin / layer)
+    with pytest.raises(ValueError, match="efficiency"):
+        cphot.make_detector(atm, **cases.RUN_TINY, efficiency=_dev(EFF))
+    # the library refuses an efficiency on an atmosphere without wavelength bins
+    eff = _dev(EFF)
+    det = cphot.make_detector(atm, **cases.RUN_TINY)
+    det.efficiency = eff.data_ptr()
     with pytest.raises(cphot.CphotError, match="efficiency"):
-        cphot.propagate(S, cphot.make_detector(atm, **cases.RUN_TINY, efficiency=_dev(EFF)), bins)
+        cphot.propagate(S, det, bins)
     with pytest.raises(cphot.CphotError):
         cphot.reduction_table(atm, 2200.0, None)
