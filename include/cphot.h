@@ -608,6 +608,21 @@ int cphot_surrogate_train(cphot_surrogate* s, const float* X, const float* Y, in
 int cphot_surrogate_gradient(cphot_surrogate* s, const float* X, const float* Y, int64_t n, float* grad,
                              float* loss, void* stream);
 
+/* cphot_surrogate_gradient for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the per-block partial gradients and loss shares live in a static
+ * workspace of the library instead of the surrogate's buffers, so the call makes
+ * no allocation of any kind. Limit: n a multiple of 64, at most 4096 samples (the
+ * workspace holds 64 blocks x 4804 partial gradients + 64 loss shares, 1.23 MB per
+ * device, kept until the process ends). Every call on one device shares that
+ * device's workspace: calls that overlap on one device (other streams, other host
+ * threads) race and must be ordered by the caller. Results equal those of
+ * cphot_surrogate_gradient bit for bit. Must be called with the surrogate's device
+ * current. Asynchronous. Errors: INVALID_ARG (null buffers, n out of range, another
+ * device current), HIP. */
+int cphot_surrogate_gradient_noalloc(cphot_surrogate* s, const float* X, const float* Y, int64_t n, float* grad,
+                                     float* loss, void* stream);
+
 /* Network outputs Y [n][4] for inputs X [n][5] (device, raw units). Asynchronous. */
 int cphot_surrogate_forward(const cphot_surrogate* s, const float* X, float* Y, int64_t n, void* stream);
 

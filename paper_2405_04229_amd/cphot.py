@@ -138,6 +138,8 @@ def lib():
             L.cphot_surrogate_fit_normalization.argtypes = [P, P, C.c_int64, P]
             L.cphot_surrogate_train.argtypes = [P, P, P, C.c_int64, C.c_int32, C.c_int32, C.c_float, P, P]
             L.cphot_surrogate_gradient.argtypes = [P, P, P, C.c_int64, P, P, P]
+            L.cphot_surrogate_gradient_noalloc.argtypes = [P, P, P, C.c_int64, P, P, P]
+            L.cphot_surrogate_gradient_noalloc.restype = C.c_int
             L.cphot_surrogate_forward.argtypes = [P, P, P, C.c_int64, P]
             L.cphot_surrogate_get_params.argtypes = [P, P, P]
             L.cphot_surrogate_set_params.argtypes = [P, P, P]
@@ -629,6 +631,19 @@ class Surrogate:
                                               C.c_void_p(g.data_ptr()), C.c_void_p(loss.data_ptr()),
                                               _stream_ptr(stream)))
         return g, loss
+
+    def gradient_noalloc(self, X, Y, grad, loss, stream=None):
+        """cphot_surrogate_gradient_noalloc into caller-owned device buffers: grad
+        float32 [4804], loss float32 [1]."""
+        import torch
+        if grad.numel() < N_PARAMS or loss.numel() < 1:
+            raise ValueError(f"grad needs {N_PARAMS} elements and loss one")
+        _check("cphot_surrogate_gradient_noalloc",
+               lib().cphot_surrogate_gradient_noalloc(self._h, C.c_void_p(_dptr(X, torch.float32, "X")),
+                                                      C.c_void_p(_dptr(Y, torch.float32, "Y")), X.shape[0],
+                                                      C.c_void_p(_dptr(grad, torch.float32, "grad")),
+                                                      C.c_void_p(_dptr(loss, torch.float32, "loss")),
+                                                      _stream_ptr(stream)))
 
     def forward(self, X, stream=None):
         import torch

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -510,6 +511,16 @@ __global__ __launch_bounds__(256) void k_forward(const MlpImage* __restrict__ im
 
 // ================================================================================ host API
 
+// Per-block partial gradients and loss shares of cphot_surrogate_gradient_noalloc:
+// at most kNoAllocSamples samples, i.e. kNoAllocSamples / 64 single-wave blocks, each
+// writing all kMlpParams entries of its row and its loss share (so nothing needs
+// clearing between calls). 1.23 MB per device, held until the process ends. In host
+// code `scratch` only names the symbol: its device address comes from
+// hipGetSymbolAddress (once per device, kept in g_scratch_addr).
+constexpr int kNoAllocSamples = 4096;
+constexpr int kNoAllocBlocks = kNoAllocSamples / 64;
+static __device__ __align__(256) float scratch[(size_t)kNoAllocBlocks * cphot::kMlpParams + kNoAllocBlocks];
+
 struct cphot_surrogate {
   cphot_surrogate_desc d;
   int device = 0;
@@ -548,6 +559,26 @@ double init_uniform(uint64_t& s) {
 hipError_t pack(cphot_surrogate* s, hipStream_t st) {
   hipLaunchKernelGGL(cphot::k_pack, dim3(16), dim3(256), 0, st, s->master, s->norm, s->tw, s->img);
   return hipGetLastError();
+}
+
+// Device address of `scratch` on device `dev` (the current device), looked up on
+// the first call per device and kept: each device holds its own copy of the array.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(int dev, float** out) {
+  if (dev < 0 || dev >= kMaxDevices) return sfail(CPHOT_ERR_INVALID_ARG, "device index beyond 64");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return shfail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return sfail(CPHOT_ERR_HIP, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_addr[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch_addr[dev];
+  return CPHOT_OK;
 }
 
 }  // namespace
@@ -687,7 +718,7 @@ int cphot_surrogate_fit_normalization(cphot_surrogate* s, const float* Y, int64_
 
 static int run_steps(cphot_surrogate* s, const float* X, const float* Y, int64_t n, int batch, int steps,
                      int total_steps, float lr, int64_t start, float* loss_out, float* grad_out, int update,
-                     hipStream_t st) {
+                     float* partial, float* loss_partial, hipStream_t st) {
   const int blocks = batch / 64;
   for (int k = 0; k < steps; ++k) {
     cphot::StepParams sp;
@@ -699,12 +730,12 @@ static int run_steps(cphot_surrogate* s, const float* X, const float* Y, int64_t
     sp.norm = s->norm;
     sp.master = s->master;
     sp.tw = s->tw;
-    sp.partial = s->partial;
-    sp.loss_partial = s->loss_partial;
+    sp.partial = partial;
+    sp.loss_partial = loss_partial;
     hipLaunchKernelGGL(cphot::k_train_step, dim3(blocks), dim3(64), 0, st, sp);
     cphot::AdamParams ap;
-    ap.partial = s->partial;
-    ap.loss_partial = s->loss_partial;
+    ap.partial = partial;
+    ap.loss_partial = loss_partial;
     ap.blocks = blocks;
     ap.master = s->master;
     ap.m1 = s->m1;
@@ -735,7 +766,8 @@ int cphot_surrogate_train(cphot_surrogate* s, const float* X, const float* Y, in
     return sfail(CPHOT_ERR_INVALID_ARG, "batch must be a multiple of 64 up to max_batch");
   if (n < batch) return sfail(CPHOT_ERR_INVALID_ARG, "training set smaller than one batch");
   if (steps < 0 || !(lr > 0.f) || !std::isfinite(lr)) return sfail(CPHOT_ERR_INVALID_ARG, "bad steps or lr");
-  return run_steps(s, X, Y, n, batch, steps, steps, lr, 0, loss_out, nullptr, 1, (hipStream_t)stream);
+  return run_steps(s, X, Y, n, batch, steps, steps, lr, 0, loss_out, nullptr, 1, s->partial, s->loss_partial,
+                   (hipStream_t)stream);
 }
 
 int cphot_surrogate_gradient(cphot_surrogate* s, const float* X, const float* Y, int64_t n, float* grad,
@@ -743,7 +775,24 @@ int cphot_surrogate_gradient(cphot_surrogate* s, const float* X, const float* Y,
   if (!s || !X || !Y || !grad) return sfail(CPHOT_ERR_INVALID_ARG, "null argument");
   if (n < 64 || n % 64 || n > s->d.max_batch)
     return sfail(CPHOT_ERR_INVALID_ARG, "n must be a multiple of 64 up to max_batch");
-  return run_steps(s, X, Y, n, (int)n, 1, 1, 1.f, 0, loss, grad, 0, (hipStream_t)stream);
+  return run_steps(s, X, Y, n, (int)n, 1, 1, 1.f, 0, loss, grad, 0, s->partial, s->loss_partial,
+                   (hipStream_t)stream);
+}
+
+int cphot_surrogate_gradient_noalloc(cphot_surrogate* s, const float* X, const float* Y, int64_t n, float* grad,
+                                     float* loss, void* stream) {
+  if (!s || !X || !Y || !grad) return sfail(CPHOT_ERR_INVALID_ARG, "null argument");
+  if (n < 64 || n % 64 || n > kNoAllocSamples)
+    return sfail(CPHOT_ERR_INVALID_ARG, "n must be a multiple of 64 up to 4096 (the static workspace)");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return shfail(e, "hipGetDevice");
+  if (dev != s->device) return sfail(CPHOT_ERR_INVALID_ARG, "call on the device the surrogate was created on");
+  float* ws = nullptr;
+  const int rc = scratch_address(dev, &ws);
+  if (rc) return rc;
+  return run_steps(s, X, Y, n, (int)n, 1, 1, 1.f, 0, loss, grad, 0, ws, ws + (size_t)kNoAllocBlocks * cphot::kMlpParams,
+                   (hipStream_t)stream);
 }
 
 int cphot_surrogate_forward(const cphot_surrogate* s, const float* X, float* Y, int64_t n, void* stream) {
