@@ -248,39 +248,75 @@ def bench_inclined(torch, cphot, W, args, stream):
             "photons": photons, "segments": sh.n, "fluorescence_records": float(c[10]),
             "records_walked": float(c[9]), "photons_binned": float(c[8]), "tuning": tune}
     extra = {}
-    # the plain exact tracer: every ray walked shell by shell (Sec. 3.4.2 over shells)
-    det_w, tune_w = tuned_detector(cphot, S, atm, {**run, "transport": "curved_walk"}, bins, None, cnt, stream, reps=1)
-    ms_w, kern_w, b_w, c_w = run_path(torch, cphot, S, det_w, nb, stream, max(3, steps // 2), 1, torch.float64)
-    extra["walk"] = {"value": float(c_w[3]) * run["bunch"] / (ms_w * 1e-3), "unit": "photons/s", "ms_per_step": ms_w,
-                     "kernel_ms": kern_w, "tuning": tune_w, "bins_identical_to_headline": bool(
-                         np.array_equal(b_w, exact_bins)),
-                     "bins_diff_l1": float(np.abs(b_w - exact_bins).sum()),
-                     "note": "the iterative tracer: every ray walked shell by shell"}
-    log(f"inclined walk: {ms_w:.3f} ms/step")
-    if not args.no_surrogate:
+    paths = [x for x in args.inclined_paths.split(",") if x]
+    # the same step with filter level 3 for the grid (an exact bound: identical bins)
+    det_c = cphot.make_detector(atm, **run, cuts=("photon",), block_size=tune["block_size"],
+                                grid_blocks=tune["grid_blocks"], lds_hist=tune["lds_hist"],
+                                hist_window=tune["hist_window"])
+    ms_c, kern_c, b_c, c_c = run_path(torch, cphot, S, det_c, nb, stream, steps, 1, torch.float64)
+    extra["exact_photon_cut"] = {
+        "value": photons / (ms_c * 1e-3), "unit": "photons/s (uncut records)", "ms_per_step": ms_c,
+        "kernel_ms": kern_c, "speedup_vs_exact": ms / ms_c, "bins_identical": bool(np.array_equal(b_c, exact_bins)),
+        "records_culled": float(c_c[12]), "records_walked": float(c_c[9]),
+        "note": "filter level 3 on the ground grid (Sec. 4.3.4): records whose straight line lands beyond the "
+                "Bouguer bound of the grid are outside before transport; same launch shape"}
+    log(f"inclined exact with photon cut: {ms_c:.3f} ms/step, identical bins "
+        f"{extra['exact_photon_cut']['bins_identical']}")
+    ms_w = None
+    if "walk" in paths:
+        # the plain exact tracer: every ray walked shell by shell (Sec. 3.4.2 over shells)
+        det_w, tune_w = tuned_detector(cphot, S, atm, {**run, "transport": "curved_walk"}, bins, None, cnt, stream,
+                                       reps=1)
+        ms_w, kern_w, b_w, c_w = run_path(torch, cphot, S, det_w, nb, stream, max(3, steps // 2), 1, torch.float64)
+        extra["walk"] = {"value": float(c_w[3]) * run["bunch"] / (ms_w * 1e-3), "unit": "photons/s",
+                         "ms_per_step": ms_w, "kernel_ms": kern_w, "tuning": tune_w,
+                         "bins_identical_to_headline": bool(np.array_equal(b_w, exact_bins)),
+                         "bins_diff_l1": float(np.abs(b_w - exact_bins).sum()),
+                         "note": "the iterative tracer: every ray walked shell by shell"}
+        log(f"inclined walk: {ms_w:.3f} ms/step")
+    if not args.no_surrogate and "surrogate" in paths:
         sur = cphot.Surrogate(W.SURROGATE_CURVED_LO, W.SURROGATE_CURVED_HI, max_batch=4096, init_seed=2,
                               geometry="curved")
         t0 = time.perf_counter()
         X, Y = sur.make_training_set(atm, args.train_samples, seed=1005)
         sur.fit_normalization(Y)
-        loss = sur.train(X, Y, batch=4096, steps=2 * args.train_steps, lr=3e-3)
+        loss = sur.train(X, Y, batch=4096, steps=4 * args.train_steps, lr=3e-3)
         torch.cuda.synchronize()
         train_s = time.perf_counter() - t0
         del X, Y
         det_s, tune_s = tuned_detector(cphot, S, atm, {**run, "transport": "surrogate"}, bins, None, cnt, stream,
                                        reps=1, surrogate=sur)
         ms_s, kern_s, b_s, c_s = run_path(torch, cphot, S, det_s, nb, stream, max(3, steps // 2), 1, torch.float64)
+        shape_s = {k: tune_s[k] for k in ("block_size", "grid_blocks", "lds_hist", "hist_window")}
+        det_sc = cphot.make_detector(atm, **{**run, "transport": "surrogate"}, surrogate=sur, cuts=("photon",),
+                                     **shape_s)
+        ms_sc, kern_sc, b_sc, c_sc = run_path(torch, cphot, S, det_sc, nb, stream, max(3, steps // 2), 1,
+                                              torch.float64)
         extra["surrogate"] = {
             "value": float(c_s[3]) * run["bunch"] / (ms_s * 1e-3), "unit": "photons/s", "ms_per_step": ms_s,
-            "kernel_ms": kern_s, "speedup_vs_exact": ms / ms_s, "speedup_vs_walk": ms_w / ms_s,
+            "kernel_ms": kern_s, "speedup_vs_exact": ms / ms_s,
+            "speedup_vs_walk": ms_w / ms_s if ms_w else None,
             "density_error_vs_exact": density_error(b_s, exact_bins),
             "fallback_fraction": float(c_s[9]) / max(float(c_s[3]), 1.0), "tuning": tune_s,
-            "training": {"samples": args.train_samples, "steps": 2 * args.train_steps, "train_s": train_s,
+            "with_photon_cut": {
+                "value": float(c_sc[3]) * run["bunch"] / (ms_sc * 1e-3), "unit": "photons/s", "ms_per_step": ms_sc,
+                "kernel_ms": kern_sc, "speedup_vs_exact_with_cut": ms_c / ms_sc,
+                "speedup_vs_walk": ms_w / ms_sc if ms_w else None,
+                "density_error_vs_exact": density_error(b_sc, exact_bins),
+                "fallback_fraction": float(c_sc[9]) / max(float(c_sc[3]), 1.0),
+                "records_culled": float(c_sc[12])},
+            "training": {"samples": args.train_samples, "steps": 4 * args.train_steps, "train_s": train_s,
                          "final_loss": float(loss[-100:].mean().item())},
             "domain": {"lo": list(W.SURROGATE_CURVED_LO), "hi": list(W.SURROGATE_CURVED_HI)}}
         log(f"inclined surrogate: {extra['surrogate']['value']:.3e} photons/s, "
             f"worst bin {extra['surrogate']['density_error_vs_exact']['worst_bin']}")
         sur.close()
+    if "table" in paths:
+        bench_inclined_table(torch, cphot, S, atm, run, bins, cnt, stream, steps, nb, exact_bins, ms, ms_w, extra)
+    return finish_inclined(torch, cphot, W, args, stream, sh, g, geom, det, run, atm, bins, cnt, head, roof, extra)
+
+
+def bench_inclined_table(torch, cphot, S, atm, run, bins, cnt, stream, steps, nb, exact_bins, ms, ms_w, extra):
     t0 = time.perf_counter()
     tab = cphot.Table(atm, run["h_obs"], "curved", n_c=512, c_lo=0.15)
     tab_build_s = time.perf_counter() - t0
@@ -288,13 +324,19 @@ def bench_inclined(torch, cphot, W, args, stream):
                                    table=tab)
     ms_t, kern_t, b_t, c_t = run_path(torch, cphot, S, det_t, nb, stream, max(3, steps // 2), 1, torch.float64)
     extra["table"] = {"value": float(c_t[3]) * run["bunch"] / (ms_t * 1e-3), "unit": "photons/s", "ms_per_step": ms_t,
-                      "kernel_ms": kern_t, "speedup_vs_exact": ms / ms_t, "speedup_vs_walk": ms_w / ms_t,
+                      "kernel_ms": kern_t, "speedup_vs_exact": ms / ms_t,
+                      "speedup_vs_walk": ms_w / ms_t if ms_w else None,
                       "density_error_vs_exact": density_error(b_t, exact_bins),
                       "fallback_fraction": float(c_t[9]) / max(float(c_t[3]), 1.0), "build_s": tab_build_s,
                       "tuning": tune_t,
                       "note": "interpolation tracing (Sec. 4.4.1), curved shells: 4 heights per shell x 512 "
                               "tan-zenith nodes up to 81 deg"}
     log(f"inclined table: {extra['table']['value']:.3e} photons/s")
+    tab.close()
+
+
+def finish_inclined(torch, cphot, W, args, stream, sh, g, geom, det, run, atm, bins, cnt, head, roof, extra):
+    """The whole shower streamed from host memory with the headline's detector."""
     if args.inclined_chunks > 0:
         chunks = [sh] + [W.workload_inclined_chunk(k, beta=args.beta) for k in range(1, args.inclined_chunks)]
         streamer = cphot.Streamer(sh.n)
@@ -749,6 +791,8 @@ def main():
     ap.add_argument("--no-cuts", action="store_true", help="skip the telescope steps with cuts, reduction and options")
     ap.add_argument("--telescope-shape", default="512,512,1", metavar="BS,GRID,LDS|auto",
                     help="launch shape of the exact telescope step: a fixed shape (default) or 'auto'")
+    ap.add_argument("--inclined-paths", default="walk,surrogate,table",
+                    help="paths run beside the headline on the inclined chunk (comma list; empty for none)")
     ap.add_argument("--inclined-chunks", type=int, default=10,
                     help="chunks of 1e7 segments streamed from host memory (0: only the resident chunk)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
@@ -790,7 +834,8 @@ def main():
                    "path": "exact (closed-form shell sums, shell walk beyond them)",
                    "records_per_step": head["records"], "photons_per_step": head["photons"],
                    "segments_per_s": head["segments"] / (head["ms_per_step"] * 1e-3),
-                   "kernel_ms": head["kernel_ms"], "tuning": head["tuning"]},
+                   "kernel_ms": head["kernel_ms"], "tuning": head["tuning"],
+                   "records_walked": head["records_walked"], "fluorescence_records": head["fluorescence_records"]},
         "roofline": roof,
         "inclined": inclined,
     }

@@ -150,6 +150,14 @@ extern "C" {
  * Refraction bound: H tan(zeta) E (1 + 3 tan^2(zeta)) x 1.1 + 0.5 m, E the largest
  *   |n_i - n_j| / n_i over the layers above the observation layer (0 for STRAIGHT).
  *   Directions with cos(zeta) <= 0.2, or with 2.2 tan^2(zeta) E > 0.25, are never cut.
+ * GRID (PHOTON only; STRAIGHT, LAYERED, planar TABLE or any curved transport): a record
+ *   whose straight line lands farther from the grid rectangle than the refraction bound
+ *   is outside before its transport. Planar layers: the bound above. Spherical shells
+ *   (n - 1 non-increasing with height, else UNSUPPORTED): E sec^2(z_end) (R + h_obs)
+ *   psi_s x 1.1 + 1 m, psi_s the central angle the straight line sweeps to the sphere
+ *   R + h_obs and z_end its local zenith there (Bouguer's invariant bounds the shortfall
+ *   of the refracted path's central angle); rays whose straight line misses the sphere
+ *   are never cut.
  * Cuts act in cphot_propagate (and captured steps) only; the parity entry points
  * (counts, records) ignore them. */
 #define CPHOT_CUT_TRACK 1
@@ -260,7 +268,8 @@ typedef struct {
   int32_t hist_window;      /* tuning: GRID LDS window side in cells (0 = the largest that fits) */
   const cphot_surrogate* surrogate; /* SURROGATE transport: a trained network (else NULL) */
   int32_t emission;         /* CPHOT_EMIT_* bits (0 = Cherenkov) */
-  int32_t cuts;             /* CPHOT_CUT_* bits (SPHERES with STRAIGHT, LAYERED or TABLE transport; else 0) */
+  int32_t cuts;             /* CPHOT_CUT_* bits (SPHERES: STRAIGHT, LAYERED or TABLE transport; GRID: PHOTON
+                               with STRAIGHT, LAYERED, planar TABLE or curved transports; else 0) */
   double fl_yield[3];       /* fluorescence photons per MeV deposited, per band */
   double fl_lambda[3];      /* band wavelengths, nm (inside the atmosphere's band) */
   const cphot_table* table; /* TABLE transport: a correction table built for this atmosphere and h_obs */

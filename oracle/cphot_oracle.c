@@ -1029,8 +1029,13 @@ int orc_layered_ray(const orc_atmo* A, const double* P, const double* u, double 
  * the optical path excess e = sum n_i l_i - l_straight (m) and log T = -tau. */
 
 /* Training inputs i = first .. first+n-1 drawn from two Philox blocks with
- * counters (i low, 0, i high, 8) and (i low, 1, i high, 8): h_obs, h_e, cos(theta), phi uniform in
- * the domain box (h_e at or above h_obs), the wavelength a uniformly drawn bin. */
+ * counters (i low, 0, i high, 8) and (i low, 1, i high, 8): h_obs, cos(theta), phi uniform in
+ * the domain box, the wavelength a uniformly drawn bin, and h_e the lower boundary of a
+ * uniformly drawn layer above the observation layer. A photon is straight inside its
+ * homogeneous start layer; the network is asked for the correction from that layer's
+ * lower boundary on, which is a smooth function of the boundary height, whereas the
+ * correction from the emission point jumps wherever the emission height crosses a layer
+ * boundary (Snell's invariant takes the start layer's index). */
 void orc_surrogate_inputs(const orc_atmo* A, uint64_t seed, const double* lo, const double* hi, int64_t first,
                           int64_t n, double* X) {
   for (int64_t j = 0; j < n; ++j) {
@@ -1042,8 +1047,19 @@ void orc_surrogate_inputs(const orc_atmo* A, uint64_t seed, const double* lo, co
     orc_philox(ctr0, key, w);
     orc_philox(ctr1, key, v);
     double h_obs = lo[4] + (hi[4] - lo[4]) * u24(w[0]);
-    double he_lo = lo[0] > h_obs ? lo[0] : h_obs;
-    double h_e = he_lo + (hi[0] - he_lo) * u24(w[1]);
+    /* the start: the lower boundary of a layer (shell) above the observation layer,
+       drawn uniformly among those inside the box, j = j_lo + floor(u m) formed from
+       the word's top 24 bits in integer arithmetic; inside its start layer a photon
+       travels straight, so the correction from there is that of the whole path */
+    double dh = A->p.h_top / A->p.n_layers;
+    int64_t j_obs = (int64_t)floor(h_obs / dh);
+    int64_t j_lo = (int64_t)ceil(lo[0] / dh);
+    if (j_lo < j_obs + 1) j_lo = j_obs + 1;
+    int64_t j_hi = (int64_t)floor(hi[0] / dh);
+    int64_t m = j_hi - j_lo + 1;
+    if (m < 1) m = 1;
+    int64_t jj = j_lo + (int64_t)(((uint64_t)(w[1] >> 8) * (uint64_t)m) >> 24);
+    double h_e = (double)jj * dh;
     double ct = lo[1] + (hi[1] - lo[1]) * u24(w[2]);
     double phi = lo[2] + (hi[2] - lo[2]) * u24(w[3]);
     int K = A->p.n_lam;

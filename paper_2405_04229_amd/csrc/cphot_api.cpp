@@ -19,6 +19,7 @@ struct cphot_atmosphere {
   cphot::AtmoDevice dev;
   std::vector<double> layer_delta;  // host copies (FP64) for checks
   std::vector<double> cut_e;        // per observation layer: largest |n_i - n_j| / n_i of the layers above
+  bool delta_monotone = false;      // layer n - 1 non-increasing with height (curved grid cut)
 };
 
 namespace {
@@ -148,10 +149,17 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
   if (det->cuts & ~(CPHOT_CUT_TRACK | CPHOT_CUT_PHOTON)) return fail(CPHOT_ERR_INVALID_ARG, "unknown cut bits");
   if ((det->efficiency || det->reduction) && d.n_layers < 1)
     return fail(CPHOT_ERR_INVALID_ARG, "efficiency and reduction need an atmosphere with layers and wavelength bins");
-  if (det->cuts && (det->detector != CPHOT_DETECTOR_SPHERES || curved ||
-                    (det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED &&
-                     det->transport != CPHOT_TRANSPORT_TABLE)))
-    return fail(CPHOT_ERR_UNSUPPORTED, "cuts need SPHERES with STRAIGHT, LAYERED or planar TABLE transport");
+  if (det->cuts && det->detector == CPHOT_DETECTOR_SPHERES &&
+      det->transport != CPHOT_TRANSPORT_STRAIGHT && det->transport != CPHOT_TRANSPORT_LAYERED &&
+      det->transport != CPHOT_TRANSPORT_TABLE)
+    return fail(CPHOT_ERR_UNSUPPORTED, "cuts on SPHERES need STRAIGHT, LAYERED or planar TABLE transport");
+  if (det->cuts && det->detector == CPHOT_DETECTOR_GRID) {
+    if (det->cuts & CPHOT_CUT_TRACK) return fail(CPHOT_ERR_UNSUPPORTED, "the track cut is for SPHERES");
+    if (det->transport == CPHOT_TRANSPORT_SURROGATE && !curved_sur)
+      return fail(CPHOT_ERR_UNSUPPORTED, "the grid photon cut takes no planar surrogate transport");
+    if (curved && !a->delta_monotone)
+      return fail(CPHOT_ERR_UNSUPPORTED, "the curved grid photon cut needs n - 1 non-increasing with height");
+  }
   if ((det->emission & CPHOT_EMIT_FLUORESCENCE) && seg->n > 0 && !seg->dedx)
     return fail(CPHOT_ERR_INVALID_ARG, "fluorescence needs the dedx column");
   if (det->detector != CPHOT_DETECTOR_GRID && det->detector != CPHOT_DETECTOR_SPHERES)
@@ -273,6 +281,9 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     p.nx = det->nx; p.ny = det->ny;
     p.cell = (float)det->cell;
     p.inv_cell = (float)(1.0 / det->cell);
+    p.cuts = need_bins ? det->cuts : 0;  // the parity entry points trace every record
+    if (det->transport != CPHOT_TRANSPORT_STRAIGHT && d.n_layers > 0)
+      p.cut_e = (float)(a->cut_e[(size_t)p.obs_layer] * (1.0 + 1e-6));
     if (need_bins && out->bins_capacity < ns * (int64_t)det->nx * det->ny)
       return fail(CPHOT_ERR_INVALID_ARG, "bins_capacity below n_showers * nx * ny");
   } else {
@@ -611,6 +622,8 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
     // refraction bound of the data-reduction cuts: for the layers from obs up,
     // |n_i - n_j| / n_i <= (max delta - min delta) / (1 + min delta)
     a->cut_e.assign(L, 0.0);
+    a->delta_monotone = true;
+    for (int i = 0; i + 1 < L; ++i) a->delta_monotone = a->delta_monotone && lay[i].x >= lay[i + 1].x;
     double dmin = 1e300, dmax = -1e300;
     for (int obs = L - 1; obs >= 0; --obs) {
       dmin = std::min(dmin, (double)lay[obs].x);

@@ -273,6 +273,64 @@ __device__ __forceinline__ bool photon_may_hit(const KParams& p, float Px, float
   return nearest_sphere_d2(p, core_x, core_y, qx, qy) <= lim * lim;
 }
 
+// Distance from (qx, qy) on the observation level to the shower's ground grid
+// (zero inside it), squared.
+__device__ __forceinline__ float grid_out_d2(const KParams& p, float core_x, float core_y, float qx, float qy) {
+  const float gx0 = core_x - 0.5f * (float)p.nx * p.cell, gy0 = core_y - 0.5f * (float)p.ny * p.cell;
+  const float gx1 = fmaf((float)p.nx, p.cell, gx0), gy1 = fmaf((float)p.ny, p.cell, gy0);
+  const float dx = fmaxf(fmaxf(gx0 - qx, qx - gx1), 0.f), dy = fmaxf(fmaxf(gy0 - qy, qy - gy1), 0.f);
+  return fmaf(dx, dx, dy * dy);
+}
+
+// Filter level 3 for the ground grid over planar layers: the photon's straight
+// line against the grid rectangle, widened by the refraction bound of the sphere
+// cut (the landing point moves by at most H tan(z) E (1 + 3 tan^2 z) x 1.1 + 0.5 m).
+__device__ __forceinline__ bool grid_may_hit(const KParams& p, float Px, float Py, float Pz, float ux, float uy,
+                                             float uz, float core_x, float core_y) {
+  const float c = -uz;
+  if (!(c > 0.2f)) return true;
+  const float H = Pz - p.h_obs;
+  const float ic = rcp_fast(c);
+  const float t2 = fmaf(ux, ux, uy * uy) * ic * ic;
+  if (!(2.2f * t2 * p.cut_e <= 0.25f)) return true;
+  const float dref = fmaf(H * sqrt_fast(t2) * p.cut_e * fmaf(3.0f, t2, 1.0f), 1.1f, 0.5f);
+  const float s = H * ic;
+  const float qx = fmaf(s, ux, Px), qy = fmaf(s, uy, Py);
+  const float lim = dref + cut_slack(qx, qy, core_x, core_y, H);
+  return grid_out_d2(p, core_x, core_y, qx, qy) <= lim * lim;
+}
+
+// Filter level 3 for the ground grid over spherical shells, an exact bound. With the
+// refractive index non-decreasing downwards, Bouguer's invariant n r sin(z) gives
+// sin z <= sin z_s at every radius (z_s of the straight line from the same start), so
+// the ray reaches the sphere R + h_obs whenever the straight line does, never turns,
+// and tan z_s - tan z <= E tan z_s sec^2 z_s with E >= (n(r) - n_start) / n(r). The
+// central angle swept falls short of the straight line's psi_s by at most
+// E sec^2(z_end) psi_s (z_end the straight line's local zenith at the sphere, its
+// largest), and the vertical projection onto the ground plane does not stretch arcs:
+// the arrival lies within E sec^2(z_end) (R + h_obs) psi_s of the straight line's.
+// Rays whose straight line misses the sphere are never cut.
+__device__ __forceinline__ bool curved_may_land(const KParams& p, float Px, float Py, float Pz, float ux,
+                                                float uy, float uz, float rq, float h0, float core_x,
+                                                float core_y) {
+  const float Rf = (float)p.earth_radius, r1 = Rf + p.h_obs;
+  const float irq = rcp_fast(rq);
+  const float c0 = -fmaf(ux, Px * irq, fmaf(uy, Py * irq, uz * ((Pz + Rf) * irq)));
+  if (!(c0 > 0.f)) return true;
+  const float drs = (h0 - p.h_obs) * (rq + r1);  // r0^2 - r1^2
+  const float rc = rq * c0;
+  const float disc = fmaf(rc, rc, -drs);
+  if (!(disc > 0.f)) return true;
+  const float s_ch = drs * rcp_fast(rc + sqrt_fast(disc));
+  const float s0 = sqrt_fast(fmaxf((1.0f - c0) * (1.0f + c0), 0.f));
+  const float se = fminf(rq * s0 * rcp_fast(r1), 1.0f);  // sin z_end
+  const float sec2 = rcp_fast(fmaxf((1.0f - se) * (1.0f + se), 1e-30f));
+  const float psi_s = asinf(fminf(s_ch * s0 * rcp_fast(r1), 1.0f));
+  const float qx = fmaf(s_ch, ux, Px), qy = fmaf(s_ch, uy, Py);
+  const float lim = fmaf(p.cut_e * sec2, r1 * psi_s * 1.1f, 1.0f) + 1e-5f * (fabsf(qx - core_x) + fabsf(qy - core_y) + s_ch);
+  return grid_out_d2(p, core_x, core_y, qx, qy) <= lim * lim;
+}
+
 // Integral of n - 1 from height lo to height hi (m), closed form per profile.
 __device__ __forceinline__ float opt_integral(const KParams& p, float lo, float hi, float X_lo, float X_hi) {
   if (p.profile == CPHOT_PROFILE_LINSLEY5) return p.opt_scale * (X_lo - X_hi);
@@ -418,21 +476,45 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     const float qz = Pz + Rf;
     const float rq = sqrtf(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
     const float h0 = fmaf(Px, Px, fmaf(Py, Py, Pz * (2.0f * Rf + Pz))) / (rq + Rf);
+    bool cull = false;  // filter level 3: cannot land on the grid
+    if constexpr (TRANSPORT != kTransportCurvedExact) {
+      if ((p.cuts & CPHOT_CUT_PHOTON) && uz < 0.f && h0 >= p.h_obs)
+        cull = !curved_may_land(p, Px, Py, Pz, ux, uy, uz, rq, h0, core_x, core_y);
+    }
     float ym[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
     bool use_mlp = false;
-    float c0 = 0.f;  // cos of the local zenith angle (angle between -u and the upward radial)
+    float c0 = 0.f;    // cos of the local zenith angle (angle between -u and the upward radial)
+    float leg = 0.f;   // straight path inside the start shell, down to its lower boundary
+    int j0 = 0;        // start shell
     if constexpr (TRANSPORT == kTransportCurvedSurrogate) {
       const float irq = 1.0f / rq;
       c0 = -fmaf(ux, Px * irq, fmaf(uy, Py * irq, uz * (qz * irq)));
-      const bool alive = valid && emitted && (uz < 0.f) && (h0 >= p.h_obs);
-      float xin[kMlpIn] = {h0, c0, atan2f(uy, ux),
+      const bool alive = valid && emitted && (uz < 0.f) && (h0 >= p.h_obs) && !cull;
+      // the network starts at the start shell's lower boundary R + h_b (the photon is
+      // straight inside its homogeneous start shell); a start inside the observation
+      // shell is straight all the way (h_b = h_obs, nothing left to correct)
+      j0 = min((int)(h0 / p.dh), p.n_layers - 1);
+      const bool in_obs = j0 <= p.obs_layer;
+      const float h_b = in_obs ? p.h_obs : (float)j0 * p.dh;
+      const float rc0 = (Rf + h0) * c0;
+      const float dJ = (h0 - h_b) * (2.0f * Rf + h0 + h_b);  // r0^2 - r_b^2
+      const float gb = fmaf(rc0, rc0, -dJ);                   // r_b^2 cos^2 at the boundary
+      const bool reach = c0 > 0.f && gb > 0.f;
+      const float sgb = sqrtf(fmaxf(gb, 0.f));
+      leg = reach ? dJ / (rc0 + sgb) : 0.f;
+      float xin[kMlpIn] = {h_b, sgb / (Rf + h_b), atan2f(uy, ux),
                            p.lam_min + ((float)kb + 0.5f) * ((p.lam_max - p.lam_min) / (float)p.n_lam), p.h_obs};
-      use_mlp = alive && mlp_in_domain(s_img, xin);
-      if (!use_mlp) {
+      use_mlp = alive && reach && (in_obs || mlp_in_domain(s_img, xin));
+      if (!use_mlp || in_obs) {
 #pragma unroll
         for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
       }
-      mlp_forward_wave(s_img, xin, ym, s_stage);
+      // the whole wave evaluates the network together, or skips it when no lane needs it
+      if (__ballot(use_mlp && !in_obs)) mlp_forward_wave(s_img, xin, ym, s_stage);
+      if (in_obs) {
+#pragma unroll
+        for (int q = 0; q < kMlpOut; ++q) ym[q] = 0.f;
+      }
       if (EXT && !emitted) {
         o.state = 4;
         return;
@@ -444,6 +526,11 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     }
     if (h0 < p.h_obs) {
       o.state = 3;
+      return;
+    }
+    if (cull) {
+      o.state = 3;
+      o.culled = 1;
       return;
     }
     if constexpr (TRANSPORT == kTransportCurvedTable) {
@@ -470,12 +557,15 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       const float s_ch = drs / (rc + sqrtf(fmaf(rc, rc, -drs)));
       const float xs = s_ch * s0 / r1;
       const float psi_s = fmaf(xs * xs * (1.0f / 6.0f), xs, xs);
-      // the network's outputs are per metre of chord, the table's absolute
-      const float scale = (TRANSPORT == kTransportCurvedTable) ? 1.0f : s_ch;
+      // the network's outputs are per metre of the chord from the start shell's lower
+      // boundary (the same straight line, shortened by the leg inside the start
+      // shell, whose optical depth and n - 1 are added exactly); the table's are absolute
+      const float scale = (TRANSPORT == kTransportCurvedTable) ? 1.0f : s_ch - leg;
       const double psi = (double)psi_s + (double)(ym[0] * scale) / (double)r1;
       curved_arrival(p.earth_radius, p.h_obs, Px, Py, Pz, ux, uy, uz, psi, (double)(ym[1] * scale), cw.ax, cw.ay,
                      cw.az);
-      cw.tau = -ym[3] * scale;
+      const float4 Lj = s_lay[j0];
+      cw.tau = fmaf(fmaf(Lj.z, s_lam[kb].x, Lj.w * s_lam[kb].y), leg, -ym[3] * scale);
       cw.arrived = 1;
       cw.geo = 0.f;
       cw.opt = 0.f;
@@ -486,7 +576,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
                      ez = (double)Pz + (double)s_ch * uz;
         const float shift = (float)((cw.ax - ex) * axx + (cw.ay - ey) * axy + (cw.az - ez) * axz);
         cw.geo = fmaf(s_ch * 0.5f, fmaf(gx, gx, fmaf(gy, gy, gz * gz)), -shift);
-        cw.opt = ym[2] * scale;
+        cw.opt = fmaf(Lj.x, leg, ym[2] * scale);
       }
     } else {
       if constexpr (TRANSPORT == kTransportCurvedSurrogate || TRANSPORT == kTransportCurvedTable) {
@@ -541,16 +631,28 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   } else {
   float ym[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
   bool use_mlp = false;
+  float h_b = Pz;   // the network's start: the lower boundary of the start layer (no leg otherwise)
+  int j0 = 0;       // start layer
   if constexpr (TRANSPORT == CPHOT_TRANSPORT_SURROGATE) {
     const bool alive = valid && emitted && (uz < 0.f) && (Pz >= p.h_obs);
-    float xin[kMlpIn] = {Pz, -uz, atan2f(uy, ux),
+    // straight inside the homogeneous start layer; the network takes over at its lower
+    // boundary; a start inside the observation layer is straight all the way
+    j0 = min((int)(Pz * p.inv_dh), p.n_layers - 1);
+    const bool in_obs = j0 <= p.obs_layer;
+    h_b = in_obs ? p.h_obs : (float)j0 * p.dh;
+    float xin[kMlpIn] = {h_b, -uz, atan2f(uy, ux),
                          p.lam_min + ((float)kb + 0.5f) * ((p.lam_max - p.lam_min) / (float)p.n_lam), p.h_obs};
-    use_mlp = alive && mlp_in_domain(s_img, xin);
-    if (!use_mlp) {
+    use_mlp = alive && (in_obs || mlp_in_domain(s_img, xin));
+    if (!use_mlp || in_obs) {
 #pragma unroll
       for (int q = 0; q < kMlpIn; ++q) xin[q] = s_img->in_lo[q];  // finite filler for lanes that do not use it
     }
-    mlp_forward_wave(s_img, xin, ym, s_stage);
+    // the whole wave evaluates the network together, or skips it when no lane needs it
+    if (__ballot(use_mlp && !in_obs)) mlp_forward_wave(s_img, xin, ym, s_stage);
+    if (in_obs) {
+#pragma unroll
+      for (int q = 0; q < kMlpOut; ++q) ym[q] = 0.f;
+    }
     if (EXT && !emitted) {
       o.state = 4;
       return;
@@ -567,6 +669,13 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
   if constexpr (DETECTOR == CPHOT_DETECTOR_SPHERES && !kMlpTransport<TRANSPORT>) {
     if ((p.cuts & CPHOT_CUT_PHOTON) && !photon_may_hit(p, Px, Py, Pz, ux, uy, uz, core_x, core_y)) {
       o.state = 3;  // filter level 3: cannot reach a sphere
+      o.culled = 1;
+      return;
+    }
+  }
+  if constexpr (DETECTOR == CPHOT_DETECTOR_GRID && !kMlpTransport<TRANSPORT>) {
+    if ((p.cuts & CPHOT_CUT_PHOTON) && !grid_may_hit(p, Px, Py, Pz, ux, uy, uz, core_x, core_y)) {
+      o.state = 3;  // filter level 3: cannot land on the grid
       o.culled = 1;
       return;
     }
@@ -626,11 +735,14 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       vx = ux;
       vy = uy;
       vz = uz;
-      tau = -ym[3];
+      // the leg inside the start layer, down to the network's start h_b, exactly
+      const float leg = (Pz - h_b) / -uz;
+      const float4 Lj = s_lay[j0];
+      tau = fmaf(fmaf(Lj.z, s_lam[kb].x, Lj.w * s_lam[kb].y), leg, -ym[3]);
       if constexpr (NEED_TIME) {
         const float gx = ux - axx, gy = uy - axy, gz = uz - axz;
         geo = s_pl * 0.5f * (gx * gx + gy * gy + gz * gz) - (odx * axx + ody * axy);
-        opt = ym[2];
+        opt = fmaf(Lj.x, leg, ym[2]);
       }
       const float4 L = s_lay[p.obs_layer];
       const float2 sp = s_lam[kb];

@@ -65,8 +65,16 @@ __global__ __launch_bounds__(256) void k_training_set(TrainSetParams p) {
   const uint4 w = philox((uint32_t)i, 0u, (uint32_t)(i >> 32), TAG_TRAIN, p.key0, p.key1);
   const uint4 v = philox((uint32_t)i, 1u, (uint32_t)(i >> 32), TAG_TRAIN, p.key0, p.key1);
   const float h_obs = p.lo[4] + (p.hi[4] - p.lo[4]) * u24(w.x);
-  const float he_lo = fmaxf(p.lo[0], h_obs);
-  const float h_e = he_lo + (p.hi[0] - he_lo) * u24(w.y);
+  // start: the lower boundary of a layer (shell) above the observation layer, drawn
+  // uniformly among those in the box (integer arithmetic on the word's top 24 bits);
+  // inside its start layer a photon is straight, so the network learns the
+  // correction from that boundary on, a smooth function of the boundary height
+  const int j_obs = (int)floorf(h_obs / p.dh);
+  const int j_lo = max((int)ceilf(p.lo[0] / p.dh), j_obs + 1);
+  const int j_hi = (int)floorf(p.hi[0] / p.dh);
+  const int m = max(j_hi - j_lo + 1, 1);
+  const int jj = j_lo + (int)(((uint64_t)(w.y >> 8) * (uint64_t)m) >> 24);
+  const float h_e = (float)jj * p.dh;
   const float ct = p.lo[1] + (p.hi[1] - p.lo[1]) * u24(w.z);
   const float phi = p.lo[2] + (p.hi[2] - p.lo[2]) * u24(w.w);
   int kb = (int)floorf(u24(v.x) * (float)p.n_lam);
@@ -675,6 +683,13 @@ int cphot_surrogate_make_training_set(const cphot_surrogate* s, const cphot_atmo
     return sfail(CPHOT_ERR_INVALID_ARG, "domain wavelengths must cover the atmosphere's band");
   if (s->d.in_lo[0] < s->d.in_lo[4])
     return sfail(CPHOT_ERR_INVALID_ARG, "domain emission heights must start at or above the lowest observation level");
+  {  // the starts are layer boundaries above the observation layer: the box must hold one for every h_obs
+    const double dh = (double)p.dh;
+    if (!((std::floor(s->d.in_hi[4] / dh) + 1.0) * dh <= s->d.in_hi[0]) ||
+        !(std::ceil(s->d.in_lo[0] / dh) * dh <= s->d.in_hi[0]))
+      return sfail(CPHOT_ERR_INVALID_ARG, "the emission-height range must hold a layer boundary above every "
+                                          "observation layer of the box");
+  }
   p.geometry = s->d.geometry;
   p.earth_radius = cphot::atmosphere_earth_radius(atm);
   if (p.geometry == CPHOT_SURROGATE_CURVED && !(p.earth_radius > 1e5 && std::isfinite(p.earth_radius)))

@@ -171,8 +171,16 @@ def compare_records(gpu, orc, core, atm_kw, run_kw, surv_thr=None):
         lam_edge = lbm < FLIP_LAMBIN
     ok_tau = live & ~lam_edge
     assert np.all(dtau[ok_tau] <= TAU_REL * orc["tau"][ok_tau] + TAU_ABS), f"max tau error {dtau[ok_tau].max()}"
-    return int(flips.sum()), dict(n=len(orc), flips=int(flips.sum()), max_pos_frac=float(
-        np.max(dpos[live] / pos_tol[live])) if live.any() else 0.0)
+    def mx(a):
+        return float(a.max()) if a.size else 0.0
+    report = dict(n=len(orc), flips=int(flips.sum()), compared=int(live.sum()),
+                  max_pos_frac=mx(dpos[live] / pos_tol[live]),
+                  max_pos_m=mx(dpos[live]), max_pos_rel=mx(dpos[live] / np.maximum(r[live], POS_FLOOR)),
+                  max_t_ns=mx(dt[live]), max_t_rel=mx(dt[live] / np.maximum(np.abs(orc["t"][live]), 1e-9)),
+                  max_tau=mx(dtau[ok_tau]), max_tau_rel=mx(dtau[ok_tau] / np.maximum(orc["tau"][ok_tau], 1e-12)),
+                  max_dir=float(np.abs(du).max()) if du.size else 0.0)
+    print("parity errors:", report)
+    return int(flips.sum()), report
 
 
 def chi2_two_sample(a, b, min_count=20):

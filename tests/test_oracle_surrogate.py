@@ -23,6 +23,16 @@ def test_inputs_in_box_and_counter_based(atm):
     for j in range(5):
         assert X[:, j].min() >= LO[j] and X[:, j].max() <= HI[j]
     assert np.all(X[:, 0] >= X[:, 4])
+    # starts are lower layer boundaries above the observation layer, each allowed
+    # boundary equally likely
+    dh = 250.0
+    j = X[:, 0] / dh
+    np.testing.assert_array_equal(j, np.round(j))
+    j_lo = np.maximum(np.ceil(LO[0] / dh), np.floor(X[:, 4] / dh) + 1)
+    j_hi = np.floor(HI[0] / dh)
+    assert np.all(j >= j_lo) and np.all(j <= j_hi)
+    assert stats.kstest((j - j_lo + np.random.default_rng(1).random(len(j))) / (j_hi - j_lo + 1),
+                        "uniform").pvalue > 1e-3
     centres = 300.0 + (np.arange(64) + 0.5) * 300.0 / 64
     assert np.all(np.isin(X[:, 3], centres))
     # counter-based: a window reproduces the same rows
@@ -177,11 +187,13 @@ def test_curved_targets_flat_earth_limit(atm):
     targets reduce to the planar ones."""
     flat = O.Atmosphere(**{**cases.ATMO_LAYERED, "earth_radius": 1e12})
     X = O.surrogate_inputs(flat, 12, LO, HI, 0, 400)
-    # keep clear of layer boundaries, where the planar and spherical walks may
-    # take a different layer sequence for the same start
+    # starts are layer boundaries (both walks begin in the layer above it); keep the
+    # observation level clear of boundaries, where the planar and spherical walks may
+    # end in different layers
     dh = 250.0
     m = lambda h: np.abs(h / dh - np.round(h / dh)) * dh
-    X = X[(m(X[:, 0]) > 0.05) & (m(X[:, 4]) > 0.05)]
+    X = X[m(X[:, 4]) > 0.05]
+    assert len(X) > 300
     Yc = O.surrogate_targets(flat, X, "curved") * ((X[:, 0] - X[:, 4]) / X[:, 1])[:, None]
     Yp = O.surrogate_targets(flat, X, "planar")  # absolute; the chord is (h_e - h_obs) / cos in the limit
     # what is left of the curvature: the sphere sags by x^2 / 2R below the plane
@@ -213,3 +225,43 @@ def test_curved_targets_earth_curvature_effect(atm):
 def test_curved_targets_nan_when_the_sphere_is_missed(atm):
     X = np.array([[20000.0, 0.01, 0.0, 405.46875, 2200.0]])
     assert np.all(np.isnan(O.surrogate_targets(atm, X, "curved")))
+
+
+@pytest.mark.parametrize("geometry", ["planar", "curved"])
+def test_targets_from_the_start_layer_boundary(atm, geometry):
+    """The network starts at the start layer's lower boundary: the exact correction
+    from an emission point inside layer j equals the correction from that layer's
+    lower boundary (same straight line) plus the straight leg through layer j, whose
+    optical depth and n - 1 part are ext_j l and delta_j l."""
+    rng = np.random.default_rng(5)
+    n = 300
+    dh, R, h_obs = 250.0, 6.371e6, 2200.0
+    j = rng.integers(10, 70, n)
+    he = (j + rng.uniform(0.05, 0.95, n)) * dh
+    ct = rng.uniform(0.45, 0.98, n)
+    lam = 300.0 + (rng.integers(0, 64, n) + 0.5) * 300.0 / 64
+    X = np.stack([he, ct, rng.uniform(-3, 3, n), lam, np.full(n, h_obs)], 1)
+    hb = j * dh
+    if geometry == "planar":
+        leg = (he - hb) / ct
+        cb = ct
+    else:
+        r0, rb = R + he, R + hb
+        g = (r0 * ct) ** 2 - (r0 ** 2 - rb ** 2)
+        cb = np.sqrt(g) / rb
+        leg = (r0 ** 2 - rb ** 2) / (r0 * ct + np.sqrt(g))
+    Xb = X.copy()
+    Xb[:, 0], Xb[:, 1] = hb, cb
+    Y = O.surrogate_targets(atm, X, geometry)
+    Yb = O.surrogate_targets(atm, Xb, geometry)
+    d, ext = atm.layer_tables()
+    k = np.floor((lam - 300.0) / 300.0 * 64).astype(int)
+    if geometry == "curved":   # per metre of chord: back to absolute values
+        def chord(h, c):
+            r, r1 = R + h, R + h_obs
+            return (r ** 2 - r1 ** 2) / (r * c + np.sqrt((r * c) ** 2 - (r ** 2 - r1 ** 2)))
+        Y = Y * chord(he, ct)[:, None]
+        Yb = Yb * chord(hb, cb)[:, None]
+    np.testing.assert_allclose(Y[:, 0], Yb[:, 0], rtol=1e-6, atol=1e-6)                    # landing offset (m)
+    np.testing.assert_allclose(Y[:, 2], Yb[:, 2] + d[j] * leg, rtol=1e-6, atol=1e-6)         # path excess (m)
+    np.testing.assert_allclose(Y[:, 3], Yb[:, 3] - ext[j, k] * leg, rtol=1e-9, atol=1e-9)   # log T
