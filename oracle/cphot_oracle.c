@@ -1026,7 +1026,11 @@ int orc_layered_ray(const orc_atmo* A, const double* P, const double* u, double 
  * layered path from the straight line started at the same point and direction,
  * expressed along and across the photon's horizontal direction (the frame the
  * configuration leaves open; in a planar atmosphere the offset lies along it),
- * the optical path excess e = sum n_i l_i - l_straight (m) and log T = -tau. */
+ * and the parts of the optical path excess sum n_i l_i - l_straight (m) and of
+ * log T = -tau that refraction adds to the straight line's own sums over the same
+ * layers (sum (n_i - 1) and extinction times the straight line's slant span in each
+ * layer): what the correction has to carry, the straight line's share being exact
+ * and cheap. */
 
 /* Training inputs i = first .. first+n-1 drawn from two Philox blocks with
  * counters (i low, 0, i high, 8) and (i low, 1, i high, 8): h_obs, cos(theta), phi uniform in
@@ -1103,14 +1107,27 @@ void orc_surrogate_targets(const orc_atmo* A, int64_t n, const double* X, double
     optical += (1.0 + A->layer_delta[layer]) * s;
     tau += A->layer_ext[(size_t)layer * p->n_lam + kbin] * s;
     double s_straight = (h_obs - h_e) / u[2];
+    /* the straight line's own sums over the same layers: n - 1 and extinction
+     * times the slant length of each layer's span between h_obs and h_e */
+    double opt_straight = 0.0, tau_straight = 0.0;
+    int top_layer = (int)floor(h_e / dh);
+    if (top_layer > p->n_layers - 1) top_layer = p->n_layers - 1;
+    for (int i = obs_layer; i <= top_layer; ++i) {
+      double lo = i * dh > h_obs ? i * dh : h_obs;
+      double hi = (i + 1) * dh < h_e ? (i + 1) * dh : h_e;
+      if (i == p->n_layers - 1) hi = h_e;
+      if (!(hi > lo)) continue;
+      opt_straight += A->layer_delta[i] * (hi - lo) / ct;
+      tau_straight += A->layer_ext[(size_t)i * p->n_lam + kbin] * (hi - lo) / ct;
+    }
     double* y = Y + 4 * j;
     /* landing offset in the photon's azimuthal frame: along and across its
      * horizontal direction (cos phi, sin phi) */
     double ox = pos[0] - s_straight * u[0], oy = pos[1] - s_straight * u[1];
     y[0] = ox * cos(phi) + oy * sin(phi);
     y[1] = -ox * sin(phi) + oy * cos(phi);
-    y[2] = optical - s_straight;
-    y[3] = -tau;
+    y[2] = (optical - s_straight) - opt_straight;
+    y[3] = -tau + tau_straight;
   }
 }
 

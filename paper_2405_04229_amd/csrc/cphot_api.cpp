@@ -500,6 +500,7 @@ int atmosphere_layer_view(const cphot_atmosphere* a, const float4** layers, cons
   *lam_max = (float)a->d.lambda_max_nm;
   return CPHOT_OK;
 }
+const float4* atmosphere_layer_moments(const cphot_atmosphere* a) { return a ? a->dev.moments : nullptr; }
 }  // namespace cphot
 
 extern "C" {

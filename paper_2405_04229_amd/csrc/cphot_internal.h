@@ -138,6 +138,10 @@ int atmosphere_layer_view(const cphot_atmosphere* atm, const float4** layers, co
 // Inference image of a surrogate and whether its normalisation is set.
 const MlpImage* surrogate_image(const cphot_surrogate* s);
 double atmosphere_earth_radius(const cphot_atmosphere* a);
+// Closed-form layer-sum moments [obs][j][5] (null without layers): the m = 0 entries
+// r[2].x, r[2].w, r[3].z hold dh sum (n_i - 1), dh sum of the Rayleigh and aerosol
+// parts over the full layers between observation layer obs and layer j.
+const float4* atmosphere_layer_moments(const cphot_atmosphere* a);
 int surrogate_geometry(const cphot_surrogate* s);
 bool surrogate_ready(const cphot_surrogate* s);
 // internal transport ids: SURROGATE / TABLE transport over curved shells

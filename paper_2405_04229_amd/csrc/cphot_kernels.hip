@@ -735,17 +735,31 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       vx = ux;
       vy = uy;
       vz = uz;
-      // the leg inside the start layer, down to the network's start h_b, exactly
-      const float leg = (Pz - h_b) / -uz;
+      // the leg inside the start layer down to the network's start h_b, exactly, and
+      // for the table its absolute sums; the network predicts what refraction adds to
+      // the straight line's own sums below h_b (full layers from the layer-sum
+      // moments, the observation layer's span directly)
+      const float ic = 1.0f / -uz;
+      const float leg = (Pz - h_b) * ic;
       const float4 Lj = s_lay[j0];
-      tau = fmaf(fmaf(Lj.z, s_lam[kb].x, Lj.w * s_lam[kb].y), leg, -ym[3]);
+      const float2 sp = s_lam[kb];
+      float tau_s = 0.f, opt_s = 0.f;
+      if constexpr (TRANSPORT == CPHOT_TRANSPORT_SURROGATE) {
+        if (j0 > p.obs_layer) {
+          const float4* mr = p.moments + 5 * j0;
+          const float4 Lo = s_lay[p.obs_layer];
+          const float top = (float)(p.obs_layer + 1) * p.dh - p.h_obs;
+          tau_s = ic * fmaf(sp.x, mr[2].w, fmaf(sp.y, mr[3].z, fmaf(Lo.z, sp.x, Lo.w * sp.y) * top));
+          opt_s = ic * fmaf(Lo.x, top, mr[2].x);
+        }
+      }
+      tau = fmaf(fmaf(Lj.z, sp.x, Lj.w * sp.y), leg, tau_s - ym[3]);
       if constexpr (NEED_TIME) {
         const float gx = ux - axx, gy = uy - axy, gz = uz - axz;
         geo = s_pl * 0.5f * (gx * gx + gy * gy + gz * gz) - (odx * axx + ody * axy);
-        opt = fmaf(Lj.x, leg, ym[2]);
+        opt = fmaf(Lj.x, leg, opt_s + ym[2]);
       }
       const float4 L = s_lay[p.obs_layer];
-      const float2 sp = s_lam[kb];
       last_delta = L.x;
       last_ext = fmaf(L.z, sp.x, L.w * sp.y);
     }

@@ -41,6 +41,7 @@ __device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
 struct TrainSetParams {
   float4 const* layers;
+  float4 const* moments;  // closed-form layer-sum moments [obs][j][5] (planar targets)
   float2 const* lambins;
   int n_layers, n_lam;
   int geometry;  // CPHOT_SURROGATE_PLANAR | CPHOT_SURROGATE_CURVED
@@ -123,10 +124,19 @@ __global__ __launch_bounds__(256) void k_training_set(TrainSetParams p) {
   leg_excess(lw, span_last, lw.last_delta, s_lay[iobs].y, dr, gex);
   const float opt = fmaf(lw.last_delta, s_last, lw.opt);
   const float tau = fmaf(lw.last_ext, s_last, lw.tau);
+  // the straight line's own sums from the start boundary down to h_obs (full layers
+  // from the moments, the observation layer's span directly): the network learns
+  // only what refraction adds to them
+  const float4* mr = p.moments + ((size_t)iobs * p.n_layers + i0) * 5;
+  const float4 Lo = s_lay[iobs];
+  const float top = (float)(iobs + 1) * p.dh - h_obs, ict = 1.0f / ct;
+  const float2 sp = s_lam[kb];
+  const float opt_s = ict * fmaf(Lo.x, top, mr[2].x);
+  const float tau_s = ict * fmaf(sp.x, mr[2].w, fmaf(sp.y, mr[3].z, fmaf(Lo.z, sp.x, Lo.w * sp.y) * top));
   y[0] = dr;   // along the photon's horizontal direction
   y[1] = 0.f;  // across it: zero for horizontal layers
-  y[2] = gex + opt;
-  y[3] = -tau;
+  y[2] = (gex + opt) - opt_s;
+  y[3] = tau_s - tau;
 }
 
 // ---------------------------------------------------------------------------- normalisation
@@ -676,6 +686,8 @@ int cphot_surrogate_make_training_set(const cphot_surrogate* s, const cphot_atmo
   int rc = cphot::atmosphere_layer_view(atm, &p.layers, &p.lambins, &p.n_layers, &p.n_lam, &p.dh, &p.lam_min,
                                         &p.lam_max);
   if (rc) return sfail(rc, "the surrogate is trained on a layered atmosphere (n_layers > 0)");
+  p.moments = cphot::atmosphere_layer_moments(atm);
+  if (!p.moments) return sfail(CPHOT_ERR_INVALID_ARG, "the atmosphere has no layer-sum moments");
   const double top = (double)p.dh * p.n_layers;
   if (s->d.in_hi[0] > top || s->d.in_hi[4] > top || s->d.in_lo[4] < 0.0)
     return sfail(CPHOT_ERR_INVALID_ARG, "domain heights must lie inside the layered atmosphere");

@@ -130,7 +130,7 @@ def trained(atm):
     sur = cphot.Surrogate(LO, HI, max_batch=4096, init_seed=1)
     X, Y = sur.make_training_set(atm, 4_000_000, seed=77)
     sur.fit_normalization(Y)
-    loss = sur.train(X, Y, batch=4096, steps=12000, lr=3e-3)
+    loss = sur.train(X, Y, batch=4096, steps=30000, lr=3e-3)
     torch.cuda.synchronize()
     return sur, loss.cpu().numpy(), (X, Y)
 

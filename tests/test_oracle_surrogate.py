@@ -42,17 +42,20 @@ def test_inputs_in_box_and_counter_based(atm):
 
 
 def test_targets_homogeneous_medium():
-    """No refraction in a homogeneous medium: zero offset, excess = (n-1) l, and
-    the aerosol optical depth over the slant path."""
+    """No refraction in a homogeneous medium: the straight line is the path, so the
+    landing offset and the refraction's shares of the optical path excess and of
+    the optical depth all vanish (the straight line's own sums, (n - 1) l and the
+    aerosol depth over the slant path, are what the kernel adds itself)."""
     atm = O.Atmosphere(profile="homogeneous", delta0=2.5e-4, h_top=25000.0, n_layers=100, n_lam=8,
                        aer_tau350=0.1, aer_H=1500.0)
     X = O.surrogate_inputs(atm, 3, LO, HI, 0, 500)
     Y = O.surrogate_targets(atm, X)
     np.testing.assert_allclose(Y[:, :2], 0.0, atol=1e-8)
     ell = (X[:, 0] - X[:, 4]) / X[:, 1]
-    np.testing.assert_allclose(Y[:, 2], 2.5e-4 * ell, rtol=1e-9)
-    # homogeneous layers carry constant extinction: tau = sum over spans of ext_i span_i / cos(theta),
-    # and full layers hold the exact aerosol column at the bin centre
+    np.testing.assert_allclose(Y[:, 2], 0.0, atol=1e-9 * ell.max())
+    np.testing.assert_allclose(Y[:, 3], 0.0, atol=1e-12)
+    # homogeneous layers carry constant extinction; full layers hold the exact aerosol
+    # column at the bin centre (the straight-line sums the kernel forms from them)
     d, ext = atm.layer_tables()
     lam = X[:, 3]
     k = np.floor((lam - 300.0) / 300.0 * 8).astype(int)
@@ -60,15 +63,6 @@ def test_targets_homogeneous_medium():
     i_full = 40
     col = 0.1 * (lam / 350.0) ** -1.0 * (math.exp(-i_full * dh / 1500.0) - math.exp(-(i_full + 1) * dh / 1500.0))
     np.testing.assert_allclose(ext[i_full, k] * dh, col, rtol=1e-12)
-    tau_closed = []
-    for i in range(len(X)):
-        he, ho = X[i, 0], X[i, 4]
-        tau = 0.0
-        for layer in range(int(ho // dh), min(int(he // dh), 99) + 1):
-            lo_, hi_ = max(layer * dh, ho), min((layer + 1) * dh, he)
-            tau += ext[layer, k[i]] * (hi_ - lo_)
-        tau_closed.append(tau / X[i, 1])
-    np.testing.assert_allclose(-Y[:, 3], tau_closed, rtol=1e-9)
 
 
 def test_targets_by_snell_closed_form(atm):
@@ -101,10 +95,13 @@ def test_targets_by_snell_closed_form(atm):
             tau += ext[i, k] * sp / ci
         ls = (he - ho) / ct
         r_straight = (he - ho) * st / ct
+        # the straight line's own sums over the same spans
+        opt_s = sum(d[i] * sp for i, sp in spans.items()) / ct
+        tau_s = sum(ext[i, k] * sp for i, sp in spans.items()) / ct
         assert y[0] == pytest.approx(r - r_straight, abs=1e-7)   # along the photon's azimuth
         assert y[1] == pytest.approx(0.0, abs=1e-7)              # planar layers: no sideways offset
-        assert y[2] == pytest.approx(opt - ls, rel=1e-9, abs=1e-9)
-        assert y[3] == pytest.approx(-tau, rel=1e-10)
+        assert y[2] == pytest.approx((opt - ls) - opt_s, rel=1e-7, abs=1e-9)
+        assert y[3] == pytest.approx(-tau + tau_s, rel=1e-7, abs=1e-12)
 
 
 def test_bf16_rounding_matches_torch():
@@ -196,6 +193,13 @@ def test_curved_targets_flat_earth_limit(atm):
     assert len(X) > 300
     Yc = O.surrogate_targets(flat, X, "curved") * ((X[:, 0] - X[:, 4]) / X[:, 1])[:, None]
     Yp = O.surrogate_targets(flat, X, "planar")  # absolute; the chord is (h_e - h_obs) / cos in the limit
+    # the planar excess and log T are the refraction's shares: add the straight line's own sums back
+    d, ext = flat.layer_tables()
+    k = np.floor((X[:, 3] - 300.0) / 300.0 * ext.shape[1]).astype(int)
+    for n_, (he, ct, _, _, ho) in enumerate(X):
+        spans = [(i, min((i + 1) * dh, he) - max(i * dh, ho)) for i in range(int(ho // dh), min(int(he // dh), 99) + 1)]
+        Yp[n_, 2] += sum(d[i] * sp for i, sp in spans if sp > 0) / ct
+        Yp[n_, 3] -= sum(ext[i, k[n_]] * sp for i, sp in spans if sp > 0) / ct
     # what is left of the curvature: the sphere sags by x^2 / 2R below the plane
     # over the horizontal span x (2e-4 m at 20 km), which moves lengths by about as
     # much; and FP64 resolves positions 1e12 m from the centre to 1.2e-4 m
@@ -263,5 +267,9 @@ def test_targets_from_the_start_layer_boundary(atm, geometry):
         Y = Y * chord(he, ct)[:, None]
         Yb = Yb * chord(hb, cb)[:, None]
     np.testing.assert_allclose(Y[:, 0], Yb[:, 0], rtol=1e-6, atol=1e-6)                    # landing offset (m)
-    np.testing.assert_allclose(Y[:, 2], Yb[:, 2] + d[j] * leg, rtol=1e-6, atol=1e-6)         # path excess (m)
-    np.testing.assert_allclose(Y[:, 3], Yb[:, 3] - ext[j, k] * leg, rtol=1e-9, atol=1e-9)   # log T
+    if geometry == "planar":   # the refraction's shares: the straight leg adds nothing to them
+        np.testing.assert_allclose(Y[:, 2], Yb[:, 2], rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(Y[:, 3], Yb[:, 3], rtol=1e-6, atol=1e-12)
+    else:                      # absolute sums: the leg adds its own
+        np.testing.assert_allclose(Y[:, 2], Yb[:, 2] + d[j] * leg, rtol=1e-6, atol=1e-6)       # path excess (m)
+        np.testing.assert_allclose(Y[:, 3], Yb[:, 3] - ext[j, k] * leg, rtol=1e-9, atol=1e-9)  # log T
