@@ -262,7 +262,7 @@ def bench_inclined(torch, cphot, W, args, stream):
                 "Bouguer bound of the grid are outside before transport; same launch shape"}
     log(f"inclined exact with photon cut: {ms_c:.3f} ms/step, identical bins "
         f"{extra['exact_photon_cut']['bins_identical']}")
-    ms_w = None
+    ms_w = ms_wc = None
     if "walk" in paths:
         # the plain exact tracer: every ray walked shell by shell (Sec. 3.4.2 over shells)
         det_w, tune_w = tuned_detector(cphot, S, atm, {**run, "transport": "curved_walk"}, bins, None, cnt, stream,
@@ -273,7 +273,13 @@ def bench_inclined(torch, cphot, W, args, stream):
                          "bins_identical_to_headline": bool(np.array_equal(b_w, exact_bins)),
                          "bins_diff_l1": float(np.abs(b_w - exact_bins).sum()),
                          "note": "the iterative tracer: every ray walked shell by shell"}
-        log(f"inclined walk: {ms_w:.3f} ms/step")
+        det_wc = cphot.make_detector(atm, **{**run, "transport": "curved_walk"}, cuts=("photon",),
+                                     **{k: tune_w[k] for k in ("block_size", "grid_blocks", "lds_hist", "hist_window")})
+        ms_wc, kern_wc, b_wc, c_wc = run_path(torch, cphot, S, det_wc, nb, stream, max(3, steps // 2), 1,
+                                              torch.float64)
+        extra["walk"]["with_photon_cut"] = {"ms_per_step": ms_wc, "kernel_ms": kern_wc,
+                                            "bins_identical_to_walk": bool(np.array_equal(b_wc, b_w))}
+        log(f"inclined walk: {ms_w:.3f} ms/step, with the photon cut {ms_wc:.3f}")
     if not args.no_surrogate and "surrogate" in paths:
         sur = cphot.Surrogate(W.SURROGATE_CURVED_LO, W.SURROGATE_CURVED_HI, max_batch=4096, init_seed=2,
                               geometry="curved")
@@ -301,7 +307,7 @@ def bench_inclined(torch, cphot, W, args, stream):
             "with_photon_cut": {
                 "value": float(c_sc[3]) * run["bunch"] / (ms_sc * 1e-3), "unit": "photons/s", "ms_per_step": ms_sc,
                 "kernel_ms": kern_sc, "speedup_vs_exact_with_cut": ms_c / ms_sc,
-                "speedup_vs_walk": ms_w / ms_sc if ms_w else None,
+                "speedup_vs_walk_with_cut": ms_wc / ms_sc if ms_wc else None,
                 "density_error_vs_exact": density_error(b_sc, exact_bins),
                 "fallback_fraction": float(c_sc[9]) / max(float(c_sc[3]), 1.0),
                 "records_culled": float(c_sc[12])},

@@ -138,3 +138,62 @@ def test_trained_curved_surrogate_density_within_one_percent(trained_curved, atm
     l1 = float(np.abs(bs.astype(np.float64) - be).sum() / be.sum())
     print(dict(worst=worst, l1=l1, bins=int(m.sum()), fallback=int(cs[9])))
     assert worst <= 0.01 and l1 <= 0.01, (worst, l1)
+
+
+def _run_segments(atm, run, S, transport, sur=None, cuts=()):
+    det = cphot.make_detector(atm, **{**run, "transport": transport}, surrogate=sur, cuts=cuts)
+    bins = torch.zeros(run["nx"] * run["ny"], dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    cphot.propagate(S, det, bins, None, cnt)
+    torch.cuda.synchronize()
+    return bins.cpu().numpy(), cnt.cpu().numpy()
+
+
+def test_trained_curved_surrogate_on_the_inclined_workload(trained_curved, atm):
+    """The large inclined workload's own emission (Cherenkov and three fluorescence
+    bands, FP64 bins on the 1000 x 1000 grid of 10 m) over the first 2e6 segments of
+    its resident chunk: the network's bins within 1 % of the exact tracer's in every
+    cell with >= 1000 photons and in L1; with the grid photon cut (exact: the same
+    bins for either transport) under 2 % of the records fall back to the exact
+    tracer; and on the chunk's every-1000th-segment subset the network's bins,
+    coarsened to 100 m cells, against the FP64 oracle's."""
+    sur, _ = trained_curved
+    sh = W.workload_inclined_chunk(0)
+    n = 2_000_000
+    part = {k: v[:n] for k, v in sh.seg.items()}
+    g = np.array([[*sh.core, *sh.axis]])
+    seg, gg, off = cphot.upload(part, g)
+    S = cphot.make_segments(seg, gg, off, first_id=sh.first_id)
+    run = {**cases.RUN_INCLINED, "seed": 5}
+    be, ce = _run_segments(atm, run, S, "curved")
+    bs, cs = _run_segments(atm, run, S, "surrogate", sur)
+    bc, cc = _run_segments(atm, run, S, "surrogate", sur, cuts=("photon",))
+    assert cs[3] == ce[3] and cs[10] == ce[10] > 0     # the same records, fluorescence included
+    m = be >= 1000
+    assert m.sum() >= 200
+    worst = float(np.max(np.abs(bs[m] - be[m]) / be[m]))
+    l1 = float(np.abs(bs - be).sum() / be.sum())
+    fb, fb_cut = cs[9] / cs[3], cc[9] / cc[3]
+    print(dict(worst=worst, l1=l1, bins=int(m.sum()), fallback=float(fb), fallback_with_cut=float(fb_cut),
+               culled=int(cc[12])))
+    assert worst <= 0.01 and l1 <= 0.01, (worst, l1)
+    assert fb_cut < 0.02, fb_cut
+    # with the cut: identical to the uncut network wherever the exact tracer lands photons
+    assert float(np.abs(bc - bs).sum()) <= 1e-4 * bs.sum()
+    # against the oracle on the subset (same ids and random streams as the full launch)
+    stride = 1000
+    sub = {k: np.ascontiguousarray(v[::stride]) for k, v in sh.seg.items()}
+    sg, sgg, soff = cphot.upload(sub, g)
+    SS = cphot.make_segments(sg, sgg, soff, first_id=sh.first_id, id_stride=stride)
+    bsub, csub = _run_segments(atm, run, SS, "surrogate", sur)
+    ob, _, oc = O.propagate(O.Atmosphere(**cases.ATMO_LAYERED), O.make_run(**run), sub, g, first_id=sh.first_id,
+                            threads=8, id_stride=stride)
+    assert csub[3] == oc[3]
+    coarse = lambda b: b.reshape(100, 10, 100, 10).sum(axis=(1, 3))
+    os_, ss_ = coarse(ob[0].astype(np.float64)), coarse(bsub)
+    mo = os_ >= 1000
+    assert mo.sum() >= 20
+    worst_o = float(np.max(np.abs(ss_[mo] - os_[mo]) / os_[mo]))
+    l1_o = float(np.abs(ss_ - os_).sum() / os_.sum())
+    print(dict(oracle_worst_100m=worst_o, oracle_l1_100m=l1_o, oracle_bins=int(mo.sum())))
+    assert worst_o <= 0.01 and l1_o <= 0.01, (worst_o, l1_o)
