@@ -20,6 +20,7 @@ struct cphot_atmosphere {
   std::vector<double> layer_delta;  // host copies (FP64) for checks
   std::vector<double> cut_e;        // per observation layer: largest |n_i - n_j| / n_i of the layers above
   bool delta_monotone = false;      // layer n - 1 non-increasing with height (curved grid cut)
+  bool nb_rising = false;           // n_i b_i (index times lower radius) increasing with i (curved arrival test)
 };
 
 namespace {
@@ -272,6 +273,7 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
       p.shells = a->dev.shells + (size_t)p.obs_layer * d.n_layers * cphot::kShellRow;
       p.shell_tmax = a->dev.shell_tmax;
       p.shell_rho = (float)cphot::kShellRhoMax;
+      p.shell_nb_rising = a->nb_rising ? 1 : 0;
     }
   }
   const int64_t ns = seg->n_showers;
@@ -625,6 +627,13 @@ int cphot_make_atmosphere(const cphot_atmosphere_desc* desc, cphot_atmosphere** 
     a->cut_e.assign(L, 0.0);
     a->delta_monotone = true;
     for (int i = 0; i + 1 < L; ++i) a->delta_monotone = a->delta_monotone && lay[i].x >= lay[i + 1].x;
+    // Bouguer's invariant over the shells: with n_i b_i increasing in i the ray's
+    // impact parameter in shell i, n_j p / n_i, falls below every lower radius b_i
+    // on the way down exactly when it does so in the lowest full shell
+    a->nb_rising = finite_pos(d.earth_radius);
+    for (int i = 0; i + 1 < L && a->nb_rising; ++i)
+      a->nb_rising = (1.0 + (double)lay[i + 1].x) * (d.earth_radius + (i + 1) * dh) >
+                     (1.0 + (double)lay[i].x) * (d.earth_radius + i * dh);
     double dmin = 1e300, dmax = -1e300;
     for (int obs = L - 1; obs >= 0; --obs) {
       dmin = std::min(dmin, (double)lay[obs].x);

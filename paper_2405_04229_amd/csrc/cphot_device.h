@@ -511,7 +511,13 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
   w.geo = geo;
   w.opt = opt;
   w.arrived = arrived;
-  curved_arrival(Re, h_obs, Px, Py, Pz, ux, uy, uz, psi, 0.0, w.ax, w.ay, w.az);
+  if (arrived) {
+    curved_arrival(Re, h_obs, Px, Py, Pz, ux, uy, uz, psi, 0.0, w.ax, w.ay, w.az);
+  } else {  // left the atmosphere: no arrival point
+    w.ax = (double)Px;
+    w.ay = (double)Py;
+    w.az = (double)Pz;
+  }
 }
 
 // Closed-form shell sums for a downward ray over spherical shells (Sec. 3.3.4;
@@ -560,7 +566,8 @@ __device__ __forceinline__ float shell_acc4(float4 v, float b0, float b1, float 
 template <bool NEED_TIME>
 __device__ __forceinline__ bool curved_series(const float4* __restrict__ lay, const float* __restrict__ rows,
                                               float2 sp, float dh, int n_layers, int obs, float h_obs, double Re,
-                                              float rho_max, float t_max, float Px, float Py, float Pz, float h0,
+                                              float rho_max, float t_max, bool nb_rising, float Px, float Py,
+                                              float Pz, float h0,
                                               float ux, float uy, float uz, float axx, float axy, float axz,
                                               CurvedWalk& w) {
   const float Rf = (float)Re, twoR = (float)(2.0 * Re);
@@ -581,9 +588,32 @@ __device__ __forceinline__ bool curved_series(const float4* __restrict__ lay, co
   // straight chord from r0 to the observation sphere
   const float dO = (h0 - h_obs) * (twoR + h0 + h_obs);
   const float Gobs = G0 - dO;
-  if (!(Gobs > 0.f)) return false;
-  const float Ls = dO * rcp_fast(rc0 + sqrt_fast(Gobs));
   const float4 Lj = lay[j];
+  if (!(Gobs > 0.f)) {
+    // The straight line misses the observation sphere. Refraction bends the ray
+    // down, and it reaches the sphere iff its impact parameter in every shell,
+    // n_j p / n_i, stays below that shell's lower radius (b_i, r_obs in the
+    // observation shell); with n_i b_i increasing in i the binding shells are the
+    // observation shell and the one above it. Rays failing this turn round above
+    // the sphere and leave the atmosphere: they never arrive (no walk needed).
+    if (!nb_rising) return false;
+    const float gap = (h0 - h_obs) - r0 * (c0 * c0) * rcp_fast(1.0f + s0);  // p - r_obs
+    float g = 0.f;                                                          // bound on p - r_obs
+    if (j > obs) {
+      const float hb1 = (float)(obs + 1) * dh - h_obs;                     // b_{obs+1} - r_obs
+      g = fminf(robs * ((lay[obs].x - Lj.x) * Lj.y), fmaf(robs + hb1, (lay[obs + 1].x - Lj.x) * Lj.y, hb1));
+    }
+    if (gap < g) return false;  // bent onto the sphere: the shell walk traces it
+    w.tau = 0.f;
+    w.geo = 0.f;
+    w.opt = 0.f;
+    w.arrived = 0;
+    w.ax = (double)Px;  // no arrival point
+    w.ay = (double)Py;
+    w.az = (double)Pz;
+    return true;
+  }
+  const float Ls = dO * rcp_fast(rc0 + sqrt_fast(Gobs));
   const float extj = fmaf(Lj.z, sp.x, Lj.w * sp.y);
   float tau, dpsi = 0.f, dL = 0.f, opt = 0.f;
   if (j <= obs) {

@@ -86,6 +86,7 @@ struct KParams {
   float series_tmax;      // 0: crossing loop only
   const float* shells;    // curved: shell-moment rows of the observation shell's slice, by start shell
   float shell_tmax, shell_rho;  // curved series domain (0: shell walk only)
+  int32_t shell_nb_rising;      // n_i b_i increases with i over the shells: a closed-form arrival test holds
   int32_t cuts;           // CPHOT_CUT_* (SPHERES, propagate mode)
   const double* eff;      // detector efficiency per wavelength bin (NULL: 1)
   const double* red;      // pre-emission reduction bound per layer (NULL: none)

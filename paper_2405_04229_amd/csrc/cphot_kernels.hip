@@ -587,8 +587,8 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
         // closed-form shell sums; rays outside their domain are walked, in a
         // compacted pass (CURVED) or in place (records that are compacted already)
         if (!curved_series<NEED_TIME>(s_lay, p.shells, s_lam[kb], p.dh, p.n_layers, p.obs_layer, p.h_obs,
-                                      p.earth_radius, p.shell_rho, p.shell_tmax, Px, Py, Pz, h0, ux, uy, uz, axx,
-                                      axy, axz, cw)) {
+                                      p.earth_radius, p.shell_rho, p.shell_tmax, p.shell_nb_rising != 0, Px, Py, Pz,
+                                      h0, ux, uy, uz, axx, axy, axz, cw)) {
           if constexpr (TRANSPORT == CPHOT_TRANSPORT_CURVED) {
             o.state = kStateDeferred;
             return;

@@ -176,6 +176,16 @@ def test_shell_series_serves_most_rays_and_equals_walk(zen):
     gw = parity.device_records(cases.ATMO_LAYERED, {**run, "transport": "curved_walk"}, sh.seg, _geom(sh))
     assert len(gs) == len(gw) and len(gs) > 50_000
     both = (gs["state"] != 1) & (gw["state"] != 1)
+    # rays that never reach the observation sphere carry no arrival point (the walk
+    # leaves them at the top of the atmosphere, the series at their start); they are
+    # the same rays on both sides up to decision flips
+    def arrived(g):
+        x, y, z = (g[c].astype(np.float64) for c in "xyz")
+        return np.abs(np.sqrt(x * x + y * y + (z + 6.371e6) ** 2) - 6.371e6 - run["h_obs"]) < 1.0
+    aw, as_ = arrived(gw), arrived(gs)
+    assert (aw != as_)[both].mean() < 1e-4
+    assert np.all(gs["state"][both & ~as_] == 3)
+    both &= aw & as_
     d = np.hypot(gs["x"][both].astype(np.float64) - gw["x"][both], gs["y"][both].astype(np.float64) - gw["y"][both])
     r = np.hypot(gw["x"][both].astype(np.float64) - sh.core[0], gw["y"][both].astype(np.float64) - sh.core[1])
     assert np.all(d <= 1e-4 * np.maximum(r, 10.0) + 0.05), d.max()

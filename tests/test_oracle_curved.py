@@ -146,3 +146,48 @@ def test_start_on_a_shell_boundary(zen):
     ok1, end1, _ = O.curved_ray(atm, 2200.0, [0.0, 0.0, 12000.0 + 1e-6], u)
     assert ok0 and ok1
     np.testing.assert_allclose(end0, end1, atol=1e-5)
+
+
+def test_arrival_decided_by_bouguer_bound():
+    """A downward ray reaches the observation sphere iff its invariant K = n_j r0 sin(z)
+    stays below n_i b_i for every shell it must leave through its lower radius b_i
+    (r_obs in the observation shell). With n_i b_i increasing in i (true for air) the
+    binding values are the observation shell's and the next one's, so arrival is
+    K < min(n_obs r_obs, n_{obs+1} b_{obs+1}). Checked against the oracle's shell walk
+    on rays near the bound, where a wrong index or a dropped refraction term in
+    either would flip the outcome."""
+    atm = _atm()
+    d, _ = atm.layer_tables()
+    dh, h_obs = 250.0, 2200.0
+    obs = int(h_obs // dh)
+    nb = (1 + d) * (RE + dh * np.arange(len(d)))
+    assert np.all(np.diff(nb) > 0)
+    M = min((1 + d[obs]) * (RE + h_obs), nb[obs + 1])
+    rng = np.random.default_rng(11)
+    seen = {True: 0, False: 0}
+    for _ in range(400):
+        h0 = rng.uniform(2500.0, 20000.0)
+        j = int(h0 // dh)
+        r0 = RE + h0
+        # zenith with K / M in [1 - 2e-4, 1 + 2e-4]: around the bound, on either side
+        q = 1.0 + rng.uniform(-2e-4, 2e-4)
+        s = q * M / ((1 + d[j]) * r0)
+        if not s < 1.0:
+            continue
+        zen = math.degrees(math.asin(s))
+        ok, _, _ = O.curved_ray(atm, h_obs, [0.0, 0.0, h0], _dir(zen, rng.uniform(0.0, 360.0)))
+        K = (1 + d[j]) * r0 * math.sin(math.radians(zen))
+        if abs(K / M - 1.0) < 1e-9:
+            continue
+        assert ok == (K < M), (h0, zen, K / M - 1.0)
+        seen[bool(ok)] += 1
+    assert seen[True] > 50 and seen[False] > 50, seen
+    # the straight line misses the sphere on part of the arriving side: refraction
+    # alone brings those rays down
+    h0 = 8000.0
+    j = int(h0 // dh)
+    s_straight = (RE + h_obs) / (RE + h0)
+    s_bent = 0.5 * (s_straight + M / ((1 + d[j]) * (RE + h0)))
+    assert M / ((1 + d[j]) * (RE + h0)) > s_straight
+    ok, _, _ = O.curved_ray(atm, h_obs, [0.0, 0.0, h0], _dir(math.degrees(math.asin(s_bent)), 0.0))
+    assert ok
