@@ -167,7 +167,7 @@ def tuned_detector(cphot, S, atm, run, bins, th, cnt, stream, reps=3, **extra):
     t0 = time.perf_counter()
     tune = cphot.autotune(S, det0, bins, th, cnt, bunches=[run["bunch"]], reps=reps, stream=stream)
     tune["tune_s"] = time.perf_counter() - t0
-    shape = {k: tune[k] for k in ("block_size", "grid_blocks", "lds_hist", "hist_window")}
+    shape = cphot.shape_of(tune)
     return cphot.make_detector(atm, **run, **shape, **extra), tune
 
 
@@ -250,9 +250,7 @@ def bench_inclined(torch, cphot, W, args, stream):
     extra = {}
     paths = [x for x in args.inclined_paths.split(",") if x]
     # the same step with filter level 3 for the grid (an exact bound: identical bins)
-    det_c = cphot.make_detector(atm, **run, cuts=("photon",), block_size=tune["block_size"],
-                                grid_blocks=tune["grid_blocks"], lds_hist=tune["lds_hist"],
-                                hist_window=tune["hist_window"])
+    det_c = cphot.make_detector(atm, **run, cuts=("photon",), **cphot.shape_of(tune))
     ms_c, kern_c, b_c, c_c = run_path(torch, cphot, S, det_c, nb, stream, steps, 1, torch.float64)
     extra["exact_photon_cut"] = {
         "value": photons / (ms_c * 1e-3), "unit": "photons/s (uncut records)", "ms_per_step": ms_c,
@@ -274,7 +272,7 @@ def bench_inclined(torch, cphot, W, args, stream):
                          "bins_diff_l1": float(np.abs(b_w - exact_bins).sum()),
                          "note": "the iterative tracer: every ray walked shell by shell"}
         det_wc = cphot.make_detector(atm, **{**run, "transport": "curved_walk"}, cuts=("photon",),
-                                     **{k: tune_w[k] for k in ("block_size", "grid_blocks", "lds_hist", "hist_window")})
+                                     **cphot.shape_of(tune_w))
         ms_wc, kern_wc, b_wc, c_wc = run_path(torch, cphot, S, det_wc, nb, stream, max(3, steps // 2), 1,
                                               torch.float64)
         extra["walk"]["with_photon_cut"] = {"ms_per_step": ms_wc, "kernel_ms": kern_wc,
@@ -293,7 +291,7 @@ def bench_inclined(torch, cphot, W, args, stream):
         det_s, tune_s = tuned_detector(cphot, S, atm, {**run, "transport": "surrogate"}, bins, None, cnt, stream,
                                        reps=1, surrogate=sur)
         ms_s, kern_s, b_s, c_s = run_path(torch, cphot, S, det_s, nb, stream, max(3, steps // 2), 1, torch.float64)
-        shape_s = {k: tune_s[k] for k in ("block_size", "grid_blocks", "lds_hist", "hist_window")}
+        shape_s = cphot.shape_of(tune_s)
         det_sc = cphot.make_detector(atm, **{**run, "transport": "surrogate"}, surrogate=sur, cuts=("photon",),
                                      **shape_s)
         ms_sc, kern_sc, b_sc, c_sc = run_path(torch, cphot, S, det_sc, nb, stream, max(3, steps // 2), 1,
@@ -740,8 +738,7 @@ def bench_batched(torch, cphot, W, args, stream):
                                    min_count=1000.0, stream=stream)
     tune_s = time.perf_counter() - t0
     log(f"autotune: {tune} in {tune_s:.1f} s")
-    det = cphot.make_detector(atm, **{**run, "bunch": tune["bunch"]}, block_size=tune["block_size"],
-                              grid_blocks=tune["grid_blocks"], lds_hist=tune["lds_hist"])
+    det = cphot.make_detector(atm, **{**run, "bunch": tune["bunch"]}, **cphot.shape_of(tune))
     step_g = cphot.Step(S, det, bins, None, cnt, clear=True)
 
     def step(ev):
@@ -761,8 +758,7 @@ def bench_batched(torch, cphot, W, args, stream):
                        "200x200 grid of 5 m per shower, straight rays, Rayleigh; one HIP-graph launch per step"}
     if tune["bunch"] == 1:
         # the rate the rejected bunch of 5 would give, with the same shape, labelled as such
-        det5 = cphot.make_detector(atm, **{**run, "bunch": 5}, block_size=tune["block_size"],
-                                   grid_blocks=tune["grid_blocks"], lds_hist=tune["lds_hist"])
+        det5 = cphot.make_detector(atm, **{**run, "bunch": 5}, **cphot.shape_of(tune))
         step_5 = cphot.Step(S, det5, bins, None, cnt, clear=True)
 
         def step5(ev):
@@ -804,6 +800,8 @@ def main():
     ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--train-steps", type=int, default=20_000)
     ap.add_argument("--batch-showers", type=int, default=256)
+    ap.add_argument("--part", choices=["telescope", "batched"], default=None,
+                    help="run only this part and print its figures (for profiling; not the benchmark line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -827,6 +825,10 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
         return
     stream = torch.cuda.current_stream()
+    if args.part:
+        part = (bench_telescope if args.part == "telescope" else bench_batched)(torch, cphot, W, args, stream)
+        print(json.dumps({"part": args.part, **part}), flush=True)
+        return
     head, roof, inclined, ctx = bench_inclined(torch, cphot, W, args, stream)
     out = {
         "metric": METRIC,

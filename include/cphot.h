@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define CPHOT_ABI_VERSION 3
+#define CPHOT_ABI_VERSION 4
 #define CPHOT_NCOUNTERS 16
 
 #define CPHOT_OK 0
@@ -262,10 +262,15 @@ typedef struct {
   int32_t block_size;       /* tuning: threads per block (0 = library choice) */
   int32_t grid_blocks;      /* tuning: blocks of the persistent grid (0 = library choice) */
   int32_t lds_hist;         /* tuning: 1 = privatise the counts in LDS (GRID: the whole grid if it
-                               fits, else a window around the grid centre; SPHERES: the whole sphere
-                               array, an error if it does not fit), 0 = global atomics only,
-                               -1 = library choice */
-  int32_t hist_window;      /* tuning: GRID LDS window side in cells (0 = the largest that fits) */
+                               fits, else a window of it; SPHERES: the whole sphere array, an error
+                               if it does not fit), 0 = global atomics only, -1 = library choice */
+  int32_t hist_window;      /* tuning: GRID LDS window width in cells (0 = the largest square that fits,
+                               centred on the grid) */
+  int32_t hist_window_h;    /* tuning: GRID LDS window height in cells (0 = hist_window: a square); a
+                               window larger than the LDS allows is shrunk to fit */
+  int32_t hist_window_dx;   /* tuning: GRID LDS window centre minus grid centre, cells along x (0 =
+                               centred; clamped so that the window stays inside the grid) */
+  int32_t hist_window_dy;   /* tuning: the same along y */
   const cphot_surrogate* surrogate; /* SURROGATE transport: a trained network (else NULL) */
   int32_t emission;         /* CPHOT_EMIT_* bits (0 = Cherenkov) */
   int32_t cuts;             /* CPHOT_CUT_* bits (SPHERES: STRAIGHT, LAYERED or TABLE transport; GRID: PHOTON
@@ -395,15 +400,20 @@ typedef struct {
   int32_t grid_blocks;   /* 0 = one block per tile */
   int32_t lds_hist;
   int32_t bunch;
-  int32_t hist_window;   /* LDS window side in cells (0 with lds_hist 0) */
-  int32_t reserved0;
+  int32_t hist_window;   /* LDS window width in cells (0 with lds_hist 0) */
+  int32_t hist_window_h; /* LDS window height in cells (0 with lds_hist 0) */
   double ms;             /* mean time of one propagation with this shape */
   double photons_per_s;  /* records generated x bunch / time */
+  int32_t hist_window_dx, hist_window_dy;  /* window centre minus grid centre, cells */
 } cphot_tuning;
 
 /* Times cphot_propagate over candidate launch shapes (block size 128 / 256 /
  * 512; one block per tile or a persistent grid of 2 or 4 blocks per CU; LDS grid
- * histogram on / off where it fits) and over the bunch sizes in
+ * histogram off, or on with the whole grid when it fits, else with windows:
+ * the largest centred square, and rectangles fitted to the photon footprint of
+ * a pilot launch (global atomics only; counts summed over showers): for a few
+ * areas up to the LDS budget and aspect ratios from 1:4 to 4:1, the rectangle
+ * that holds the most photons) and over the bunch sizes in
  * `bunch_candidates` (n_bunch values >= 1; NULL = the detector's own), `reps`
  * timed launches each after one warm-up, and returns the shape and bunch with
  * the most photons per second. Larger bunches trade statistical resolution for

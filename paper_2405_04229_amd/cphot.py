@@ -65,6 +65,7 @@ class Detector(C.Structure):
                 ("pitch", C.c_double), ("radius", C.c_double), ("n_time_bins", C.c_int32),
                 ("counts_rule", C.c_int32), ("time_bin_ns", C.c_double), ("block_size", C.c_int32),
                 ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32), ("hist_window", C.c_int32),
+                ("hist_window_h", C.c_int32), ("hist_window_dx", C.c_int32), ("hist_window_dy", C.c_int32),
                 ("surrogate", C.c_void_p), ("emission", C.c_int32), ("cuts", C.c_int32),
                 ("fl_yield", C.c_double * 3), ("fl_lambda", C.c_double * 3), ("table", C.c_void_p),
                 ("efficiency", C.c_void_p), ("reduction", C.c_void_p), ("lambda_ref_nm", C.c_double)]
@@ -82,8 +83,24 @@ class TableDesc(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("grid_blocks", C.c_int32), ("lds_hist", C.c_int32),
-                ("bunch", C.c_int32), ("hist_window", C.c_int32), ("reserved0", C.c_int32), ("ms", C.c_double),
-                ("photons_per_s", C.c_double)]
+                ("bunch", C.c_int32), ("hist_window", C.c_int32), ("hist_window_h", C.c_int32), ("ms", C.c_double),
+                ("photons_per_s", C.c_double), ("hist_window_dx", C.c_int32), ("hist_window_dy", C.c_int32)]
+
+
+# launch-shape fields of cphot_detector that cphot_autotune returns
+SHAPE_KEYS = ("block_size", "grid_blocks", "lds_hist", "hist_window", "hist_window_h", "hist_window_dx",
+              "hist_window_dy")
+
+
+def shape_of(tuning: dict) -> dict:
+    """The launch shape of an autotune result, as make_detector keywords."""
+    return {k: tuning[k] for k in SHAPE_KEYS}
+
+
+def _tuning_dict(t) -> dict:
+    return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, hist_window=t.hist_window,
+                hist_window_h=t.hist_window_h, hist_window_dx=t.hist_window_dx, hist_window_dy=t.hist_window_dy,
+                bunch=t.bunch, ms=t.ms, photons_per_s=t.photons_per_s)
 
 
 class HostSegments(C.Structure):
@@ -104,7 +121,7 @@ RECORD_BYTES = 64
 
 _lock = threading.Lock()
 _lib = None
-ABI_VERSION = 3  # CPHOT_ABI_VERSION of include/cphot.h that the ctypes structs below mirror
+ABI_VERSION = 4  # CPHOT_ABI_VERSION of include/cphot.h that the ctypes structs below mirror
 
 
 def lib():
@@ -238,7 +255,8 @@ class Atmosphere:
 
 def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectrum="uniform", bunch=1, seed=0,
                   h_obs=2200.0, nx=100, ny=100, cell=10.0, snx=10, sny=10, pitch=150.0, radius=6.0, n_t=0,
-                  dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, surrogate=None,
+                  dt=1.0, block_size=0, grid_blocks=0, lds_hist=-1, hist_window=0, hist_window_h=0,
+                  hist_window_dx=0, hist_window_dy=0, surrogate=None,
                   emission="cherenkov", fl_yield=(7.0, 5.0, 2.0), fl_lambda=(337.0, 357.0, 391.0), cuts=(),
                   table=None, efficiency=None, reduction=None, counts="rounded", lambda_ref=400.0) -> Detector:
     """Fields of cphot_detector by name. `spectrum`: "uniform", "frank_tamm" or
@@ -255,7 +273,8 @@ def make_detector(atm: Atmosphere, transport="straight", detector="grid", spectr
     d.snx, d.sny, d.pitch, d.radius = int(snx), int(sny), float(pitch), float(radius)
     d.n_time_bins, d.time_bin_ns = int(n_t), float(dt)
     d.block_size, d.grid_blocks, d.lds_hist = int(block_size), int(grid_blocks), int(lds_hist)
-    d.hist_window = int(hist_window)
+    d.hist_window, d.hist_window_h = int(hist_window), int(hist_window_h)
+    d.hist_window_dx, d.hist_window_dy = int(hist_window_dx), int(hist_window_dy)
     d.emission = EMISSION[emission]
     d.cuts = sum(CUTS[c] for c in cuts)
     d.counts_rule = COUNTS[counts]
@@ -493,8 +512,7 @@ def autotune(seg: Segments, det: Detector, bins, time_hist=None, counters=None, 
     else:
         _check("cphot_autotune", lib().cphot_autotune(C.byref(seg), C.byref(det), C.byref(b), bp, nb, int(reps),
                                                       C.byref(t), _stream_ptr(stream)))
-    return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, hist_window=t.hist_window,
-                bunch=t.bunch, ms=t.ms, photons_per_s=t.photons_per_s, cached=bool(hit.value))
+    return dict(_tuning_dict(t), cached=bool(hit.value))
 
 
 def autotune_accuracy(seg: Segments, det: Detector, bins, time_hist=None, counters=None, bunches=(1,), reps=3,
@@ -511,8 +529,7 @@ def autotune_accuracy(seg: Segments, det: Detector, bins, time_hist=None, counte
            lib().cphot_autotune_accuracy(C.byref(seg), C.byref(det), C.byref(b), bc.ctypes.data_as(C.c_void_p),
                                          len(bc), int(reps), float(max_error), float(min_count),
                                          errs.ctypes.data_as(C.c_void_p), C.byref(t), _stream_ptr(stream)))
-    return dict(block_size=t.block_size, grid_blocks=t.grid_blocks, lds_hist=t.lds_hist, hist_window=t.hist_window,
-                bunch=t.bunch, ms=t.ms, photons_per_s=t.photons_per_s,
+    return dict(_tuning_dict(t),
                 bin_errors={int(k): float(e) for k, e in zip(bc, errs)}, max_error=float(max_error),
                 min_count=float(min_count))
 

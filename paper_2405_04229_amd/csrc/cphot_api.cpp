@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "cphot_internal.h"
@@ -283,6 +284,7 @@ int fill_params(const cphot_segments* seg, const cphot_detector* det, cphot::KPa
     p.nx = det->nx; p.ny = det->ny;
     p.cell = (float)det->cell;
     p.inv_cell = (float)(1.0 / det->cell);
+    p.inv_cell64 = 1.0 / (double)det->cell;
     p.cuts = need_bins ? det->cuts : 0;  // the parity entry points trace every record
     if (det->transport != CPHOT_TRANSPORT_STRAIGHT && d.n_layers > 0)
       p.cut_e = (float)(a->cut_e[(size_t)p.obs_layer] * (1.0 + 1e-6));
@@ -413,7 +415,8 @@ size_t lds_at_four_waves(int bs) {
 int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchShape& s) {
   int bs = det->block_size ? det->block_size : 256;
   if (bs != 128 && bs != 256 && bs != 512) return fail(CPHOT_ERR_INVALID_ARG, "block_size must be 0, 128, 256 or 512");
-  if (det->hist_window < 0) return fail(CPHOT_ERR_INVALID_ARG, "hist_window must be >= 0");
+  if (det->hist_window < 0 || det->hist_window_h < 0)
+    return fail(CPHOT_ERR_INVALID_ARG, "hist_window and hist_window_h must be >= 0");
   size_t lds = 0;
   p.lds_hist = 0;
   p.hist_w = p.hist_h = p.hist_x0 = p.hist_y0 = p.hist_tw = 0;
@@ -422,8 +425,16 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
   if (mode == cphot::MODE_PROPAGATE && p.detector == CPHOT_DETECTOR_GRID && det->lds_hist != 0) {
     const size_t room = stat < kLdsBudget ? (kLdsBudget - stat) / 4 : 0;  // cells that fit
     int w = p.nx, h = p.ny;
-    if ((size_t)w * h > room || det->hist_window > 0) {
-      int side = det->hist_window > 0 ? det->hist_window : (int)std::sqrt((double)room);
+    if (det->hist_window > 0) {
+      // the caller's window, shrunk (longer side first) until it fits
+      w = std::min(p.nx, det->hist_window);
+      h = std::min(p.ny, det->hist_window_h > 0 ? det->hist_window_h : det->hist_window);
+      while ((size_t)w * h > room && w > 0 && h > 0) {
+        if (w >= h) --w;
+        else --h;
+      }
+    } else if ((size_t)w * h > room) {
+      int side = (int)std::sqrt((double)room);
       while (side > 0 && (size_t)side * side > room) --side;
       w = std::min(p.nx, side);
       h = std::min(p.ny, side);
@@ -440,8 +451,8 @@ int choose_shape(const cphot_detector* det, cphot::KParams& p, int mode, LaunchS
       p.lds_hist = 1;
       p.hist_w = w;
       p.hist_h = h;
-      p.hist_x0 = (p.nx - w) / 2;
-      p.hist_y0 = (p.ny - h) / 2;
+      p.hist_x0 = std::min(std::max((p.nx - w) / 2 + det->hist_window_dx, 0), p.nx - w);
+      p.hist_y0 = std::min(std::max((p.ny - h) / 2 + det->hist_window_dy, 0), p.ny - h);
       lds = (size_t)w * h * 4;
     }
   }
@@ -990,6 +1001,86 @@ int cphot_streamer_run(cphot_streamer* s, const cphot_host_segments* host, const
 
 // ---------------------------------------------------------------- autotuner
 
+}  // extern "C"
+
+namespace {
+
+// An LDS window of the grid: width, height, and the shift of its centre from the
+// grid centre (cells), as cphot_detector carries it.
+struct Window {
+  int w, h, dx, dy;
+};
+
+// Photon footprint of one pilot launch with global atomics only: counts per grid
+// cell summed over showers (the window is the same for every shower of a launch).
+int grid_footprint(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out, hipStream_t st,
+                   std::vector<double>& foot) {
+  cphot_detector d = *det;
+  d.lds_hist = 0;
+  d.block_size = 256;
+  d.grid_blocks = 0;
+  cphot::KParams p;
+  int rc = fill_params(seg, &d, p, true, out);
+  if (rc) return rc;
+  LaunchShape sh;
+  if ((rc = choose_shape(&d, p, cphot::MODE_PROPAGATE, sh))) return rc;
+  const int64_t cells = (int64_t)det->nx * det->ny, n = cells * seg->n_showers;
+  const size_t esz = out->bins_dtype == CPHOT_BINS_U32 ? 4 : 8;
+  std::vector<unsigned char> host((size_t)n * esz);
+  hipError_t e = clear_outputs(out, st);
+  if (e == hipSuccess && p.n > 0) e = cphot::launch_propagate(p, cphot::MODE_PROPAGATE, sh.block, sh.grid, sh.lds, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), out->bins, host.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "autotune footprint");
+  foot.assign((size_t)cells, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    double v;
+    if (out->bins_dtype == CPHOT_BINS_U32) v = (double)reinterpret_cast<const uint32_t*>(host.data())[i];
+    else if (out->bins_dtype == CPHOT_BINS_U64) v = (double)reinterpret_cast<const uint64_t*>(host.data())[i];
+    else v = reinterpret_cast<const double*>(host.data())[i];
+    foot[(size_t)(i % cells)] += v;
+  }
+  return CPHOT_OK;
+}
+
+// The rectangle of at most `area` cells (sides >= 8, aspect ratios 1:4 to 4:1)
+// that holds the most footprint counts, by a summed-area table over every
+// position. False when the footprint is empty.
+bool fit_window(const std::vector<double>& foot, int nx, int ny, size_t area, Window& best) {
+  const size_t W = (size_t)nx + 1;
+  std::vector<double> S(W * ((size_t)ny + 1), 0.0);
+  for (int y = 0; y < ny; ++y) {
+    double row = 0.0;
+    for (int x = 0; x < nx; ++x) {
+      row += foot[(size_t)y * nx + x];
+      S[(size_t)(y + 1) * W + x + 1] = S[(size_t)y * W + x + 1] + row;
+    }
+  }
+  double top = 0.0;
+  bool found = false;
+  for (double r : {0.25, 1.0 / 3.0, 0.5, 2.0 / 3.0, 1.0, 1.5, 2.0, 3.0, 4.0}) {
+    const int w = std::min(nx, (int)std::sqrt((double)area * r));
+    if (w < 8) continue;
+    const int h = std::min(ny, (int)(area / (size_t)w));
+    if (h < 8) continue;
+    for (int y0 = 0; y0 + h <= ny; ++y0)
+      for (int x0 = 0; x0 + w <= nx; ++x0) {
+        const double v = S[(size_t)(y0 + h) * W + x0 + w] - S[(size_t)y0 * W + x0 + w] -
+                         S[(size_t)(y0 + h) * W + x0] + S[(size_t)y0 * W + x0];
+        if (v > top) {
+          top = v;
+          found = true;
+          best = {w, h, x0 - (nx - w) / 2, y0 - (ny - h) / 2};
+        }
+      }
+  }
+  return found;
+}
+
+}  // namespace
+
+extern "C" {
+
 int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_bins* out,
                    const int32_t* bunch_candidates, int32_t n_bunch, int32_t reps, cphot_tuning* best,
                    void* stream) {
@@ -1013,19 +1104,41 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
   cphot_tuning top{};
   top.photons_per_s = -1.0;
   int rc = CPHOT_OK;
+  // grids too large for LDS: windows fitted to the footprint of a pilot launch
+  std::vector<double> foot;
+  if (det->detector == CPHOT_DETECTOR_GRID && det->lds_hist != 0 && (int64_t)det->nx * det->ny > 4096)
+    rc = grid_footprint(seg, det, out, st, foot);
   for (int32_t b : bunches) {
     for (int bs : {128, 256, 512}) {
       for (int gpol = 0; gpol < 3 && rc == CPHOT_OK; ++gpol) {
-        int tried_w[8], n_tried = 0;
-        // LDS histogram: off, then windows of the largest size that fits and of 48 / 64 / 96 cells
-        for (int hw : {-1, 0, 48, 64, 96}) {
+        // LDS histogram: off; the largest centred square that fits; a centred 64 x 64;
+        // rectangles fitted to the footprint with up to 4096 and 9216 cells and
+        // with all the room the block's LDS budget leaves
+        std::vector<Window> wins = {{-1, 0, 0, 0}, {0, 0, 0, 0}, {64, 64, 0, 0}};
+        if (!foot.empty()) {
+          cphot_detector d = *det;
+          d.block_size = bs;
+          cphot::KParams p;
+          if ((rc = fill_params(seg, &d, p, true, out))) break;
+          const size_t stat = cphot::propagate_static_lds(p, cphot::MODE_PROPAGATE, bs);
+          const size_t room = stat < kLdsBudget ? (kLdsBudget - stat) / 4 : 0;
+          for (size_t area : {(size_t)4096, (size_t)9216, room}) {
+            Window f;
+            if (area <= room && fit_window(foot, det->nx, det->ny, area, f)) wins.push_back(f);
+          }
+        }
+        std::vector<std::array<int, 4>> tried;
+        for (const Window& win : wins) {
           if (rc != CPHOT_OK) break;
           cphot_detector d = *det;
           d.bunch = b;
           d.block_size = bs;
           d.grid_blocks = gpol == 0 ? 0 : cus * (gpol == 1 ? 2 : 4);
-          d.lds_hist = hw < 0 ? 0 : 1;
-          d.hist_window = hw < 0 ? 0 : hw;
+          d.lds_hist = win.w < 0 ? 0 : 1;
+          d.hist_window = win.w < 0 ? 0 : win.w;
+          d.hist_window_h = win.w < 0 ? 0 : win.h;
+          d.hist_window_dx = win.w < 0 ? 0 : win.dx;
+          d.hist_window_dy = win.w < 0 ? 0 : win.dy;
           cphot::KParams p;
           if ((rc = fill_params(seg, &d, p, true, out))) break;
           if (p.n == 0) break;
@@ -1034,11 +1147,12 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
             rc = CPHOT_OK;  // shape not applicable (e.g. no window fits)
             continue;
           }
-          if (hw >= 0) {  // skip windows that came out the same as one already timed
+          if (d.lds_hist) {  // skip windows that came out the same as one already timed
+            const std::array<int, 4> key = {p.hist_w, p.hist_h, p.hist_x0, p.hist_y0};
             bool seen = false;
-            for (int q = 0; q < n_tried; ++q) seen = seen || tried_w[q] == p.hist_w * 65536 + p.hist_h;
+            for (const auto& k : tried) seen = seen || k == key;
             if (seen) continue;
-            tried_w[n_tried++] = p.hist_w * 65536 + p.hist_h;
+            tried.push_back(key);
           }
           hipError_t e = clear_outputs(out, st);
           if (e == hipSuccess) e = cphot::launch_propagate(p, cphot::MODE_PROPAGATE, sh.block, sh.grid, sh.lds, st);
@@ -1064,6 +1178,9 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
             top.grid_blocks = d.grid_blocks;
             top.lds_hist = d.lds_hist;
             top.hist_window = d.lds_hist ? p.hist_w : 0;
+            top.hist_window_h = d.lds_hist ? p.hist_h : 0;
+            top.hist_window_dx = d.lds_hist ? p.hist_x0 - (p.nx - p.hist_w) / 2 : 0;
+            top.hist_window_dy = d.lds_hist ? p.hist_y0 - (p.ny - p.hist_h) / 2 : 0;
             top.bunch = b;
             top.ms = t;
             top.photons_per_s = pps;
@@ -1133,8 +1250,9 @@ void read_tune_file(TuneCache& c, const char* path) {
     if (!bar) continue;
     *bar = 0;
     cphot_tuning t{};
-    if (std::sscanf(bar + 1, "%d %d %d %d %d %lf %lf", &t.block_size, &t.grid_blocks, &t.lds_hist, &t.bunch,
-                    &t.hist_window, &t.ms, &t.photons_per_s) != 7)
+    if (std::sscanf(bar + 1, "%d %d %d %d %d %d %d %d %lf %lf", &t.block_size, &t.grid_blocks, &t.lds_hist,
+                    &t.bunch, &t.hist_window, &t.hist_window_h, &t.hist_window_dx, &t.hist_window_dy, &t.ms,
+                    &t.photons_per_s) != 10)
       continue;
     bool have = false;
     for (auto& e : c.entries) have = have || e.first == line;
@@ -1174,8 +1292,9 @@ int cphot_autotune_cached(const cphot_segments* seg, const cphot_detector* det, 
   if (cache_path) {
     FILE* fp = std::fopen(cache_path, "a");
     if (!fp) return fail(CPHOT_ERR_INVALID_ARG, std::string("cannot append to the tuning cache ") + cache_path);
-    std::fprintf(fp, "%s|%d %d %d %d %d %.17g %.17g\n", sig.c_str(), t.block_size, t.grid_blocks, t.lds_hist,
-                 t.bunch, t.hist_window, t.ms, t.photons_per_s);
+    std::fprintf(fp, "%s|%d %d %d %d %d %d %d %d %.17g %.17g\n", sig.c_str(), t.block_size, t.grid_blocks,
+                 t.lds_hist, t.bunch, t.hist_window, t.hist_window_h, t.hist_window_dx, t.hist_window_dy, t.ms,
+                 t.photons_per_s);
     std::fclose(fp);
   }
   *best = t;

@@ -346,13 +346,13 @@ __device__ __forceinline__ void curved_arrival(double Re, float h_obs, float Px,
                                                float uy, float uz, double psi, double across, double& ax,
                                                double& ay, double& az) {
   const double dqz = (double)Pz + Re;
-  const double irq = 1.0 / sqrt((double)Px * Px + (double)Py * Py + dqz * dqz);
+  const double irq = rsqrt((double)Px * Px + (double)Py * Py + dqz * dqz);
   const double dex = Px * irq, dey = Py * irq, dez = dqz * irq;
   const double dmu = ux * dex + uy * dey + uz * dez;
   double tx = ux - dmu * dex, ty = uy - dmu * dey, tz = uz - dmu * dez;
-  const double tn = sqrt(tx * tx + ty * ty + tz * tz);
-  if (tn > 0.0) {
-    const double itn = 1.0 / tn;
+  const double tn2 = tx * tx + ty * ty + tz * tz;
+  if (tn2 > 0.0) {
+    const double itn = rsqrt(tn2);
     tx *= itn;
     ty *= itn;
     tz *= itn;

@@ -96,6 +96,7 @@ struct KParams {
   const float2* lambins;
   int32_t nx, ny;
   float cell, inv_cell;
+  double inv_cell64;      // 1 / cell in FP64 (curved arrival points)
   int32_t snx, sny;
   float pitch, inv_pitch, radius;
   int32_t n_t;

@@ -618,7 +618,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     // bins in the tangent plane at the core, in FP64
     const double gx0 = (double)core_x - 0.5 * (double)p.nx * (double)p.cell;
     const double gy0 = (double)core_y - 0.5 * (double)p.ny * (double)p.cell;
-    const double fxc = floor((cw.ax - gx0) / (double)p.cell), fyc = floor((cw.ay - gy0) / (double)p.cell);
+    const double fxc = floor((cw.ax - gx0) * p.inv_cell64), fyc = floor((cw.ay - gy0) * p.inv_cell64);
     if (!(fxc >= 0.0 && fyc >= 0.0 && fxc < (double)p.nx && fyc < (double)p.ny)) {
       o.state = 3;
       return;

@@ -82,8 +82,7 @@ def test_autotune_returns_equivalent_shape():
     cnt.zero_()
     cphot.propagate(S, det, bins, None, cnt)
     ref = bins.clone()
-    tuned = cphot.make_detector(atm, **run, block_size=best["block_size"], grid_blocks=best["grid_blocks"],
-                                lds_hist=best["lds_hist"], hist_window=best["hist_window"])
+    tuned = cphot.make_detector(atm, **run, **cphot.shape_of(best))
     bins.zero_()
     cphot.propagate(S, tuned, bins, None, cnt)
     torch.cuda.synchronize()
