@@ -68,7 +68,16 @@ METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density 
 # plain copy's factors), valid only for the sources and shape they were taken on
 # (sha256 prefixes of the kernel sources), else reported as null.
 KERNEL_SOURCES = ("cphot_kernels.hip", "cphot_device.h", "cphot_internal.h", "cphot_mlp.h")
-MEASURED = {}
+MEASURED = {
+    # profiles/k_propagate_curved_inclined_1e7.md: mean of the six launches of the timed step
+    "inclined_curved": {"sha": "b2263f1e9ec1644e", "shape": [128, 1024, 1, 90, 45, 1, 1],
+                        "valu_insts": 1.0911446115e10, "hbm_bytes": (176776.03 * 2.0 + 548443.61 * 1.0) * 1024,
+                        "profile": "profiles/k_propagate_curved_inclined_1e7.md"},
+    # profiles/k_propagate_telescope_1e6.md: mean of the six launches of the timed step
+    "telescope_layered": {"sha": "b2263f1e9ec1644e", "shape": [512, 512, 1, 0, 0, 0, 0],
+                          "valu_insts": 7.3860573e7, "hbm_bytes": (16268.69 * 2.0 + 144.03 * 1.0) * 1024,
+                          "profile": "profiles/k_propagate_telescope_1e6.md"},
+}
 
 
 def sources_sha():
@@ -83,7 +92,9 @@ def measured_if_current(key, tune):
     m = MEASURED.get(key)
     if not m or m["sha"] != sources_sha():
         return None
-    if (tune["block_size"], tune["grid_blocks"], tune["lds_hist"]) != tuple(m["shape"]):
+    keys = ("block_size", "grid_blocks", "lds_hist", "hist_window", "hist_window_h", "hist_window_dx",
+            "hist_window_dy")
+    if [int(tune.get(k, 0)) for k in keys] != list(m["shape"]):
         return None
     return m
 

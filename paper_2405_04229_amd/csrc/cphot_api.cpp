@@ -1110,6 +1110,7 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
     rc = grid_footprint(seg, det, out, st, foot);
   for (int32_t b : bunches) {
     for (int bs : {128, 256, 512}) {
+      std::vector<std::array<int, 6>> tried;  // launches already timed at this block size
       for (int gpol = 0; gpol < 3 && rc == CPHOT_OK; ++gpol) {
         // LDS histogram: off; the largest centred square that fits; a centred 64 x 64;
         // rectangles fitted to the footprint with up to 4096 and 9216 cells and
@@ -1127,7 +1128,6 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
             if (area <= room && fit_window(foot, det->nx, det->ny, area, f)) wins.push_back(f);
           }
         }
-        std::vector<std::array<int, 4>> tried;
         for (const Window& win : wins) {
           if (rc != CPHOT_OK) break;
           cphot_detector d = *det;
@@ -1147,8 +1147,8 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
             rc = CPHOT_OK;  // shape not applicable (e.g. no window fits)
             continue;
           }
-          if (d.lds_hist) {  // skip windows that came out the same as one already timed
-            const std::array<int, 4> key = {p.hist_w, p.hist_h, p.hist_x0, p.hist_y0};
+          {  // skip shapes that came out the same as one already timed
+            const std::array<int, 6> key = {sh.grid, p.lds_hist, p.hist_w, p.hist_h, p.hist_x0, p.hist_y0};
             bool seen = false;
             for (const auto& k : tried) seen = seen || k == key;
             if (seen) continue;
@@ -1175,7 +1175,9 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
           const double pps = (double)gen / reps * b / (t * 1e-3);
           if (pps > top.photons_per_s) {
             top.block_size = bs;
-            top.grid_blocks = d.grid_blocks;
+            // a persistent grid by library choice is reported with its block count
+            top.grid_blocks = (d.grid_blocks == 0 && p.lds_hist && p.detector == CPHOT_DETECTOR_GRID) ? sh.grid
+                                                                                                     : d.grid_blocks;
             top.lds_hist = d.lds_hist;
             top.hist_window = d.lds_hist ? p.hist_w : 0;
             top.hist_window_h = d.lds_hist ? p.hist_h : 0;
