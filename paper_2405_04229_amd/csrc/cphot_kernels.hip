@@ -949,11 +949,11 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
   __shared__ float4 s_lay[kLayers ? kMaxLayers : 1];
   __shared__ float2 s_lam[kLayers ? kMaxLambdaBins : 1];
   __shared__ uint4 s_imgw[kMlp ? sizeof(MlpImage) / 16 : 1];
-  // compaction queue of deferred records (slot, k): at most BS enter per round and
-  // it is drained once it holds BS, so 2 BS entries suffice
+  // compaction queues of deferred records (slot, k), one ring of 128 entries per
+  // wave: at most 64 enter per round and the wave drains 64 at a time once it
+  // holds that many, so a ring never holds more than 127
   __shared__ uint16_t s_qlo[kDefer ? 2 * BS : 1];
   __shared__ uint32_t s_qk[kDefer ? 2 * BS : 1];
-  __shared__ uint32_t s_qn;
   __shared__ uint4 s_mlpx[kMlp ? BS : 1];  // per-wave staging of the network's inputs and outputs
   __shared__ KConst s_k;
   __shared__ float s_eff[kMaxLambdaBins];  // detector efficiency per wavelength bin
@@ -986,7 +986,6 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
   if (tid == 0) {
     s_win_sh = -1;
     s_since = 0u;
-    s_qn = 0u;
   }
   __syncthreads();
 
@@ -1171,6 +1170,7 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
         }
       }
     };
+    uint32_t q_head = 0, q_len = 0;  // this wave's ring of deferred records (same in every lane)
     for (uint32_t base = 0; base + tid < rounds_end; base += BS) {
       const uint32_t jr = base + tid;
       const bool valid = jr < total;
@@ -1185,30 +1185,33 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       trace<TRANSPORT, DETECTOR, kTime, EXT>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
                                         s_q1[lo], s_q2[lo], r3, s_q4[lo], s_axz[lo], s_q5[lo], k, valid, ph);
       if constexpr (kDefer) {
-        // wave-level compaction: deferred records take consecutive queue slots
-        // (ballot, prefix count of the lanes below, one LDS atomic per wave)
+        // wave-level compaction: deferred records take consecutive entries of this
+        // wave's ring (ballot and prefix count of the lanes below); the wave traces
+        // them exactly, 64 at a time, with no block barrier
         const bool push = valid && ph.state == kStateDeferred;
         const uint64_t mask = __ballot(push);
-        if (mask) {
-          const int lane = tid & 63;
-          const int leader = __ffsll((unsigned long long)mask) - 1;
-          uint32_t wbase = 0;
-          if (lane == leader) wbase = atomicAdd(&s_qn, (uint32_t)__popcll(mask));
-          wbase = __shfl(wbase, leader, 64);
-          if (push) {
-            const uint32_t pos = wbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            s_qlo[pos] = (uint16_t)lo;
-            s_qk[pos] = k;
-          }
+        const uint32_t lane = (uint32_t)(tid & 63);
+        uint16_t* q_lo = s_qlo + 2 * (tid & ~63);
+        uint32_t* q_k = s_qk + 2 * (tid & ~63);
+        if (push) {
+          const uint32_t pos = (q_head + q_len + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))) & 127u;
+          q_lo[pos] = (uint16_t)lo;
+          q_k[pos] = k;
         }
+        q_len += (uint32_t)__popcll(mask);
         if (valid && !push) consume(ph, lo, k, r3);
-        // drain the queue with full waves once it holds a round's worth, and at the end
-        __syncthreads();
-        const uint32_t qn = s_qn;
-        if (qn >= BS || (base + BS >= rounds_end && qn > 0)) {
-          for (uint32_t q = tid; q < qn; q += BS) {
-            const int qlo = s_qlo[q];
-            const uint32_t qk = s_qk[q];
+        const bool last = base + BS >= rounds_end;
+        while (q_len >= 64u || (last && q_len > 0u)) {
+          // the ring's entries written by other lanes of this wave are complete
+          // (the fences order the LDS accesses; no other wave touches this ring)
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          const uint32_t take = min(q_len, 64u);
+          if (lane < take) {
+            const uint32_t e = (q_head + lane) & 127u;
+            const int qlo = q_lo[e];
+            const uint32_t qk = q_k[e];
             const float4 q3 = s_q3[qlo];
             Photon pe;
             trace<kExact, DETECTOR, kTime, EXT>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx, s_q0[qlo], s_q1[qlo], s_q2[qlo], q3,
@@ -1216,9 +1219,12 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
             pe.fallback = 1;
             consume(pe, qlo, qk, q3);
           }
-          __syncthreads();
-          if (tid == 0) s_qn = 0u;
-          __syncthreads();
+          // every lane has read its entry before the ring takes new ones
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          q_head = (q_head + take) & 127u;
+          q_len -= take;
         }
       } else {
         if (valid) consume(ph, lo, k, r3);
