@@ -1111,10 +1111,10 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
   for (int32_t b : bunches) {
     for (int bs : {128, 256, 512}) {
       std::vector<std::array<int, 6>> tried;  // launches already timed at this block size
-      for (int gpol = 0; gpol < 3 && rc == CPHOT_OK; ++gpol) {
+      for (int gpol = 0; gpol < 4 && rc == CPHOT_OK; ++gpol) {
         // LDS histogram: off; the largest centred square that fits; a centred 64 x 64;
-        // rectangles fitted to the footprint with up to 4096 and 9216 cells and
-        // with all the room the block's LDS budget leaves
+        // rectangles fitted to the footprint with up to 2304, 4096 and 9216 cells
+        // and with all the room the block's LDS budget leaves
         std::vector<Window> wins = {{-1, 0, 0, 0}, {0, 0, 0, 0}, {64, 64, 0, 0}};
         if (!foot.empty()) {
           cphot_detector d = *det;
@@ -1123,7 +1123,7 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
           if ((rc = fill_params(seg, &d, p, true, out))) break;
           const size_t stat = cphot::propagate_static_lds(p, cphot::MODE_PROPAGATE, bs);
           const size_t room = stat < kLdsBudget ? (kLdsBudget - stat) / 4 : 0;
-          for (size_t area : {(size_t)4096, (size_t)9216, room}) {
+          for (size_t area : {(size_t)2304, (size_t)4096, (size_t)9216, room}) {
             Window f;
             if (area <= room && fit_window(foot, det->nx, det->ny, area, f)) wins.push_back(f);
           }
@@ -1133,7 +1133,7 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
           cphot_detector d = *det;
           d.bunch = b;
           d.block_size = bs;
-          d.grid_blocks = gpol == 0 ? 0 : cus * (gpol == 1 ? 2 : 4);
+          d.grid_blocks = gpol == 0 ? 0 : cus * (gpol == 1 ? 2 : (gpol == 2 ? 3 : 4));
           d.lds_hist = win.w < 0 ? 0 : 1;
           d.hist_window = win.w < 0 ? 0 : win.w;
           d.hist_window_h = win.w < 0 ? 0 : win.h;
