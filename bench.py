@@ -93,9 +93,9 @@ def measured_if_current(key, tune):
     m = MEASURED.get(key)
     if not m or m["sha"] != sources_sha():
         return None
-    keys = ("block_size", "grid_blocks", "lds_hist", "hist_window", "hist_window_h", "hist_window_dx",
-            "hist_window_dy")
-    if [int(tune.get(k, 0)) for k in keys] != list(m["shape"]):
+    # the kernel variant (block size) and the histogram mode fix the instructions issued per launch;
+    # the grid size and the window change them by under 1 % (the autotuner trials of one variant)
+    if (int(tune["block_size"]), int(tune["lds_hist"])) != (m["shape"][0], m["shape"][2]):
         return None
     return m
 
