@@ -336,50 +336,63 @@ __device__ __forceinline__ void layer_series(const float4* __restrict__ lay, con
 //   l = (ha - hb)(2R + ha + hb) / (ra ca + rb cb),  dpsi = asin(p l / (ra rb)).
 // A ray turns round inside a shell where D would become negative, and is
 // totally reflected at a boundary where the next shell's D is not positive.
-// The swept central angle is summed in FP64 and the arrival point on the
-// sphere R + h_obs is formed from it in FP64.
+// The swept central angle is summed in FP64; the arrival point on the sphere
+// R + h_obs is formed as a displacement from the emission point (below).
 // Point of the sphere R + h_obs reached after sweeping the central angle psi
-// from the emission point P in the plane of the Earth centre and the direction
-// u, moved by `across` metres normal to that plane; in FP64 (the large-radius
-// arithmetic of the curved geometry).
-__device__ __forceinline__ void curved_arrival(double Re, float h_obs, float Px, float Py, float Pz, float ux,
-                                               float uy, float uz, double psi, double across, double& ax,
+// from the emission point P (radial height h0) in the plane of the Earth centre
+// and the direction u, moved by `across` metres normal to that plane. With the
+// radial unit vector e_r at P, the unit tangent e_t (the direction's component
+// across e_r) and r1 = R + h_obs, the point is C + r1 (cos psi e_r + sin psi e_t)
+// and P = C + (R + h0) e_r, so
+//   A - P = -((h0 - h_obs) + r1 (1 - cos psi)) e_r + r1 sin psi e_t,
+// a sum of terms no larger than the path itself: FP32 carries it to about 1e-7 of
+// the displacement (a few mm over tens of km), with no radius-sized value
+// subtracted; A = P + (A - P) is formed in FP64 for the binning.
+__device__ __forceinline__ void curved_arrival(double Re, float h_obs, float Px, float Py, float Pz, float h0,
+                                               float ux, float uy, float uz, float psi, float across, double& ax,
                                                double& ay, double& az) {
-  const double dqz = (double)Pz + Re;
-  const double irq = rsqrt((double)Px * Px + (double)Py * Py + dqz * dqz);
-  const double dex = Px * irq, dey = Py * irq, dez = dqz * irq;
-  const double dmu = ux * dex + uy * dey + uz * dez;
-  double tx = ux - dmu * dex, ty = uy - dmu * dey, tz = uz - dmu * dez;
-  const double tn2 = tx * tx + ty * ty + tz * tz;
-  if (tn2 > 0.0) {
-    const double itn = rsqrt(tn2);
+  const float Rf = (float)Re;
+  const float rq = Rf + h0;  // |P - C| (its rounding scales e_r by 1 +- 6e-8)
+  const float irq = rcp_fast(rq);
+  // e_r = (Px, Py, Pz + R) / rq, its z component kept as 1 + ez1 (Pz + R - rq = Pz - h0)
+  const float erx = Px * irq, ery = Py * irq, ez1 = (Pz - h0) * irq;
+  const float mu = fmaf(ux, erx, fmaf(uy, ery, fmaf(uz, ez1, uz)));
+  float tx = fmaf(-mu, erx, ux), ty = fmaf(-mu, ery, uy), tz = fmaf(-mu, ez1, uz - mu);
+  const float tn2 = fmaf(tx, tx, fmaf(ty, ty, tz * tz));
+  if (tn2 > 0.f) {
+    const float itn = rsqrtf(tn2);
     tx *= itn;
     ty *= itn;
     tz *= itn;
   } else {
-    tx = 1.0;
-    ty = 0.0;
-    tz = 0.0;
+    tx = 1.f;
+    ty = 0.f;
+    tz = 0.f;
   }
-  double sps, cps;
-  if (fabs(psi) <= 0.5) {
-    // Taylor series to psi^9 / psi^10: the first omitted terms are below 1.2e-11
-    // and 5e-13 at |psi| = 0.5 (an arc of 3200 km), 4e-5 m and 3e-6 m on the sphere
-    const double q = psi * psi;
-    sps = psi * (1.0 + q * (-1.0 / 6 + q * (1.0 / 120 + q * (-1.0 / 5040 + q * (1.0 / 362880)))));
-    cps = 1.0 + q * (-0.5 + q * (1.0 / 24 + q * (-1.0 / 720 + q * (1.0 / 40320 + q * (-1.0 / 3628800)))));
+  float sps, omc;  // sin psi and 1 - cos psi
+  if (fabsf(psi) <= 0.5f) {
+    // Taylor series: the first omitted terms are below 3e-9 and 2e-10 of the sums at |psi| = 0.5
+    const float q = psi * psi;
+    sps = psi * fmaf(q * (-1.0f / 6.0f), fmaf(q * (-1.0f / 20.0f), fmaf(q * (-1.0f / 42.0f), fmaf(q, -1.0f / 72.0f, 1.0f), 1.0f), 1.0f), 1.0f);
+    omc = (0.5f * q) * fmaf(q * (-1.0f / 12.0f), fmaf(q * (-1.0f / 30.0f), fmaf(q * (-1.0f / 56.0f), fmaf(q, -1.0f / 90.0f, 1.0f), 1.0f), 1.0f), 1.0f);
   } else {
-    sincos(psi, &sps, &cps);
+    const float sh = sinf(0.5f * psi);
+    sps = sinf(psi);
+    omc = 2.0f * sh * sh;
   }
-  const double robs = Re + (double)h_obs;
-  ax = robs * (cps * dex + sps * tx);
-  ay = robs * (cps * dey + sps * ty);
-  az = robs * (cps * dez + sps * tz) - Re;
-  if (across != 0.0) {  // normal of the plane: e_r x e_t
-    ax += across * (dey * tz - dez * ty);
-    ay += across * (dez * tx - dex * tz);
-    az += across * (dex * ty - dey * tx);
+  const float r1 = Rf + h_obs;
+  const float rad = -fmaf(r1, omc, h0 - h_obs);  // along e_r
+  const float tan = r1 * sps;                    // along e_t
+  float dx = fmaf(rad, erx, tan * tx), dy = fmaf(rad, ery, tan * ty), dz = fmaf(rad, ez1, fmaf(tan, tz, rad));
+  if (across != 0.f) {  // normal of the plane: e_r x e_t
+    const float erz = 1.0f + ez1;
+    dx = fmaf(across, ery * tz - erz * ty, dx);
+    dy = fmaf(across, erz * tx - erx * tz, dy);
+    dz = fmaf(across, erx * ty - ery * tx, dz);
   }
+  ax = (double)Px + (double)dx;
+  ay = (double)Py + (double)dy;
+  az = (double)Pz + (double)dz;
 }
 
 struct CurvedWalk {
@@ -512,7 +525,7 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
   w.opt = opt;
   w.arrived = arrived;
   if (arrived) {
-    curved_arrival(Re, h_obs, Px, Py, Pz, ux, uy, uz, psi, 0.0, w.ax, w.ay, w.az);
+    curved_arrival(Re, h_obs, Px, Py, Pz, h0, ux, uy, uz, (float)psi, 0.f, w.ax, w.ay, w.az);
   } else {  // left the atmosphere: no arrival point
     w.ax = (double)Px;
     w.ay = (double)Py;
@@ -716,7 +729,7 @@ __device__ __forceinline__ bool curved_series(const float4* __restrict__ lay, co
     w.geo = fmaf(0.5f * Ls, fmaf(gx, gx, fmaf(gy, gy, gz * gz)), dL) - dpsi * robs * fmaf(a_t, cps, -a_r * sps);
   }
   w.arrived = 1;
-  curved_arrival(Re, h_obs, Px, Py, Pz, ux, uy, uz, (double)psi_s + (double)dpsi, 0.0, w.ax, w.ay, w.az);
+  curved_arrival(Re, h_obs, Px, Py, Pz, h0, ux, uy, uz, psi_s + dpsi, 0.f, w.ax, w.ay, w.az);
   return true;
 }
 

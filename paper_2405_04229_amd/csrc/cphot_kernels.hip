@@ -561,9 +561,8 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       // boundary (the same straight line, shortened by the leg inside the start
       // shell, whose optical depth and n - 1 are added exactly); the table's are absolute
       const float scale = (TRANSPORT == kTransportCurvedTable) ? 1.0f : s_ch - leg;
-      const double psi = (double)psi_s + (double)(ym[0] * scale) / (double)r1;
-      curved_arrival(p.earth_radius, p.h_obs, Px, Py, Pz, ux, uy, uz, psi, (double)(ym[1] * scale), cw.ax, cw.ay,
-                     cw.az);
+      const float psi = fmaf(ym[0] * scale, rcp_fast(r1), psi_s);
+      curved_arrival(p.earth_radius, p.h_obs, Px, Py, Pz, h0, ux, uy, uz, psi, ym[1] * scale, cw.ax, cw.ay, cw.az);
       const float4 Lj = s_lay[j0];
       cw.tau = fmaf(fmaf(Lj.z, s_lam[kb].x, Lj.w * s_lam[kb].y), leg, -ym[3] * scale);
       cw.arrived = 1;

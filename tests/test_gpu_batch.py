@@ -104,15 +104,20 @@ def test_lds_window_bins_identical_to_global_atomics(bs):
     torch.cuda.synchronize()
     ref_b, ref_c = bins.clone(), cnt.clone()
     assert int(ref_c[7]) > 10_000
-    for window in (0, 9, 16, 40):
+    # square windows, rectangles shifted off the centre (clamped at the grid's edges), and a
+    # rectangle larger than the LDS budget (shrunk to fit)
+    windows = [(0, 0, 0, 0), (9, 0, 0, 0), (16, 0, 0, 0), (40, 0, 0, 0), (48, 12, 5, -3), (12, 40, -7, 9),
+               (30, 20, 10_000, -10_000), (400, 300, 0, 0)]
+    for w, h, dx, dy in windows:
         for grid in (0, 7, 1024):
-            d = cphot.make_detector(atm, **run, block_size=bs, grid_blocks=grid, lds_hist=1, hist_window=window)
+            d = cphot.make_detector(atm, **run, block_size=bs, grid_blocks=grid, lds_hist=1, hist_window=w,
+                                    hist_window_h=h, hist_window_dx=dx, hist_window_dy=dy)
             bins.zero_()
             cnt.zero_()
             cphot.propagate(S, d, bins, None, cnt)
             torch.cuda.synchronize()
-            assert torch.equal(bins, ref_b), (window, grid)
-            assert torch.equal(cnt, ref_c), (window, grid)
+            assert torch.equal(bins, ref_b), (w, h, dx, dy, grid)
+            assert torch.equal(cnt, ref_c), (w, h, dx, dy, grid)
 
 
 @pytest.mark.parametrize("bs", [128, 256, 512])
@@ -237,3 +242,35 @@ def test_autotune_cache_in_memory_and_file(tmp_path):
     assert cphot.autotune(S, det, bins, None, cnt, bunches=[1, 2], reps=1, cache=True)["cached"]
     cphot.autotune_cache_clear()
     assert not cphot.autotune(S, det, bins, None, cnt, bunches=[1, 2], reps=1, cache=True)["cached"]
+
+
+def test_autotune_fitted_window_on_an_inclined_shower():
+    """A grid too large for LDS: the autotuner's pilot launch finds the footprint of a
+    60-degree shower (elongated along its azimuth) and its windows are fitted to it;
+    whatever shape wins, its bins equal those of global atomics alone, and a window
+    fitted to the footprint holds more of the photons than the centred square of the
+    same area."""
+    sh = W.make_shower(20_000, seed=77, xmax=600.0, zenith_deg=60.0, azimuth_deg=15.0, beta="R", dedx=(0.1, 2.0))
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    run = {**cases.RUN_INCLINED, "seed": 21}
+    geom = np.array([[*sh.core, *sh.axis]])
+    seg, g, off = cphot.upload(sh.seg, geom)
+    S = cphot.make_segments(seg, g, off)
+    nb = run["nx"] * run["ny"]
+    bins = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    cphot.propagate(S, cphot.make_detector(atm, **run, lds_hist=0), bins, None, cnt)
+    torch.cuda.synchronize()
+    ref = bins.cpu().numpy().reshape(run["ny"], run["nx"])
+    best = cphot.autotune(S, cphot.make_detector(atm, **run), bins, None, cnt, reps=1)
+    bins.zero_()
+    cphot.propagate(S, cphot.make_detector(atm, **run, **cphot.shape_of(best)), bins, None, cnt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(bins.cpu().numpy().reshape(run["ny"], run["nx"]), ref)
+    # the footprint: a 2:1 rectangle along x beats the centred square of the same area
+    def held(w, h, dx, dy):
+        x0 = min(max((run["nx"] - w) // 2 + dx, 0), run["nx"] - w)
+        y0 = min(max((run["ny"] - h) // 2 + dy, 0), run["ny"] - h)
+        return ref[y0:y0 + h, x0:x0 + w].sum()
+    best_rect = max(held(90, 45, dx, dy) for dx in range(-20, 21, 2) for dy in range(-10, 11, 2))
+    assert best_rect > 1.05 * held(64, 64, 0, 0), (best_rect, held(64, 64, 0, 0), ref.sum())
