@@ -70,13 +70,12 @@ METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density 
 KERNEL_SOURCES = ("cphot_kernels.hip", "cphot_device.h", "cphot_internal.h", "cphot_mlp.h")
 MEASURED = {
     # profiles/k_propagate_curved_inclined_1e7.md: mean of the six launches of the timed step
-    "inclined_curved": {"sha": "ba87d75b2c36286f", "shape": [256, 768, 1, 90, 45, 1, 1],
-                        "valu_insts": 1.07427521525e10, "hbm_bytes": (176774.72 * 2.0 + 540798.33 * 1.0) * 1024,
+    "inclined_curved": {"sha": "232f6f13ae42117c", "shape": [256, 768, 1, 90, 45, 1, 1],
+                        "valu_insts": 1.02483638013e10, "hbm_bytes": (176755.89 * 2.0 + 540798.21 * 1.0) * 1024,
                         "profile": "profiles/k_propagate_curved_inclined_1e7.md"},
-    # profiles/k_propagate_telescope_1e6.md: mean of the six launches of the timed step (the write
-    # counter was not taken at these sources: traffic unknown)
-    "telescope_layered": {"sha": "ba87d75b2c36286f", "shape": [512, 512, 1, 0, 0, 0, 0],
-                          "valu_insts": 7.836316317e7, "hbm_bytes": None,
+    # profiles/k_propagate_telescope_1e6.md: mean of the six launches of the timed step
+    "telescope_layered": {"sha": "232f6f13ae42117c", "shape": [512, 512, 1, 0, 0, 0, 0],
+                          "valu_insts": 7.836496233e7, "hbm_bytes": (16278.57 * 2.0 + 144.03 * 1.0) * 1024,
                           "profile": "profiles/k_propagate_telescope_1e6.md"},
 }
 
