@@ -464,10 +464,12 @@ void cphot_autotune_cache_clear(void);
 /* ---------------------------------------------------------------- streaming from host memory
  * A segment set too large to keep in device memory at once (the thesis feeds the
  * photon stage chunk by chunk from the shower simulation, Sec. 5.1, 5.4) is read
- * from host memory in chunks: each chunk is copied host -> pinned staging -> device
- * on the streamer's own copy stream while the previous chunk propagates on the
- * caller's stream; chunk c gets first_id + c * chunk_segments, so the photons are
- * those of one cphot_propagate over the whole set. Bins accumulate across chunks.
+ * from host memory in chunks: each chunk is copied host -> pinned staging (by up to
+ * 8 host threads) -> device on the streamer's own copy stream while the previous
+ * chunk propagates on the caller's stream; columns that are page-locked already
+ * (hipHostMalloc, a pinned tensor; every column of the call) are copied to the device
+ * directly. Chunk c gets first_id + c * chunk_segments, so the photons are those of
+ * one cphot_propagate over the whole set. Bins accumulate across chunks.
  *
  * cphot_streamer_create allocates two device chunk buffers and two pinned host
  * staging buffers of `chunk_segments` segments (36 B each with dE/dx) on the

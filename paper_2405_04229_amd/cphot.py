@@ -434,21 +434,29 @@ class Streamer:
         self._h = h
 
     def run(self, seg_np: dict, geom, det: Detector, bins, time_hist=None, counters=None, first_id=0, stream=None):
-        """`seg_np`: dict of host float32 arrays (x0..charge, optional dedx); `geom`:
-        float64 CUDA tensor [1, 5]. Accumulates into the outputs."""
+        """`seg_np`: dict of host float32 arrays (x0..charge, optional dedx): numpy
+        arrays, or CPU tensors (pinned ones are copied to the device without staging);
+        `geom`: float64 CUDA tensor [1, 5]. Accumulates into the outputs."""
         import numpy as np
         import torch
         cols = {}
         hs = HostSegments()
-        n = int(np.asarray(seg_np["x0"]).shape[0])
+        n = int(seg_np["x0"].shape[0])
         for f in SEGMENT_FIELDS + ("dedx",):
             if f == "dedx" and seg_np.get("dedx") is None:
                 continue
-            a = np.ascontiguousarray(seg_np[f], dtype=np.float32)
+            v = seg_np[f]
+            if isinstance(v, torch.Tensor):
+                if v.device.type != "cpu" or v.dtype != torch.float32 or not v.is_contiguous() or v.dim() != 1:
+                    raise ValueError(f"segment field {f} must be a contiguous 1-D float32 CPU tensor")
+                a, ptr = v, v.data_ptr()
+            else:
+                a = np.ascontiguousarray(v, dtype=np.float32)
+                ptr = a.ctypes.data
             if a.shape[0] != n:
                 raise ValueError(f"segment field {f} has length {a.shape[0]}, expected {n}")
             cols[f] = a
-            setattr(hs, f, a.ctypes.data)
+            setattr(hs, f, ptr)
         hs.n = n
         hs.first_id = int(first_id)
         if not isinstance(geom, torch.Tensor) or tuple(geom.shape) != (1, 5):
@@ -457,7 +465,7 @@ class Streamer:
         b = make_bins(bins, time_hist, counters)
         _check("cphot_streamer_run", lib().cphot_streamer_run(self._h, C.byref(hs), C.byref(det), C.byref(b),
                                                                _stream_ptr(stream)))
-        del cols  # copied into pinned staging before run returns
+        del cols  # copied (or, pinned, read by the copy engine) before run returns
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <array>
 #include <vector>
 
@@ -936,6 +937,46 @@ int cphot_streamer_create(int64_t chunk_segments, cphot_streamer** out) {
   return CPHOT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Host threads that fill a pinned staging buffer: one copy thread reads pageable
+// memory at ~10 GB/s, too slow to keep up with a chunk's propagation.
+constexpr int kStageThreads = 8;
+
+// Copies rows [c0, c0 + n) of each column into the staging buffer (column f at
+// dst + f * C), the rows split over host threads.
+void stage_columns(float* dst, const float* const* cols, int ncol, int64_t C, int64_t c0, int64_t n) {
+  const int T = (int)std::max<int64_t>(1, std::min<int64_t>(kStageThreads, n / 65536));
+  auto work = [&](int t) {
+    const int64_t a = n * t / T, b = n * (t + 1) / T;
+    for (int f = 0; f < ncol; ++f)
+      std::memcpy(dst + (size_t)f * C + a, cols[f] + c0 + a, (size_t)(b - a) * sizeof(float));
+  };
+  std::vector<std::thread> th;
+  th.reserve((size_t)T);
+  for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& x : th) x.join();
+}
+
+// Page-locked host memory known to HIP (hipHostMalloc, or a pinned tensor): the copy
+// engine reads it directly. Other pointers leave an error that is cleared here.
+bool host_pinned(const void* p) {
+  hipPointerAttribute_t a;
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeHost;
+}
+
+}  // namespace
+
+extern "C" {
+
 int cphot_streamer_run(cphot_streamer* s, const cphot_host_segments* host, const cphot_detector* det,
                        cphot_bins* out, void* stream) {
   if (!s || !host || !det || !out) return fail(CPHOT_ERR_INVALID_ARG, "null argument");
@@ -967,6 +1008,11 @@ int cphot_streamer_run(cphot_streamer* s, const cphot_host_segments* host, const
   }
   hipStream_t st = (hipStream_t)stream;
   const int64_t C = s->chunk;
+  // columns in page-locked memory are copied to the device directly, without staging
+  bool direct = host->n > 0;
+  for (int f = 0; f < ncol && direct; ++f)
+    direct = host_pinned(cols[f]) && host_pinned(cols[f] + (host->n - 1));
+  int last = -1;
   for (int64_t c0 = 0, k = 0; c0 < host->n; c0 += C, ++k) {
     const int b = (int)(k & 1);
     const int64_t n = std::min(C, host->n - c0);
@@ -974,11 +1020,11 @@ int cphot_streamer_run(cphot_streamer* s, const cphot_host_segments* host, const
     // once the propagation that read it has finished (the copy stream waits for it)
     hipError_t e = hipEventSynchronize(s->copied[b]);
     if (e != hipSuccess) return hip_fail(e, "streamer wait");
-    for (int f = 0; f < ncol; ++f) std::memcpy(s->hbuf[b] + (size_t)f * C, cols[f] + c0, (size_t)n * sizeof(float));
+    if (!direct) stage_columns(s->hbuf[b], cols, ncol, C, c0, n);
     e = hipStreamWaitEvent(s->copy, s->done[b], 0);
     for (int f = 0; f < ncol && e == hipSuccess; ++f)
-      e = hipMemcpyAsync(s->dbuf[b] + (size_t)f * C, s->hbuf[b] + (size_t)f * C, (size_t)n * sizeof(float),
-                         hipMemcpyHostToDevice, s->copy);
+      e = hipMemcpyAsync(s->dbuf[b] + (size_t)f * C, direct ? cols[f] + c0 : s->hbuf[b] + (size_t)f * C,
+                         (size_t)n * sizeof(float), hipMemcpyHostToDevice, s->copy);
     if (e == hipSuccess) e = hipEventRecord(s->copied[b], s->copy);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, s->copied[b], 0);
     if (e != hipSuccess) return hip_fail(e, "streamer copy");
@@ -995,6 +1041,12 @@ int cphot_streamer_run(cphot_streamer* s, const cphot_host_segments* host, const
     if (rc) return rc;
     e = hipEventRecord(s->done[b], st);
     if (e != hipSuccess) return hip_fail(e, "streamer record");
+    last = b;
+  }
+  // direct copies read the caller's memory until they complete
+  if (direct && last >= 0) {
+    const hipError_t e = hipEventSynchronize(s->copied[last]);
+    if (e != hipSuccess) return hip_fail(e, "streamer wait");
   }
   return CPHOT_OK;
 }

@@ -52,6 +52,33 @@ def test_streamed_curved_fluorescence_equals_resident(chunk):
     assert rc[10] > 0 and rb.sum() > 1e5
 
 
+@pytest.mark.parametrize("chunk", [9_000, 400_000])
+def test_streamed_from_pinned_and_threaded_staging_equal_resident(chunk):
+    """Pinned host columns (copied to the device without staging) and pageable ones
+    large enough to be staged by several host threads give the resident launch's
+    bins and counters; pinned columns may be reused once run returns."""
+    sh = W.make_shower(400_000, seed=504, xmax=600.0, zenith_deg=60.0, beta="R", dedx=(0.1, 2.0))
+    run = {**cases.RUN_INCLINED, "nx": 300, "ny": 300, "cell": 30.0, "seed": 33}
+    atm = cphot.Atmosphere(**cases.ATMO_LAYERED)
+    rb, rc, gg = _resident(atm, run, sh, torch.float64, 777)
+    sb, sc = _streamed(atm, run, sh, torch.float64, chunk, 777, gg)
+    np.testing.assert_array_equal(sb, rb)
+    np.testing.assert_array_equal(sc, rc)
+    pinned = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).pin_memory() for k, v in sh.seg.items()}
+    assert all(t.is_pinned() for t in pinned.values())
+    st = cphot.Streamer(chunk)
+    det = cphot.make_detector(atm, **run)
+    bins = torch.zeros(run["nx"] * run["ny"], dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(cphot.NCOUNTERS, dtype=torch.int64, device="cuda")
+    st.run(pinned, gg, det, bins, None, cnt, first_id=777)
+    for t in pinned.values():
+        t.fill_(float("nan"))  # the copies have completed: overwriting cannot reach the device
+    torch.cuda.synchronize()
+    st.close()
+    np.testing.assert_array_equal(bins.cpu().numpy(), rb)
+    np.testing.assert_array_equal(cnt.cpu().numpy(), rc)
+
+
 def test_streamed_straight_tiny_chunks_and_repeat():
     sh = W.make_shower(3_001, seed=502, beta="R")
     run = {**cases.RUN_TINY, "seed": 32}
