@@ -955,8 +955,13 @@ void stage_columns(float* dst, const float* const* cols, int ncol, int64_t C, in
       std::memcpy(dst + (size_t)f * C + a, cols[f] + c0 + a, (size_t)(b - a) * sizeof(float));
   };
   std::vector<std::thread> th;
-  th.reserve((size_t)T);
-  for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+  int started = 1;  // share 0 is this thread's; shares without a thread are copied here too
+  try {
+    th.reserve((size_t)T);
+    for (; started < T; ++started) th.emplace_back(work, started);
+  } catch (...) {
+  }
+  for (int t = started; t < T; ++t) work(t);
   work(0);
   for (auto& x : th) x.join();
 }
