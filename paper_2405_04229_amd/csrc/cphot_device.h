@@ -432,7 +432,7 @@ __device__ __forceinline__ void curved_walk(const float4* __restrict__ lay, floa
     a_t = fmaf(axx, etx, fmaf(axy, ety, axz * etz));
     a_n = fmaf(axx, enx, fmaf(axy, eny, axz * enz));
   }
-  int i = min((int)(h0 / dh), n_layers - 1);
+  int i = min((int)(h0 * (1.0f / dh)), n_layers - 1);
   const int obs = (int)floorf(h_obs / dh);
   const float A = Rf + h0;
   const float c1 = mu * mu / (1.0f + s0);  // 1 - s_0
@@ -593,7 +593,7 @@ __device__ __forceinline__ bool curved_series(const float4* __restrict__ lay, co
   if (!(c0 > 0.f)) return false;
   const float etx0 = fmaf(-mu, erx, ux), ety0 = fmaf(-mu, ery, uy), etz0 = fmaf(-mu, erz, uz);
   const float s0 = sqrt_fast(fmaf(etx0, etx0, fmaf(ety0, ety0, etz0 * etz0)));
-  const int j = min((int)(h0 / dh), n_layers - 1);
+  const int j = min((int)(h0 * (1.0f / dh)), n_layers - 1);
   const float r0 = Rf + h0;
   const float rc0 = r0 * c0, p = r0 * s0;
   const float G0 = rc0 * rc0;

@@ -474,8 +474,8 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     // height above the sphere R without subtracting R: (x^2 + y^2 + z (2R + z)) / (|P - C| + R)
     const float Rf = (float)p.earth_radius;
     const float qz = Pz + Rf;
-    const float rq = sqrtf(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
-    const float h0 = fmaf(Px, Px, fmaf(Py, Py, Pz * (2.0f * Rf + Pz))) / (rq + Rf);
+    const float rq = sqrt_fast(fmaf(Px, Px, fmaf(Py, Py, qz * qz)));
+    const float h0 = fmaf(Px, Px, fmaf(Py, Py, Pz * (2.0f * Rf + Pz))) * rcp_fast(rq + Rf);
     bool cull = false;  // filter level 3: cannot land on the grid
     if constexpr (TRANSPORT != kTransportCurvedExact) {
       if ((p.cuts & CPHOT_CUT_PHOTON) && uz < 0.f && h0 >= p.h_obs)
@@ -493,7 +493,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       // the network starts at the start shell's lower boundary R + h_b (the photon is
       // straight inside its homogeneous start shell); a start inside the observation
       // shell is straight all the way (h_b = h_obs, nothing left to correct)
-      j0 = min((int)(h0 / p.dh), p.n_layers - 1);
+      j0 = min((int)(h0 * p.inv_dh), p.n_layers - 1);
       const bool in_obs = j0 <= p.obs_layer;
       const float h_b = in_obs ? p.h_obs : (float)j0 * p.dh;
       const float rc0 = (Rf + h0) * c0;
@@ -539,7 +539,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       c0 = -fmaf(ux, Px * irq, fmaf(uy, Py * irq, uz * (qz * irq)));
       float4 v;
       const float tz = sqrtf(fmaxf((1.0f - c0) * (1.0f + c0), 0.f)) / c0;
-      use_mlp = c0 > 0.f && table_lookup(p.ctab, min((int)(h0 / p.dh), p.n_layers - 1), h0, tz, v);
+      use_mlp = c0 > 0.f && table_lookup(p.ctab, min((int)(h0 * p.inv_dh), p.n_layers - 1), h0, tz, v);
       const float2 sp = s_lam[kb];
       ym[0] = v.x;
       ym[2] = v.y;
