@@ -360,7 +360,7 @@ __device__ __forceinline__ void curved_arrival(double Re, float h_obs, float Px,
   float tx = fmaf(-mu, erx, ux), ty = fmaf(-mu, ery, uy), tz = fmaf(-mu, ez1, uz - mu);
   const float tn2 = fmaf(tx, tx, fmaf(ty, ty, tz * tz));
   if (tn2 > 0.f) {
-    const float itn = rsqrtf(tn2);
+    const float itn = __builtin_amdgcn_rsqf(tn2);
     tx *= itn;
     ty *= itn;
     tz *= itn;

@@ -487,7 +487,7 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     float leg = 0.f;   // straight path inside the start shell, down to its lower boundary
     int j0 = 0;        // start shell
     if constexpr (TRANSPORT == kTransportCurvedSurrogate) {
-      const float irq = 1.0f / rq;
+      const float irq = rcp_fast(rq);
       c0 = -fmaf(ux, Px * irq, fmaf(uy, Py * irq, uz * (qz * irq)));
       const bool alive = valid && emitted && (uz < 0.f) && (h0 >= p.h_obs) && !cull;
       // the network starts at the start shell's lower boundary R + h_b (the photon is
@@ -500,9 +500,9 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       const float dJ = (h0 - h_b) * (2.0f * Rf + h0 + h_b);  // r0^2 - r_b^2
       const float gb = fmaf(rc0, rc0, -dJ);                   // r_b^2 cos^2 at the boundary
       const bool reach = c0 > 0.f && gb > 0.f;
-      const float sgb = sqrtf(fmaxf(gb, 0.f));
-      leg = reach ? dJ / (rc0 + sgb) : 0.f;
-      float xin[kMlpIn] = {h_b, sgb / (Rf + h_b), atan2f(uy, ux),
+      const float sgb = sqrt_fast(fmaxf(gb, 0.f));
+      leg = reach ? dJ * rcp_fast(rc0 + sgb) : 0.f;
+      float xin[kMlpIn] = {h_b, sgb * rcp_fast(Rf + h_b), atan2f(uy, ux),
                            p.lam_min + ((float)kb + 0.5f) * ((p.lam_max - p.lam_min) / (float)p.n_lam), p.h_obs};
       use_mlp = alive && reach && (in_obs || mlp_in_domain(s_img, xin));
       if (!use_mlp || in_obs) {
@@ -535,10 +535,10 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
     }
     if constexpr (TRANSPORT == kTransportCurvedTable) {
       // correction interpolated from the table (Sec. 4.4.1), in the start shell
-      const float irq = 1.0f / rq;
+      const float irq = rcp_fast(rq);
       c0 = -fmaf(ux, Px * irq, fmaf(uy, Py * irq, uz * (qz * irq)));
       float4 v;
-      const float tz = sqrtf(fmaxf((1.0f - c0) * (1.0f + c0), 0.f)) / c0;
+      const float tz = sqrt_fast(fmaxf((1.0f - c0) * (1.0f + c0), 0.f)) * rcp_fast(c0);
       use_mlp = c0 > 0.f && table_lookup(p.ctab, min((int)(h0 * p.inv_dh), p.n_layers - 1), h0, tz, v);
       const float2 sp = s_lam[kb];
       ym[0] = v.x;
@@ -551,11 +551,11 @@ __device__ __forceinline__ void trace(const KParams& p, const float4* __restrict
       // central angle, plus the predicted extra ground distance, offset across,
       // optical path excess and log T (the network predicts them per metre of chord)
       const float r0 = Rf + h0, r1 = Rf + p.h_obs;
-      const float s0 = sqrtf(fmaxf((1.0f - c0) * (1.0f + c0), 0.f));
+      const float s0 = sqrt_fast(fmaxf((1.0f - c0) * (1.0f + c0), 0.f));
       const float drs = (h0 - p.h_obs) * (r0 + r1);
       const float rc = r0 * c0;
-      const float s_ch = drs / (rc + sqrtf(fmaf(rc, rc, -drs)));
-      const float xs = s_ch * s0 / r1;
+      const float s_ch = drs * rcp_fast(rc + sqrt_fast(fmaf(rc, rc, -drs)));
+      const float xs = s_ch * s0 * rcp_fast(r1);
       const float psi_s = fmaf(xs * xs * (1.0f / 6.0f), xs, xs);
       // the network's outputs are per metre of the chord from the start shell's lower
       // boundary (the same straight line, shortened by the leg inside the start
