@@ -70,12 +70,12 @@ METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density 
 KERNEL_SOURCES = ("cphot_kernels.hip", "cphot_device.h", "cphot_internal.h", "cphot_mlp.h")
 MEASURED = {
     # profiles/k_propagate_curved_inclined_1e7.md: mean of the six launches of the timed step
-    "inclined_curved": {"sha": "232f6f13ae42117c", "shape": [256, 768, 1, 90, 45, 1, 1],
-                        "valu_insts": 1.02483638013e10, "hbm_bytes": (176755.89 * 2.0 + 540798.21 * 1.0) * 1024,
+    "inclined_curved": {"sha": "6651564ceec86061", "shape": [256, 768, 1, 90, 45, 1, 1],
+                        "valu_insts": 9.777037921e9, "hbm_bytes": (176758.76 * 2.0 + 540796.13 * 1.0) * 1024,
                         "profile": "profiles/k_propagate_curved_inclined_1e7.md"},
     # profiles/k_propagate_telescope_1e6.md: mean of the six launches of the timed step
-    "telescope_layered": {"sha": "232f6f13ae42117c", "shape": [256, 1024, 1, 0, 0, 0, 0],
-                          "valu_insts": 7.388207217e7, "hbm_bytes": (16265.73 * 2.0 + 288.0 * 1.0) * 1024,
+    "telescope_layered": {"sha": "6651564ceec86061", "shape": [256, 1024, 1, 0, 0, 0, 0],
+                          "valu_insts": 7.388208e7, "hbm_bytes": (16270.16 * 2.0 + 288.0 * 1.0) * 1024,
                           "profile": "profiles/k_propagate_telescope_1e6.md"},
 }
 
@@ -418,6 +418,8 @@ def output_errors(gpu, orc, core, h_obs, dh, curved, lam_range=(300.0, 600.0), n
     dt = np.abs(gpu["t"] - orc["t"])
     dtau = np.abs(gpu["tau"] - orc["tau"])
     ddir = np.max(np.abs(np.stack([gpu["dx"] - orc["dx"], gpu["dy"] - orc["dy"], gpu["dz"] - orc["dz"]], 1)), 1)
+    # the position bar: 1e-4 max(r, 10 m) plus a 4e-7 rad direction error carried over the descent
+    pos_bar = 1e-4 * np.maximum(r, 10.0) + 4e-7 * np.maximum(h_e - h_obs, 0.0) / np.maximum(orc["dz"] ** 2, 1e-12)
     L = live
 
     def mx(a):
@@ -425,6 +427,8 @@ def output_errors(gpu, orc, core, h_obs, dh, curved, lam_range=(300.0, 600.0), n
     return {"records": int(len(orc)), "records_compared": int(L.sum()),
             "decision_flips": int((~same).sum()),
             "position_abs_m": mx(dpos[L]), "position_rel": mx(dpos[L] / np.maximum(r[L], 10.0)),
+            "position_vs_bar": mx(dpos[L] / pos_bar[L]),
+            "position_rel_worst_r_m": float(r[L][np.argmax(dpos[L] / np.maximum(r[L], 10.0))]) if L.any() else None,
             "time_abs_ns": mx(dt[L]), "time_rel": mx(dt[L] / np.maximum(np.abs(orc["t"][L]), 1e-9)),
             "tau_abs": mx(dtau[L]), "tau_rel": mx(dtau[L] / np.maximum(orc["tau"][L], 1e-12)),
             "direction_abs": mx(ddir), "wavelength_rel": mx(np.abs(gpu["lambda"] - orc["lambda"]) / orc["lambda"]),
