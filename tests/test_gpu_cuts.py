@@ -17,7 +17,7 @@ if not torch.cuda.is_available():
 from paper_2405_04229_amd import cphot  # noqa: E402
 
 C_GEN, C_UP, C_ABS, C_OUT, C_BIN = 3, 4, 5, 6, 7
-C_TRACK, C_PHOTON = 11, 12
+C_FALLBACK, C_TRACK, C_PHOTON = 9, 11, 12
 
 
 def _run(atm, S, ns, run, cuts, table=None):
@@ -43,6 +43,7 @@ def _check(atm, S, ns, run, table=None, expect_track=True):
         assert c[C_BIN] == c0[C_BIN]
         assert c[C_GEN] == c[C_UP] + c[C_ABS] + c[C_OUT] + c[C_BIN]
         assert c[C_GEN] + c[C_TRACK] == c0[C_GEN]
+        assert c[C_FALLBACK] == 0  # records compacted after the photon cut are no fallbacks
         if "track" in cuts and expect_track:
             assert c[C_TRACK] > 0, cuts
         if "photon" in cuts:
