@@ -546,7 +546,41 @@ def bench_telescope(torch, cphot, W, args, stream):
     if not args.no_surrogate:
         res["surrogate"] = bench_surrogate(torch, cphot, W, args, atm, S, run, exact_bins, ms, stream)
         log(f"telescope surrogate: {res['surrogate']['value']:.3e} photons/s")
+    if not args.no_cpu_baseline:
+        res["cpu_oracle"] = oracle_rate_subset(W, sh, geom, run, stride=100)
+        log(f"telescope oracle: {res['cpu_oracle']['value']:.3e} photons/s on {res['cpu_oracle']['cores']} cores")
     return res
+
+
+def oracle_rate_subset(W, sh, geom, run, stride, target_s=4.0):
+    """The FP64 oracle's rate on the segments with id = 0 mod stride of a
+    workload: one thread, then all host cores (a context figure beside the
+    telescope step; the headline's baseline is the inclined subset's)."""
+    from oracle import oracle as O
+    sub = {k: np.ascontiguousarray(v[::stride]) for k, v in sh.seg.items()}
+    oatm = O.Atmosphere(**W.ATMO_LAYERED)
+    orun = O.make_run(**run)
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(threads, 64))
+    passes1, t1 = 0, 0.0
+    while t1 < 0.25 * target_s and passes1 < 200:
+        t0 = time.perf_counter()
+        _, _, oc = O.propagate(oatm, orun, sub, geom, threads=1, id_stride=stride)
+        t1 += time.perf_counter() - t0
+        passes1 += 1
+    t1 /= passes1
+    photons = float(oc[3]) * run["bunch"]
+    passes, total = 0, 0.0
+    while total < target_s and passes < 200:
+        t0 = time.perf_counter()
+        O.propagate(oatm, orun, sub, geom, threads=threads, id_stride=stride)
+        total += time.perf_counter() - t0
+        passes += 1
+    return {"value": photons * passes / total, "unit": "photons/s", "cores": threads, "kind": "oracle",
+            "per_core": photons / t1, "single_thread_s": t1,
+            "sample": f"segments with id = 0 mod {stride} ({len(sub['x0'])} segments, the full launch's ids and random streams), "
+                      f"{int(oc[3])} records of bunch {run['bunch']} per pass; one thread {t1:.3f} s per pass, {threads} "
+                      f"threads {passes} passes in {total:.1f} s"}
 
 
 def bench_cuts(torch, cphot, S, atm, run, out_buf, bins, th, cnt, stream, args, exact_bins, exact_th, photons,
