@@ -124,6 +124,41 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   return pre + x - v;
 }
 
+// Two exclusive block scans at once (one barrier): returns the exclusive prefixes
+// of a and b, and their block totals. s_wave holds 2 * BS / 64 entries.
+template <int BS>
+__device__ __forceinline__ uint2 block_exclusive_scan2(uint32_t a, uint32_t b, uint32_t* s_wave, uint32_t& total_a,
+                                                      uint32_t& total_b) {
+  constexpr int kWaves = BS / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = a, y = b;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t xu = __shfl_up(x, d, 64), yu = __shfl_up(y, d, 64);
+    if (lane >= d) {
+      x += xu;
+      y += yu;
+    }
+  }
+  if (lane == 63) {
+    s_wave[wid] = x;
+    s_wave[kWaves + wid] = y;
+  }
+  __syncthreads();
+  uint32_t pa = 0, pb = 0, ta = 0, tb = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) {
+    const uint32_t u = s_wave[q], v = s_wave[kWaves + q];
+    pa += (q < wid) ? u : 0u;
+    pb += (q < wid) ? v : 0u;
+    ta += u;
+    tb += v;
+  }
+  total_a = ta;
+  total_b = tb;
+  return make_uint2(pa + x - a, pb + y - b);
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);

@@ -927,6 +927,10 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
   constexpr bool kDefer = kMlp || TRANSPORT == CPHOT_TRANSPORT_TABLE || TRANSPORT == kTransportCurvedTable ||
                           TRANSPORT == CPHOT_TRANSPORT_CURVED;
   constexpr bool kSort = kLayers && (MODE != MODE_COUNTS);
+  // ground-grid kernels number a tile's records Cherenkov first, then fluorescence,
+  // so that a wave holds one kind of record (one emission branch, one Philox call)
+  // except at the single boundary
+  constexpr bool kSplit = (DETECTOR == CPHOT_DETECTOR_GRID) && (MODE != MODE_COUNTS);
   // exact transport behind a surrogate: records outside the network's domain
   constexpr int kExact =
       (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == CPHOT_TRANSPORT_TABLE)       ? CPHOT_TRANSPORT_LAYERED
@@ -942,7 +946,8 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
   __shared__ float s_axz[BS];
   __shared__ uint4 s_q5[BS];  // record boundaries: Cherenkov, + band 0, + band 1
   __shared__ uint32_t s_off[BS + 1];
-  __shared__ uint32_t s_wave[BS / 64];
+  __shared__ uint32_t s_offf[kSplit ? BS + 1 : 1];  // fluorescence record offsets
+  __shared__ uint32_t s_wave[2 * (BS / 64)];
   __shared__ uint32_t s_src[kSort ? BS : 1];          // tile-local segment index of each slot
   __shared__ uint32_t s_bucket[kSort ? kMaxLayers + 1 : 1];
   __shared__ float4 s_lay[kLayers ? kMaxLayers : 1];
@@ -1096,17 +1101,24 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
     s_q4[slot] = q4;
     s_axz[slot] = axz;
     s_q5[slot] = q5;
-    s_off[slot] = nrec;
+    s_off[slot] = kSplit ? q5.x : nrec;
+    if constexpr (kSplit) s_offf[slot] = nrec - q5.x;
     __syncthreads();
-    uint32_t total;
-    const uint32_t mine = s_off[tid];
-    const uint32_t excl = block_exclusive_scan<BS>(mine, s_wave, total);
-    __syncthreads();
-    s_off[tid] = excl;
-    if (tid == BS - 1) {
-      s_off[BS] = total;
-      s_since += total;
+    uint32_t total, total_c = 0;
+    if constexpr (kSplit) {
+      uint32_t total_f;
+      const uint2 excl = block_exclusive_scan2<BS>(s_off[tid], s_offf[tid], s_wave, total_c, total_f);
+      __syncthreads();
+      s_off[tid] = excl.x;
+      s_offf[tid] = excl.y;
+      total = total_c + total_f;
+    } else {
+      const uint32_t mine = s_off[tid];
+      const uint32_t excl = block_exclusive_scan<BS>(mine, s_wave, total);
+      __syncthreads();
+      s_off[tid] = excl;
     }
+    if (tid == BS - 1) s_since += total;
     __syncthreads();
     // with the surrogate every lane of a wave runs each round (the tail lanes
     // repeat the last record and discard it); otherwise lanes stop at `total`
@@ -1174,11 +1186,15 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
       const uint32_t jr = base + tid;
       const bool valid = jr < total;
       const uint32_t j = valid ? jr : total - 1;
-      // largest slot lo in [0, BS) with s_off[lo] <= j (offsets never decrease)
+      // largest slot lo in [0, BS) with offset <= j (offsets never decrease); with
+      // the split numbering, records from total_c on are the fluorescence records
+      const bool fl = kSplit && j >= total_c;
+      const uint32_t* offs = fl ? s_offf : s_off;
+      const uint32_t jj = fl ? j - total_c : j;
       int lo = 0;
 #pragma unroll
-      for (int step = BS / 2; step >= 1; step >>= 1) lo += (s_off[lo + step] <= j) ? step : 0;
-      const uint32_t k = j - s_off[lo];
+      for (int step = BS / 2; step >= 1; step >>= 1) lo += (offs[lo + step] <= jj) ? step : 0;
+      const uint32_t k = jj - offs[lo] + (fl ? s_q5[lo].x : 0u);
       Photon ph;
       const float4 r3 = s_q3[lo];
       trace<TRANSPORT, DETECTOR, kTime, EXT>(p, s_lay, s_lam, s_img, &s_k, s_eff, s_mlpx + (kMlp ? (tid & ~63) : 0), s_q0[lo],
