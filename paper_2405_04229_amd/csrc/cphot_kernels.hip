@@ -929,8 +929,10 @@ __global__ __launch_bounds__(BS, kMinWavesPerSimd<TRANSPORT>) void k_propagate(K
   constexpr bool kSort = kLayers && (MODE != MODE_COUNTS);
   // ground-grid kernels number a tile's records Cherenkov first, then fluorescence,
   // so that a wave holds one kind of record (one emission branch, one Philox call)
-  // except at the single boundary
-  constexpr bool kSplit = (DETECTOR == CPHOT_DETECTOR_GRID) && (MODE != MODE_COUNTS);
+  // except at the single boundary; straight rays cost too little per record for the
+  // second scan and its LDS to pay
+  constexpr bool kSplit =
+      (DETECTOR == CPHOT_DETECTOR_GRID) && (MODE != MODE_COUNTS) && (TRANSPORT != CPHOT_TRANSPORT_STRAIGHT);
   // exact transport behind a surrogate: records outside the network's domain
   constexpr int kExact =
       (TRANSPORT == CPHOT_TRANSPORT_SURROGATE || TRANSPORT == CPHOT_TRANSPORT_TABLE)       ? CPHOT_TRANSPORT_LAYERED
