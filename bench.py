@@ -860,7 +860,29 @@ def bench_batched(torch, cphot, W, args, stream):
                                   "note": "coarser statistics: per-shower bins beyond 1 % of bunch 1"}
         step_5.close()
     step_g.close()
+    res["block_balance"] = block_balance(torch, cphot, S, det, n, tune)
     return res
+
+
+def block_balance(torch, cphot, S, det, n, tune):
+    """Records per block of the persistent grid's static partition (each block
+    walks a contiguous range of tiles), from the per-segment record counts."""
+    counts = torch.zeros(n, dtype=torch.int32, device="cuda")
+    cphot.segment_counts(S, det, counts)
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy().astype(np.int64)
+    bs = int(tune["block_size"])
+    tiles = np.add.reduceat(c, np.arange(0, n, bs))
+    nt = len(tiles)
+    grid = min(int(tune["grid_blocks"]), nt)  # the library clamps the grid to the tile count
+    first = (np.arange(grid, dtype=np.int64) * nt) // grid
+    per_block = np.add.reduceat(tiles, first)
+    mean = float(per_block.mean())
+    return {"blocks": grid, "tiles": nt, "records_per_block_mean": mean,
+            "records_per_block_max_over_mean": float(per_block.max()) / mean,
+            "records_per_block_cv": float(per_block.std()) / mean,
+            "note": "static contiguous tile ranges; more blocks than fit on the chip at once, so the "
+                    "dispatcher starts the later ones as earlier ones finish"}
 
 
 # ------------------------------------------------------------------------------ main

@@ -408,7 +408,7 @@ typedef struct {
 } cphot_tuning;
 
 /* Times cphot_propagate over candidate launch shapes (block size 128 / 256 /
- * 512; one block per tile or a persistent grid of 2, 3 or 4 blocks per CU; LDS grid
+ * 512; one block per tile or a persistent grid of 2, 3, 4 or 8 blocks per CU; LDS grid
  * histogram off, or on with the whole grid when it fits, else with windows:
  * the largest centred square, and rectangles fitted to the photon footprint of
  * a pilot launch (global atomics only; counts summed over showers): for a few

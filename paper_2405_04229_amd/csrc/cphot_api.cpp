@@ -1168,7 +1168,9 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
   for (int32_t b : bunches) {
     for (int bs : {128, 256, 512}) {
       std::vector<std::array<int, 6>> tried;  // launches already timed at this block size
-      for (int gpol = 0; gpol < 4 && rc == CPHOT_OK; ++gpol) {
+      // grids: one block per tile, or a persistent grid of 2, 3, 4 or 8 blocks per CU (more
+      // blocks than fit at once: the dispatcher starts later ones as earlier ones finish)
+      for (int gpol = 0; gpol < 5 && rc == CPHOT_OK; ++gpol) {
         // LDS histogram: off; the largest centred square that fits; a centred 64 x 64;
         // rectangles fitted to the footprint with up to 2304, 4096 and 9216 cells
         // and with all the room the block's LDS budget leaves
@@ -1190,7 +1192,7 @@ int cphot_autotune(const cphot_segments* seg, const cphot_detector* det, cphot_b
           cphot_detector d = *det;
           d.bunch = b;
           d.block_size = bs;
-          d.grid_blocks = gpol == 0 ? 0 : cus * (gpol == 1 ? 2 : (gpol == 2 ? 3 : 4));
+          d.grid_blocks = gpol == 0 ? 0 : cus * (gpol == 1 ? 2 : (gpol == 2 ? 3 : (gpol == 3 ? 4 : 8)));
           d.lds_hist = win.w < 0 ? 0 : 1;
           d.hist_window = win.w < 0 ? 0 : win.w;
           d.hist_window_h = win.w < 0 ? 0 : win.h;
