@@ -70,8 +70,8 @@ METRIC = "photons propagated/s, exact vs MLP surrogate, at <=1% per-bin density 
 KERNEL_SOURCES = ("cphot_kernels.hip", "cphot_device.h", "cphot_internal.h", "cphot_mlp.h")
 MEASURED = {
     # profiles/k_propagate_curved_inclined_1e7.md: mean of the six launches of the timed step
-    "inclined_curved": {"sha": "66494fdc41f0885c", "shape": [256, 768, 1, 90, 45, 1, 1],
-                        "valu_insts": 8.547437999e9, "hbm_bytes": (176754.41 * 2.0 + 538517.85 * 1.0) * 1024,
+    "inclined_curved": {"sha": "66494fdc41f0885c", "shape": [256, 2048, 1, 90, 45, 1, 1],
+                        "valu_insts": 8.553303493e9, "hbm_bytes": (176773.29 * 2.0 + 576439.55 * 1.0) * 1024,
                         "profile": "profiles/k_propagate_curved_inclined_1e7.md"},
     # profiles/k_propagate_telescope_1e6.md: mean of the six launches of the timed step
     "telescope_layered": {"sha": "66494fdc41f0885c", "shape": [256, 1024, 1, 0, 0, 0, 0],
