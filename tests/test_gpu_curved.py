@@ -77,10 +77,13 @@ def test_fluorescence_counts_bit_exact(transport):
     np.testing.assert_array_equal(gf, o["nf"].sum(axis=1))
 
 
+@pytest.mark.parametrize("emission", ["both", "fluorescence"])
 @pytest.mark.parametrize("transport", ["layered", "curved", "curved_walk"])
-def test_fluorescence_records_match_oracle(transport):
+def test_fluorescence_records_match_oracle(transport, emission):
+    """Grid kernels number a tile's Cherenkov records before its fluorescence
+    records; with fluorescence alone every tile has no Cherenkov record at all."""
     sh = W.make_shower(800, seed=91, xmax=600.0, zenith_deg=40.0, azimuth_deg=75.0, beta="R", dedx=(0.1, 2.0))
-    run = {**CURVED, "transport": transport, "emission": "both", "cell": 200.0, "seed": 16}
+    run = {**CURVED, "transport": transport, "emission": emission, "cell": 200.0, "seed": 16}
     g = parity.device_records(cases.ATMO_LAYERED, run, sh.seg, _geom(sh))
     o = O.trace(parity.oracle_atm(cases.ATMO_LAYERED), _orc_run(run, 16), sh.seg, core=sh.core, axis=sh.axis)
     flips, rep = parity.compare_records(g, o, sh.core, cases.ATMO_LAYERED, run)
@@ -90,6 +93,8 @@ def test_fluorescence_records_match_oracle(transport):
     want = np.asarray(O.FL_LAMBDA, dtype=np.float32)[o["source"][fl] - 1]
     np.testing.assert_array_equal(g["lambda"][fl], want)
     assert (o["source"] > 0).sum() > 5000 and ((o["source"] > 0) & (o["state"] == 0)).sum() > 500
+    if emission == "fluorescence":
+        assert (o["source"] == 0).sum() == 0
     assert flips <= max(3, parity.MAX_FLIP_FRACTION * len(o))
 
 
